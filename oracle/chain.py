@@ -1,0 +1,71 @@
+"""Which factors make up each preconditioner, and how they are applied.
+
+Algorithm 4 (AIRGA with reuse of the SPAI preconditioner) builds, for outer
+round z and shift i:
+
+* z = 1, i = 1: ``P_1^(1)`` by SPAI at ``s_1^(1)``;
+* z = 1, i > 1: ``Q_i^(1)`` from ``min ||A_{i-1}^(1) - A_i^(1) Q||_F``
+  (horizontal direction);
+* z > 1, i = 1: ``Q_1^(z)`` from ``min ||A_1^(z-1) - A_1^(z) Q||_F``
+  (vertical direction, only between the first shifts of consecutive rounds);
+* z > 1, i > 1: ``Q_i^(z)`` from ``min ||A_{i-1}^(z) - A_i^(z) Q||_F``;
+
+and solves with the preconditioner
+``Q_i^(z) ... Q_2^(z) Q_1^(z) ... Q_1^(2) P_1^(1)``, i.e. ``i + z - 1``
+factors.  The product is never formed (Section III-B): applying it to a
+vector means applying ``P_1^(1)`` first and ``Q_i^(z)`` last; its transpose
+applies the transposed factors in the reverse order.
+
+Pinned by: a hand-written expected schedule for three rounds, and the chain
+apply against the explicitly formed dense product on small matrices
+(tests/test_oracle_pins.py).
+"""
+from __future__ import annotations
+
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+FactorSpec = Tuple  # ("spai", sigma) or ("update", sigma_prev, sigma_new)
+
+
+def schedule(rounds: Sequence[Sequence[float]]):
+    """Return ``(specs, chains)``.
+
+    ``specs[f]`` describes factor f; ``chains[z][i]`` is the list of factor
+    indices of the preconditioner for shift i of round z, in application
+    order (first applied first)."""
+    specs: List[FactorSpec] = []
+    chains: List[List[List[int]]] = []
+    vertical: List[int] = []  # P_1^(1), Q_1^(2), ..., Q_1^(z)
+    for z, sig in enumerate(rounds):
+        sig = [float(s) for s in sig]
+        if z == 0:
+            specs.append(("spai", sig[0]))
+        else:
+            specs.append(("update", float(rounds[z - 1][0]), sig[0]))
+        vertical.append(len(specs) - 1)
+        horizontal: List[int] = []
+        round_chains = [list(vertical)]
+        for i in range(1, len(sig)):
+            specs.append(("update", sig[i - 1], sig[i]))
+            horizontal.append(len(specs) - 1)
+            round_chains.append(list(vertical) + list(horizontal))
+        chains.append(round_chains)
+    return specs, chains
+
+
+def apply(factors, chain: Sequence[int], v: np.ndarray) -> np.ndarray:
+    """``F_chain[-1] ( ... F_chain[1] (F_chain[0] v))``, factors never multiplied together."""
+    out = np.asarray(v, dtype=np.float64)
+    for f in chain:
+        out = factors[f] @ out
+    return out
+
+
+def apply_transpose(factors, chain: Sequence[int], v: np.ndarray) -> np.ndarray:
+    """Transpose of :func:`apply`: ``F_chain[0]^T ( ... (F_chain[-1]^T v))``."""
+    out = np.asarray(v, dtype=np.float64)
+    for f in reversed(chain):
+        out = factors[f].T @ out
+    return out
