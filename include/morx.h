@@ -1,0 +1,195 @@
+/*
+ * morx.h -- C ABI of libmorx: shifted sparse solves with a reused SPAI
+ * preconditioner on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Singh & Ahuja, "Reusing Preconditioners in Projection based Model
+ * Order Reduction Algorithms"; Section III-B lists the sequence
+ * A_1 X_1 = F_1, ..., A_l X_l = F_l, appendix B gives the first-order form
+ * A_i = sigma_i D - K used here with D -> E, K -> A, F -> B):
+ *
+ *     (sigma_i E - A) x_ij = b_j,   (sigma_i E - A)^T y_ij = c_j
+ *
+ * for every shift sigma_i of a shift set and every column j of B and C,
+ * solved by right-preconditioned two-sided BiCG (Section III-A).  The
+ * preconditioner of the first shift is a sparse approximate inverse (SPAI,
+ * eqs. gen-precond / gen-precond-par); every later shift reuses it through a
+ * column-wise least-squares update Q_i with min ||A_{i-1} - A_i Q_i||_F and
+ * P_i = Q_i P_{i-1} (Table 2, second approach; Section III-C horizontal and
+ * vertical directions; Algorithm 4 for the order), applied as a chain of
+ * sparse products and never formed.
+ *
+ * Conventions for every call:
+ *  - Matrices are FP64; indices are int32; dense blocks are column-major with
+ *    a leading dimension (ld >= n).  Arguments marked (dev) are device
+ *    pointers on the context's device, (host) are host pointers.
+ *  - The caller owns every buffer it passes and keeps it alive until the call
+ *    returns.  Calls that take a stream (a hipStream_t passed as void*, NULL
+ *    for the null stream) order their device work after work already queued
+ *    on it; every call in this header returns only after its device work is
+ *    complete, so outputs are ready on return.
+ *  - Every call returns a morx_status; on failure morx_last_error() describes
+ *    the first failing check of the calling thread.  Inputs are not modified.
+ *  - Calls on one context are not thread-safe unless stated otherwise.
+ *  - The factor pattern S is pattern(A) plus the diagonal, shared by every
+ *    SPAI and update factor; limits: |column of S| <= 31 entries, the union
+ *    of rows touched by one column's pattern <= 512 rows, n < 2^31,
+ *    nnz(S) < 2^31.  Larger patterns give MORX_E_UNSUPPORTED.
+ */
+#ifndef MORX_H
+#define MORX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct morx_ctx_s* morx_ctx;        /* library-owned device context            */
+typedef struct morx_system_s* morx_system;  /* library-owned resident copy of A, E, S  */
+typedef struct morx_factor_s* morx_factor;  /* library-owned SPAI or update factor     */
+
+typedef enum {
+  MORX_OK = 0,
+  MORX_E_INVALID = -1,       /* bad argument (size, pointer, unsorted CSR, ...)     */
+  MORX_E_NOMEM = -2,         /* device or host allocation failed                    */
+  MORX_E_HIP = -3,           /* a HIP runtime call failed                           */
+  MORX_E_SINGULAR_LS = -4,   /* a local least-squares matrix is rank deficient      */
+  MORX_E_NOT_CONVERGED = -5, /* a column missed the tolerance within the limits     */
+  MORX_E_BREAKDOWN = -6,     /* BiCG breakdown persisted through every restart      */
+  MORX_E_NONFINITE = -7,     /* NaN or Inf in an input                              */
+  MORX_E_ADMISSION = -8,     /* serving: request does not fit the memory budget     */
+  MORX_E_UNSUPPORTED = -9,   /* pattern beyond the documented limits                */
+  MORX_E_PENDING = -10       /* serving: request not finished yet                   */
+} morx_status;
+
+typedef enum { MORX_F64 = 0, MORX_F32 = 1, MORX_BF16 = 2 } morx_prec;
+
+typedef enum {
+  MORX_CHAIN_RESET = 0,      /* SPAI at sigmas[0], then horizontal updates (round 1)  */
+  MORX_CHAIN_NEXT_ROUND = 1  /* vertical update from the previous call's first shift
+                                to sigmas[0], then horizontal updates (round z > 1)   */
+} morx_chain_policy;
+
+/* Solver options.  morx_opts_default() fills the defaults given here. */
+typedef struct {
+  double tol;            /* target true relative residual, primal and dual (1e-10) */
+  int32_t maxit;         /* iterations per restart cycle; <= 0 means min(n, 20000)  */
+  int32_t max_restarts;  /* true-residual restarts per column (3)                   */
+  int32_t precond_prec;  /* morx_prec: storage of factor values (MORX_F64)          */
+  int32_t chain;         /* morx_chain_policy (MORX_CHAIN_RESET)                    */
+  int32_t want_dual;     /* 1: also solve the transposed systems with C (1)         */
+  int32_t batched;       /* 1: all shifts x columns in one multi-column solve;
+                            0: one shift and one column at a time (1)              */
+  int32_t poll_iters;    /* iterations between host convergence checks (8)          */
+  int32_t use_graph;     /* 1: replay the iteration segment as a HIP graph (1)      */
+  int32_t reserved;
+} morx_opts;
+
+/* Per-column result.  status is a morx_status. */
+typedef struct {
+  int32_t status;
+  int32_t iters;         /* BiCG iterations over all restart cycles                */
+  int32_t restarts;
+  int32_t reserved;
+  double relres_primal;  /* ||b - A_s x|| / ||b||, recomputed in FP64 at the end    */
+  double relres_dual;    /* ||c - A_s^T y|| / ||c||                                 */
+} morx_col_stats;
+
+void morx_opts_default(morx_opts* opts);
+const char* morx_status_str(int32_t status);
+/* Message for the calling thread's last failure ("" if none). */
+const char* morx_last_error(void);
+
+/* Context on HIP device `device`.  Owns internal streams and graphs. */
+morx_status morx_create(morx_ctx* out, int device);
+morx_status morx_destroy(morx_ctx ctx);
+
+/*
+ * Copy A (CSR: rowptr[n+1], colind[nnz], val[nnz], all (dev); columns sorted
+ * strictly increasing within each row) and E = diag(e_diag[n]) (dev) into
+ * library-owned device memory, and prepare the pattern S, its transpose and
+ * the sliced-ELL layouts used by every kernel (Section III-A: the n column
+ * problems of the SPAI all come from S).  Unsorted or out-of-range indices
+ * give MORX_E_INVALID; NaN/Inf values give MORX_E_NONFINITE.
+ */
+morx_status morx_system_create(morx_ctx ctx, int64_t n, int64_t nnz, const int32_t* rowptr,
+                               const int32_t* colind, const double* val, const double* e_diag,
+                               void* stream, morx_system* out);
+morx_status morx_system_destroy(morx_system sys);
+/* nnz(S) and the device bytes held by the system (excluding factors). */
+morx_status morx_system_info(morx_system sys, int64_t* nnz_pattern, int64_t* resident_bytes);
+/* Copy S in CSR form: rowptr[n+1], colind[nnz(S)] (dev, caller-allocated). */
+morx_status morx_system_pattern(morx_system sys, int32_t* rowptr, int32_t* colind, void* stream);
+
+/*
+ * Y = (sigma E - A) X, or (sigma E - A)^T X when trans != 0, for ncol
+ * columns (X, Y (dev), column-major, ldx, ldy >= n).  The shifted matrix is
+ * never formed: E's diagonal is applied inside the product (appendix B form).
+ */
+morx_status morx_shifted_apply(morx_system sys, double sigma, int32_t trans, int32_t ncol,
+                               const double* X, int64_t ldx, double* Y, int64_t ldy,
+                               void* stream);
+
+/*
+ * SPAI factor of A_s = sigma E - A on the pattern S: column k minimises
+ * ||e_k - A_s p_k||_2 over vectors supported on column k of S (eq.
+ * gen-precond-par).  Values are computed in FP64 and stored at `prec`.
+ */
+morx_status morx_factor_spai(morx_system sys, double sigma, int32_t prec, void* stream,
+                             morx_factor* out);
+/*
+ * Reuse factor Q with min ||A_prev - A_new Q||_F on the pattern S, where
+ * A_prev = sigma_prev E - A and A_new = sigma_new E - A (Table 2, second
+ * approach; Section III-C).  The new preconditioner is Q P_prev.
+ */
+morx_status morx_factor_update(morx_system sys, double sigma_prev, double sigma_new,
+                               int32_t prec, void* stream, morx_factor* out);
+/* Stored values widened to FP64, in the CSR order of S (val[nnz(S)], dev). */
+morx_status morx_factor_values(morx_factor f, double* val, void* stream);
+morx_status morx_factor_destroy(morx_factor f);
+
+/*
+ * Apply the product F_{k-1} ... F_1 F_0 (chain[0] applied first) to ncol
+ * columns, or its transpose F_0^T ... F_{k-1}^T when trans != 0, one sparse
+ * product per factor (Section III-B: the product is never formed).
+ * X and Y (dev) may not overlap.
+ */
+morx_status morx_chain_apply(morx_system sys, int32_t nfactor, const morx_factor* chain,
+                             int32_t trans, int32_t ncol, const double* X, int64_t ldx,
+                             double* Y, int64_t ldy, void* stream);
+
+/*
+ * The hot path.  For the nshift shifts sigmas[] (host, chain order) and the
+ * m columns of B (dev, n x m, ldb) and C (dev, n x m, ldc; NULL when
+ * opts->want_dual == 0), build the preconditioner chain as Algorithm 4 does
+ * (policy opts->chain; the system remembers the vertical chain and the first
+ * shift between calls) and solve every pair to opts->tol.  Output X (dev,
+ * n x (m*nshift), ldx) holds column j of shift i at column i*m + j; Y
+ * likewise (NULL when want_dual == 0).  stats (host) has m*nshift entries in
+ * the same order.  Returns the worst column status; other columns' results
+ * stay valid.
+ */
+morx_status morx_solve_shifts(morx_system sys, int32_t nshift, const double* sigmas, int32_t m,
+                              const double* B, int64_t ldb, const double* C, int64_t ldc,
+                              double* X, int64_t ldx, double* Y, int64_t ldy,
+                              const morx_opts* opts, morx_col_stats* stats, void* stream);
+
+/*
+ * Two-sided Petrov-Galerkin projection (Section II, reduced model after
+ * Algorithm 2; descriptor form for E != I):
+ *   Ar = W^T A V, Er = W^T E V (r x r), Br = W^T B (r x m), Cr = V^T C (r x q)
+ * with V, W (dev, n x r, ldv/ldw) orthonormalised first when
+ * orthonormalize != 0 (shifted Cholesky-QR, three passes).  Outputs are host
+ * column-major arrays.  r <= 64, m, q <= 64.
+ */
+morx_status morx_project(morx_system sys, int32_t r, const double* V, int64_t ldv,
+                         const double* W, int64_t ldw, int32_t m, const double* B, int64_t ldb,
+                         int32_t q, const double* C, int64_t ldc, double* Ar, double* Er,
+                         double* Br, double* Cr, int32_t orthonormalize, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MORX_H */

@@ -1,0 +1,103 @@
+"""Convenience wrappers over the libmorx binding (marshalling only).
+
+``Context`` and ``System`` own the C handles; ``System.solve_shifts`` and
+``System.project`` move host arrays to the device, call the C entry points
+and return torch tensors.  No step of the method runs here.
+"""
+from __future__ import annotations
+
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import morx
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.device = device
+        self.handle = morx.morx_create(device)
+
+    def close(self):
+        if self.handle:
+            morx.morx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def to_dev(a, dtype=torch.float64, device="cuda"):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
+
+
+def block_to_dev(M: np.ndarray, device="cuda") -> torch.Tensor:
+    """Column-major (n, m) device block from a host array (n,) or (n, m)."""
+    M = np.asarray(M, dtype=np.float64)
+    if M.ndim == 1:
+        M = M[:, None]
+    t = torch.as_tensor(np.ascontiguousarray(M.T), device=device)
+    return t.t()
+
+
+class System:
+    """Resident ``A`` (scipy CSR) and ``E = diag(e)`` on the context's device."""
+
+    def __init__(self, ctx: Context, A, e, stream=None):
+        self.ctx = ctx
+        A = A.tocsr()
+        A.sort_indices()
+        self.n = A.shape[0]
+        dev = f"cuda:{ctx.device}"
+        rowptr = to_dev(A.indptr, torch.int32, dev)
+        colind = to_dev(A.indices, torch.int32, dev)
+        val = to_dev(A.data, torch.float64, dev)
+        ed = to_dev(e, torch.float64, dev)
+        self.handle = morx.morx_system_create(ctx.handle, rowptr, colind, val, ed, stream)
+        self.nnz_pattern, self.resident_bytes = morx.morx_system_info(self.handle)
+        self.device = dev
+
+    def close(self):
+        if self.handle:
+            morx.morx_system_destroy(self.handle)
+            self.handle = None
+
+    def pattern(self):
+        rp = torch.empty(self.n + 1, dtype=torch.int32, device=self.device)
+        ci = torch.empty(self.nnz_pattern, dtype=torch.int32, device=self.device)
+        morx.morx_system_pattern(self.handle, rp, ci)
+        return rp.cpu().numpy(), ci.cpu().numpy()
+
+    def solve_shifts(self, sigmas: Sequence[float], B, C=None, prec: str = "f64", tol: float = 1e-10,
+                     batched: bool = True, next_round: bool = False, use_graph: bool = True,
+                     poll_iters: int = 8, maxit: int = 0, max_restarts: int = 3,
+                     raise_on_error: bool = True):
+        """Returns (X, Y, status, stats); X, Y are column-major (n, m*nshift) tensors."""
+        Bd = B if isinstance(B, torch.Tensor) else block_to_dev(B, self.device)
+        Cd = None
+        if C is not None:
+            Cd = C if isinstance(C, torch.Tensor) else block_to_dev(C, self.device)
+        m = Bd.shape[1]
+        ns = len(sigmas)
+        X = morx.colmajor(m * ns, self.n, device=self.device)
+        Y = morx.colmajor(m * ns, self.n, device=self.device) if Cd is not None else None
+        o = morx.morx_opts_default()
+        o.tol = tol
+        o.precond_prec = morx.PREC[prec]
+        o.chain = morx.MORX_CHAIN_NEXT_ROUND if next_round else morx.MORX_CHAIN_RESET
+        o.want_dual = 1 if Cd is not None else 0
+        o.batched = 1 if batched else 0
+        o.use_graph = 1 if use_graph else 0
+        o.poll_iters = poll_iters
+        o.maxit = maxit
+        o.max_restarts = max_restarts
+        st, stats = morx.morx_solve_shifts(self.handle, sigmas, Bd, Cd, X, Y, o,
+                                           raise_on_error=raise_on_error)
+        return X, Y, st, stats
+
+    def project(self, V, W, B=None, C=None, orthonormalize=True):
+        return morx.morx_project(self.handle, V, W, B, C, orthonormalize)

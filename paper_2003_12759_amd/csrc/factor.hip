@@ -1,0 +1,488 @@
+// SPAI and reuse-update factors as n independent column least-squares
+// problems, one wavefront per column (Section III-A, eq. gen-precond-par; the
+// note under Algorithm 4 says the update minimisations are solved the same way).
+//
+// Column k of a factor is supported on J_k = column k of S.  Its problem only
+// touches the rows I_k of S[:, J_k]; the wave gathers those nonzeros, sorts
+// their row indices to get I_k, builds the dense |I_k| x |J_k| matrix of
+// A_s = sigma E - A in LDS and solves it with Householder QR:
+//   SPAI:    min || e_k        - A_new[I_k, J_k] p ||
+//   update:  min || A_prev[I_k, k] - A_new[I_k, J_k] q ||
+// One wave handles several shifts for the same column, so the gather and sort
+// are done once per column.
+#include <math.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace {
+
+constexpr int kLdsBudget = 60 * 1024;  // dynamic LDS, below the 64 KiB workgroup limit
+
+struct LsLayout {
+  int Tpad, Tmax, ldm, mmax;
+  size_t off_keys, off_tri, off_tv, off_uniq, off_J, off_q, off_M, bytes;
+};
+
+LsLayout ls_layout(int maxJ, int maxT, int maxI) {
+  LsLayout L;
+  L.Tmax = std::max(maxT, 1);
+  L.Tpad = 64;
+  while (L.Tpad < L.Tmax) L.Tpad <<= 1;
+  L.ldm = std::max(maxI, 1) | 1;  // odd stride: fewer LDS bank conflicts
+  L.mmax = std::max(maxJ, 1);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o += (bytes + 15) / 16 * 16;
+    return r;
+  };
+  L.off_keys = take((size_t)L.Tpad * 4);
+  L.off_tri = take((size_t)L.Tmax * 4);
+  L.off_tv = take((size_t)L.Tmax * 8);
+  L.off_uniq = take((size_t)std::max(maxI, 1) * 4);
+  L.off_J = take(32 * 4);
+  L.off_q = take(32 * 8);
+  L.off_M = take((size_t)L.ldm * (L.mmax + 1) * 8);
+  L.bytes = o;
+  return L;
+}
+
+__device__ __forceinline__ int wave_excl_scan(int v, int lane, int* total) {
+  int inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int t = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += t;
+  }
+  *total = __shfl(inc, 63, 64);
+  return inc - v;
+}
+
+// Gather the nonzeros of S[:, J_k] (rows into keys[], (row-local, col) later),
+// sort the rows and compact them into uniq[].  Returns m = |J_k|, T, nI.
+__device__ void gather_sort_unique(const int32_t* __restrict__ trowptr,
+                                   const int32_t* __restrict__ tcol,
+                                   const double* __restrict__ tval, int64_t k, int lane, int Tpad,
+                                   int* keys, int* tri, double* tv, int* uniq, int* J, int* m_out,
+                                   int* T_out, int* nI_out) {
+  const int lo = trowptr[k];
+  const int m = trowptr[k + 1] - lo;
+  int len = 0, j = 0;
+  if (lane < m) {
+    j = tcol[lo + lane];
+    J[lane] = j;
+    len = trowptr[j + 1] - trowptr[j];
+  }
+  int T;
+  int off = wave_excl_scan(len, lane, &T);
+  if (lane < m) {
+    const int b = trowptr[j];
+    for (int u = 0; u < len; ++u) {
+      keys[off + u] = tcol[b + u];
+      tri[off + u] = lane;  // local column; the local row is added below
+      if (tv) tv[off + u] = tval[b + u];
+    }
+  }
+  for (int t = T + lane; t < Tpad; t += 64) keys[t] = 0x7fffffff;
+  __syncthreads();
+  // bitonic sort of the row indices (ascending)
+  for (int size = 2; size <= Tpad; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = lane; t < Tpad; t += 64) {
+        int p = t ^ stride;
+        if (p > t) {
+          int a = keys[t], b = keys[p];
+          bool up = ((t & size) == 0);
+          if ((a > b) == up) {
+            keys[t] = b;
+            keys[p] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // compact unique rows
+  int base = 0;
+  for (int t0 = 0; t0 < T; t0 += 64) {
+    int t = t0 + lane;
+    bool first = (t < T) && (t == 0 || keys[t] != keys[t - 1]);
+    unsigned long long mask = __ballot(first);
+    int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+    if (first) uniq[pos] = keys[t];
+    base += __popcll(mask);
+  }
+  __syncthreads();
+  *m_out = m;
+  *T_out = T;
+  *nI_out = base;
+}
+
+__device__ __forceinline__ int find_row(const int* uniq, int nI, int row) {
+  int lo = 0, hi = nI - 1;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (uniq[mid] < row) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_ls_count(const int32_t* __restrict__ trowptr,
+                                                  const int32_t* __restrict__ tcol, int64_t n,
+                                                  int* __restrict__ stats) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int lo = trowptr[k], m = trowptr[k + 1] - lo;
+  int T = 0;
+  for (int a = 0; a < m; ++a) {
+    int j = tcol[lo + a];
+    T += trowptr[j + 1] - trowptr[j];
+  }
+  atomicMax(&stats[0], m);
+  atomicMax(&stats[1], T);
+}
+
+__global__ __launch_bounds__(64) void k_ls_unique(const int32_t* __restrict__ trowptr,
+                                                  const int32_t* __restrict__ tcol, int64_t n,
+                                                  LsLayout L, int* __restrict__ stats) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  int* keys = (int*)(lds + L.off_keys);
+  int* tri = (int*)(lds + L.off_tri);
+  int* uniq = (int*)(lds + L.off_uniq);
+  int* J = (int*)(lds + L.off_J);
+  const int lane = threadIdx.x;
+  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+    int m, T, nI;
+    gather_sort_unique(trowptr, tcol, nullptr, k, lane, L.Tpad, keys, tri, nullptr, uniq, J, &m,
+                       &T, &nI);
+    if (lane == 0) atomicMax(&stats[2], nI);
+    __syncthreads();
+  }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(64) void k_factor_ls(
+    const int32_t* __restrict__ trowptr, const int32_t* __restrict__ tcol,
+    const double* __restrict__ tval, const double* __restrict__ e,
+    const int32_t* __restrict__ tp2s, const int32_t* __restrict__ sellT_off, int64_t n,
+    const FactorJob* __restrict__ jobs, int njobs, LsLayout L, int* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  int* keys = (int*)(lds + L.off_keys);
+  int* tri = (int*)(lds + L.off_tri);
+  double* tv = (double*)(lds + L.off_tv);
+  int* uniq = (int*)(lds + L.off_uniq);
+  int* J = (int*)(lds + L.off_J);
+  double* q = (double*)(lds + L.off_q);
+  double* M = (double*)(lds + L.off_M);
+  const int lane = threadIdx.x;
+  const int ldm = L.ldm;
+
+  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+    int m, T, nI;
+    gather_sort_unique(trowptr, tcol, tval, k, lane, L.Tpad, keys, tri, tv, uniq, J, &m, &T, &nI);
+    // local row of every gathered nonzero (keys[] is sorted now, so walk the
+    // columns again in gather order)
+    {
+      int len = 0, j = 0;
+      if (lane < m) {
+        j = J[lane];
+        len = trowptr[j + 1] - trowptr[j];
+      }
+      int Tt;
+      int off = wave_excl_scan(len, lane, &Tt);
+      if (lane < m) {
+        const int b = trowptr[j];
+        for (int u = 0; u < len; ++u) {
+          int li = find_row(uniq, nI, tcol[b + u]);
+          tri[off + u] = (li << 5) | lane;
+        }
+      }
+    }
+    __shared__ int s_kloc, s_ak;
+    if (lane == 0) s_kloc = find_row(uniq, nI, (int)k);
+    if (lane < m && J[lane] == (int)k) s_ak = lane;
+    __syncthreads();
+    const int kloc = s_kloc, ak = s_ak;
+    const double ek = e[k];
+    int CG = 1;
+    while (CG < m + 1) CG <<= 1;
+    const int RG = 64 / CG;
+    const int cc = lane % CG, g = lane / CG;
+
+    for (int jb = 0; jb < njobs; ++jb) {
+      const FactorJob job = jobs[jb];
+      const double sn = job.sigma_new;
+      // dense local matrix [A_new(I_k, J_k) | rhs], column-major with stride ldm
+      for (int t = lane; t < (m + 1) * ldm; t += 64) M[t] = 0.0;
+      __syncthreads();
+      for (int t = lane; t < T; t += 64) {
+        int a = tri[t] & 31, li = tri[t] >> 5;
+        double v = -tv[t];
+        if (uniq[li] == J[a]) v += sn * e[J[a]];
+        M[a * ldm + li] = v;
+      }
+      __syncthreads();
+      if (job.is_spai) {
+        if (lane == 0) M[m * ldm + kloc] = 1.0;
+      } else {
+        for (int r = lane; r < nI; r += 64) M[m * ldm + r] = M[ak * ldm + r];
+        __syncthreads();
+        if (lane == 0) M[m * ldm + kloc] -= (sn - job.sigma_prev) * ek;
+      }
+      __syncthreads();
+      // Householder QR of the m columns, applied to the right-hand side too
+      bool singular = false;
+      for (int c = 0; c < m; ++c) {
+        double s = 0.0;
+        if (cc >= c && cc <= m) {
+          for (int r = c + g; r < nI; r += RG) s += M[c * ldm + r] * M[cc * ldm + r];
+        }
+        for (int off = CG; off < 64; off <<= 1) s += __shfl_xor(s, off, 64);
+        s = __shfl(s, cc, 64);  // one value per column for every row group
+        const double norm2 = __shfl(s, c, 64);
+        const double x0 = M[c * ldm + c];
+        double scale = 0.0;
+        for (int a = 0; a <= c; ++a) scale = fmax(scale, fabs(M[a * ldm + a]));
+        if (!(norm2 > 0.0) || sqrt(norm2) <= 1e-14 * fmax(scale, 1e-300)) singular = true;
+        const double alpha = (x0 > 0.0) ? -sqrt(norm2) : sqrt(norm2);
+        const double vtv = 2.0 * alpha * (alpha - x0);
+        if (cc > c && cc <= m && vtv > 0.0) {
+          const double d = s - alpha * M[cc * ldm + c];
+          const double tau = 2.0 * d / vtv;
+          for (int r = c + g; r < nI; r += RG) {
+            const double vr = (r == c) ? (x0 - alpha) : M[c * ldm + r];
+            M[cc * ldm + r] -= tau * vr;
+          }
+        }
+        __syncthreads();
+        if (lane == 0) M[c * ldm + c] = alpha;
+        __syncthreads();
+      }
+      // back substitution R q = (Q^T rhs)(0:m)
+      if (lane == 0) {
+        for (int i = m - 1; i >= 0; --i) {
+          double acc = M[m * ldm + i];
+          for (int j2 = i + 1; j2 < m; ++j2) acc -= M[j2 * ldm + i] * q[j2];
+          q[i] = singular ? 0.0 : acc / M[i * ldm + i];
+        }
+      }
+      __syncthreads();
+      if (lane < m) {
+        const double v = q[lane];
+        const int64_t posT = (int64_t)sellT_off[k / kSlice] + (int64_t)lane * kSlice + (k % kSlice);
+        store_val<VT>((VT*)job.valsT + posT, v);
+        store_val<VT>((VT*)job.vals + tp2s[trowptr[k] + lane], v);
+      }
+      if (singular && lane == 0) atomicOr(status, 1);
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void k_fill_zero_bytes(uint32_t* p, int64_t words) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < words) p[i] = 0u;
+}
+
+template <typename VT>
+__global__ void k_factor_to_csr(const VT* __restrict__ vals, const int32_t* __restrict__ csr2sell,
+                                int64_t nnz, double* __restrict__ out) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nnz) out[p] = load_val<VT>(vals + csr2sell[p]);
+}
+
+int ls_grid(morx_system sys) {
+  int64_t cap = (int64_t)std::max(sys->ctx->num_cu, 1) * 64;
+  return (int)std::min<int64_t>(sys->n, std::max<int64_t>(cap, 1));
+}
+
+}  // namespace
+
+morx_status ls_pattern_stats(morx_system sys, hipStream_t st) {
+  DevBuf sb;
+  MORX_TRY(dev_alloc(sb, 4 * sizeof(int)));
+  MORX_HIP(hipMemsetAsync(sb.p, 0, 4 * sizeof(int), st));
+  int* stats = (int*)sb.p;
+  k_ls_count<<<(unsigned)((sys->n + 255) / 256), 256, 0, st>>>(sys->trowptr, sys->tcol, sys->n,
+                                                              stats);
+  int h[4] = {0, 0, 0, 0};
+  hipError_t err = hipGetLastError();
+  if (err == hipSuccess) err = hipMemcpyAsync(h, stats, 4 * sizeof(int), hipMemcpyDeviceToHost, st);
+  if (err == hipSuccess) err = hipStreamSynchronize(st);
+  if (err != hipSuccess) {
+    dev_free(sb);
+    morx_set_error("ls_pattern_stats: %s", hipGetErrorString(err));
+    return MORX_E_HIP;
+  }
+  sys->max_J = h[0];
+  sys->max_T = h[1];
+  sys->ls_supported = (h[0] <= kMaxJ && h[1] <= kMaxTriples);
+  if (sys->ls_supported) {
+    // the unique-row pass needs room for up to T rows and no dense matrix
+    LsLayout L = ls_layout(h[0], h[1], h[1]);
+    L.bytes = L.off_M;
+    k_ls_unique<<<ls_grid(sys), 64, L.bytes, st>>>(sys->trowptr, sys->tcol, sys->n, L, stats);
+    err = hipGetLastError();
+    if (err == hipSuccess) err = hipMemcpyAsync(h, stats, 4 * sizeof(int), hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipStreamSynchronize(st);
+    if (err != hipSuccess) {
+      dev_free(sb);
+      morx_set_error("ls_pattern_stats: %s", hipGetErrorString(err));
+      return MORX_E_HIP;
+    }
+    sys->max_I = h[2];
+    LsLayout L2 = ls_layout(sys->max_J, sys->max_T, sys->max_I);
+    sys->ls_supported = (sys->max_I <= kMaxI) && (L2.bytes <= (size_t)kLdsBudget);
+  }
+  dev_free(sb);
+  return MORX_OK;
+}
+
+morx_status factor_alloc(morx_system sys, int32_t prec, morx_factor* out) {
+  for (size_t i = 0; i < sys->factor_pool.size(); ++i) {
+    if (sys->factor_pool[i]->prec == prec) {
+      *out = sys->factor_pool[i];
+      sys->factor_pool.erase(sys->factor_pool.begin() + i);
+      return MORX_OK;
+    }
+  }
+  morx_factor f = new morx_factor_s();
+  f->sys = sys;
+  f->prec = prec;
+  f->pooled = true;
+  const size_t b = prec_bytes(prec);
+  morx_status s = dev_alloc(f->vals, (size_t)sys->sell.nnz_sell * b);
+  if (s == MORX_OK) s = dev_alloc(f->valsT, (size_t)sys->sellT.nnz_sell * b);
+  if (s != MORX_OK) {
+    dev_free(f->vals);
+    dev_free(f->valsT);
+    delete f;
+    return s;
+  }
+  // padding slots are never written by the least-squares kernel: zero them once
+  hipStream_t st = sys->ctx->stream;
+  int64_t w1 = (int64_t)(f->vals.bytes / 4), w2 = (int64_t)(f->valsT.bytes / 4);
+  k_fill_zero_bytes<<<(unsigned)((w1 + 255) / 256), 256, 0, st>>>((uint32_t*)f->vals.p, w1);
+  k_fill_zero_bytes<<<(unsigned)((w2 + 255) / 256), 256, 0, st>>>((uint32_t*)f->valsT.p, w2);
+  MORX_HIP(hipGetLastError());
+  *out = f;
+  return MORX_OK;
+}
+
+void factor_release(morx_factor f) {
+  if (!f) return;
+  f->sys->factor_pool.push_back(f);
+}
+
+morx_status factor_build_many(morx_system sys, int32_t prec, const FactorJob* jobs, int njobs,
+                              hipStream_t st) {
+  MORX_REQUIRE(sys->ls_supported, MORX_E_UNSUPPORTED,
+               "factor pattern exceeds the local least-squares limits (|J_k|=%d, triples=%d, "
+               "|I_k|=%d)",
+               sys->max_J, sys->max_T, sys->max_I);
+  if (njobs <= 0) return MORX_OK;
+  LsLayout L = ls_layout(sys->max_J, sys->max_T, sys->max_I);
+  DevBuf jb, sb;
+  MORX_TRY(dev_alloc(jb, njobs * sizeof(FactorJob)));
+  MORX_TRY(dev_alloc(sb, sizeof(int)));
+  MORX_HIP(hipMemcpyAsync(jb.p, jobs, njobs * sizeof(FactorJob), hipMemcpyHostToDevice, st));
+  MORX_HIP(hipMemsetAsync(sb.p, 0, sizeof(int), st));
+  const int grid = ls_grid(sys);
+  switch (prec) {
+    case MORX_F64:
+      k_factor_ls<double><<<grid, 64, L.bytes, st>>>(sys->trowptr, sys->tcol, sys->tval, sys->e,
+                                                     sys->tp2s, sys->sellT.off, sys->n,
+                                                     (FactorJob*)jb.p, njobs, L, (int*)sb.p);
+      break;
+    case MORX_F32:
+      k_factor_ls<float><<<grid, 64, L.bytes, st>>>(sys->trowptr, sys->tcol, sys->tval, sys->e,
+                                                    sys->tp2s, sys->sellT.off, sys->n,
+                                                    (FactorJob*)jb.p, njobs, L, (int*)sb.p);
+      break;
+    default:
+      k_factor_ls<uint16_t><<<grid, 64, L.bytes, st>>>(sys->trowptr, sys->tcol, sys->tval,
+                                                       sys->e, sys->tp2s, sys->sellT.off, sys->n,
+                                                       (FactorJob*)jb.p, njobs, L, (int*)sb.p);
+  }
+  MORX_HIP(hipGetLastError());
+  int singular = 0;
+  MORX_HIP(hipMemcpyAsync(&singular, sb.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  MORX_HIP(hipStreamSynchronize(st));
+  dev_free(jb);
+  dev_free(sb);
+  MORX_REQUIRE(!singular, MORX_E_SINGULAR_LS, "a local least-squares matrix is rank deficient");
+  return MORX_OK;
+}
+
+// ---------------------------------------------------------------------------
+
+static morx_status factor_make(morx_system sys, bool spai, double sp, double sn, int32_t prec,
+                               void* stream, morx_factor* out) {
+  MORX_REQUIRE(sys && out, MORX_E_INVALID, "factor: null argument");
+  MORX_REQUIRE(prec >= MORX_F64 && prec <= MORX_BF16, MORX_E_INVALID, "factor: bad precision");
+  MORX_REQUIRE(std::isfinite(sn) && (spai || std::isfinite(sp)), MORX_E_NONFINITE, "factor: shift not finite");
+  *out = nullptr;
+  morx_ctx ctx = sys->ctx;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  MORX_HIP(hipSetDevice(ctx->device));
+  MORX_TRY(stream_enter(ctx, (hipStream_t)stream));
+  morx_factor f = nullptr;
+  MORX_TRY(factor_alloc(sys, prec, &f));
+  f->is_spai = spai;
+  f->sigma_prev = sp;
+  f->sigma_new = sn;
+  FactorJob job{sn, sp, spai ? 1 : 0, f->vals.p, f->valsT.p};
+  morx_status s = factor_build_many(sys, prec, &job, 1, ctx->stream);
+  if (s != MORX_OK) {
+    factor_release(f);
+    return s;
+  }
+  MORX_TRY(stream_leave(ctx, (hipStream_t)stream));
+  *out = f;
+  return MORX_OK;
+}
+
+extern "C" morx_status morx_factor_spai(morx_system sys, double sigma, int32_t prec, void* stream,
+                                        morx_factor* out) {
+  return factor_make(sys, true, 0.0, sigma, prec, stream, out);
+}
+
+extern "C" morx_status morx_factor_update(morx_system sys, double sigma_prev, double sigma_new,
+                                          int32_t prec, void* stream, morx_factor* out) {
+  return factor_make(sys, false, sigma_prev, sigma_new, prec, stream, out);
+}
+
+extern "C" morx_status morx_factor_values(morx_factor f, double* val, void* stream) {
+  MORX_REQUIRE(f && val, MORX_E_INVALID, "morx_factor_values: null argument");
+  morx_system sys = f->sys;
+  std::lock_guard<std::mutex> lk(sys->ctx->mu);
+  MORX_HIP(hipSetDevice(sys->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  unsigned g = (unsigned)((sys->nnzS + 255) / 256);
+  switch (f->prec) {
+    case MORX_F64:
+      k_factor_to_csr<double><<<g, 256, 0, st>>>((double*)f->vals.p, sys->csr2sell, sys->nnzS, val);
+      break;
+    case MORX_F32:
+      k_factor_to_csr<float><<<g, 256, 0, st>>>((float*)f->vals.p, sys->csr2sell, sys->nnzS, val);
+      break;
+    default:
+      k_factor_to_csr<uint16_t><<<g, 256, 0, st>>>((uint16_t*)f->vals.p, sys->csr2sell, sys->nnzS,
+                                                    val);
+  }
+  MORX_HIP(hipGetLastError());
+  MORX_HIP(hipStreamSynchronize(st));
+  return MORX_OK;
+}
+
+extern "C" morx_status morx_factor_destroy(morx_factor f) {
+  if (!f) return MORX_OK;
+  std::lock_guard<std::mutex> lk(f->sys->ctx->mu);
+  hipSetDevice(f->sys->ctx->device);
+  hipStreamSynchronize(f->sys->ctx->stream);
+  factor_release(f);
+  return MORX_OK;
+}

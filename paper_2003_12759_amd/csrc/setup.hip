@@ -1,0 +1,472 @@
+// System set-up: copy A and E, form the factor pattern S = pattern(A) + diag,
+// its transpose, and the sliced-ELL (height 64) layouts used by every
+// product kernel.  All of it is integer and copy work done once per system.
+//
+// The SPAI column problems (Section III-A, eq. gen-precond-par) and the reuse
+// updates (Section III-C) all read column k of S and the columns of S listed
+// there, so the transpose of S is kept in CSR form as well.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <algorithm>
+
+#include "common.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// ---- prefix sums (int64, exclusive) ---------------------------------------
+
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__global__ __launch_bounds__(kBlock) void k_scan_tile(const int64_t* __restrict__ in,
+                                                      int64_t* __restrict__ out,
+                                                      int64_t* __restrict__ tile_sums,
+                                                      int64_t count) {
+  __shared__ int64_t sh[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int64_t v[kScanItems];
+  int64_t run = 0;
+#pragma unroll
+  for (int t = 0; t < kScanItems; ++t) {
+    int64_t i = base + t;
+    v[t] = (i < count) ? in[i] : 0;
+    run += v[t];
+  }
+  sh[threadIdx.x] = run;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the per-thread sums
+  for (int off = 1; off < kBlock; off <<= 1) {
+    int64_t add = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int64_t prefix = sh[threadIdx.x] - run;
+#pragma unroll
+  for (int t = 0; t < kScanItems; ++t) {
+    int64_t i = base + t;
+    if (i < count) out[i] = prefix;
+    prefix += v[t];
+  }
+  if (threadIdx.x == kBlock - 1) tile_sums[blockIdx.x] = sh[kBlock - 1];
+}
+
+__global__ void k_scan_add(int64_t* __restrict__ out, const int64_t* __restrict__ tile_off,
+                           int64_t count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] += tile_off[i / kScanTile];
+}
+
+// exclusive scan of `count` values; total returned through `total_dev` (out[count])
+morx_status scan_exclusive(const int64_t* in, int64_t* out, int64_t count, hipStream_t st,
+                           std::vector<DevBuf>& tmp) {
+  if (count <= 0) return MORX_OK;
+  int64_t tiles = (count + kScanTile - 1) / kScanTile;
+  DevBuf sums, offs;
+  MORX_TRY(dev_alloc(sums, (tiles + 1) * sizeof(int64_t)));
+  MORX_TRY(dev_alloc(offs, (tiles + 1) * sizeof(int64_t)));
+  tmp.push_back(sums);
+  tmp.push_back(offs);
+  k_scan_tile<<<dim3((unsigned)tiles), dim3(kBlock), 0, st>>>(in, out, (int64_t*)sums.p, count);
+  MORX_HIP(hipGetLastError());
+  if (tiles > 1) {
+    MORX_TRY(scan_exclusive((int64_t*)sums.p, (int64_t*)offs.p, tiles, st, tmp));
+    k_scan_add<<<dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, st>>>(
+        out, (int64_t*)offs.p, count);
+    MORX_HIP(hipGetLastError());
+  }
+  return MORX_OK;
+}
+
+// ---- validation and pattern S ----------------------------------------------
+
+enum : int { ERR_INVALID = 1, ERR_NONFINITE = 2 };
+
+__global__ void k_check_rows(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                             const double* __restrict__ val, const double* __restrict__ e,
+                             int64_t n, int64_t nnz, int64_t* __restrict__ lenS,
+                             int* __restrict__ err) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t lo = rowptr[i], hi = rowptr[i + 1];
+  int bad = 0;
+  if (lo < 0 || hi < lo || hi > nnz) bad |= ERR_INVALID;
+  if (i == 0 && lo != 0) bad |= ERR_INVALID;
+  if (i == n - 1 && hi != nnz) bad |= ERR_INVALID;
+  bool has_diag = false;
+  if (!(bad & ERR_INVALID)) {
+    int64_t prev = -1;
+    for (int64_t p = lo; p < hi; ++p) {
+      int64_t c = col[p];
+      if (c < 0 || c >= n || c <= prev) bad |= ERR_INVALID;
+      if (c == i) has_diag = true;
+      if (!isfinite(val[p])) bad |= ERR_NONFINITE;
+      prev = c;
+    }
+  }
+  if (!isfinite(e[i])) bad |= ERR_NONFINITE;
+  lenS[i] = (bad & ERR_INVALID) ? 0 : (hi - lo) + (has_diag ? 0 : 1);
+  if (bad) atomicOr(err, bad);
+}
+
+__global__ void k_fill_S(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                         const double* __restrict__ val, const int64_t* __restrict__ offS,
+                         int64_t n, int32_t* __restrict__ rowptrS, int32_t* __restrict__ colS,
+                         double* __restrict__ valS) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  rowptrS[i] = (int32_t)offS[i];
+  if (i == n) return;
+  int64_t q = offS[i];
+  bool placed = false;
+  for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+    int32_t c = col[p];
+    if (!placed && c > i) {
+      colS[q] = (int32_t)i;
+      valS[q] = 0.0;
+      ++q;
+      placed = true;
+    }
+    if (c == i) placed = true;
+    colS[q] = c;
+    valS[q] = val[p];
+    ++q;
+  }
+  if (!placed) {
+    colS[q] = (int32_t)i;
+    valS[q] = 0.0;
+  }
+}
+
+// ---- transpose of S ----------------------------------------------------------
+
+__global__ void k_count_cols(const int32_t* __restrict__ colS, int64_t nnzS,
+                             int32_t* __restrict__ cnt) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nnzS) atomicAdd(&cnt[colS[p]], 1);
+}
+
+__global__ void k_widen(const int32_t* __restrict__ in, int64_t* __restrict__ out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i];
+}
+
+__global__ void k_scatter_T(const int32_t* __restrict__ rowptrS, const int32_t* __restrict__ colS,
+                            int64_t n, const int64_t* __restrict__ toff,
+                            int32_t* __restrict__ cursor, int32_t* __restrict__ tcol,
+                            int32_t* __restrict__ tsrc) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int32_t p = rowptrS[i]; p < rowptrS[i + 1]; ++p) {
+    int32_t c = colS[p];
+    int32_t slot = atomicAdd(&cursor[c], 1);
+    int64_t q = toff[c] + slot;
+    tcol[q] = (int32_t)i;
+    tsrc[q] = p;
+  }
+}
+
+// rows of S^T are filled in arbitrary order by the scatter; sort each by
+// column so the layout (and every result) is deterministic
+__global__ void k_sort_T_rows(const int64_t* __restrict__ toff, int64_t n,
+                              int32_t* __restrict__ tcol, int32_t* __restrict__ tsrc,
+                              int32_t* __restrict__ trowptr, const double* __restrict__ valS,
+                              double* __restrict__ tval) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > n) return;
+  trowptr[k] = (int32_t)toff[k];
+  if (k == n) return;
+  int64_t lo = toff[k], hi = toff[k + 1];
+  for (int64_t a = lo + 1; a < hi; ++a) {
+    int32_t c = tcol[a], s = tsrc[a];
+    int64_t b = a - 1;
+    while (b >= lo && tcol[b] > c) {
+      tcol[b + 1] = tcol[b];
+      tsrc[b + 1] = tsrc[b];
+      --b;
+    }
+    tcol[b + 1] = c;
+    tsrc[b + 1] = s;
+  }
+  for (int64_t a = lo; a < hi; ++a) tval[a] = valS[tsrc[a]];
+}
+
+__global__ void k_compare(const int32_t* __restrict__ a, const int32_t* __restrict__ b, int64_t n,
+                          int* __restrict__ diff) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && a[i] != b[i]) atomicOr(diff, 1);
+}
+
+// ---- sliced ELL ------------------------------------------------------------------
+
+__global__ void k_slice_width(const int32_t* __restrict__ rowptr, int64_t n, int64_t nslice,
+                              int64_t* __restrict__ w64) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nslice) return;
+  int32_t w = 0;
+  for (int64_t r = s * kSlice; r < (s + 1) * kSlice && r < n; ++r)
+    w = max(w, rowptr[r + 1] - rowptr[r]);
+  w64[s] = (int64_t)w * kSlice;
+}
+
+__global__ void k_narrow_off(const int64_t* __restrict__ in, int32_t* __restrict__ out,
+                             int64_t count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = (int32_t)in[i];
+}
+
+// fill the ELL arrays; padding uses an in-range column (the row itself, or 0
+// for rows past n) with a zero value so gathers never leave [0, n)
+__global__ void k_fill_sell(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                            const double* __restrict__ val, int64_t n, int64_t n_pad,
+                            const int32_t* __restrict__ off, int32_t* __restrict__ scol,
+                            double* __restrict__ sval, int32_t* __restrict__ csr2sell) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  int64_t s = i / kSlice, lane = i % kSlice;
+  int32_t w = (off[s + 1] - off[s]) / kSlice;
+  int32_t len = (i < n) ? rowptr[i + 1] - rowptr[i] : 0;
+  int32_t lo = (i < n) ? rowptr[i] : 0;
+  for (int32_t m = 0; m < w; ++m) {
+    int64_t pos = (int64_t)off[s] + (int64_t)m * kSlice + lane;
+    if (m < len) {
+      scol[pos] = col[lo + m];
+      if (sval) sval[pos] = val[lo + m];
+      if (csr2sell) csr2sell[lo + m] = (int32_t)pos;
+    } else {
+      scol[pos] = (i < n) ? (int32_t)i : 0;
+      if (sval) sval[pos] = 0.0;
+    }
+  }
+}
+
+__global__ void k_compose(const int32_t* __restrict__ tsrc, const int32_t* __restrict__ csr2sell,
+                          int64_t nnz, int32_t* __restrict__ tp2s) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nnz) tp2s[p] = csr2sell[tsrc[p]];
+}
+
+__global__ void k_copy_pad(const double* __restrict__ in, double* __restrict__ out, int64_t n,
+                           int64_t n_pad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_pad) out[i] = (i < n) ? in[i] : 0.0;
+}
+
+inline unsigned nblk(int64_t count) { return (unsigned)((count + kBlock - 1) / kBlock); }
+
+template <typename T>
+morx_status owned_alloc(morx_system sys, T** p, int64_t count) {
+  DevBuf b;
+  MORX_TRY(dev_alloc(b, (size_t)std::max<int64_t>(count, 1) * sizeof(T)));
+  sys->owned.push_back(b);
+  sys->resident_bytes += (int64_t)b.bytes;
+  *p = (T*)b.p;
+  return MORX_OK;
+}
+
+morx_status build_sell(morx_system sys, const int32_t* rowptr, const int32_t* col,
+                       const double* val, Sell& out, double** sval, int32_t* csr2sell,
+                       hipStream_t st, std::vector<DevBuf>& tmp) {
+  const int64_t n = sys->n, ns = sys->nslice;
+  DevBuf w64, off64;
+  MORX_TRY(dev_alloc(w64, (ns + 1) * sizeof(int64_t)));
+  MORX_TRY(dev_alloc(off64, (ns + 1) * sizeof(int64_t)));
+  tmp.push_back(w64);
+  tmp.push_back(off64);
+  MORX_HIP(hipMemsetAsync(w64.p, 0, (ns + 1) * sizeof(int64_t), st));
+  k_slice_width<<<nblk(ns), kBlock, 0, st>>>(rowptr, n, ns, (int64_t*)w64.p);
+  MORX_HIP(hipGetLastError());
+  MORX_TRY(scan_exclusive((int64_t*)w64.p, (int64_t*)off64.p, ns + 1, st, tmp));
+  int64_t total = 0;
+  MORX_HIP(hipMemcpyAsync(&total, (int64_t*)off64.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  MORX_HIP(hipStreamSynchronize(st));
+  MORX_REQUIRE(total < (int64_t)INT32_MAX, MORX_E_UNSUPPORTED,
+               "sliced-ELL size %lld exceeds 2^31", (long long)total);
+  out.nnz_sell = total;
+  MORX_TRY(owned_alloc(sys, &out.off, ns + 1));
+  MORX_TRY(owned_alloc(sys, &out.col, total));
+  MORX_TRY(owned_alloc(sys, sval, total));
+  k_narrow_off<<<nblk(ns + 1), kBlock, 0, st>>>((int64_t*)off64.p, out.off, ns + 1);
+  k_fill_sell<<<nblk(sys->n_pad), kBlock, 0, st>>>(rowptr, col, val, n, sys->n_pad, out.off,
+                                                   out.col, *sval, csr2sell);
+  MORX_HIP(hipGetLastError());
+  return MORX_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+morx_status ls_pattern_stats(morx_system sys, hipStream_t st);  // factor.hip
+
+static morx_status system_build(morx_system sys, const int32_t* rowptr, const int32_t* colind,
+                                const double* val, const double* e_diag, hipStream_t st,
+                                std::vector<DevBuf>& tmp) {
+  const int64_t n = sys->n, nnz = sys->nnz_in;
+  DevBuf lenS, offS, errb;
+  MORX_TRY(dev_alloc(lenS, (n + 1) * sizeof(int64_t)));
+  MORX_TRY(dev_alloc(offS, (n + 1) * sizeof(int64_t)));
+  MORX_TRY(dev_alloc(errb, sizeof(int)));
+  tmp.push_back(lenS);
+  tmp.push_back(offS);
+  tmp.push_back(errb);
+  MORX_HIP(hipMemsetAsync(errb.p, 0, sizeof(int), st));
+  MORX_HIP(hipMemsetAsync(lenS.p, 0, (n + 1) * sizeof(int64_t), st));
+  k_check_rows<<<nblk(n), kBlock, 0, st>>>(rowptr, colind, val, e_diag, n, nnz,
+                                           (int64_t*)lenS.p, (int*)errb.p);
+  MORX_HIP(hipGetLastError());
+  int err = 0;
+  MORX_HIP(hipMemcpyAsync(&err, errb.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  MORX_HIP(hipStreamSynchronize(st));
+  MORX_REQUIRE(!(err & ERR_INVALID), MORX_E_INVALID,
+               "CSR of A is malformed (rowptr not monotone from 0 to nnz, or column indices "
+               "out of range / not strictly increasing within a row)");
+  MORX_REQUIRE(!(err & ERR_NONFINITE), MORX_E_NONFINITE, "A or E holds NaN or Inf");
+
+  MORX_TRY(scan_exclusive((int64_t*)lenS.p, (int64_t*)offS.p, n + 1, st, tmp));
+  int64_t nnzS = 0;
+  MORX_HIP(hipMemcpyAsync(&nnzS, (int64_t*)offS.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  MORX_HIP(hipStreamSynchronize(st));
+  MORX_REQUIRE(nnzS < (int64_t)INT32_MAX, MORX_E_UNSUPPORTED, "nnz(S) >= 2^31");
+  sys->nnzS = nnzS;
+
+  MORX_TRY(owned_alloc(sys, &sys->rowptr, n + 1));
+  MORX_TRY(owned_alloc(sys, &sys->colind, nnzS));
+  MORX_TRY(owned_alloc(sys, &sys->valA, nnzS));
+  k_fill_S<<<nblk(n + 1), kBlock, 0, st>>>(rowptr, colind, val, (int64_t*)offS.p, n, sys->rowptr,
+                                           sys->colind, sys->valA);
+  MORX_HIP(hipGetLastError());
+
+  // transpose
+  DevBuf cnt, cnt64, toff, tsrc;
+  MORX_TRY(dev_alloc(cnt, (n + 1) * sizeof(int32_t)));
+  MORX_TRY(dev_alloc(cnt64, (n + 1) * sizeof(int64_t)));
+  MORX_TRY(dev_alloc(toff, (n + 1) * sizeof(int64_t)));
+  tmp.push_back(cnt);
+  tmp.push_back(cnt64);
+  tmp.push_back(toff);
+  MORX_HIP(hipMemsetAsync(cnt.p, 0, (n + 1) * sizeof(int32_t), st));
+  k_count_cols<<<nblk(nnzS), kBlock, 0, st>>>(sys->colind, nnzS, (int32_t*)cnt.p);
+  k_widen<<<nblk(n + 1), kBlock, 0, st>>>((int32_t*)cnt.p, (int64_t*)cnt64.p, n + 1);
+  MORX_HIP(hipGetLastError());
+  MORX_TRY(scan_exclusive((int64_t*)cnt64.p, (int64_t*)toff.p, n + 1, st, tmp));
+  MORX_TRY(owned_alloc(sys, &sys->trowptr, n + 1));
+  MORX_TRY(owned_alloc(sys, &sys->tcol, nnzS));
+  MORX_TRY(owned_alloc(sys, &sys->tval, nnzS));
+  int32_t* tsrcp = nullptr;
+  MORX_TRY(dev_alloc(tsrc, nnzS * sizeof(int32_t)));
+  tmp.push_back(tsrc);
+  tsrcp = (int32_t*)tsrc.p;
+  MORX_HIP(hipMemsetAsync(cnt.p, 0, (n + 1) * sizeof(int32_t), st));
+  k_scatter_T<<<nblk(n), kBlock, 0, st>>>(sys->rowptr, sys->colind, n, (int64_t*)toff.p,
+                                          (int32_t*)cnt.p, sys->tcol, tsrcp);
+  k_sort_T_rows<<<nblk(n + 1), kBlock, 0, st>>>((int64_t*)toff.p, n, sys->tcol, tsrcp,
+                                                sys->trowptr, sys->valA, sys->tval);
+  MORX_HIP(hipGetLastError());
+
+  // structural symmetry: S^T has exactly the rows of S
+  MORX_HIP(hipMemsetAsync(errb.p, 0, sizeof(int), st));
+  k_compare<<<nblk(n + 1), kBlock, 0, st>>>(sys->rowptr, sys->trowptr, n + 1, (int*)errb.p);
+  k_compare<<<nblk(nnzS), kBlock, 0, st>>>(sys->colind, sys->tcol, nnzS, (int*)errb.p);
+  MORX_HIP(hipGetLastError());
+  int diff = 0;
+  MORX_HIP(hipMemcpyAsync(&diff, errb.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  MORX_HIP(hipStreamSynchronize(st));
+  sys->symmetric_pattern = (diff == 0);
+
+  // sliced ELL for S (values of A) and S^T (values of A^T)
+  MORX_TRY(owned_alloc(sys, &sys->csr2sell, nnzS));
+  MORX_TRY(build_sell(sys, sys->rowptr, sys->colind, sys->valA, sys->sell, &sys->sell_val,
+                      sys->csr2sell, st, tmp));
+  MORX_TRY(build_sell(sys, sys->trowptr, sys->tcol, sys->tval, sys->sellT, &sys->sellT_val,
+                      nullptr, st, tmp));
+  MORX_TRY(owned_alloc(sys, &sys->tp2s, nnzS));
+  k_compose<<<nblk(nnzS), kBlock, 0, st>>>(tsrcp, sys->csr2sell, nnzS, sys->tp2s);
+  MORX_TRY(owned_alloc(sys, &sys->e, sys->n_pad));
+  k_copy_pad<<<nblk(sys->n_pad), kBlock, 0, st>>>(e_diag, sys->e, n, sys->n_pad);
+  MORX_HIP(hipGetLastError());
+
+  MORX_TRY(ls_pattern_stats(sys, st));
+  MORX_HIP(hipStreamSynchronize(st));
+  return MORX_OK;
+}
+
+extern "C" morx_status morx_system_create(morx_ctx ctx, int64_t n, int64_t nnz,
+                                          const int32_t* rowptr, const int32_t* colind,
+                                          const double* val, const double* e_diag, void* stream,
+                                          morx_system* out) {
+  MORX_REQUIRE(ctx && out, MORX_E_INVALID, "morx_system_create: null context or output");
+  *out = nullptr;
+  MORX_REQUIRE(n > 0 && n < (int64_t)INT32_MAX - kSlice, MORX_E_INVALID,
+               "morx_system_create: n=%lld out of range", (long long)n);
+  MORX_REQUIRE(nnz >= 0 && nnz < (int64_t)INT32_MAX, MORX_E_INVALID,
+               "morx_system_create: nnz=%lld out of range", (long long)nnz);
+  MORX_REQUIRE(rowptr && e_diag && (nnz == 0 || (colind && val)), MORX_E_INVALID,
+               "morx_system_create: null input pointer");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  MORX_HIP(hipSetDevice(ctx->device));
+  hipStream_t caller = (hipStream_t)stream;
+  MORX_TRY(stream_enter(ctx, caller));
+  morx_system sys = new morx_system_s();
+  sys->ctx = ctx;
+  sys->n = n;
+  sys->n_pad = (n + kSlice - 1) / kSlice * kSlice;
+  sys->nslice = sys->n_pad / kSlice;
+  sys->nnz_in = nnz;
+  std::vector<DevBuf> tmp;
+  morx_status s = system_build(sys, rowptr, colind, val, e_diag, ctx->stream, tmp);
+  hipStreamSynchronize(ctx->stream);
+  for (auto& b : tmp) dev_free(b);
+  if (s != MORX_OK) {
+    morx_system_destroy(sys);
+    return s;
+  }
+  MORX_TRY(stream_leave(ctx, caller));
+  *out = sys;
+  return MORX_OK;
+}
+
+extern "C" morx_status morx_system_destroy(morx_system sys) {
+  if (!sys) return MORX_OK;
+  hipSetDevice(sys->ctx->device);
+  hipStreamSynchronize(sys->ctx->stream);
+  hipStreamSynchronize(sys->ctx->stream2);
+  for (morx_factor f : sys->vertical) factor_release(f);
+  sys->vertical.clear();
+  for (morx_factor f : sys->factor_pool) {
+    dev_free(f->vals);
+    dev_free(f->valsT);
+    delete f;
+  }
+  sys->factor_pool.clear();
+  if (sys->ws) workspace_free(sys->ws);
+  for (auto& b : sys->owned) dev_free(b);
+  delete sys;
+  return MORX_OK;
+}
+
+extern "C" morx_status morx_system_info(morx_system sys, int64_t* nnz_pattern,
+                                        int64_t* resident_bytes) {
+  MORX_REQUIRE(sys, MORX_E_INVALID, "morx_system_info: null system");
+  if (nnz_pattern) *nnz_pattern = sys->nnzS;
+  if (resident_bytes) *resident_bytes = sys->resident_bytes;
+  return MORX_OK;
+}
+
+extern "C" morx_status morx_system_pattern(morx_system sys, int32_t* rowptr, int32_t* colind,
+                                           void* stream) {
+  MORX_REQUIRE(sys && rowptr && colind, MORX_E_INVALID, "morx_system_pattern: null argument");
+  morx_ctx ctx = sys->ctx;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  MORX_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  MORX_HIP(hipMemcpyAsync(rowptr, sys->rowptr, (sys->n + 1) * sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, st));
+  MORX_HIP(hipMemcpyAsync(colind, sys->colind, sys->nnzS * sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, st));
+  MORX_HIP(hipStreamSynchronize(st));
+  return MORX_OK;
+}

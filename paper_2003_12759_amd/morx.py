@@ -1,0 +1,281 @@
+"""Thin ctypes binding of libmorx (include/morx.h).
+
+Argument marshalling only: every function forwards to the C entry point of
+the same name; torch tensors supply device pointers and streams.  Dense
+blocks are column-major ``(n, m)`` tensors (``stride(0) == 1``, e.g.
+``torch.empty(m, n).t()``) or 1-D vectors.  A non-OK status raises
+:class:`MorxError`.  Importing this module fails loudly when the library has
+not been built; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libmorx.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_2003_12759_amd.build` "
+        "(there is no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+MORX_OK = 0
+STATUS = {
+    0: "MORX_OK", -1: "MORX_E_INVALID", -2: "MORX_E_NOMEM", -3: "MORX_E_HIP",
+    -4: "MORX_E_SINGULAR_LS", -5: "MORX_E_NOT_CONVERGED", -6: "MORX_E_BREAKDOWN",
+    -7: "MORX_E_NONFINITE", -8: "MORX_E_ADMISSION", -9: "MORX_E_UNSUPPORTED",
+    -10: "MORX_E_PENDING",
+}
+PREC = {"f64": 0, "f32": 1, "bf16": 2}
+MORX_CHAIN_RESET = 0
+MORX_CHAIN_NEXT_ROUND = 1
+
+
+class morx_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32),
+                ("max_restarts", ctypes.c_int32), ("precond_prec", ctypes.c_int32),
+                ("chain", ctypes.c_int32), ("want_dual", ctypes.c_int32),
+                ("batched", ctypes.c_int32), ("poll_iters", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class morx_col_stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("restarts", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("relres_primal", ctypes.c_double), ("relres_dual", ctypes.c_double)]
+
+
+class MorxError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.morx_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({msg})")
+
+
+_p = ctypes.c_void_p
+_i32, _i64, _d = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_SIG = {
+    "morx_opts_default": (None, [ctypes.POINTER(morx_opts)]),
+    "morx_status_str": (ctypes.c_char_p, [_i32]),
+    "morx_last_error": (ctypes.c_char_p, []),
+    "morx_create": (_i32, [ctypes.POINTER(_p), ctypes.c_int]),
+    "morx_destroy": (_i32, [_p]),
+    "morx_system_create": (_i32, [_p, _i64, _i64, _p, _p, _p, _p, _p, ctypes.POINTER(_p)]),
+    "morx_system_destroy": (_i32, [_p]),
+    "morx_system_info": (_i32, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "morx_system_pattern": (_i32, [_p, _p, _p, _p]),
+    "morx_shifted_apply": (_i32, [_p, _d, _i32, _i32, _p, _i64, _p, _i64, _p]),
+    "morx_factor_spai": (_i32, [_p, _d, _i32, _p, ctypes.POINTER(_p)]),
+    "morx_factor_update": (_i32, [_p, _d, _d, _i32, _p, ctypes.POINTER(_p)]),
+    "morx_factor_values": (_i32, [_p, _p, _p]),
+    "morx_factor_destroy": (_i32, [_p]),
+    "morx_chain_apply": (_i32, [_p, _i32, ctypes.POINTER(_p), _i32, _i32, _p, _i64, _p, _i64, _p]),
+    "morx_solve_shifts": (_i32, [_p, _i32, ctypes.POINTER(_d), _i32, _p, _i64, _p, _i64, _p, _i64,
+                                 _p, _i64, ctypes.POINTER(morx_opts),
+                                 ctypes.POINTER(morx_col_stats), _p]),
+    "morx_project": (_i32, [_p, _i32, _p, _i64, _p, _i64, _i32, _p, _i64, _i32, _p, _i64,
+                            ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
+                            ctypes.POINTER(_d), _i32, _p]),
+}
+for _name, (_res, _args) in _SIG.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def exported_symbols() -> Sequence[str]:
+    return tuple(_SIG)
+
+
+def _check(status: int, where: str):
+    if status != MORX_OK:
+        raise MorxError(status, where)
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous() and t.dim() == 1:
+        raise TypeError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _block(t: torch.Tensor, name: str):
+    """(pointer, ld, ncols) of a column-major float64 block or a vector."""
+    _dev(t, torch.float64, name)
+    if t.dim() == 1:
+        if t.stride(0) != 1:
+            raise TypeError(f"{name} must be contiguous")
+        return t.data_ptr(), t.shape[0], 1
+    if t.dim() == 2 and (t.stride(0) == 1 or t.shape[0] == 1):
+        return t.data_ptr(), max(t.stride(1), t.shape[0]), t.shape[1]
+    raise TypeError(f"{name} must be a column-major (n, m) block (stride(0) == 1)")
+
+
+def colmajor(m: int, n: int, device="cuda", dtype=torch.float64) -> torch.Tensor:
+    """An uninitialised column-major (n, m) block."""
+    return torch.empty(m, n, device=device, dtype=dtype).t()
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+
+
+def morx_opts_default() -> morx_opts:
+    o = morx_opts()
+    _lib.morx_opts_default(ctypes.byref(o))
+    return o
+
+
+def morx_status_str(status: int) -> str:
+    return _lib.morx_status_str(status).decode()
+
+
+def morx_last_error() -> str:
+    return _lib.morx_last_error().decode(errors="replace")
+
+
+def morx_create(device: int = 0) -> int:
+    h = _p()
+    _check(_lib.morx_create(ctypes.byref(h), device), "morx_create")
+    return h.value
+
+
+def morx_destroy(ctx: int) -> None:
+    _check(_lib.morx_destroy(ctx), "morx_destroy")
+
+
+def morx_system_create(ctx: int, rowptr: torch.Tensor, colind: torch.Tensor, val: torch.Tensor,
+                       e_diag: torch.Tensor, stream=None) -> int:
+    n = rowptr.numel() - 1
+    nnz = colind.numel()
+    h = _p()
+    _check(_lib.morx_system_create(
+        ctx, n, nnz, _dev(rowptr, torch.int32, "rowptr"), _dev(colind, torch.int32, "colind"),
+        _dev(val, torch.float64, "val"), _dev(e_diag, torch.float64, "e_diag"), _stream(stream),
+        ctypes.byref(h)), "morx_system_create")
+    return h.value
+
+
+def morx_system_destroy(sys: int) -> None:
+    _check(_lib.morx_system_destroy(sys), "morx_system_destroy")
+
+
+def morx_system_info(sys: int):
+    a, b = _i64(), _i64()
+    _check(_lib.morx_system_info(sys, ctypes.byref(a), ctypes.byref(b)), "morx_system_info")
+    return a.value, b.value
+
+
+def morx_system_pattern(sys: int, rowptr: torch.Tensor, colind: torch.Tensor, stream=None) -> None:
+    _check(_lib.morx_system_pattern(sys, _dev(rowptr, torch.int32, "rowptr"),
+                                    _dev(colind, torch.int32, "colind"), _stream(stream)),
+           "morx_system_pattern")
+
+
+def morx_shifted_apply(sys: int, sigma: float, trans: bool, X: torch.Tensor, Y: torch.Tensor,
+                       stream=None) -> None:
+    px, ldx, nc = _block(X, "X")
+    py, ldy, nc2 = _block(Y, "Y")
+    if nc != nc2:
+        raise ValueError("X and Y column counts differ")
+    _check(_lib.morx_shifted_apply(sys, float(sigma), int(bool(trans)), nc, px, ldx, py, ldy,
+                                   _stream(stream)), "morx_shifted_apply")
+
+
+def morx_factor_spai(sys: int, sigma: float, prec: str = "f64", stream=None) -> int:
+    h = _p()
+    _check(_lib.morx_factor_spai(sys, float(sigma), PREC[prec], _stream(stream), ctypes.byref(h)),
+           "morx_factor_spai")
+    return h.value
+
+
+def morx_factor_update(sys: int, sigma_prev: float, sigma_new: float, prec: str = "f64",
+                       stream=None) -> int:
+    h = _p()
+    _check(_lib.morx_factor_update(sys, float(sigma_prev), float(sigma_new), PREC[prec],
+                                   _stream(stream), ctypes.byref(h)), "morx_factor_update")
+    return h.value
+
+
+def morx_factor_values(f: int, val: torch.Tensor, stream=None) -> None:
+    _check(_lib.morx_factor_values(f, _dev(val, torch.float64, "val"), _stream(stream)),
+           "morx_factor_values")
+
+
+def morx_factor_destroy(f: int) -> None:
+    _check(_lib.morx_factor_destroy(f), "morx_factor_destroy")
+
+
+def morx_chain_apply(sys: int, chain: Sequence[int], trans: bool, X: torch.Tensor, Y: torch.Tensor,
+                     stream=None) -> None:
+    arr = (_p * len(chain))(*chain)
+    px, ldx, nc = _block(X, "X")
+    py, ldy, nc2 = _block(Y, "Y")
+    if nc != nc2:
+        raise ValueError("X and Y column counts differ")
+    _check(_lib.morx_chain_apply(sys, len(chain), arr, int(bool(trans)), nc, px, ldx, py, ldy,
+                                 _stream(stream)), "morx_chain_apply")
+
+
+def morx_solve_shifts(sys: int, sigmas: Sequence[float], B: torch.Tensor, C: Optional[torch.Tensor],
+                      X: torch.Tensor, Y: Optional[torch.Tensor], opts: Optional[morx_opts] = None,
+                      stream=None, raise_on_error: bool = True):
+    """Returns (status, list of morx_col_stats)."""
+    if opts is None:
+        opts = morx_opts_default()
+    pb, ldb, m = _block(B, "B")
+    px, ldx, mx = _block(X, "X")
+    if C is not None:
+        pc, ldc, mc = _block(C, "C")
+        py, ldy, _ = _block(Y, "Y")
+    else:
+        pc, ldc, py, ldy = None, B.shape[0], None, B.shape[0]
+    ns = len(sigmas)
+    sig = (_d * ns)(*[float(s) for s in sigmas])
+    stats = (morx_col_stats * (ns * m))()
+    st = _lib.morx_solve_shifts(sys, ns, sig, m, pb, ldb, pc, ldc, px, ldx, py, ldy,
+                                ctypes.byref(opts), stats, _stream(stream))
+    if raise_on_error and st != MORX_OK:
+        raise MorxError(st, "morx_solve_shifts")
+    return st, list(stats)
+
+
+def morx_project(sys: int, V: torch.Tensor, W: torch.Tensor, B: Optional[torch.Tensor],
+                 C: Optional[torch.Tensor], orthonormalize: bool = True, stream=None):
+    """Returns numpy arrays (Ar, Er, Br, Cr) (column-major data, shapes r x r, r x m, r x q)."""
+    import numpy as np
+
+    pv, ldv, r = _block(V, "V")
+    pw, ldw, r2 = _block(W, "W")
+    if r != r2:
+        raise ValueError("V and W column counts differ")
+    pb, ldb, m = _block(B, "B") if B is not None else (None, V.shape[0], 0)
+    pc, ldc, q = _block(C, "C") if C is not None else (None, V.shape[0], 0)
+    Ar = (_d * (r * r))()
+    Er = (_d * (r * r))()
+    Br = (_d * max(r * m, 1))()
+    Cr = (_d * max(r * q, 1))()
+    _check(_lib.morx_project(sys, r, pv, ldv, pw, ldw, m, pb, ldb, q, pc, ldc, Ar, Er, Br, Cr,
+                             int(bool(orthonormalize)), _stream(stream)), "morx_project")
+
+    def mat(buf, rows, cols):
+        return np.frombuffer(buf, dtype=np.float64, count=rows * cols).reshape(cols, rows).T.copy()
+
+    return mat(Ar, r, r), mat(Er, r, r), mat(Br, r, m), mat(Cr, r, q)
