@@ -188,6 +188,28 @@ morx_status morx_project(morx_system sys, int32_t r, const double* V, int64_t ld
                          int32_t q, const double* C, int64_t ldc, double* Ar, double* Er,
                          double* Br, double* Cr, int32_t orthonormalize, void* stream);
 
+/*
+ * Kernel tracing (measurement only).  While enabled on a context, solves do
+ * not use graphs; every launch of the listed kernel classes is bracketed by
+ * HIP events on the library's stream and the algorithmic bytes each launch
+ * must move (matrix or factor values and indices once per launch, each
+ * vector it reads or writes once) are added up on the device.  Enabling
+ * resets the totals.  Classes: "chain_step" (one factor of every
+ * preconditioner chain, forward and transposed), "spmv_pair" (shifted
+ * operator and its transpose), "update" (iterate and residual update),
+ * "factor_ls" (least-squares factor construction; no byte count).
+ */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;   /* sum of event-bracketed launch durations */
+  double alg_bytes;  /* algorithmic bytes over those launches   */
+} morx_trace_entry;
+
+morx_status morx_trace_enable(morx_ctx ctx, int32_t enable);
+/* Fill up to cap entries (host); *count receives the number of classes. */
+morx_status morx_trace_read(morx_ctx ctx, morx_trace_entry* out, int32_t cap, int32_t* count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,18 +9,25 @@
 // column whose chain contains it, and the transposed chain reads it once in
 // the reverse order.
 //
-// One iteration = L_max chain launches (forward and transposed halves side
-// by side) + one launch for p, p~ and both shifted products + one update
-// launch.  Scalars (rho, beta, delta, alpha, norms, state) stay on the
-// device; each reduction ends in the last block to arrive, which sums the
-// per-block partials in a fixed order (deterministic) and advances the
-// column's state.  The host only polls the states every few iterations.
+// One iteration is
+//   L_max chain launches (forward and transposed halves side by side; the
+//   last one also forms the partial sums of rho = z~^T r),
+//   fin_rho   (one block: convergence test on the previous update, rho, beta),
+//   spmv_pair (p, p~ formed on the fly, q = A_s p, q~ = A_s^T p~, delta sums),
+//   fin_delta (one block: alpha),
+//   update    (x, x~, r, r~ and the partial sums of their norms).
+// Scalars stay on the device; every reduction is block partials summed in a
+// fixed order by the next one-block kernel (deterministic, and no grid-wide
+// fences inside a kernel).  The host polls the column states every few
+// iterations.
 #include <math.h>
 #include <string.h>
 
 #include <algorithm>
 #include <cmath>
 #include <vector>
+
+#include <hip/hip_ext.h>
 
 #include "common.h"
 
@@ -46,11 +53,13 @@ enum Vec : int {
   V_T0, V_T1, V_TT0, V_TT1, kNumVec
 };
 
+// trace counters (algorithmic bytes per kernel class)
+enum TraceClass : int { TR_CHAIN = 0, TR_SPMV = 1, TR_UPDATE = 2, TR_FACTOR = 3, kTraceClasses = 8 };
+
 struct Workspace {
   int64_t ld = 0;
   int cap = 0;
-  int nblk_cap = 0;
-  DevBuf vec, cols, partial, counters;
+  DevBuf vec, cols, part;
   ColInfo* hcols = nullptr;  // pinned host mirror
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -58,301 +67,389 @@ struct Workspace {
 
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
-constexpr int kNC = 4;           // columns per thread
-constexpr int kMaxBlocks = 2048;  // row blocks (grid-stride beyond)
+constexpr int kMaxW = 16;          // columns (waves) per block row group
+constexpr int kMaxBlocks = 1024;   // row slabs per launch (partials per column)
+constexpr int kFinThreads = 1024;  // finalize kernels: one wave per column
 constexpr double kBreakdown = 1e-14;
 
+// Launch geometry shared by every iteration kernel: block = R row groups x W
+// waves; wave (r, w) handles column blockIdx.y * W + w on the 64-row slices
+// r, r + R, ... of its slab.  Slab index is remapped so that consecutive slabs
+// run on one XCD (workgroups are dealt to the 8 XCDs round robin), keeping
+// the stencil neighbours of a slab in that XCD's L2.
 struct IterArgs {
-  int64_t n, ld;
-  int cap, nc, nblk;
+  int64_t n, ld, nnzS, nslices;
+  int cap, nc, nblk, spb, W, R, vbytes, maxL;
   const int32_t *off, *col, *offT, *colT;
   const double *valA, *valAT, *e;
   double* vec;
   ColInfo* cols;
-  double* partial;
-  unsigned* counter;
+  double* part_rho;    // [3][cap][nblk]
+  double* part_delta;  // [3][cap][nblk]
+  double* part_norm;   // [2][cap][nblk]
+  double* trace;       // [kTraceClasses] or null
 };
 
 __device__ __forceinline__ double* vptr(const IterArgs& a, int slot, int c) {
   return a.vec + ((int64_t)slot * a.cap + c) * a.ld;
 }
 
+struct WaveCtx {
+  int lane, w, r, c, slab;
+  int64_t s_begin, s_end;
+};
+
+__device__ __forceinline__ WaveCtx wave_ctx(const IterArgs& a) {
+  WaveCtx t;
+  const int wave = threadIdx.x >> 6;
+  t.lane = threadIdx.x & 63;
+  t.w = wave % a.W;
+  t.r = wave / a.W;
+  t.c = blockIdx.y * a.W + t.w;
+  const int per_xcd = a.nblk >> 3;  // nblk is a multiple of 8
+  t.slab = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  t.s_begin = (int64_t)t.slab * a.spb;
+  t.s_end = min(a.nslices, t.s_begin + a.spb);
+  return t;
+}
+
 // ---- reductions --------------------------------------------------------------
 
-// reduce NQ values per column over the block and store one partial per block
+// Sum NQ per-wave values over the R row groups of a block and store one
+// partial per (quantity, column, slab).  Every wave of the block calls it.
 template <int NQ>
-__device__ void block_partials(double (&v)[kNC][NQ], unsigned mask, const IterArgs& a, int c0) {
-  __shared__ double sh[kWaves][kNC * NQ];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+__device__ void wave_partials(const IterArgs& a, const WaveCtx& t, bool valid, double (&v)[NQ],
+                              double* part) {
+  __shared__ double sh[4][kMaxW][NQ];
+  double s[NQ];
 #pragma unroll
-  for (int j = 0; j < kNC; ++j)
+  for (int q = 0; q < NQ; ++q) s[q] = wave_sum(v[q]);
+  if (a.R == 1) {
+    if (valid && t.lane == 0)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) part[((int64_t)q * a.cap + t.c) * a.nblk + t.slab] = s[q];
+    return;
+  }
+  if (t.lane == 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) sh[t.r][t.w][q] = s[q];
+  __syncthreads();
+  if (t.r == 0 && valid && t.lane == 0) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      double s = wave_sum(v[j][q]);
-      if (lane == 0) sh[w][j * NQ + q] = s;
+      double tot = 0.0;
+      for (int rr = 0; rr < a.R; ++rr) tot += sh[rr][t.w][q];
+      part[((int64_t)q * a.cap + t.c) * a.nblk + t.slab] = tot;
     }
-  __syncthreads();
-  if (threadIdx.x < kNC * NQ) {
-    const int j = threadIdx.x / NQ, q = threadIdx.x % NQ;
-    double t = 0.0;
+  }
+}
+
+// One wave sums the nblk partials of NQ quantities of column c, every load of
+// the column issued before the first add (nblk <= 1024: 16 per lane and
+// quantity), then a fixed-order reduction.
+template <int NQ>
+__device__ __forceinline__ void wave_totals(const IterArgs& a, const double* part, int c,
+                                            double (&out)[NQ]) {
+  const int lane = threadIdx.x & 63;
+  double v[NQ][kMaxBlocks / 64];
 #pragma unroll
-    for (int ww = 0; ww < kWaves; ++ww) t += sh[ww][threadIdx.x];
-    if (mask & (1u << j)) a.partial[((int64_t)q * a.cap + c0 + j) * a.nblk + blockIdx.x] = t;
+  for (int q = 0; q < NQ; ++q) {
+    const double* p = part + ((int64_t)q * a.cap + c) * a.nblk;
+#pragma unroll
+    for (int k = 0; k < kMaxBlocks / 64; ++k) {
+      const int b = lane + 64 * k;
+      v[q][k] = b < a.nblk ? p[b] : 0.0;
+    }
   }
-}
-
-__device__ bool arrive_last(unsigned* counter, unsigned total) {
-  __shared__ int last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == total - 1u);
-    if (last) atomicExch(counter, 0u);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxBlocks / 64; ++k) s += v[q][k];
+    out[q] = wave_sum(s);
   }
-  __syncthreads();
-  if (last) __threadfence();
-  return last;
-}
-
-// one wave sums the nblk partials of quantity q of column c (fixed order)
-__device__ __forceinline__ double wave_total(const IterArgs& a, int q, int c) {
-  const double* p = a.partial + ((int64_t)q * a.cap + c) * a.nblk;
-  double s = 0.0;
-  for (int b = threadIdx.x & 63; b < a.nblk; b += 64) s += p[b];
-  return wave_sum(s);
 }
 
 __device__ __forceinline__ bool passed(const ColInfo& ci, double rr, double rtrt) {
   return (!ci.check_p || sqrt(rr) <= ci.tol * ci.nb) && (!ci.check_d || sqrt(rtrt) <= ci.tol * ci.nc);
 }
 
+__device__ __forceinline__ bool stopped(int st) {
+  return st == COL_CONVERGED || st == COL_BREAKDOWN || st == COL_MAXIT;
+}
+
+// Slots of a slice are processed kUnroll at a time: all index and value loads
+// of a chunk are issued before its gathers, so a wave keeps kUnroll gathers in
+// flight instead of one (the loop is latency-bound otherwise).
+constexpr int kUnroll = 8;
+
+// one row of the slice-ELL product: sum_m val[m] * x[col[m]]
+template <typename VT>
+__device__ __forceinline__ double sell_dot(const int32_t* __restrict__ off,
+                                           const int32_t* __restrict__ col,
+                                           const VT* __restrict__ val, int64_t sl, int lane,
+                                           const double* __restrict__ x) {
+  const int32_t base = off[sl];
+  const int32_t w = (off[sl + 1] - base) >> 6;
+  const int32_t p0 = base + lane;
+  double acc = 0.0;
+  for (int32_t m0 = 0; m0 < w; m0 += kUnroll) {
+    int32_t c[kUnroll];
+    double v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const bool ok = m0 + u < w;
+      const int32_t p = p0 + (ok ? (m0 + u) * kSlice : 0);
+      c[u] = col[p];
+      v[u] = load_val<VT>(val + p);
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const double xv = x[c[u]];
+      acc = (m0 + u < w) ? fma(v[u], xv, acc) : acc;
+    }
+  }
+  return acc;
+}
+
+// the same row product with p = z + beta * p_old formed at every gathered index
+__device__ __forceinline__ double sell_dot_p(const int32_t* __restrict__ off,
+                                             const int32_t* __restrict__ col,
+                                             const double* __restrict__ val, int64_t sl, int lane,
+                                             const double* __restrict__ z,
+                                             const double* __restrict__ po, double beta,
+                                             bool first) {
+  const int32_t base = off[sl];
+  const int32_t w = (off[sl + 1] - base) >> 6;
+  const int32_t p0 = base + lane;
+  double acc = 0.0;
+  for (int32_t m0 = 0; m0 < w; m0 += kUnroll) {
+    int32_t c[kUnroll];
+    double v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const bool ok = m0 + u < w;
+      const int32_t p = p0 + (ok ? (m0 + u) * kSlice : 0);
+      c[u] = col[p];
+      v[u] = val[p];
+    }
+    if (first) {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const double zv = z[c[u]];
+        acc = (m0 + u < w) ? fma(v[u], zv, acc) : acc;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const double pk = fma(beta, po[c[u]], z[c[u]]);
+        acc = (m0 + u < w) ? fma(v[u], pk, acc) : acc;
+      }
+    }
+  }
+  return acc;
+}
+
 // ---- kernels -------------------------------------------------------------------
 
-// x = x~ = 0, r = b, r~ = c; norms of b and c
-__global__ __launch_bounds__(kBlock) void k_init(IterArgs a) {
-  const int c0 = blockIdx.y * kNC;
-  unsigned mask = 0;
-  const double* b[kNC];
-  const double* cc[kNC];
-  double* x[kNC];
-  double* xt[kNC];
-  double* r[kNC];
-  double* rt[kNC];
-  double v[kNC][2];
-#pragma unroll
-  for (int j = 0; j < kNC; ++j) {
-    const int c = min(c0 + j, a.nc - 1);
-    if (c0 + j < a.nc && a.cols[c].state == COL_ACTIVE) mask |= 1u << j;
-    b[j] = a.cols[c].bsrc;
-    cc[j] = a.cols[c].csrc;
-    x[j] = vptr(a, V_X, c);
-    xt[j] = vptr(a, V_XT, c);
-    r[j] = vptr(a, V_R, c);
-    rt[j] = vptr(a, V_RT, c);
-    v[j][0] = v[j][1] = 0.0;
+// x = x~ = 0, r = b, r~ = c; partial norms of b and c
+__global__ __launch_bounds__(1024) void k_init(IterArgs a) {
+  const WaveCtx t = wave_ctx(a);
+  const bool valid = t.c < a.nc && a.cols[t.c].state == COL_ACTIVE;
+  double v[2] = {0.0, 0.0};
+  if (valid) {
+    const ColInfo& ci = a.cols[t.c];
+    double* x = vptr(a, V_X, t.c);
+    double* xt = vptr(a, V_XT, t.c);
+    double* r = vptr(a, V_R, t.c);
+    double* rt = vptr(a, V_RT, t.c);
+    for (int64_t sl = t.s_begin + t.r; sl < t.s_end; sl += a.R) {
+      const int64_t i = sl * kSlice + t.lane;
+      if (i >= a.n) continue;
+      const double bi = ci.bsrc[i], cv = ci.csrc[i];
+      x[i] = 0.0;
+      xt[i] = 0.0;
+      r[i] = bi;
+      rt[i] = cv;
+      v[0] = fma(bi, bi, v[0]);
+      v[1] = fma(cv, cv, v[1]);
+    }
   }
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += (int64_t)a.nblk * kBlock) {
-#pragma unroll
-    for (int j = 0; j < kNC; ++j)
-      if (mask & (1u << j)) {
-        const double bi = b[j][i], ci = cc[j][i];
-        x[j][i] = 0.0;
-        xt[j][i] = 0.0;
-        r[j][i] = bi;
-        rt[j][i] = ci;
-        v[j][0] = fma(bi, bi, v[j][0]);
-        v[j][1] = fma(ci, ci, v[j][1]);
-      }
-  }
-  block_partials<2>(v, mask, a, c0);
-  if (!arrive_last(a.counter, gridDim.x * gridDim.y)) return;
-  for (int c = threadIdx.x >> 6; c < a.nc; c += kWaves) {
+  wave_partials<2>(a, t, valid, v, a.part_norm);
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_fin_init(IterArgs a) {
+  for (int c = threadIdx.x >> 6; c < a.nc; c += kFinThreads / 64) {
     ColInfo& ci = a.cols[c];
     if (ci.state != COL_ACTIVE) continue;
-    const double bb = wave_total(a, 0, c), cc2 = wave_total(a, 1, c);
+    double t2[2];
+    wave_totals<2>(a, a.part_norm, c, t2);
     if ((threadIdx.x & 63) == 0) {
-      ci.nb = sqrt(bb);
-      ci.nc = sqrt(cc2);
-      ci.rr = bb;
-      ci.rtrt = cc2;
+      ci.nb = sqrt(t2[0]);
+      ci.nc = sqrt(t2[1]);
       ci.first = 1;
       ci.it_cycle = 0;
-      if (passed(ci, bb, cc2)) {
-        ci.state = COL_DONE;
-        ci.relp = ci.nb > 0.0 ? 1.0 : 0.0;
-        ci.reld = ci.nc > 0.0 ? 1.0 : 0.0;
-        if (ci.check_p && ci.nb == 0.0) ci.relp = 0.0;
-        if (ci.check_d && ci.nc == 0.0) ci.reld = 0.0;
-      }
     }
   }
 }
 
-// one chain step: forward half applies G[s] (rows of S), transposed half
-// applies G[maxL-1-s]^T (rows of S^T); the last step also forms rho = z~^T r
+// one chain step: the forward half (blockIdx.z == 0) applies G[s] on the rows
+// of S, the transposed half applies G[maxL-1-s]^T on the rows of S^T; the
+// last step also forms the partial sums of rho = z~^T r, ||z~||^2, ||r||^2
 template <typename VT>
-__global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, const VT* __restrict__ fval,
-                                                       const VT* __restrict__ bval, int s, int maxL,
-                                                       int do_rho) {
-  const int c0 = blockIdx.y * kNC;
+__global__ __launch_bounds__(1024) void k_chain_step(IterArgs a, const VT* __restrict__ fval,
+                                                     const VT* __restrict__ bval, int s,
+                                                     int do_rho) {
+  const WaveCtx t = wave_ctx(a);
   const bool bwd = blockIdx.z == 1;
-  const int jf = bwd ? maxL - 1 - s : s;  // factor index applied by this half
-  unsigned mask = 0;
-  const double* src[kNC];
-  double* dst[kNC];
-  const double* rv[kNC];
-#pragma unroll
-  for (int j = 0; j < kNC; ++j) {
-    const int c = min(c0 + j, a.nc - 1);
-    const ColInfo& ci = a.cols[c];
-    const int L = ci.L;
-    if (c0 + j < a.nc && ci.state == COL_ACTIVE && L > jf) mask |= 1u << j;
-    if (!bwd) {
-      src[j] = (jf == 0) ? vptr(a, V_R, c) : vptr(a, V_T0 + ((jf - 1) & 1), c);
-      dst[j] = (jf == L - 1) ? vptr(a, V_Z, c) : vptr(a, V_T0 + (jf & 1), c);
-    } else {
-      const int t = L - 1 - jf;  // how many transposed factors this column applied before
-      src[j] = (t <= 0) ? vptr(a, V_RT, c) : vptr(a, V_TT0 + ((t - 1) & 1), c);
-      dst[j] = (jf == 0) ? vptr(a, V_ZT, c) : vptr(a, V_TT0 + ((t < 0 ? 0 : t) & 1), c);
-    }
-    rv[j] = vptr(a, V_R, c);
-  }
-  const int32_t* off = bwd ? a.offT : a.off;
-  const int32_t* col = bwd ? a.colT : a.col;
-  const VT* val = bwd ? bval : fval;
+  const int jf = bwd ? a.maxL - 1 - s : s;  // factor index applied by this half
   const bool rho_half = bwd && do_rho;
-  double v[kNC][3];
-#pragma unroll
-  for (int j = 0; j < kNC; ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
-  if (mask) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n;
-         i += (int64_t)a.nblk * kBlock) {
-      double acc[kNC];
-#pragma unroll
-      for (int j = 0; j < kNC; ++j) acc[j] = 0.0;
-      sell_row<VT, kNC>(off, col, val, i, src, mask, acc);
-#pragma unroll
-      for (int j = 0; j < kNC; ++j)
-        if (mask & (1u << j)) {
-          dst[j][i] = acc[j];
-          if (rho_half) {
-            const double ri = rv[j][i];
-            v[j][0] = fma(acc[j], ri, v[j][0]);
-            v[j][1] = fma(acc[j], acc[j], v[j][1]);
-            v[j][2] = fma(ri, ri, v[j][2]);
-          }
-        }
+  bool valid = false;
+  const double* src = nullptr;
+  double* dst = nullptr;
+  if (t.c < a.nc) {
+    const ColInfo& ci = a.cols[t.c];
+    const int L = ci.L;
+    valid = ci.state == COL_ACTIVE && L > jf;
+    if (!bwd) {
+      src = (jf == 0) ? vptr(a, V_R, t.c) : vptr(a, V_T0 + ((jf - 1) & 1), t.c);
+      dst = (jf == L - 1) ? vptr(a, V_Z, t.c) : vptr(a, V_T0 + (jf & 1), t.c);
+    } else {
+      const int k = max(L - 1 - jf, 0);  // transposed factors this column applied before
+      src = (k == 0) ? vptr(a, V_RT, t.c) : vptr(a, V_TT0 + ((k - 1) & 1), t.c);
+      dst = (jf == 0) ? vptr(a, V_ZT, t.c) : vptr(a, V_TT0 + (k & 1), t.c);
     }
   }
-  if (!rho_half) return;
-  block_partials<3>(v, mask, a, c0);
-  if (!arrive_last(a.counter, gridDim.x * gridDim.y)) return;
-  for (int c = threadIdx.x >> 6; c < a.nc; c += kWaves) {
+  double v[3] = {0.0, 0.0, 0.0};
+  if (valid) {
+    const int32_t* off = bwd ? a.offT : a.off;
+    const int32_t* col = bwd ? a.colT : a.col;
+    const VT* val = bwd ? bval : fval;
+    const double* rv = vptr(a, V_R, t.c);
+    for (int64_t sl = t.s_begin + t.r; sl < t.s_end; sl += a.R) {
+      const int64_t i = sl * kSlice + t.lane;
+      const double acc = sell_dot<VT>(off, col, val, sl, t.lane, src);
+      if (i < a.n) {
+        dst[i] = acc;
+        if (rho_half) {
+          const double ri = rv[i];
+          v[0] = fma(acc, ri, v[0]);
+          v[1] = fma(acc, acc, v[1]);
+          v[2] = fma(ri, ri, v[2]);
+        }
+      }
+    }
+  }
+  if (rho_half) wave_partials<3>(a, t, valid, v, a.part_rho);
+}
+
+// convergence test on the residuals of the previous update (or of the start
+// of the cycle), the iteration limit, then rho and beta
+__global__ __launch_bounds__(kFinThreads) void k_fin_rho(IterArgs a) {
+  __shared__ double chain_cols, act_cols, vec_cols, first_cols;
+  if (threadIdx.x == 0) chain_cols = act_cols = vec_cols = first_cols = 0.0;
+  __syncthreads();
+  for (int c = threadIdx.x >> 6; c < a.nc; c += kFinThreads / 64) {
     ColInfo& ci = a.cols[c];
     if (ci.state != COL_ACTIVE) continue;
-    const double rho = wave_total(a, 0, c), zz = wave_total(a, 1, c), rr = wave_total(a, 2, c);
+    double tn[2], tr[3];
+    wave_totals<2>(a, a.part_norm, c, tn);
+    wave_totals<3>(a, a.part_rho, c, tr);
+    const double rr = tn[0], rtrt = tn[1], rho = tr[0], zz = tr[1], r2 = tr[2];
     if ((threadIdx.x & 63) == 0) {
-      if (fabs(rho) <= kBreakdown * sqrt(zz) * sqrt(rr)) {
+      if (a.trace) {
+        atomicAdd(&chain_cols, (double)ci.L);
+        atomicAdd(&act_cols, 1.0);
+      }
+      ci.rr = rr;
+      ci.rtrt = rtrt;
+      if (passed(ci, rr, rtrt)) {
+        ci.state = COL_CONVERGED;
+      } else if (ci.it_cycle >= ci.maxit) {
+        ci.state = COL_MAXIT;
+      } else if (fabs(rho) <= kBreakdown * sqrt(zz) * sqrt(r2)) {
         ci.state = COL_BREAKDOWN;
         ci.broke = 1;
       } else {
         ci.beta = ci.first ? 0.0 : rho / ci.rho_prev;
         ci.rho = rho;
+        if (a.trace) {
+          atomicAdd(&vec_cols, 1.0);
+          if (ci.first) atomicAdd(&first_cols, 1.0);
+        }
       }
+    }
+  }
+  if (!a.trace) return;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // algorithmic bytes of this iteration's chain launches and of spmv_pair
+    const double n = (double)a.n, nnz = (double)a.nnzS;
+    const double mat = (double)(a.vbytes + 4) * nnz + 4.0 * (n + 1.0);
+    if (chain_cols > 0.0) {
+      // maxL factor passes per direction; per (column, factor, direction) one
+      // n-vector read and one written; r read once per column for rho
+      a.trace[TR_CHAIN] += 2.0 * a.maxL * mat + 2.0 * 16.0 * n * chain_cols + 8.0 * n * act_cols;
+    }
+    if (vec_cols > 0.0) {
+      const double amat = 2.0 * (12.0 * nnz + 4.0 * (n + 1.0)) + 8.0 * n;
+      a.trace[TR_SPMV] += amat + 64.0 * n * vec_cols - 16.0 * n * first_cols;
     }
   }
 }
 
 // p = z + beta p, p~ = z~ + beta p~ (formed on the fly at every gathered
-// index), q = (sigma E - A) p, q~ = (sigma E - A)^T p~, delta = p~^T q
-__global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
-  const int c0 = blockIdx.y * kNC;
-  unsigned mask = 0;
-  const double *z[kNC], *zt[kNC], *po[kNC], *pto[kNC];
-  double *pn[kNC], *ptn[kNC], *q[kNC], *qt[kNC];
-  double beta[kNC], sig[kNC];
-  bool first[kNC];
-#pragma unroll
-  for (int j = 0; j < kNC; ++j) {
-    const int c = min(c0 + j, a.nc - 1);
-    const ColInfo& ci = a.cols[c];
-    if (c0 + j < a.nc && ci.state == COL_ACTIVE) mask |= 1u << j;
-    z[j] = vptr(a, V_Z, c);
-    zt[j] = vptr(a, V_ZT, c);
-    po[j] = vptr(a, V_P0 + (par ^ 1), c);
-    pto[j] = vptr(a, V_PT0 + (par ^ 1), c);
-    pn[j] = vptr(a, V_P0 + par, c);
-    ptn[j] = vptr(a, V_PT0 + par, c);
-    q[j] = vptr(a, V_Q, c);
-    qt[j] = vptr(a, V_QT, c);
-    beta[j] = ci.beta;
-    sig[j] = ci.sigma;
-    first[j] = ci.first != 0;
-  }
-  double v[kNC][3];
-#pragma unroll
-  for (int j = 0; j < kNC; ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
-  if (mask) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n;
-         i += (int64_t)a.nblk * kBlock) {
-      double acc[kNC], acct[kNC];
-#pragma unroll
-      for (int j = 0; j < kNC; ++j) acc[j] = acct[j] = 0.0;
-      const int64_t sl = i >> 6;
-      const int32_t lane = (int32_t)(i & 63);
-      {
-        const int32_t o1 = a.off[sl + 1];
-        for (int32_t p = a.off[sl] + lane; p < o1; p += kSlice) {
-          const int32_t cidx = a.col[p];
-          const double av = a.valA[p];
-#pragma unroll
-          for (int j = 0; j < kNC; ++j)
-            if (mask & (1u << j)) {
-              const double pc = first[j] ? z[j][cidx] : fma(beta[j], po[j][cidx], z[j][cidx]);
-              acc[j] = fma(av, pc, acc[j]);
-            }
-        }
+// index), q = (sigma E - A) p, q~ = (sigma E - A)^T p~, partial sums of
+// delta = p~^T q, ||p~||^2, ||q||^2
+__global__ __launch_bounds__(1024) void k_spmv_pair(IterArgs a, int par) {
+  const WaveCtx t = wave_ctx(a);
+  const bool valid = t.c < a.nc && a.cols[t.c].state == COL_ACTIVE;
+  double v[3] = {0.0, 0.0, 0.0};
+  if (valid) {
+    const ColInfo& ci = a.cols[t.c];
+    const double beta = ci.beta, sig = ci.sigma;
+    const bool first = ci.first != 0;
+    const double* z = vptr(a, V_Z, t.c);
+    const double* zt = vptr(a, V_ZT, t.c);
+    const double* po = vptr(a, V_P0 + (par ^ 1), t.c);
+    const double* pto = vptr(a, V_PT0 + (par ^ 1), t.c);
+    double* pn = vptr(a, V_P0 + par, t.c);
+    double* ptn = vptr(a, V_PT0 + par, t.c);
+    double* q = vptr(a, V_Q, t.c);
+    double* qt = vptr(a, V_QT, t.c);
+    for (int64_t sl = t.s_begin + t.r; sl < t.s_end; sl += a.R) {
+      const int64_t i = sl * kSlice + t.lane;
+      const double acc = sell_dot_p(a.off, a.col, a.valA, sl, t.lane, z, po, beta, first);
+      const double acct = sell_dot_p(a.offT, a.colT, a.valAT, sl, t.lane, zt, pto, beta, first);
+      if (i < a.n) {
+        const double se = sig * a.e[i];
+        const double pi = first ? z[i] : fma(beta, po[i], z[i]);
+        const double pti = first ? zt[i] : fma(beta, pto[i], zt[i]);
+        const double qi = fma(se, pi, -acc);
+        const double qti = fma(se, pti, -acct);
+        pn[i] = pi;
+        ptn[i] = pti;
+        q[i] = qi;
+        qt[i] = qti;
+        v[0] = fma(pti, qi, v[0]);
+        v[1] = fma(pti, pti, v[1]);
+        v[2] = fma(qi, qi, v[2]);
       }
-      {
-        const int32_t o1 = a.offT[sl + 1];
-        for (int32_t p = a.offT[sl] + lane; p < o1; p += kSlice) {
-          const int32_t cidx = a.colT[p];
-          const double av = a.valAT[p];
-#pragma unroll
-          for (int j = 0; j < kNC; ++j)
-            if (mask & (1u << j)) {
-              const double pc = first[j] ? zt[j][cidx] : fma(beta[j], pto[j][cidx], zt[j][cidx]);
-              acct[j] = fma(av, pc, acct[j]);
-            }
-        }
-      }
-      const double ei = a.e[i];
-#pragma unroll
-      for (int j = 0; j < kNC; ++j)
-        if (mask & (1u << j)) {
-          const double pi = first[j] ? z[j][i] : fma(beta[j], po[j][i], z[j][i]);
-          const double pti = first[j] ? zt[j][i] : fma(beta[j], pto[j][i], zt[j][i]);
-          const double qi = fma(sig[j] * ei, pi, -acc[j]);
-          const double qti = fma(sig[j] * ei, pti, -acct[j]);
-          pn[j][i] = pi;
-          ptn[j][i] = pti;
-          q[j][i] = qi;
-          qt[j][i] = qti;
-          v[j][0] = fma(pti, qi, v[j][0]);
-          v[j][1] = fma(pti, pti, v[j][1]);
-          v[j][2] = fma(qi, qi, v[j][2]);
-        }
     }
   }
-  block_partials<3>(v, mask, a, c0);
-  if (!arrive_last(a.counter, gridDim.x * gridDim.y)) return;
-  for (int c = threadIdx.x >> 6; c < a.nc; c += kWaves) {
+  wave_partials<3>(a, t, valid, v, a.part_delta);
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_fin_delta(IterArgs a) {
+  __shared__ double upd_cols;
+  if (threadIdx.x == 0) upd_cols = 0.0;
+  __syncthreads();
+  for (int c = threadIdx.x >> 6; c < a.nc; c += kFinThreads / 64) {
     ColInfo& ci = a.cols[c];
     if (ci.state != COL_ACTIVE) continue;
-    const double delta = wave_total(a, 0, c), pp = wave_total(a, 1, c), qq = wave_total(a, 2, c);
+    double td[3];
+    wave_totals<3>(a, a.part_delta, c, td);
+    const double delta = td[0], pp = td[1], qq = td[2];
     if ((threadIdx.x & 63) == 0) {
       if (fabs(delta) <= kBreakdown * sqrt(pp) * sqrt(qq)) {
         ci.state = COL_BREAKDOWN;
@@ -360,139 +457,95 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
       } else {
         ci.delta = delta;
         ci.alpha = ci.rho / delta;
+        ci.it_cycle += 1;
+        ci.iters += 1;
+        ci.rho_prev = ci.rho;
+        ci.first = 0;
+        if (a.trace) atomicAdd(&upd_cols, 1.0);
       }
     }
   }
+  if (!a.trace) return;
+  __syncthreads();
+  if (threadIdx.x == 0) a.trace[TR_UPDATE] += 96.0 * (double)a.n * upd_cols;
 }
 
-// x += alpha p, x~ += alpha p~, r -= alpha q, r~ -= alpha q~; convergence test
-__global__ __launch_bounds__(kBlock) void k_update(IterArgs a, int par) {
-  const int c0 = blockIdx.y * kNC;
-  unsigned mask = 0;
-  double *x[kNC], *xt[kNC], *r[kNC], *rt[kNC];
-  const double *p[kNC], *pt[kNC], *q[kNC], *qt[kNC];
-  double al[kNC];
-#pragma unroll
-  for (int j = 0; j < kNC; ++j) {
-    const int c = min(c0 + j, a.nc - 1);
-    const ColInfo& ci = a.cols[c];
-    if (c0 + j < a.nc && ci.state == COL_ACTIVE) mask |= 1u << j;
-    x[j] = vptr(a, V_X, c);
-    xt[j] = vptr(a, V_XT, c);
-    r[j] = vptr(a, V_R, c);
-    rt[j] = vptr(a, V_RT, c);
-    p[j] = vptr(a, V_P0 + par, c);
-    pt[j] = vptr(a, V_PT0 + par, c);
-    q[j] = vptr(a, V_Q, c);
-    qt[j] = vptr(a, V_QT, c);
-    al[j] = ci.alpha;
-  }
-  double v[kNC][2];
-#pragma unroll
-  for (int j = 0; j < kNC; ++j) v[j][0] = v[j][1] = 0.0;
-  if (mask) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n;
-         i += (int64_t)a.nblk * kBlock) {
-#pragma unroll
-      for (int j = 0; j < kNC; ++j)
-        if (mask & (1u << j)) {
-          x[j][i] = fma(al[j], p[j][i], x[j][i]);
-          xt[j][i] = fma(al[j], pt[j][i], xt[j][i]);
-          const double ri = fma(-al[j], q[j][i], r[j][i]);
-          const double rti = fma(-al[j], qt[j][i], rt[j][i]);
-          r[j][i] = ri;
-          rt[j][i] = rti;
-          v[j][0] = fma(ri, ri, v[j][0]);
-          v[j][1] = fma(rti, rti, v[j][1]);
-        }
+// x += alpha p, x~ += alpha p~, r -= alpha q, r~ -= alpha q~; partial norms
+__global__ __launch_bounds__(1024) void k_update(IterArgs a, int par) {
+  const WaveCtx t = wave_ctx(a);
+  const bool valid = t.c < a.nc && a.cols[t.c].state == COL_ACTIVE;
+  double v[2] = {0.0, 0.0};
+  if (valid) {
+    const double al = a.cols[t.c].alpha;
+    double* x = vptr(a, V_X, t.c);
+    double* xt = vptr(a, V_XT, t.c);
+    double* r = vptr(a, V_R, t.c);
+    double* rt = vptr(a, V_RT, t.c);
+    const double* p = vptr(a, V_P0 + par, t.c);
+    const double* pt = vptr(a, V_PT0 + par, t.c);
+    const double* q = vptr(a, V_Q, t.c);
+    const double* qt = vptr(a, V_QT, t.c);
+    for (int64_t sl = t.s_begin + t.r; sl < t.s_end; sl += a.R) {
+      const int64_t i = sl * kSlice + t.lane;
+      if (i >= a.n) continue;
+      x[i] = fma(al, p[i], x[i]);
+      xt[i] = fma(al, pt[i], xt[i]);
+      const double ri = fma(-al, q[i], r[i]);
+      const double rti = fma(-al, qt[i], rt[i]);
+      r[i] = ri;
+      rt[i] = rti;
+      v[0] = fma(ri, ri, v[0]);
+      v[1] = fma(rti, rti, v[1]);
     }
   }
-  block_partials<2>(v, mask, a, c0);
-  if (!arrive_last(a.counter, gridDim.x * gridDim.y)) return;
-  for (int c = threadIdx.x >> 6; c < a.nc; c += kWaves) {
+  wave_partials<2>(a, t, valid, v, a.part_norm);
+}
+
+// true residuals r = b - A_s x, r~ = c - A_s^T x~ of the columns that stopped
+__global__ __launch_bounds__(1024) void k_true_residual(IterArgs a) {
+  const WaveCtx t = wave_ctx(a);
+  const bool valid = t.c < a.nc && stopped(a.cols[t.c].state);
+  double v[2] = {0.0, 0.0};
+  if (valid) {
+    const ColInfo& ci = a.cols[t.c];
+    const double sig = ci.sigma;
+    const double* x = vptr(a, V_X, t.c);
+    const double* xt = vptr(a, V_XT, t.c);
+    double* r = vptr(a, V_R, t.c);
+    double* rt = vptr(a, V_RT, t.c);
+    for (int64_t sl = t.s_begin + t.r; sl < t.s_end; sl += a.R) {
+      const int64_t i = sl * kSlice + t.lane;
+      const double acc = sell_dot<double>(a.off, a.col, a.valA, sl, t.lane, x);
+      const double acct = sell_dot<double>(a.offT, a.colT, a.valAT, sl, t.lane, xt);
+      if (i >= a.n) continue;
+      const double se = sig * a.e[i];
+      // b - (sigma E x - A x)
+      const double ri = ci.bsrc[i] - fma(se, x[i], -acc);
+      const double rti = ci.csrc[i] - fma(se, xt[i], -acct);
+      r[i] = ri;
+      rt[i] = rti;
+      v[0] = fma(ri, ri, v[0]);
+      v[1] = fma(rti, rti, v[1]);
+    }
+  }
+  wave_partials<2>(a, t, valid, v, a.part_norm);
+}
+
+// accept, restart from the current iterates (true residuals are in r, r~ and
+// their norms in the norm partials, read by the next fin_rho), or give up
+__global__ __launch_bounds__(kFinThreads) void k_fin_true(IterArgs a) {
+  for (int c = threadIdx.x >> 6; c < a.nc; c += kFinThreads / 64) {
     ColInfo& ci = a.cols[c];
-    if (ci.state != COL_ACTIVE) continue;
-    const double rr = wave_total(a, 0, c), rtrt = wave_total(a, 1, c);
+    const int st = ci.state;
+    if (!stopped(st)) continue;
+    double tn[2];
+    wave_totals<2>(a, a.part_norm, c, tn);
+    const double rr = tn[0], rtrt = tn[1];
     if ((threadIdx.x & 63) == 0) {
       ci.rr = rr;
       ci.rtrt = rtrt;
-      ci.it_cycle += 1;
-      ci.iters += 1;
-      ci.rho_prev = ci.rho;
-      ci.first = 0;
-      if (passed(ci, rr, rtrt)) ci.state = COL_CONVERGED;
-      else if (ci.it_cycle >= ci.maxit) ci.state = COL_MAXIT;
-    }
-  }
-}
-
-// true residuals r = b - A_s x, r~ = c - A_s^T x~ for columns that stopped
-// iterating; accept, restart from the current iterates, or give up
-__global__ __launch_bounds__(kBlock) void k_true_residual(IterArgs a) {
-  const int c0 = blockIdx.y * kNC;
-  unsigned mask = 0;
-  const double *x[kNC], *xt[kNC], *b[kNC], *cc[kNC];
-  double *r[kNC], *rt[kNC];
-  double sig[kNC];
-#pragma unroll
-  for (int j = 0; j < kNC; ++j) {
-    const int c = min(c0 + j, a.nc - 1);
-    const ColInfo& ci = a.cols[c];
-    const int st = ci.state;
-    if (c0 + j < a.nc && (st == COL_CONVERGED || st == COL_BREAKDOWN || st == COL_MAXIT))
-      mask |= 1u << j;
-    x[j] = vptr(a, V_X, c);
-    xt[j] = vptr(a, V_XT, c);
-    r[j] = vptr(a, V_R, c);
-    rt[j] = vptr(a, V_RT, c);
-    b[j] = ci.bsrc;
-    cc[j] = ci.csrc;
-    sig[j] = ci.sigma;
-  }
-  double v[kNC][2];
-#pragma unroll
-  for (int j = 0; j < kNC; ++j) v[j][0] = v[j][1] = 0.0;
-  if (mask) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n;
-         i += (int64_t)a.nblk * kBlock) {
-      double acc[kNC], acct[kNC];
-#pragma unroll
-      for (int j = 0; j < kNC; ++j) acc[j] = acct[j] = 0.0;
-      const double* xs[kNC];
-      const double* xts[kNC];
-#pragma unroll
-      for (int j = 0; j < kNC; ++j) {
-        xs[j] = x[j];
-        xts[j] = xt[j];
-      }
-      sell_row<double, kNC>(a.off, a.col, a.valA, i, xs, mask, acc);
-      sell_row<double, kNC>(a.offT, a.colT, a.valAT, i, xts, mask, acct);
-      const double ei = a.e[i];
-#pragma unroll
-      for (int j = 0; j < kNC; ++j)
-        if (mask & (1u << j)) {
-          // b - (sigma E x - A x) = b - sigma e x + A x
-          const double ri = b[j][i] - fma(sig[j] * ei, x[j][i], -acc[j]);
-          const double rti = cc[j][i] - fma(sig[j] * ei, xt[j][i], -acct[j]);
-          r[j][i] = ri;
-          rt[j][i] = rti;
-          v[j][0] = fma(ri, ri, v[j][0]);
-          v[j][1] = fma(rti, rti, v[j][1]);
-        }
-    }
-  }
-  block_partials<2>(v, mask, a, c0);
-  if (!arrive_last(a.counter, gridDim.x * gridDim.y)) return;
-  for (int c = threadIdx.x >> 6; c < a.nc; c += kWaves) {
-    ColInfo& ci = a.cols[c];
-    const int st = ci.state;
-    if (!(st == COL_CONVERGED || st == COL_BREAKDOWN || st == COL_MAXIT)) continue;
-    const double rr = wave_total(a, 0, c), rtrt = wave_total(a, 1, c);
-    if ((threadIdx.x & 63) == 0) {
-      ci.rr = rr;
-      ci.rtrt = rtrt;
-      ci.relp = ci.nb > 0.0 ? sqrt(rr) / ci.nb : 0.0;
-      ci.reld = ci.nc > 0.0 ? sqrt(rtrt) / ci.nc : 0.0;
+      ci.relp = ci.nb > 0.0 ? sqrt(rr) / ci.nb : sqrt(rr);
+      ci.reld = ci.nc > 0.0 ? sqrt(rtrt) / ci.nc : sqrt(rtrt);
       if (passed(ci, rr, rtrt)) {
         ci.state = COL_DONE;
         ci.status = MORX_OK;
@@ -510,18 +563,16 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(IterArgs a) {
 }
 
 // copy the iterates to the caller's columns (or zeros)
-__global__ __launch_bounds__(kBlock) void k_copy_out(IterArgs a, int64_t ldx, int64_t ldy) {
+__global__ __launch_bounds__(256) void k_copy_out(IterArgs a) {
   const int c = blockIdx.y;
   const ColInfo& ci = a.cols[c];
   const double* xs = vptr(a, V_X, c);
   const double* ys = vptr(a, V_XT, c);
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n;
-       i += (int64_t)gridDim.x * kBlock) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n;
+       i += (int64_t)gridDim.x * 256) {
     if (ci.xout) ci.xout[i] = ci.out_x == 1 ? xs[i] : (ci.out_x == 2 ? ys[i] : 0.0);
     if (ci.yout) ci.yout[i] = ci.out_y == 1 ? xs[i] : (ci.out_y == 2 ? ys[i] : 0.0);
   }
-  (void)ldx;
-  (void)ldy;
 }
 
 __global__ void k_zero(double* p, int64_t count) {
@@ -529,24 +580,175 @@ __global__ void k_zero(double* p, int64_t count) {
   if (i < count) p[i] = 0.0;
 }
 
-// column norms of a dense block, one block per column (fixed order)
-__global__ __launch_bounds__(kBlock) void k_colnorm(const double* X, int64_t ld, int64_t n,
-                                                    double* out) {
-  __shared__ double sh[kWaves];
-  const double* x = X + (int64_t)blockIdx.x * ld;
+// column norms of a dense block: partial sums over row slabs, then one wave per column
+constexpr int kNormSlabs = 64;
+__global__ __launch_bounds__(256) void k_colnorm_part(const double* X, int64_t ld, int64_t n,
+                                                      double* part) {
+  __shared__ double sh[4];
+  const double* x = X + (int64_t)blockIdx.y * ld;
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += kBlock) s = fma(x[i], x[i], s);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    s = fma(x[i], x[i], s);
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < kWaves; ++w) t += sh[w];
-    out[blockIdx.x] = sqrt(t);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_colnorm_fin(const double* part, int ncol,
+                                                             double* out) {
+  for (int c = threadIdx.x >> 6; c < ncol; c += kFinThreads / 64) {
+    const int lane = threadIdx.x & 63;
+    const double v = lane < kNormSlabs ? part[(int64_t)c * kNormSlabs + lane] : 0.0;
+    const double s = wave_sum(v);
+    if (lane == 0) out[c] = sqrt(s);
   }
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// tracing: per-class launch events and algorithmic bytes
+
+struct TraceState {
+  bool on = false;
+  DevBuf counters;  // double[kTraceClasses]
+  struct Pending {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> free_events;
+  double ms[kTraceClasses] = {0};
+  int64_t launches[kTraceClasses] = {0};
+};
+
+static TraceState* trace_of(morx_ctx ctx) {
+  static std::mutex mu;
+  static std::vector<std::pair<morx_ctx, TraceState*>> all;
+  std::lock_guard<std::mutex> lk(mu);
+  for (auto& p : all)
+    if (p.first == ctx) return p.second;
+  all.push_back({ctx, new TraceState()});
+  return all.back().second;
+}
+
+static hipEvent_t trace_event(TraceState* t) {
+  if (!t->free_events.empty()) {
+    hipEvent_t e = t->free_events.back();
+    t->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch a kernel; when tracing, through hipExtLaunchKernelGGL so that the
+// start and stop events time the dispatch itself (no inter-kernel gap).
+template <typename... KArgs, typename... Args>
+static void launch(TraceState* t, int cls, void (*kernel)(KArgs...), dim3 g, dim3 b,
+                   hipStream_t st, Args... args) {
+  if (!t || !t->on) {
+    hipLaunchKernelGGL(kernel, g, b, 0, st, args...);
+    return;
+  }
+  hipEvent_t e0 = trace_event(t), e1 = trace_event(t);
+  hipExtLaunchKernelGGL(kernel, g, b, 0, st, e0, e1, 0, args...);
+  if (e0 && e1) t->pending.push_back({cls, e0, e1});
+}
+
+static void trace_collect(TraceState* t) {
+  for (auto& p : t->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      t->ms[p.cls] += ms;
+      t->launches[p.cls] += 1;
+    }
+    t->free_events.push_back(p.a);
+    t->free_events.push_back(p.b);
+  }
+  t->pending.clear();
+}
+
+static const char* kTraceNames[kTraceClasses] = {"chain_step", "spmv_pair", "update", "factor_ls",
+                                                 "", "", "", ""};
+
+TraceState* trace_state_if_on(morx_ctx ctx) {
+  TraceState* t = trace_of(ctx);
+  return t->on ? t : nullptr;
+}
+
+static double* trace_counters(morx_ctx ctx) {
+  TraceState* t = trace_of(ctx);
+  return t->on ? (double*)t->counters.p : nullptr;
+}
+
+extern "C" morx_status morx_trace_enable(morx_ctx ctx, int32_t enable) {
+  MORX_REQUIRE(ctx, MORX_E_INVALID, "morx_trace_enable: null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  MORX_HIP(hipSetDevice(ctx->device));
+  TraceState* t = trace_of(ctx);
+  if (enable && !t->counters.p) MORX_TRY(dev_alloc(t->counters, kTraceClasses * sizeof(double)));
+  if (enable) {
+    MORX_HIP(hipStreamSynchronize(ctx->stream));
+    k_zero<<<1, 64, 0, ctx->stream>>>((double*)t->counters.p, kTraceClasses);
+    MORX_HIP(hipGetLastError());
+    MORX_HIP(hipStreamSynchronize(ctx->stream));
+    for (int c = 0; c < kTraceClasses; ++c) {
+      t->ms[c] = 0.0;
+      t->launches[c] = 0;
+    }
+  }
+  t->on = enable != 0;
+  return MORX_OK;
+}
+
+extern "C" morx_status morx_trace_read(morx_ctx ctx, morx_trace_entry* out, int32_t cap,
+                                       int32_t* count) {
+  MORX_REQUIRE(ctx && count, MORX_E_INVALID, "morx_trace_read: null argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  MORX_HIP(hipSetDevice(ctx->device));
+  TraceState* t = trace_of(ctx);
+  double bytes[kTraceClasses] = {0};
+  if (t->counters.p) {
+    MORX_HIP(hipStreamSynchronize(ctx->stream));
+    MORX_HIP(hipMemcpy(bytes, t->counters.p, sizeof(bytes), hipMemcpyDeviceToHost));
+  }
+  int k = 0;
+  for (int c = 0; c < kTraceClasses; ++c) {
+    if (!kTraceNames[c][0]) continue;
+    if (out && k < cap) {
+      memset(&out[k], 0, sizeof(out[k]));
+      strncpy(out[k].name, kTraceNames[c], sizeof(out[k].name) - 1);
+      out[k].launches = t->launches[c];
+      out[k].total_ms = t->ms[c];
+      out[k].alg_bytes = bytes[c];
+    }
+    ++k;
+  }
+  *count = k;
+  return MORX_OK;
+}
+
+// factor construction launches are traced from factor.hip through these
+void trace_factor_begin(morx_ctx ctx, hipStream_t st, void** token) {
+  *token = nullptr;
+  TraceState* t = trace_state_if_on(ctx);
+  if (!t) return;
+  hipEvent_t a = trace_event(t);
+  if (a) hipEventRecord(a, st);
+  *token = a;
+}
+
+void trace_factor_end(morx_ctx ctx, hipStream_t st, void* token) {
+  TraceState* t = trace_state_if_on(ctx);
+  if (!t || !token) return;
+  hipEvent_t b = trace_event(t);
+  if (!b) return;
+  hipEventRecord(b, st);
+  t->pending.push_back({TR_FACTOR, (hipEvent_t)token, b});
+}
 
 // ---------------------------------------------------------------------------
 // host side
@@ -557,8 +759,7 @@ void workspace_free(Workspace* ws) {
   if (ws->graph) hipGraphDestroy(ws->graph);
   dev_free(ws->vec);
   dev_free(ws->cols);
-  dev_free(ws->partial);
-  dev_free(ws->counters);
+  dev_free(ws->part);
   if (ws->hcols) hipHostFree(ws->hcols);
   delete ws;
 }
@@ -567,7 +768,6 @@ static morx_status workspace_reserve(morx_system sys, int ncol) {
   Workspace* ws = sys->ws;
   if (ws && ws->cap >= ncol && ws->ld == sys->n_pad) return MORX_OK;
   int cap = std::max(ncol, ws ? 2 * ws->cap : 4);
-  cap = std::max(cap, ncol);
   if (ws) {
     MORX_HIP(hipStreamSynchronize(sys->ctx->stream));
     workspace_free(ws);
@@ -576,11 +776,9 @@ static morx_status workspace_reserve(morx_system sys, int ncol) {
   ws = new Workspace();
   ws->ld = sys->n_pad;
   ws->cap = cap;
-  ws->nblk_cap = kMaxBlocks;
   morx_status s = dev_alloc(ws->vec, (size_t)kNumVec * cap * ws->ld * sizeof(double));
   if (s == MORX_OK) s = dev_alloc(ws->cols, (size_t)cap * sizeof(ColInfo));
-  if (s == MORX_OK) s = dev_alloc(ws->partial, (size_t)4 * cap * kMaxBlocks * sizeof(double));
-  if (s == MORX_OK) s = dev_alloc(ws->counters, 64 * sizeof(unsigned));
+  if (s == MORX_OK) s = dev_alloc(ws->part, (size_t)8 * cap * kMaxBlocks * sizeof(double));
   if (s == MORX_OK && hipHostMalloc((void**)&ws->hcols, (size_t)cap * sizeof(ColInfo)) != hipSuccess)
     s = MORX_E_NOMEM;
   if (s != MORX_OK) {
@@ -589,10 +787,8 @@ static morx_status workspace_reserve(morx_system sys, int ncol) {
     return MORX_E_NOMEM;
   }
   hipStream_t st = sys->ctx->stream;
-  int64_t cnt = (int64_t)(ws->vec.bytes / sizeof(double));
+  const int64_t cnt = (int64_t)(ws->vec.bytes / sizeof(double));
   k_zero<<<(unsigned)((cnt + 255) / 256), 256, 0, st>>>((double*)ws->vec.p, cnt);
-  int64_t cc = 64 / 2;  // counters: 64 unsigned = 32 doubles of zero bits
-  k_zero<<<1, 256, 0, st>>>((double*)ws->counters.p, cc);
   MORX_HIP(hipGetLastError());
   sys->ws = ws;
   return MORX_OK;
@@ -609,13 +805,24 @@ struct BatchCol {
   morx_col_stats* stats;
 };
 
-static IterArgs make_args(morx_system sys, Workspace* ws, int nc, int slot) {
+static IterArgs make_args(morx_system sys, Workspace* ws, int nc, int prec, int maxL) {
   IterArgs a;
   a.n = sys->n;
   a.ld = ws->ld;
+  a.nnzS = sys->nnzS;
+  a.nslices = sys->nslice;
   a.cap = ws->cap;
   a.nc = nc;
-  a.nblk = (int)std::min<int64_t>((sys->n + kBlock - 1) / kBlock, kMaxBlocks);
+  // columns per block, row groups per block, slabs (a multiple of 8 for the
+  // XCD remap), slices per slab
+  a.W = std::min(nc, kMaxW);
+  a.R = a.W >= 4 ? 1 : 4 / a.W;
+  int64_t nb = std::min<int64_t>((a.nslices + a.R - 1) / a.R, kMaxBlocks);
+  nb = std::max<int64_t>(8, (nb + 7) / 8 * 8);
+  a.nblk = (int)nb;
+  a.spb = (int)((a.nslices + nb - 1) / nb);
+  a.vbytes = (int)prec_bytes(prec);
+  a.maxL = maxL;
   a.off = sys->sell.off;
   a.col = sys->sell.col;
   a.offT = sys->sellT.off;
@@ -625,36 +832,43 @@ static IterArgs make_args(morx_system sys, Workspace* ws, int nc, int slot) {
   a.e = sys->e;
   a.vec = (double*)ws->vec.p;
   a.cols = (ColInfo*)ws->cols.p;
-  a.partial = (double*)ws->partial.p;
-  a.counter = (unsigned*)ws->counters.p + slot;
+  double* part = (double*)ws->part.p;
+  const int64_t slab = (int64_t)ws->cap * kMaxBlocks;
+  a.part_rho = part;
+  a.part_delta = part + 3 * slab;
+  a.part_norm = part + 6 * slab;
+  a.trace = trace_counters(sys->ctx);
   return a;
 }
 
+static dim3 grid_of(const IterArgs& a, int halves) {
+  return dim3((unsigned)a.nblk, (unsigned)((a.nc + a.W - 1) / a.W), (unsigned)halves);
+}
+static dim3 block_of(const IterArgs& a) { return dim3((unsigned)(64 * a.W * a.R)); }
+
 template <typename VT>
-static void enqueue_chain(IterArgs a, const std::vector<morx_factor>& G, int maxL, dim3 grid,
-                          hipStream_t st) {
-  for (int s = 0; s < maxL; ++s) {
+static void enqueue_chain(const IterArgs& a, const std::vector<morx_factor>& G, hipStream_t st,
+                          TraceState* t) {
+  const dim3 g = grid_of(a, 2), b = block_of(a);
+  for (int s = 0; s < a.maxL; ++s) {
     const VT* fv = (const VT*)G[s]->vals.p;
-    const VT* bv = (const VT*)G[maxL - 1 - s]->valsT.p;
-    k_chain_step<VT><<<grid, kBlock, 0, st>>>(a, fv, bv, s, maxL, s == maxL - 1 ? 1 : 0);
+    const VT* bv = (const VT*)G[a.maxL - 1 - s]->valsT.p;
+    launch(t, TR_CHAIN, k_chain_step<VT>, g, b, st, a, fv, bv, s, s == a.maxL - 1 ? 1 : 0);
   }
 }
 
-static morx_status enqueue_iterations(morx_system sys, Workspace* ws, int nc,
-                                      const std::vector<morx_factor>& G, int maxL, int prec,
-                                      int iters, hipStream_t st) {
-  IterArgs a_chain = make_args(sys, ws, nc, 0);
-  IterArgs a_spmv = make_args(sys, ws, nc, 1);
-  IterArgs a_upd = make_args(sys, ws, nc, 2);
-  const unsigned chunks = (unsigned)((nc + kNC - 1) / kNC);
-  dim3 g2(a_chain.nblk, chunks, 2), g1(a_chain.nblk, chunks, 1);
+static morx_status enqueue_iterations(const IterArgs& a, const std::vector<morx_factor>& G,
+                                      int prec, int iters, hipStream_t st, TraceState* t) {
+  const dim3 g1 = grid_of(a, 1), b = block_of(a);
   for (int it = 0; it < iters; ++it) {
     const int par = it & 1;
-    if (prec == MORX_F64) enqueue_chain<double>(a_chain, G, maxL, g2, st);
-    else if (prec == MORX_F32) enqueue_chain<float>(a_chain, G, maxL, g2, st);
-    else enqueue_chain<uint16_t>(a_chain, G, maxL, g2, st);
-    k_spmv_pair<<<g1, kBlock, 0, st>>>(a_spmv, par);
-    k_update<<<g1, kBlock, 0, st>>>(a_upd, par);
+    if (prec == MORX_F64) enqueue_chain<double>(a, G, st, t);
+    else if (prec == MORX_F32) enqueue_chain<float>(a, G, st, t);
+    else enqueue_chain<uint16_t>(a, G, st, t);
+    k_fin_rho<<<1, kFinThreads, 0, st>>>(a);
+    launch(t, TR_SPMV, k_spmv_pair, g1, b, st, a, par);
+    k_fin_delta<<<1, kFinThreads, 0, st>>>(a);
+    launch(t, TR_UPDATE, k_update, g1, b, st, a, par);
   }
   MORX_HIP(hipGetLastError());
   return MORX_OK;
@@ -671,11 +885,10 @@ static morx_status solve_batch(morx_system sys, std::vector<BatchCol>& cols,
   MORX_REQUIRE(maxL >= 1 && maxL <= (int)G.size(), MORX_E_INVALID, "bad chain length");
   MORX_TRY(workspace_reserve(sys, nc));
   Workspace* ws = sys->ws;
+  TraceState* t = trace_state_if_on(sys->ctx);
   const int maxit = o.maxit > 0 ? o.maxit : (int)std::min<int64_t>(sys->n, 20000);
   for (int c = 0; c < nc; ++c) {
-    ColInfo ci;
-    ColInfo zero_ci = {};
-    ci = zero_ci;
+    ColInfo ci = {};
     ci.sigma = cols[c].sigma;
     ci.tol = o.tol;
     ci.bsrc = cols[c].b;
@@ -695,14 +908,13 @@ static morx_status solve_batch(morx_system sys, std::vector<BatchCol>& cols,
     ws->hcols[c] = ci;
   }
   MORX_HIP(hipMemcpyAsync(ws->cols.p, ws->hcols, nc * sizeof(ColInfo), hipMemcpyHostToDevice, st));
-  IterArgs a0 = make_args(sys, ws, nc, 3);
-  const unsigned chunks = (unsigned)((nc + kNC - 1) / kNC);
-  k_init<<<dim3(a0.nblk, chunks, 1), kBlock, 0, st>>>(a0);
+  const IterArgs a = make_args(sys, ws, nc, prec, maxL);
+  k_init<<<grid_of(a, 1), block_of(a), 0, st>>>(a);
+  k_fin_init<<<1, kFinThreads, 0, st>>>(a);
   MORX_HIP(hipGetLastError());
 
   int seg = std::max(2, o.poll_iters > 0 ? o.poll_iters : 8);
   seg += seg & 1;  // even: the p buffers alternate by iteration parity
-  bool graph_ready = false;
   if (ws->exec) {
     hipGraphExecDestroy(ws->exec);
     ws->exec = nullptr;
@@ -711,50 +923,53 @@ static morx_status solve_batch(morx_system sys, std::vector<BatchCol>& cols,
     hipGraphDestroy(ws->graph);
     ws->graph = nullptr;
   }
-  if (o.use_graph) {
+  const bool use_graph = o.use_graph && !t;
+  if (use_graph) {
     MORX_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    morx_status s = enqueue_iterations(sys, ws, nc, G, maxL, prec, seg, st);
+    morx_status s = enqueue_iterations(a, G, prec, seg, st, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(st, &g);
     MORX_TRY(s);
     MORX_REQUIRE(e == hipSuccess, MORX_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
     ws->graph = g;
     MORX_HIP(hipGraphInstantiate(&ws->exec, g, nullptr, nullptr, 0));
-    graph_ready = true;
   }
-  const int64_t guard_max = (int64_t)(o.max_restarts + 1) * (maxit + seg) / seg + 4;
-  for (int64_t guard = 0; guard <= guard_max * 2; ++guard) {
+  const int64_t guard_max = 2 * ((int64_t)(o.max_restarts + 1) * (maxit + seg) / seg + 4);
+  for (int64_t guard = 0; guard <= guard_max; ++guard) {
     MORX_HIP(hipMemcpyAsync(ws->hcols, ws->cols.p, nc * sizeof(ColInfo), hipMemcpyDeviceToHost, st));
     MORX_HIP(hipStreamSynchronize(st));
-    int active = 0, stopped = 0;
+    if (t) trace_collect(t);
+    int active = 0, stop = 0;
     for (int c = 0; c < nc; ++c) {
       const int s = ws->hcols[c].state;
       if (s == COL_ACTIVE) ++active;
-      else if (s == COL_CONVERGED || s == COL_BREAKDOWN || s == COL_MAXIT) ++stopped;
+      else if (s == COL_CONVERGED || s == COL_BREAKDOWN || s == COL_MAXIT) ++stop;
     }
-    if (active == 0 && stopped == 0) break;
+    if (active == 0 && stop == 0) break;
     if (active == 0) {
-      k_true_residual<<<dim3(a0.nblk, chunks, 1), kBlock, 0, st>>>(a0);
+      k_true_residual<<<grid_of(a, 1), block_of(a), 0, st>>>(a);
+      k_fin_true<<<1, kFinThreads, 0, st>>>(a);
       MORX_HIP(hipGetLastError());
       continue;
     }
-    if (graph_ready) {
+    if (use_graph) {
       MORX_HIP(hipGraphLaunch(ws->exec, st));
     } else {
-      MORX_TRY(enqueue_iterations(sys, ws, nc, G, maxL, prec, seg, st));
+      MORX_TRY(enqueue_iterations(a, G, prec, seg, st, t));
     }
   }
-  // outputs
-  k_copy_out<<<dim3((unsigned)std::min<int64_t>((sys->n + kBlock - 1) / kBlock, 1024), nc, 1),
-               kBlock, 0, st>>>(a0, 0, 0);
+  k_copy_out<<<dim3((unsigned)std::min<int64_t>((sys->n + 255) / 256, 1024), nc, 1), 256, 0,
+               st>>>(a);
   MORX_HIP(hipGetLastError());
   MORX_HIP(hipMemcpyAsync(ws->hcols, ws->cols.p, nc * sizeof(ColInfo), hipMemcpyDeviceToHost, st));
   MORX_HIP(hipStreamSynchronize(st));
+  if (t) trace_collect(t);
   for (int c = 0; c < nc; ++c) {
     const ColInfo& ci = ws->hcols[c];
     morx_col_stats* out = cols[c].stats;
     if (!out) continue;
-    out->status = ci.state == COL_DONE ? MORX_OK : (ci.state == COL_FAILED ? ci.status : MORX_E_NOT_CONVERGED);
+    out->status = ci.state == COL_DONE ? MORX_OK
+                                       : (ci.state == COL_FAILED ? ci.status : MORX_E_NOT_CONVERGED);
     out->iters = ci.iters;
     out->restarts = ci.restarts;
     out->relres_primal = cols[c].out_x == 2 ? ci.reld : (cols[c].out_x == 1 ? ci.relp : 0.0);
@@ -767,7 +982,6 @@ static morx_status solve_batch(morx_system sys, std::vector<BatchCol>& cols,
 // morx_solve_shifts: Algorithm 4's factor schedule around the batched solver
 
 static int worse(int a, int b) {
-  // the more severe of two statuses (0 is best)
   auto rank = [](int s) {
     switch (s) {
       case MORX_OK: return 0;
@@ -779,27 +993,42 @@ static int worse(int a, int b) {
   return rank(b) > rank(a) ? b : a;
 }
 
+static morx_status rhs_norms(morx_system sys, const double* X, int64_t ld, int m, double* out_host,
+                             hipStream_t st) {
+  DevBuf part, res;
+  MORX_TRY(dev_alloc(part, (size_t)m * kNormSlabs * sizeof(double)));
+  morx_status s = dev_alloc(res, (size_t)m * sizeof(double));
+  if (s == MORX_OK) {
+    k_colnorm_part<<<dim3(kNormSlabs, m), 256, 0, st>>>(X, ld, sys->n, (double*)part.p);
+    k_colnorm_fin<<<1, kFinThreads, 0, st>>>((double*)part.p, m, (double*)res.p);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(out_host, res.p, m * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      morx_set_error("norms: %s", hipGetErrorString(e));
+      s = MORX_E_HIP;
+    }
+  }
+  dev_free(part);
+  dev_free(res);
+  return s;
+}
+
 static morx_status solve_shifts_impl(morx_system sys, int32_t nshift, const double* sigmas,
                                      int32_t m, const double* B, int64_t ldb, const double* C,
                                      int64_t ldc, double* X, int64_t ldx, double* Y, int64_t ldy,
                                      const morx_opts& o, morx_col_stats* stats, hipStream_t st,
-                                     std::vector<morx_factor>& horizontal) {
+                                     std::vector<morx_factor>& horizontal,
+                                     std::vector<morx_factor>& fresh) {
   const bool want_dual = o.want_dual != 0;
   const int prec = o.precond_prec;
   MORX_REQUIRE(sys->ls_supported, MORX_E_UNSUPPORTED,
                "factor pattern exceeds the local least-squares limits");
   // right-hand-side norms decide how each column pair runs
-  DevBuf nb;
-  MORX_TRY(dev_alloc(nb, (size_t)2 * m * sizeof(double)));
-  k_colnorm<<<m, kBlock, 0, st>>>(B, ldb, sys->n, (double*)nb.p);
-  if (want_dual) k_colnorm<<<m, kBlock, 0, st>>>(C, ldc, sys->n, (double*)nb.p + m);
   std::vector<double> norms(2 * m, 0.0);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(norms.data(), nb.p, 2 * m * sizeof(double), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  dev_free(nb);
-  MORX_REQUIRE(e == hipSuccess, MORX_E_HIP, "norms: %s", hipGetErrorString(e));
+  MORX_TRY(rhs_norms(sys, B, ldb, m, norms.data(), st));
+  if (want_dual) MORX_TRY(rhs_norms(sys, C, ldc, m, norms.data() + m, st));
   for (int j = 0; j < 2 * m; ++j)
     MORX_REQUIRE(std::isfinite(norms[j]), MORX_E_NONFINITE, "B or C holds NaN or Inf");
 
@@ -813,7 +1042,6 @@ static morx_status solve_shifts_impl(morx_system sys, int32_t nshift, const doub
     sys->vertical.clear();
   }
   std::vector<FactorJob> jobs;
-  std::vector<morx_factor> fresh;
   for (int i = 0; i < nshift; ++i) {
     morx_factor f = nullptr;
     MORX_TRY(factor_alloc(sys, prec, &f));
@@ -834,20 +1062,16 @@ static morx_status solve_shifts_impl(morx_system sys, int32_t nshift, const doub
     f->sigma_new = jb.sigma_new;
     jobs.push_back(jb);
   }
-  auto zero_cols = [&](int i, int j) {
+  auto trivial_col = [&](int j) { return norms[j] == 0.0 && (!want_dual || norms[m + j] == 0.0); };
+  auto make_col = [&](int i, int j, int L) -> BatchCol {
     BatchCol bc{};
     bc.sigma = sigmas[i];
     bc.xout = X + (int64_t)(i * m + j) * ldx;
     bc.yout = want_dual ? Y + (int64_t)(i * m + j) * ldy : nullptr;
-    return bc;
-  };
-  auto make_col = [&](int i, int j, int L) -> BatchCol {
-    BatchCol bc = zero_cols(i, j);
     bc.L = L;
     bc.stats = stats ? &stats[i * m + j] : nullptr;
-    const bool bz = norms[j] == 0.0;
     const bool cz = !want_dual || norms[m + j] == 0.0;
-    if (!bz) {
+    if (norms[j] != 0.0) {
       bc.b = B + (int64_t)j * ldb;
       bc.c = cz ? bc.b : C + (int64_t)j * ldc;  // shadow right-hand side b when c is absent
       bc.check_p = 1;
@@ -865,50 +1089,41 @@ static morx_status solve_shifts_impl(morx_system sys, int32_t nshift, const doub
     }
     return bc;
   };
-  morx_status worst = MORX_OK;
-  std::vector<BatchCol> trivial;
-  for (int i = 0; i < nshift; ++i)
-    for (int j = 0; j < m; ++j)
-      if (norms[j] == 0.0 && (!want_dual || norms[m + j] == 0.0)) {
-        BatchCol bc = zero_cols(i, j);
-        bc.stats = stats ? &stats[i * m + j] : nullptr;
-        trivial.push_back(bc);
-      }
-
-  auto finish_status = [&](int i0, int i1) {
-    if (!stats) return;
-    for (int i = i0; i < i1; ++i)
-      for (int j = 0; j < m; ++j) worst = (morx_status)worse(worst, stats[i * m + j].status);
-  };
 
   if (o.batched) {
     MORX_TRY(factor_build_many(sys, prec, jobs.data(), nshift, st));
     sys->vertical.push_back(fresh[0]);
     for (int i = 1; i < nshift; ++i) horizontal.push_back(fresh[i]);
+    fresh.clear();
     std::vector<morx_factor> G = sys->vertical;
     const int Lv = (int)sys->vertical.size();
-    for (int i = 1; i < nshift; ++i) G.push_back(fresh[i]);
+    for (int i = 1; i < nshift; ++i) G.push_back(horizontal[i - 1]);
     std::vector<BatchCol> cols;
     for (int i = 0; i < nshift; ++i)
       for (int j = 0; j < m; ++j)
-        if (!(norms[j] == 0.0 && (!want_dual || norms[m + j] == 0.0)))
-          cols.push_back(make_col(i, j, Lv + i));
+        if (!trivial_col(j)) cols.push_back(make_col(i, j, Lv + i));
     MORX_TRY(solve_batch(sys, cols, G, prec, o, st));
   } else {
     // one shift at a time, one column at a time (factor i built just before
     // the solves that first need it, as in Algorithm 4)
     std::vector<morx_factor> G;
+    std::vector<morx_factor> mine = fresh;
+    fresh.clear();
     for (int i = 0; i < nshift; ++i) {
-      MORX_TRY(factor_build_many(sys, prec, &jobs[i], 1, st));
+      morx_status s = factor_build_many(sys, prec, &jobs[i], 1, st);
+      if (s != MORX_OK) {
+        for (int k = i; k < nshift; ++k) fresh.push_back(mine[k]);
+        return s;
+      }
       if (i == 0) {
-        sys->vertical.push_back(fresh[0]);
+        sys->vertical.push_back(mine[0]);
         G = sys->vertical;
       } else {
-        horizontal.push_back(fresh[i]);
-        G.push_back(fresh[i]);
+        horizontal.push_back(mine[i]);
+        G.push_back(mine[i]);
       }
       for (int j = 0; j < m; ++j) {
-        if (norms[j] == 0.0 && (!want_dual || norms[m + j] == 0.0)) continue;
+        if (trivial_col(j)) continue;
         std::vector<BatchCol> one{make_col(i, j, (int)G.size())};
         MORX_TRY(solve_batch(sys, one, G, prec, o, st));
       }
@@ -916,19 +1131,23 @@ static morx_status solve_shifts_impl(morx_system sys, int32_t nshift, const doub
   }
   sys->vertical_prec = prec;
   sys->last_first_shift = sigmas[0];
-  finish_status(0, nshift);
-  // trivial columns: zero solutions
-  for (auto& bc : trivial) {
-    MORX_HIP(hipMemsetAsync(bc.xout, 0, sys->n * sizeof(double), st));
-    if (bc.yout) MORX_HIP(hipMemsetAsync(bc.yout, 0, sys->n * sizeof(double), st));
-    if (bc.stats) {
-      bc.stats->status = MORX_OK;
-      bc.stats->iters = 0;
-      bc.stats->restarts = 0;
-      bc.stats->relres_primal = 0.0;
-      bc.stats->relres_dual = 0.0;
+  morx_status worst = MORX_OK;
+  for (int i = 0; i < nshift; ++i)
+    for (int j = 0; j < m; ++j) {
+      if (trivial_col(j)) {
+        MORX_HIP(hipMemsetAsync(X + (int64_t)(i * m + j) * ldx, 0, sys->n * sizeof(double), st));
+        if (want_dual)
+          MORX_HIP(hipMemsetAsync(Y + (int64_t)(i * m + j) * ldy, 0, sys->n * sizeof(double), st));
+        if (stats) {
+          stats[i * m + j].status = MORX_OK;
+          stats[i * m + j].iters = 0;
+          stats[i * m + j].restarts = 0;
+          stats[i * m + j].relres_primal = 0.0;
+          stats[i * m + j].relres_dual = 0.0;
+        }
+      }
+      if (stats) worst = (morx_status)worse(worst, stats[i * m + j].status);
     }
-  }
   MORX_HIP(hipStreamSynchronize(st));
   return worst;
 }
@@ -954,18 +1173,20 @@ extern "C" morx_status morx_solve_shifts(morx_system sys, int32_t nshift, const 
   MORX_REQUIRE(o.tol >= 0.0 && o.max_restarts >= 0, MORX_E_INVALID,
                "morx_solve_shifts: bad tolerance or restart limit");
   for (int i = 0; i < nshift; ++i)
-    MORX_REQUIRE(std::isfinite(sigmas[i]), MORX_E_NONFINITE, "morx_solve_shifts: shift %d not finite", i);
+    MORX_REQUIRE(std::isfinite(sigmas[i]), MORX_E_NONFINITE,
+                 "morx_solve_shifts: shift %d not finite", i);
   morx_ctx ctx = sys->ctx;
   std::lock_guard<std::mutex> lk(ctx->mu);
   MORX_HIP(hipSetDevice(ctx->device));
   hipStream_t caller = (hipStream_t)stream;
   MORX_TRY(stream_enter(ctx, caller));
-  std::vector<morx_factor> horizontal;
+  std::vector<morx_factor> horizontal, fresh;
   morx_status s = solve_shifts_impl(sys, nshift, sigmas, m, B, ldb, want_dual ? C : nullptr, ldc,
                                     X, ldx, want_dual ? Y : nullptr, ldy, o, stats, ctx->stream,
-                                    horizontal);
+                                    horizontal, fresh);
   hipStreamSynchronize(ctx->stream);
   for (morx_factor f : horizontal) factor_release(f);
+  for (morx_factor f : fresh) factor_release(f);
   morx_status s2 = stream_leave(ctx, caller);
   return s != MORX_OK ? s : s2;
 }

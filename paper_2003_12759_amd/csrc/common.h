@@ -158,6 +158,8 @@ morx_status launch_factor_apply(morx_system sys, morx_factor f, bool trans, int 
 
 // bicg.hip
 void workspace_free(Workspace* ws);
+void trace_factor_begin(morx_ctx ctx, hipStream_t st, void** token);
+void trace_factor_end(morx_ctx ctx, hipStream_t st, void* token);
 
 // streams: make `inner` wait for `outer` and back
 morx_status stream_enter(morx_ctx ctx, hipStream_t outer);

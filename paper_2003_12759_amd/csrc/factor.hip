@@ -391,6 +391,8 @@ morx_status factor_build_many(morx_system sys, int32_t prec, const FactorJob* jo
   MORX_HIP(hipMemcpyAsync(jb.p, jobs, njobs * sizeof(FactorJob), hipMemcpyHostToDevice, st));
   MORX_HIP(hipMemsetAsync(sb.p, 0, sizeof(int), st));
   const int grid = ls_grid(sys);
+  void* token = nullptr;
+  trace_factor_begin(sys->ctx, st, &token);
   switch (prec) {
     case MORX_F64:
       k_factor_ls<double><<<grid, 64, L.bytes, st>>>(sys->trowptr, sys->tcol, sys->tval, sys->e,
@@ -407,6 +409,7 @@ morx_status factor_build_many(morx_system sys, int32_t prec, const FactorJob* jo
                                                        sys->e, sys->tp2s, sys->sellT.off, sys->n,
                                                        (FactorJob*)jb.p, njobs, L, (int*)sb.p);
   }
+  trace_factor_end(sys->ctx, st, token);
   MORX_HIP(hipGetLastError());
   int singular = 0;
   MORX_HIP(hipMemcpyAsync(&singular, sb.p, sizeof(int), hipMemcpyDeviceToHost, st));

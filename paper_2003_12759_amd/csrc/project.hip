@@ -56,13 +56,17 @@ __global__ __launch_bounds__(1024) void k_gram_mfma(const double* __restrict__ U
   }
 }
 
-__global__ void k_sum_partials(const double* __restrict__ partial, int nb, int cnt,
-                               double* __restrict__ out, double scale) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+// out[k] = scale * sum_b partial[b][k]: one wave per output entry, fixed order
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int nb,
+                                                      int cnt, double* __restrict__ out,
+                                                      double scale) {
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (k >= cnt) return;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * cnt + k];
-  out[k] = scale * s;
+  for (int b = lane; b < nb; b += 64) s += partial[(int64_t)b * cnt + k];
+  s = wave_sum(s);
+  if (lane == 0) out[k] = scale * s;
 }
 
 // upper Cholesky G + shift*I = R^T R of an r x r Gram matrix (one workgroup);
@@ -156,7 +160,7 @@ morx_status gram(Gram& g, const double* U, int64_t ldu, int r1, const double* V,
   k_gram_mfma<<<g.nb, 64 * waves, 0, st>>>(U, ldu, r1, V, ldv, r2, w, n, g.rows_per_block,
                                           (double*)g.partial.p);
   const int cnt = r1 * r2;
-  k_sum_partials<<<(cnt + 255) / 256, 256, 0, st>>>((double*)g.partial.p, g.nb, cnt, out_dev, scale);
+  k_sum_partials<<<(cnt + 3) / 4, 256, 0, st>>>((double*)g.partial.p, g.nb, cnt, out_dev, scale);
   MORX_HIP(hipGetLastError());
   return MORX_OK;
 }

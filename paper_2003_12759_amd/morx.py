@@ -51,6 +51,11 @@ class morx_col_stats(ctypes.Structure):
                 ("relres_primal", ctypes.c_double), ("relres_dual", ctypes.c_double)]
 
 
+class morx_trace_entry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double)]
+
+
 class MorxError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -82,6 +87,8 @@ _SIG = {
     "morx_project": (_i32, [_p, _i32, _p, _i64, _p, _i64, _i32, _p, _i64, _i32, _p, _i64,
                             ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
                             ctypes.POINTER(_d), _i32, _p]),
+    "morx_trace_enable": (_i32, [_p, _i32]),
+    "morx_trace_read": (_i32, [_p, ctypes.POINTER(morx_trace_entry), _i32, ctypes.POINTER(_i32)]),
 }
 for _name, (_res, _args) in _SIG.items():
     _f = getattr(_lib, _name)
@@ -279,3 +286,16 @@ def morx_project(sys: int, V: torch.Tensor, W: torch.Tensor, B: Optional[torch.T
         return np.frombuffer(buf, dtype=np.float64, count=rows * cols).reshape(cols, rows).T.copy()
 
     return mat(Ar, r, r), mat(Er, r, r), mat(Br, r, m), mat(Cr, r, q)
+
+
+def morx_trace_enable(ctx: int, enable: bool) -> None:
+    _check(_lib.morx_trace_enable(ctx, int(bool(enable))), "morx_trace_enable")
+
+
+def morx_trace_read(ctx: int):
+    """{class name: (launches, total_ms, alg_bytes)}."""
+    buf = (morx_trace_entry * 16)()
+    cnt = _i32()
+    _check(_lib.morx_trace_read(ctx, buf, 16, ctypes.byref(cnt)), "morx_trace_read")
+    return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms, buf[i].alg_bytes)
+            for i in range(min(cnt.value, 16))}
