@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the path is one system per GPU); --gpus {args.gpus} "
@@ -153,6 +155,15 @@ def main():
                     "traffic": traffic, "kernel": "k_chain_step<float,16>",
                     "avg_launch_us": round(1e3 * ms / launches, 2),
                     "alg_bytes_per_launch": byts / launches}
+
+    if args.calibrate_copy:
+        # a plain copy of known size: 1 GiB read + 1 GiB written per launch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
 

@@ -67,19 +67,22 @@ struct Workspace {
 
 namespace {
 
-constexpr int kMaxW = 16;          // columns (waves) per block row group
-constexpr int kMaxBlocks = 1024;   // row slabs per launch (partials per column)
+constexpr int kMaxNC = 8;          // columns per wave
+constexpr int kMaxBlocks = 1024;   // row blocks per launch (partials per column)
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = 64 * kWavesPerBlock;
 constexpr int kFinThreads = 1024;  // finalize kernels: one wave per column
 constexpr double kBreakdown = 1e-14;
 
-// Launch geometry shared by every iteration kernel: block = R row groups x W
-// waves; wave (r, w) handles column blockIdx.y * W + w on the 64-row slices
-// r, r + R, ... of its slab.  Slab index is remapped so that consecutive slabs
-// run on one XCD (workgroups are dealt to the 8 XCDs round robin), keeping
-// the stencil neighbours of a slab in that XCD's L2.
+// Launch geometry shared by every iteration kernel.  A block has four waves;
+// each wave owns spw consecutive 64-row slices and handles the NC columns
+// blockIdx.y * NC ... of the batch on them, so index and value loads of the
+// matrix or factor are shared by all NC columns.  Block indices are remapped
+// so that consecutive row ranges run on one XCD (workgroups are dealt to the
+// 8 XCDs round robin), keeping a range's stencil neighbours in that XCD's L2.
 struct IterArgs {
   int64_t n, ld, nnzS, nslices;
-  int cap, nc, nblk, spb, W, R, vbytes, maxL;
+  int cap, nc, nblk, spw, vbytes, maxL;
   const int32_t *off, *col, *offT, *colT;
   const double *valA, *valAT, *e;
   double* vec;
@@ -95,51 +98,44 @@ __device__ __forceinline__ double* vptr(const IterArgs& a, int slot, int c) {
 }
 
 struct WaveCtx {
-  int lane, w, r, c, slab;
+  int lane, wave, blk;
   int64_t s_begin, s_end;
 };
 
 __device__ __forceinline__ WaveCtx wave_ctx(const IterArgs& a) {
   WaveCtx t;
-  const int wave = threadIdx.x >> 6;
+  t.wave = threadIdx.x >> 6;
   t.lane = threadIdx.x & 63;
-  t.w = wave % a.W;
-  t.r = wave / a.W;
-  t.c = blockIdx.y * a.W + t.w;
   const int per_xcd = a.nblk >> 3;  // nblk is a multiple of 8
-  t.slab = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  t.s_begin = (int64_t)t.slab * a.spb;
-  t.s_end = min(a.nslices, t.s_begin + a.spb);
+  t.blk = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  t.s_begin = ((int64_t)t.blk * kWavesPerBlock + t.wave) * a.spw;
+  t.s_end = min(a.nslices, t.s_begin + a.spw);
   return t;
 }
 
 // ---- reductions --------------------------------------------------------------
 
-// Sum NQ per-wave values over the R row groups of a block and store one
-// partial per (quantity, column, slab).  Every wave of the block calls it.
-template <int NQ>
-__device__ void wave_partials(const IterArgs& a, const WaveCtx& t, bool valid, double (&v)[NQ],
-                              double* part) {
-  __shared__ double sh[4][kMaxW][NQ];
-  double s[NQ];
+// Sum NQ per-lane values of each of the NC columns over the block and store
+// one partial per (quantity, column, block).  Every thread calls it.
+template <int NC, int NQ>
+__device__ void block_partials(const IterArgs& a, const WaveCtx& t, int c0, unsigned valid,
+                               double (&v)[NC][NQ], double* part) {
+  __shared__ double sh[kWavesPerBlock][NC][NQ];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) s[q] = wave_sum(v[q]);
-  if (a.R == 1) {
-    if (valid && t.lane == 0)
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) part[((int64_t)q * a.cap + t.c) * a.nblk + t.slab] = s[q];
-    return;
-  }
-  if (t.lane == 0)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) sh[t.r][t.w][q] = s[q];
-  __syncthreads();
-  if (t.r == 0 && valid && t.lane == 0) {
+  for (int j = 0; j < NC; ++j)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
+      const double s = wave_sum(v[j][q]);
+      if (t.lane == 0) sh[t.wave][j][q] = s;
+    }
+  __syncthreads();
+  if (threadIdx.x < NC * NQ) {
+    const int j = threadIdx.x / NQ, q = threadIdx.x % NQ;
+    if (valid & (1u << j)) {
       double tot = 0.0;
-      for (int rr = 0; rr < a.R; ++rr) tot += sh[rr][t.w][q];
-      part[((int64_t)q * a.cap + t.c) * a.nblk + t.slab] = tot;
+#pragma unroll
+      for (int w = 0; w < kWavesPerBlock; ++w) tot += sh[w][j][q];
+      part[((int64_t)q * a.cap + c0 + j) * a.nblk + t.blk] = tot;
     }
   }
 }
@@ -178,104 +174,89 @@ __device__ __forceinline__ bool stopped(int st) {
   return st == COL_CONVERGED || st == COL_BREAKDOWN || st == COL_MAXIT;
 }
 
-// Slots of a slice are processed kUnroll at a time: all index and value loads
-// of a chunk are issued before its gathers, so a wave keeps kUnroll gathers in
-// flight instead of one (the loop is latency-bound otherwise).
+// Slots of a slice are processed kUnroll at a time: the index and value loads
+// of a chunk are issued together, then every column's gathers for the chunk.
 constexpr int kUnroll = 8;
 
-// one row of the slice-ELL product: sum_m val[m] * x[col[m]]
+struct SliceChunk {
+  int32_t c[kUnroll];
+  int32_t w;  // slots of the slice
+};
+
 template <typename VT>
-__device__ __forceinline__ double sell_dot(const int32_t* __restrict__ off,
-                                           const int32_t* __restrict__ col,
-                                           const VT* __restrict__ val, int64_t sl, int lane,
-                                           const double* __restrict__ x) {
-  const int32_t base = off[sl];
-  const int32_t w = (off[sl + 1] - base) >> 6;
-  const int32_t p0 = base + lane;
-  double acc = 0.0;
-  for (int32_t m0 = 0; m0 < w; m0 += kUnroll) {
-    int32_t c[kUnroll];
-    double v[kUnroll];
+__device__ __forceinline__ void load_chunk(const int32_t* __restrict__ col,
+                                           const VT* __restrict__ val, int32_t p0, int32_t w,
+                                           int32_t m0, SliceChunk& ch, double (&v)[kUnroll]) {
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const bool ok = m0 + u < w;
-      const int32_t p = p0 + (ok ? (m0 + u) * kSlice : 0);
-      c[u] = col[p];
-      v[u] = load_val<VT>(val + p);
-    }
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const double xv = x[c[u]];
-      acc = (m0 + u < w) ? fma(v[u], xv, acc) : acc;
-    }
+  for (int u = 0; u < kUnroll; ++u) {
+    const bool ok = m0 + u < w;
+    const int32_t p = p0 + (ok ? (m0 + u) * kSlice : 0);
+    ch.c[u] = col[p];
+    v[u] = ok ? load_val<VT>(val + p) : 0.0;
   }
+}
+
+__device__ __forceinline__ double chunk_dot(const SliceChunk& ch, const double (&v)[kUnroll],
+                                            int32_t m0, int32_t w, const double* __restrict__ x,
+                                            double acc) {
+  double g[kUnroll];
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) g[u] = x[ch.c[u]];
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) acc = (m0 + u < w) ? fma(v[u], g[u], acc) : acc;
   return acc;
 }
 
-// the same row product with p = z + beta * p_old formed at every gathered index
-__device__ __forceinline__ double sell_dot_p(const int32_t* __restrict__ off,
-                                             const int32_t* __restrict__ col,
-                                             const double* __restrict__ val, int64_t sl, int lane,
-                                             const double* __restrict__ z,
-                                             const double* __restrict__ po, double beta,
-                                             bool first) {
-  const int32_t base = off[sl];
-  const int32_t w = (off[sl + 1] - base) >> 6;
-  const int32_t p0 = base + lane;
-  double acc = 0.0;
-  for (int32_t m0 = 0; m0 < w; m0 += kUnroll) {
-    int32_t c[kUnroll];
-    double v[kUnroll];
+// the same with p = z + beta * p_old formed at every gathered index
+__device__ __forceinline__ double chunk_dot_p(const SliceChunk& ch, const double (&v)[kUnroll],
+                                              int32_t m0, int32_t w, const double* __restrict__ z,
+                                              const double* __restrict__ po, double beta,
+                                              bool first, double acc) {
+  double g[kUnroll];
+  if (first) {
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const bool ok = m0 + u < w;
-      const int32_t p = p0 + (ok ? (m0 + u) * kSlice : 0);
-      c[u] = col[p];
-      v[u] = val[p];
-    }
-    if (first) {
+    for (int u = 0; u < kUnroll; ++u) g[u] = z[ch.c[u]];
+  } else {
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const double zv = z[c[u]];
-        acc = (m0 + u < w) ? fma(v[u], zv, acc) : acc;
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const double pk = fma(beta, po[c[u]], z[c[u]]);
-        acc = (m0 + u < w) ? fma(v[u], pk, acc) : acc;
-      }
-    }
+    for (int u = 0; u < kUnroll; ++u) g[u] = fma(beta, po[ch.c[u]], z[ch.c[u]]);
   }
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) acc = (m0 + u < w) ? fma(v[u], g[u], acc) : acc;
   return acc;
 }
 
 // ---- kernels -------------------------------------------------------------------
 
 // x = x~ = 0, r = b, r~ = c; partial norms of b and c
-__global__ __launch_bounds__(1024) void k_init(IterArgs a) {
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_init(IterArgs a) {
   const WaveCtx t = wave_ctx(a);
-  const bool valid = t.c < a.nc && a.cols[t.c].state == COL_ACTIVE;
-  double v[2] = {0.0, 0.0};
-  if (valid) {
-    const ColInfo& ci = a.cols[t.c];
-    double* x = vptr(a, V_X, t.c);
-    double* xt = vptr(a, V_XT, t.c);
-    double* r = vptr(a, V_R, t.c);
-    double* rt = vptr(a, V_RT, t.c);
-    for (int64_t sl = t.s_begin + t.r; sl < t.s_end; sl += a.R) {
-      const int64_t i = sl * kSlice + t.lane;
-      if (i >= a.n) continue;
+  const int c0 = blockIdx.y * NC;
+  unsigned valid = 0;
+#pragma unroll
+  for (int j = 0; j < NC; ++j)
+    if (c0 + j < a.nc && a.cols[c0 + j].state == COL_ACTIVE) valid |= 1u << j;
+  double v[NC][2];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) v[j][0] = v[j][1] = 0.0;
+  for (int64_t sl = t.s_begin; sl < t.s_end; ++sl) {
+    const int64_t i = sl * kSlice + t.lane;
+    if (i >= a.n) continue;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      if (!(valid & (1u << j))) continue;
+      const int c = c0 + j;
+      const ColInfo& ci = a.cols[c];
       const double bi = ci.bsrc[i], cv = ci.csrc[i];
-      x[i] = 0.0;
-      xt[i] = 0.0;
-      r[i] = bi;
-      rt[i] = cv;
-      v[0] = fma(bi, bi, v[0]);
-      v[1] = fma(cv, cv, v[1]);
+      vptr(a, V_X, c)[i] = 0.0;
+      vptr(a, V_XT, c)[i] = 0.0;
+      vptr(a, V_R, c)[i] = bi;
+      vptr(a, V_RT, c)[i] = cv;
+      v[j][0] = fma(bi, bi, v[j][0]);
+      v[j][1] = fma(cv, cv, v[j][1]);
     }
   }
-  wave_partials<2>(a, t, valid, v, a.part_norm);
+  block_partials<NC, 2>(a, t, c0, valid, v, a.part_norm);
 }
 
 __global__ __launch_bounds__(kFinThreads) void k_fin_init(IterArgs a) {
@@ -296,51 +277,72 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_init(IterArgs a) {
 // one chain step: the forward half (blockIdx.z == 0) applies G[s] on the rows
 // of S, the transposed half applies G[maxL-1-s]^T on the rows of S^T; the
 // last step also forms the partial sums of rho = z~^T r, ||z~||^2, ||r||^2
-template <typename VT>
-__global__ __launch_bounds__(1024) void k_chain_step(IterArgs a, const VT* __restrict__ fval,
-                                                     const VT* __restrict__ bval, int s,
-                                                     int do_rho) {
+template <typename VT, int NC>
+__global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, const VT* __restrict__ fval,
+                                                       const VT* __restrict__ bval, int s,
+                                                       int do_rho) {
   const WaveCtx t = wave_ctx(a);
+  const int c0 = blockIdx.y * NC;
   const bool bwd = blockIdx.z == 1;
   const int jf = bwd ? a.maxL - 1 - s : s;  // factor index applied by this half
   const bool rho_half = bwd && do_rho;
-  bool valid = false;
-  const double* src = nullptr;
-  double* dst = nullptr;
-  if (t.c < a.nc) {
-    const ColInfo& ci = a.cols[t.c];
+  unsigned valid = 0;
+  const double* src[NC];
+  double* dst[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const int c = min(c0 + j, a.nc - 1);
+    const ColInfo& ci = a.cols[c];
     const int L = ci.L;
-    valid = ci.state == COL_ACTIVE && L > jf;
+    if (c0 + j < a.nc && ci.state == COL_ACTIVE && L > jf) valid |= 1u << j;
     if (!bwd) {
-      src = (jf == 0) ? vptr(a, V_R, t.c) : vptr(a, V_T0 + ((jf - 1) & 1), t.c);
-      dst = (jf == L - 1) ? vptr(a, V_Z, t.c) : vptr(a, V_T0 + (jf & 1), t.c);
+      src[j] = (jf == 0) ? vptr(a, V_R, c) : vptr(a, V_T0 + ((jf - 1) & 1), c);
+      dst[j] = (jf == L - 1) ? vptr(a, V_Z, c) : vptr(a, V_T0 + (jf & 1), c);
     } else {
       const int k = max(L - 1 - jf, 0);  // transposed factors this column applied before
-      src = (k == 0) ? vptr(a, V_RT, t.c) : vptr(a, V_TT0 + ((k - 1) & 1), t.c);
-      dst = (jf == 0) ? vptr(a, V_ZT, t.c) : vptr(a, V_TT0 + (k & 1), t.c);
+      src[j] = (k == 0) ? vptr(a, V_RT, c) : vptr(a, V_TT0 + ((k - 1) & 1), c);
+      dst[j] = (jf == 0) ? vptr(a, V_ZT, c) : vptr(a, V_TT0 + (k & 1), c);
     }
   }
-  double v[3] = {0.0, 0.0, 0.0};
+  double v[NC][3];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
   if (valid) {
     const int32_t* off = bwd ? a.offT : a.off;
     const int32_t* col = bwd ? a.colT : a.col;
     const VT* val = bwd ? bval : fval;
-    const double* rv = vptr(a, V_R, t.c);
-    for (int64_t sl = t.s_begin + t.r; sl < t.s_end; sl += a.R) {
+    for (int64_t sl = t.s_begin; sl < t.s_end; ++sl) {
+      const int32_t base = off[sl];
+      const int32_t w = (off[sl + 1] - base) >> 6;
+      const int32_t p0 = base + t.lane;
       const int64_t i = sl * kSlice + t.lane;
-      const double acc = sell_dot<VT>(off, col, val, sl, t.lane, src);
+      double acc[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) acc[j] = 0.0;
+      for (int32_t m0 = 0; m0 < w; m0 += kUnroll) {
+        SliceChunk ch;
+        double vv[kUnroll];
+        load_chunk<VT>(col, val, p0, w, m0, ch, vv);
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+          if (valid & (1u << j)) acc[j] = chunk_dot(ch, vv, m0, w, src[j], acc[j]);
+      }
       if (i < a.n) {
-        dst[i] = acc;
-        if (rho_half) {
-          const double ri = rv[i];
-          v[0] = fma(acc, ri, v[0]);
-          v[1] = fma(acc, acc, v[1]);
-          v[2] = fma(ri, ri, v[2]);
-        }
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+          if (valid & (1u << j)) {
+            dst[j][i] = acc[j];
+            if (rho_half) {
+              const double ri = vptr(a, V_R, c0 + j)[i];
+              v[j][0] = fma(acc[j], ri, v[j][0]);
+              v[j][1] = fma(acc[j], acc[j], v[j][1]);
+              v[j][2] = fma(ri, ri, v[j][2]);
+            }
+          }
       }
     }
   }
-  if (rho_half) wave_partials<3>(a, t, valid, v, a.part_rho);
+  if (rho_half) block_partials<NC, 3>(a, t, c0, valid, v, a.part_rho);
 }
 
 // convergence test on the residuals of the previous update (or of the start
@@ -401,43 +403,83 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(IterArgs a) {
 // p = z + beta p, p~ = z~ + beta p~ (formed on the fly at every gathered
 // index), q = (sigma E - A) p, q~ = (sigma E - A)^T p~, partial sums of
 // delta = p~^T q, ||p~||^2, ||q||^2
-__global__ __launch_bounds__(1024) void k_spmv_pair(IterArgs a, int par) {
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
   const WaveCtx t = wave_ctx(a);
-  const bool valid = t.c < a.nc && a.cols[t.c].state == COL_ACTIVE;
-  double v[3] = {0.0, 0.0, 0.0};
+  const int c0 = blockIdx.y * NC;
+  unsigned valid = 0;
+  double beta[NC], sig[NC];
+  bool first[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const int c = min(c0 + j, a.nc - 1);
+    const ColInfo& ci = a.cols[c];
+    if (c0 + j < a.nc && ci.state == COL_ACTIVE) valid |= 1u << j;
+    beta[j] = ci.beta;
+    sig[j] = ci.sigma;
+    first[j] = ci.first != 0;
+  }
+  double v[NC][3];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
   if (valid) {
-    const ColInfo& ci = a.cols[t.c];
-    const double beta = ci.beta, sig = ci.sigma;
-    const bool first = ci.first != 0;
-    const double* z = vptr(a, V_Z, t.c);
-    const double* zt = vptr(a, V_ZT, t.c);
-    const double* po = vptr(a, V_P0 + (par ^ 1), t.c);
-    const double* pto = vptr(a, V_PT0 + (par ^ 1), t.c);
-    double* pn = vptr(a, V_P0 + par, t.c);
-    double* ptn = vptr(a, V_PT0 + par, t.c);
-    double* q = vptr(a, V_Q, t.c);
-    double* qt = vptr(a, V_QT, t.c);
-    for (int64_t sl = t.s_begin + t.r; sl < t.s_end; sl += a.R) {
+    for (int64_t sl = t.s_begin; sl < t.s_end; ++sl) {
       const int64_t i = sl * kSlice + t.lane;
-      const double acc = sell_dot_p(a.off, a.col, a.valA, sl, t.lane, z, po, beta, first);
-      const double acct = sell_dot_p(a.offT, a.colT, a.valAT, sl, t.lane, zt, pto, beta, first);
+      double acc[NC], acct[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) acc[j] = acct[j] = 0.0;
+      {
+        const int32_t base = a.off[sl];
+        const int32_t w = (a.off[sl + 1] - base) >> 6;
+        for (int32_t m0 = 0; m0 < w; m0 += kUnroll) {
+          SliceChunk ch;
+          double vv[kUnroll];
+          load_chunk<double>(a.col, a.valA, base + t.lane, w, m0, ch, vv);
+#pragma unroll
+          for (int j = 0; j < NC; ++j)
+            if (valid & (1u << j))
+              acc[j] = chunk_dot_p(ch, vv, m0, w, vptr(a, V_Z, c0 + j),
+                                   vptr(a, V_P0 + (par ^ 1), c0 + j), beta[j], first[j], acc[j]);
+        }
+      }
+      {
+        const int32_t base = a.offT[sl];
+        const int32_t w = (a.offT[sl + 1] - base) >> 6;
+        for (int32_t m0 = 0; m0 < w; m0 += kUnroll) {
+          SliceChunk ch;
+          double vv[kUnroll];
+          load_chunk<double>(a.colT, a.valAT, base + t.lane, w, m0, ch, vv);
+#pragma unroll
+          for (int j = 0; j < NC; ++j)
+            if (valid & (1u << j))
+              acct[j] = chunk_dot_p(ch, vv, m0, w, vptr(a, V_ZT, c0 + j),
+                                    vptr(a, V_PT0 + (par ^ 1), c0 + j), beta[j], first[j], acct[j]);
+        }
+      }
       if (i < a.n) {
-        const double se = sig * a.e[i];
-        const double pi = first ? z[i] : fma(beta, po[i], z[i]);
-        const double pti = first ? zt[i] : fma(beta, pto[i], zt[i]);
-        const double qi = fma(se, pi, -acc);
-        const double qti = fma(se, pti, -acct);
-        pn[i] = pi;
-        ptn[i] = pti;
-        q[i] = qi;
-        qt[i] = qti;
-        v[0] = fma(pti, qi, v[0]);
-        v[1] = fma(pti, pti, v[1]);
-        v[2] = fma(qi, qi, v[2]);
+        const double ei = a.e[i];
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+          if (valid & (1u << j)) {
+            const int c = c0 + j;
+            const double zi = vptr(a, V_Z, c)[i], zti = vptr(a, V_ZT, c)[i];
+            const double pi = first[j] ? zi : fma(beta[j], vptr(a, V_P0 + (par ^ 1), c)[i], zi);
+            const double pti = first[j] ? zti : fma(beta[j], vptr(a, V_PT0 + (par ^ 1), c)[i], zti);
+            const double se = sig[j] * ei;
+            const double qi = fma(se, pi, -acc[j]);
+            const double qti = fma(se, pti, -acct[j]);
+            vptr(a, V_P0 + par, c)[i] = pi;
+            vptr(a, V_PT0 + par, c)[i] = pti;
+            vptr(a, V_Q, c)[i] = qi;
+            vptr(a, V_QT, c)[i] = qti;
+            v[j][0] = fma(pti, qi, v[j][0]);
+            v[j][1] = fma(pti, pti, v[j][1]);
+            v[j][2] = fma(qi, qi, v[j][2]);
+          }
       }
     }
   }
-  wave_partials<3>(a, t, valid, v, a.part_delta);
+  block_partials<NC, 3>(a, t, c0, valid, v, a.part_delta);
 }
 
 __global__ __launch_bounds__(kFinThreads) void k_fin_delta(IterArgs a) {
@@ -471,64 +513,106 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_delta(IterArgs a) {
 }
 
 // x += alpha p, x~ += alpha p~, r -= alpha q, r~ -= alpha q~; partial norms
-__global__ __launch_bounds__(1024) void k_update(IterArgs a, int par) {
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_update(IterArgs a, int par) {
   const WaveCtx t = wave_ctx(a);
-  const bool valid = t.c < a.nc && a.cols[t.c].state == COL_ACTIVE;
-  double v[2] = {0.0, 0.0};
-  if (valid) {
-    const double al = a.cols[t.c].alpha;
-    double* x = vptr(a, V_X, t.c);
-    double* xt = vptr(a, V_XT, t.c);
-    double* r = vptr(a, V_R, t.c);
-    double* rt = vptr(a, V_RT, t.c);
-    const double* p = vptr(a, V_P0 + par, t.c);
-    const double* pt = vptr(a, V_PT0 + par, t.c);
-    const double* q = vptr(a, V_Q, t.c);
-    const double* qt = vptr(a, V_QT, t.c);
-    for (int64_t sl = t.s_begin + t.r; sl < t.s_end; sl += a.R) {
-      const int64_t i = sl * kSlice + t.lane;
-      if (i >= a.n) continue;
-      x[i] = fma(al, p[i], x[i]);
-      xt[i] = fma(al, pt[i], xt[i]);
-      const double ri = fma(-al, q[i], r[i]);
-      const double rti = fma(-al, qt[i], rt[i]);
+  const int c0 = blockIdx.y * NC;
+  unsigned valid = 0;
+  double al[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const int c = min(c0 + j, a.nc - 1);
+    if (c0 + j < a.nc && a.cols[c].state == COL_ACTIVE) valid |= 1u << j;
+    al[j] = a.cols[c].alpha;
+  }
+  double v[NC][2];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) v[j][0] = v[j][1] = 0.0;
+  for (int64_t sl = t.s_begin; sl < t.s_end; ++sl) {
+    const int64_t i = sl * kSlice + t.lane;
+    if (i >= a.n) continue;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      if (!(valid & (1u << j))) continue;
+      const int c = c0 + j;
+      double* x = vptr(a, V_X, c);
+      double* xt = vptr(a, V_XT, c);
+      double* r = vptr(a, V_R, c);
+      double* rt = vptr(a, V_RT, c);
+      x[i] = fma(al[j], vptr(a, V_P0 + par, c)[i], x[i]);
+      xt[i] = fma(al[j], vptr(a, V_PT0 + par, c)[i], xt[i]);
+      const double ri = fma(-al[j], vptr(a, V_Q, c)[i], r[i]);
+      const double rti = fma(-al[j], vptr(a, V_QT, c)[i], rt[i]);
       r[i] = ri;
       rt[i] = rti;
-      v[0] = fma(ri, ri, v[0]);
-      v[1] = fma(rti, rti, v[1]);
+      v[j][0] = fma(ri, ri, v[j][0]);
+      v[j][1] = fma(rti, rti, v[j][1]);
     }
   }
-  wave_partials<2>(a, t, valid, v, a.part_norm);
+  block_partials<NC, 2>(a, t, c0, valid, v, a.part_norm);
 }
 
 // true residuals r = b - A_s x, r~ = c - A_s^T x~ of the columns that stopped
-__global__ __launch_bounds__(1024) void k_true_residual(IterArgs a) {
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_true_residual(IterArgs a) {
   const WaveCtx t = wave_ctx(a);
-  const bool valid = t.c < a.nc && stopped(a.cols[t.c].state);
-  double v[2] = {0.0, 0.0};
+  const int c0 = blockIdx.y * NC;
+  unsigned valid = 0;
+#pragma unroll
+  for (int j = 0; j < NC; ++j)
+    if (c0 + j < a.nc && stopped(a.cols[c0 + j].state)) valid |= 1u << j;
+  double v[NC][2];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) v[j][0] = v[j][1] = 0.0;
   if (valid) {
-    const ColInfo& ci = a.cols[t.c];
-    const double sig = ci.sigma;
-    const double* x = vptr(a, V_X, t.c);
-    const double* xt = vptr(a, V_XT, t.c);
-    double* r = vptr(a, V_R, t.c);
-    double* rt = vptr(a, V_RT, t.c);
-    for (int64_t sl = t.s_begin + t.r; sl < t.s_end; sl += a.R) {
+    for (int64_t sl = t.s_begin; sl < t.s_end; ++sl) {
       const int64_t i = sl * kSlice + t.lane;
-      const double acc = sell_dot<double>(a.off, a.col, a.valA, sl, t.lane, x);
-      const double acct = sell_dot<double>(a.offT, a.colT, a.valAT, sl, t.lane, xt);
+      double acc[NC], acct[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) acc[j] = acct[j] = 0.0;
+      {
+        const int32_t base = a.off[sl];
+        const int32_t w = (a.off[sl + 1] - base) >> 6;
+        for (int32_t m0 = 0; m0 < w; m0 += kUnroll) {
+          SliceChunk ch;
+          double vv[kUnroll];
+          load_chunk<double>(a.col, a.valA, base + t.lane, w, m0, ch, vv);
+#pragma unroll
+          for (int j = 0; j < NC; ++j)
+            if (valid & (1u << j)) acc[j] = chunk_dot(ch, vv, m0, w, vptr(a, V_X, c0 + j), acc[j]);
+        }
+      }
+      {
+        const int32_t base = a.offT[sl];
+        const int32_t w = (a.offT[sl + 1] - base) >> 6;
+        for (int32_t m0 = 0; m0 < w; m0 += kUnroll) {
+          SliceChunk ch;
+          double vv[kUnroll];
+          load_chunk<double>(a.colT, a.valAT, base + t.lane, w, m0, ch, vv);
+#pragma unroll
+          for (int j = 0; j < NC; ++j)
+            if (valid & (1u << j)) acct[j] = chunk_dot(ch, vv, m0, w, vptr(a, V_XT, c0 + j), acct[j]);
+        }
+      }
       if (i >= a.n) continue;
-      const double se = sig * a.e[i];
-      // b - (sigma E x - A x)
-      const double ri = ci.bsrc[i] - fma(se, x[i], -acc);
-      const double rti = ci.csrc[i] - fma(se, xt[i], -acct);
-      r[i] = ri;
-      rt[i] = rti;
-      v[0] = fma(ri, ri, v[0]);
-      v[1] = fma(rti, rti, v[1]);
+      const double ei = a.e[i];
+#pragma unroll
+      for (int j = 0; j < NC; ++j)
+        if (valid & (1u << j)) {
+          const int c = c0 + j;
+          const ColInfo& ci = a.cols[c];
+          const double se = ci.sigma * ei;
+          // b - (sigma E x - A x)
+          const double ri = ci.bsrc[i] - fma(se, vptr(a, V_X, c)[i], -acc[j]);
+          const double rti = ci.csrc[i] - fma(se, vptr(a, V_XT, c)[i], -acct[j]);
+          vptr(a, V_R, c)[i] = ri;
+          vptr(a, V_RT, c)[i] = rti;
+          v[j][0] = fma(ri, ri, v[j][0]);
+          v[j][1] = fma(rti, rti, v[j][1]);
+        }
     }
   }
-  wave_partials<2>(a, t, valid, v, a.part_norm);
+  block_partials<NC, 2>(a, t, c0, valid, v, a.part_norm);
 }
 
 // accept, restart from the current iterates (true residuals are in r, r~ and
@@ -616,6 +700,7 @@ struct TraceState {
   struct Pending {
     int cls;
     hipEvent_t a, b;
+    int count = 1;  // launches bracketed by the pair
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> free_events;
@@ -655,7 +740,7 @@ static void launch(TraceState* t, int cls, void (*kernel)(KArgs...), dim3 g, dim
   }
   hipEvent_t e0 = trace_event(t), e1 = trace_event(t);
   hipExtLaunchKernelGGL(kernel, g, b, 0, st, e0, e1, 0, args...);
-  if (e0 && e1) t->pending.push_back({cls, e0, e1});
+  if (e0 && e1) t->pending.push_back({cls, e0, e1, 1});
 }
 
 static void trace_collect(TraceState* t) {
@@ -663,7 +748,7 @@ static void trace_collect(TraceState* t) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       t->ms[p.cls] += ms;
-      t->launches[p.cls] += 1;
+      t->launches[p.cls] += p.count;
     }
     t->free_events.push_back(p.a);
     t->free_events.push_back(p.b);
@@ -747,7 +832,7 @@ void trace_factor_end(morx_ctx ctx, hipStream_t st, void* token) {
   hipEvent_t b = trace_event(t);
   if (!b) return;
   hipEventRecord(b, st);
-  t->pending.push_back({TR_FACTOR, (hipEvent_t)token, b});
+  t->pending.push_back({TR_FACTOR, (hipEvent_t)token, b, 1});
 }
 
 // ---------------------------------------------------------------------------
@@ -813,14 +898,13 @@ static IterArgs make_args(morx_system sys, Workspace* ws, int nc, int prec, int 
   a.nslices = sys->nslice;
   a.cap = ws->cap;
   a.nc = nc;
-  // columns per block, row groups per block, slabs (a multiple of 8 for the
-  // XCD remap), slices per slab
-  a.W = std::min(nc, kMaxW);
-  a.R = a.W >= 4 ? 1 : 4 / a.W;
-  int64_t nb = std::min<int64_t>((a.nslices + a.R - 1) / a.R, kMaxBlocks);
+  // slices per wave: as few as the partial-sum budget allows; blocks: a
+  // multiple of 8 for the XCD remap
+  const int64_t per_blk_min = (a.nslices + kMaxBlocks - 1) / kMaxBlocks;
+  a.spw = (int)std::max<int64_t>(1, (per_blk_min + kWavesPerBlock - 1) / kWavesPerBlock);
+  int64_t nb = (a.nslices + (int64_t)kWavesPerBlock * a.spw - 1) / ((int64_t)kWavesPerBlock * a.spw);
   nb = std::max<int64_t>(8, (nb + 7) / 8 * 8);
   a.nblk = (int)nb;
-  a.spb = (int)((a.nslices + nb - 1) / nb);
   a.vbytes = (int)prec_bytes(prec);
   a.maxL = maxL;
   a.off = sys->sell.off;
@@ -841,34 +925,68 @@ static IterArgs make_args(morx_system sys, Workspace* ws, int nc, int prec, int 
   return a;
 }
 
-static dim3 grid_of(const IterArgs& a, int halves) {
-  return dim3((unsigned)a.nblk, (unsigned)((a.nc + a.W - 1) / a.W), (unsigned)halves);
+// columns per wave: the batch split into equal chunks of at most kMaxNC
+static int pick_nc(int nc) {
+  const int chunks = (nc + kMaxNC - 1) / kMaxNC;
+  return (nc + chunks - 1) / chunks;
 }
-static dim3 block_of(const IterArgs& a) { return dim3((unsigned)(64 * a.W * a.R)); }
 
-template <typename VT>
+#define MORX_NC_DISPATCH(NCV, ...)                         \
+  switch (NCV) {                                           \
+    case 1: { constexpr int NC = 1; __VA_ARGS__; } break;  \
+    case 2: { constexpr int NC = 2; __VA_ARGS__; } break;  \
+    case 3: { constexpr int NC = 3; __VA_ARGS__; } break;  \
+    case 4: { constexpr int NC = 4; __VA_ARGS__; } break;  \
+    case 5: { constexpr int NC = 5; __VA_ARGS__; } break;  \
+    case 6: { constexpr int NC = 6; __VA_ARGS__; } break;  \
+    case 7: { constexpr int NC = 7; __VA_ARGS__; } break;  \
+    default: { constexpr int NC = 8; __VA_ARGS__; } break; \
+  }
+
+static dim3 grid_of(const IterArgs& a, int ncv, int halves) {
+  return dim3((unsigned)a.nblk, (unsigned)((a.nc + ncv - 1) / ncv), (unsigned)halves);
+}
+
+// The maxL chain launches of an iteration run back to back; when tracing, one
+// event pair brackets the whole run and counts maxL launches, so the event
+// overhead is spread over the run instead of added to every launch.
+template <typename VT, int NC>
 static void enqueue_chain(const IterArgs& a, const std::vector<morx_factor>& G, hipStream_t st,
                           TraceState* t) {
-  const dim3 g = grid_of(a, 2), b = block_of(a);
+  const dim3 g = grid_of(a, NC, 2);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (t) {
+    e0 = trace_event(t);
+    e1 = trace_event(t);
+    if (e0) hipEventRecord(e0, st);
+  }
   for (int s = 0; s < a.maxL; ++s) {
     const VT* fv = (const VT*)G[s]->vals.p;
     const VT* bv = (const VT*)G[a.maxL - 1 - s]->valsT.p;
-    launch(t, TR_CHAIN, k_chain_step<VT>, g, b, st, a, fv, bv, s, s == a.maxL - 1 ? 1 : 0);
+    k_chain_step<VT, NC><<<g, kBlock, 0, st>>>(a, fv, bv, s, s == a.maxL - 1 ? 1 : 0);
+  }
+  if (t && e0 && e1) {
+    hipEventRecord(e1, st);
+    t->pending.push_back({TR_CHAIN, e0, e1, a.maxL});
   }
 }
 
 static morx_status enqueue_iterations(const IterArgs& a, const std::vector<morx_factor>& G,
                                       int prec, int iters, hipStream_t st, TraceState* t) {
-  const dim3 g1 = grid_of(a, 1), b = block_of(a);
+  const int ncv = pick_nc(a.nc);
   for (int it = 0; it < iters; ++it) {
     const int par = it & 1;
-    if (prec == MORX_F64) enqueue_chain<double>(a, G, st, t);
-    else if (prec == MORX_F32) enqueue_chain<float>(a, G, st, t);
-    else enqueue_chain<uint16_t>(a, G, st, t);
-    k_fin_rho<<<1, kFinThreads, 0, st>>>(a);
-    launch(t, TR_SPMV, k_spmv_pair, g1, b, st, a, par);
-    k_fin_delta<<<1, kFinThreads, 0, st>>>(a);
-    launch(t, TR_UPDATE, k_update, g1, b, st, a, par);
+    MORX_NC_DISPATCH(ncv, {
+      const dim3 g1 = grid_of(a, NC, 1);
+      if (prec == MORX_F64) enqueue_chain<double, NC>(a, G, st, t);
+      else if (prec == MORX_F32) enqueue_chain<float, NC>(a, G, st, t);
+      else enqueue_chain<uint16_t, NC>(a, G, st, t);
+      k_fin_rho<<<1, kFinThreads, 0, st>>>(a);
+      launch(t, TR_SPMV, k_spmv_pair<NC>, g1, dim3(kBlock), st, a, par);
+      k_fin_delta<<<1, kFinThreads, 0, st>>>(a);
+      // elementwise: one column per wave, nothing to share between columns
+      launch(t, TR_UPDATE, k_update<1>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
+    });
   }
   MORX_HIP(hipGetLastError());
   return MORX_OK;
@@ -909,7 +1027,8 @@ static morx_status solve_batch(morx_system sys, std::vector<BatchCol>& cols,
   }
   MORX_HIP(hipMemcpyAsync(ws->cols.p, ws->hcols, nc * sizeof(ColInfo), hipMemcpyHostToDevice, st));
   const IterArgs a = make_args(sys, ws, nc, prec, maxL);
-  k_init<<<grid_of(a, 1), block_of(a), 0, st>>>(a);
+  const int ncv = pick_nc(nc);
+  k_init<1><<<grid_of(a, 1, 1), kBlock, 0, st>>>(a);
   k_fin_init<<<1, kFinThreads, 0, st>>>(a);
   MORX_HIP(hipGetLastError());
 
@@ -947,7 +1066,7 @@ static morx_status solve_batch(morx_system sys, std::vector<BatchCol>& cols,
     }
     if (active == 0 && stop == 0) break;
     if (active == 0) {
-      k_true_residual<<<grid_of(a, 1), block_of(a), 0, st>>>(a);
+      MORX_NC_DISPATCH(ncv, k_true_residual<NC><<<grid_of(a, NC, 1), kBlock, 0, st>>>(a));
       k_fin_true<<<1, kFinThreads, 0, st>>>(a);
       MORX_HIP(hipGetLastError());
       continue;
