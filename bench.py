@@ -34,6 +34,17 @@ DOMINANT = "chain_step"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_chain_step_convdiff3d_n262144.json")
 
 
+def kernel_source_hash() -> str:
+    """sha256 of the sources of the iteration kernels (bicg.hip, common.h)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("bicg.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_2003_12759_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def run_job(S, w, Bd, Cd, batched: bool, use_graph: bool = True):
     stats_all = []
     for z, sig in enumerate(w.rounds):
@@ -149,10 +160,15 @@ def main():
         if os.path.exists(TRAFFIC_FILE):
             with open(TRAFFIC_FILE) as f:
                 tf = json.load(f)
-            traffic = tf.get("bytes_per_launch")
+            # counters describe the kernel source they were taken on
+            if tf.get("source_sha256") == kernel_source_hash():
+                traffic = tf.get("bytes_per_launch")
+        ncol = len(w.rounds[0]) * w.B.shape[1]
+        chunks = -(-ncol // 8)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                    "traffic": traffic, "kernel": "k_chain_step<float,16>",
+                    "traffic": traffic,
+                    "kernel": f"k_chain_step<{ {'f64': 'double', 'f32': 'float', 'bf16': 'unsigned short'}[w.prec]}, {-(-ncol // chunks)}>",
                     "avg_launch_us": round(1e3 * ms / launches, 2),
                     "alg_bytes_per_launch": byts / launches}
 
