@@ -189,6 +189,55 @@ morx_status morx_project(morx_system sys, int32_t r, const double* V, int64_t ld
                          double* Br, double* Cr, int32_t orthonormalize, void* stream);
 
 /*
+ * Serving (continuous batching).  A server owns one scheduler thread on the
+ * context's device.  Requests ask for the primal solve (sigma E - A) x = b on
+ * a resident system; they are admitted while their device memory fits the
+ * budget, run in column slots of a per-system batch (one stream per system),
+ * and slots are refilled between iteration segments, so requests that
+ * arrive while others run join the work already on the device.  Each system
+ * keeps a chain of `anchors` factors (SPAI at the first anchor, column-wise
+ * updates between consecutive anchors, log-spaced over [anchor_min,
+ * anchor_max]); a request adds one update from its nearest anchor
+ * (Section III-B, Table 2 second approach).  Systems must outlive the server;
+ * b and x (dev, n entries) stay owned by the caller until the request is
+ * finished.  submit, poll, wait and info are thread-safe.
+ */
+typedef struct morx_server_s* morx_server;
+
+typedef struct {
+  size_t hbm_budget_bytes;   /* device memory the server may hold: slot batches,
+                                anchor and request factors (16 GiB)                 */
+  int32_t slots_per_system;  /* concurrent requests per system, 1..64 (8)           */
+  int32_t anchors;           /* anchor shifts per system, 1..31 (8)                 */
+  double anchor_min;         /* anchors log-spaced over [anchor_min, anchor_max]    */
+  double anchor_max;         /* (1, 1e3)                                            */
+  int32_t segment_iters;     /* iterations between admissions (8)                   */
+  int32_t reserved;
+} morx_serve_config;
+
+void morx_serve_config_default(morx_serve_config* cfg);
+/* opts: tol, maxit, max_restarts, precond_prec, use_graph are used. */
+morx_status morx_serve_start(morx_ctx ctx, const morx_serve_config* cfg, const morx_opts* opts,
+                             morx_server* out);
+/* sigma must be finite and > 0.  *ticket identifies the request. */
+morx_status morx_serve_submit(morx_server srv, morx_system sys, double sigma, const double* b,
+                              double* x, uint64_t* ticket);
+/*
+ * MORX_E_PENDING while the request runs; otherwise the request's status
+ * (MORX_E_ADMISSION if it can never fit the budget), *st and the latency
+ * (submit to completion, seconds) are filled and the ticket is released.
+ */
+morx_status morx_serve_poll(morx_server srv, uint64_t ticket, morx_col_stats* st,
+                            double* latency_s);
+/* Like poll, but blocks until the request is finished. */
+morx_status morx_serve_wait(morx_server srv, uint64_t ticket, morx_col_stats* st,
+                            double* latency_s);
+morx_status morx_serve_info(morx_server srv, uint64_t* submitted, uint64_t* completed,
+                            int32_t* running, int32_t* queued, int64_t* bytes_in_use);
+/* Finishes every submitted request, then frees the server. */
+morx_status morx_serve_stop(morx_server srv);
+
+/*
  * Kernel tracing (measurement only).  While enabled on a context, solves do
  * not use graphs; every launch of the listed kernel classes is bracketed by
  * HIP events on the library's stream and the algorithmic bytes each launch

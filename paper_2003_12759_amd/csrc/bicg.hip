@@ -29,24 +29,7 @@
 
 #include <hip/hip_ext.h>
 
-#include "common.h"
-
-struct ColInfo {
-  double sigma;
-  double nb, nc;      // norms of the primal and dual right-hand sides
-  double tol;
-  double rho, rho_prev, alpha, beta, delta;
-  double rr, rtrt;    // squared norms of the current residuals
-  double relp, reld;  // true relative residuals at the last check
-  const double* bsrc;  // primal right-hand side (dev)
-  const double* csrc;  // dual (or shadow) right-hand side (dev)
-  double* xout;        // caller's output columns (dev) or null
-  double* yout;
-  int32_t state, L, first, it_cycle, iters, restarts, max_restarts, maxit;
-  int32_t check_p, check_d, broke, status;
-  int32_t out_x, out_y;  // 0: write zeros, 1: primal iterate, 2: dual iterate
-  int32_t pad0, pad1;
-};
+#include "krylov.h"
 
 enum Vec : int {
   V_X, V_XT, V_R, V_RT, V_P0, V_P1, V_PT0, V_PT1, V_Z, V_ZT, V_Q, V_QT,
@@ -55,15 +38,6 @@ enum Vec : int {
 
 // trace counters (algorithmic bytes per kernel class)
 enum TraceClass : int { TR_CHAIN = 0, TR_SPMV = 1, TR_UPDATE = 2, TR_FACTOR = 3, kTraceClasses = 8 };
-
-struct Workspace {
-  int64_t ld = 0;
-  int cap = 0;
-  DevBuf vec, cols, part;
-  ColInfo* hcols = nullptr;  // pinned host mirror
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-};
 
 namespace {
 
@@ -82,11 +56,12 @@ constexpr double kBreakdown = 1e-14;
 // 8 XCDs round robin), keeping a range's stencil neighbours in that XCD's L2.
 struct IterArgs {
   int64_t n, ld, nnzS, nslices;
-  int cap, nc, nblk, spw, vbytes, maxL;
+  int cap, nc, nblk, spw, vbytes, maxL, lcap;
   const int32_t *off, *col, *offT, *colT;
   const double *valA, *valAT, *e;
   double* vec;
   ColInfo* cols;
+  const void* const* ftab;  // [2][cap][lcap]: factor values, forward then transposed order
   double* part_rho;    // [3][cap][nblk]
   double* part_delta;  // [3][cap][nblk]
   double* part_norm;   // [2][cap][nblk]
@@ -235,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_init(IterArgs a) {
   unsigned valid = 0;
 #pragma unroll
   for (int j = 0; j < NC; ++j)
-    if (c0 + j < a.nc && a.cols[c0 + j].state == COL_ACTIVE) valid |= 1u << j;
+    if (c0 + j < a.nc && a.cols[c0 + j].state == COL_INIT) valid |= 1u << j;
   double v[NC][2];
 #pragma unroll
   for (int j = 0; j < NC; ++j) v[j][0] = v[j][1] = 0.0;
@@ -262,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_init(IterArgs a) {
 __global__ __launch_bounds__(kFinThreads) void k_fin_init(IterArgs a) {
   for (int c = threadIdx.x >> 6; c < a.nc; c += kFinThreads / 64) {
     ColInfo& ci = a.cols[c];
-    if (ci.state != COL_ACTIVE) continue;
+    if (ci.state != COL_INIT) continue;
     double t2[2];
     wave_totals<2>(a, a.part_norm, c, t2);
     if ((threadIdx.x & 63) == 0) {
@@ -270,31 +245,35 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_init(IterArgs a) {
       ci.nc = sqrt(t2[1]);
       ci.first = 1;
       ci.it_cycle = 0;
+      ci.state = COL_ACTIVE;
     }
   }
 }
 
-// one chain step: the forward half (blockIdx.z == 0) applies G[s] on the rows
-// of S, the transposed half applies G[maxL-1-s]^T on the rows of S^T; the
-// last step also forms the partial sums of rho = z~^T r, ||z~||^2, ||r||^2
+// one chain step: the forward half (blockIdx.z == 0) applies factor s of
+// each column's chain on the rows of S, the transposed half applies factor
+// maxL-1-s transposed on the rows of S^T; the last step also forms the
+// partial sums of rho = z~^T r, ||z~||^2, ||r||^2.  Columns whose chains
+// share a factor share its value loads.
 template <typename VT, int NC>
-__global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, const VT* __restrict__ fval,
-                                                       const VT* __restrict__ bval, int s,
-                                                       int do_rho) {
+__global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s, int do_rho) {
   const WaveCtx t = wave_ctx(a);
   const int c0 = blockIdx.y * NC;
   const bool bwd = blockIdx.z == 1;
-  const int jf = bwd ? a.maxL - 1 - s : s;  // factor index applied by this half
+  const int jf = bwd ? a.maxL - 1 - s : s;  // chain position applied by this half
   const bool rho_half = bwd && do_rho;
   unsigned valid = 0;
   const double* src[NC];
   double* dst[NC];
+  const VT* fv[NC];
 #pragma unroll
   for (int j = 0; j < NC; ++j) {
     const int c = min(c0 + j, a.nc - 1);
     const ColInfo& ci = a.cols[c];
     const int L = ci.L;
-    if (c0 + j < a.nc && ci.state == COL_ACTIVE && L > jf) valid |= 1u << j;
+    const bool on = c0 + j < a.nc && ci.state == COL_ACTIVE && L > jf;
+    if (on) valid |= 1u << j;
+    fv[j] = on ? (const VT*)a.ftab[((int64_t)(bwd ? a.cap : 0) + c) * a.lcap + jf] : nullptr;
     if (!bwd) {
       src[j] = (jf == 0) ? vptr(a, V_R, c) : vptr(a, V_T0 + ((jf - 1) & 1), c);
       dst[j] = (jf == L - 1) ? vptr(a, V_Z, c) : vptr(a, V_T0 + (jf & 1), c);
@@ -310,7 +289,6 @@ __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, const VT* __r
   if (valid) {
     const int32_t* off = bwd ? a.offT : a.off;
     const int32_t* col = bwd ? a.colT : a.col;
-    const VT* val = bwd ? bval : fval;
     for (int64_t sl = t.s_begin; sl < t.s_end; ++sl) {
       const int32_t base = off[sl];
       const int32_t w = (off[sl + 1] - base) >> 6;
@@ -321,11 +299,24 @@ __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, const VT* __r
       for (int j = 0; j < NC; ++j) acc[j] = 0.0;
       for (int32_t m0 = 0; m0 < w; m0 += kUnroll) {
         SliceChunk ch;
-        double vv[kUnroll];
-        load_chunk<VT>(col, val, p0, w, m0, ch, vv);
+        int32_t pp[kUnroll];
 #pragma unroll
-        for (int j = 0; j < NC; ++j)
-          if (valid & (1u << j)) acc[j] = chunk_dot(ch, vv, m0, w, src[j], acc[j]);
+        for (int u = 0; u < kUnroll; ++u) {
+          pp[u] = p0 + ((m0 + u < w) ? (m0 + u) * kSlice : 0);
+          ch.c[u] = col[pp[u]];
+        }
+        const VT* loaded = nullptr;
+        double vv[kUnroll];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          if (!(valid & (1u << j))) continue;
+          if (fv[j] != loaded) {
+            loaded = fv[j];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) vv[u] = (m0 + u < w) ? load_val<VT>(loaded + pp[u]) : 0.0;
+          }
+          acc[j] = chunk_dot(ch, vv, m0, w, src[j], acc[j]);
+        }
       }
       if (i < a.n) {
 #pragma unroll
@@ -646,9 +637,14 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_true(IterArgs a) {
   }
 }
 
-// copy the iterates to the caller's columns (or zeros)
-__global__ __launch_bounds__(256) void k_copy_out(IterArgs a) {
-  const int c = blockIdx.y;
+// copy the iterates of the listed slots to their output columns (or zeros)
+struct SlotList {
+  int n;
+  int s[64];
+};
+
+__global__ __launch_bounds__(256) void k_copy_out(IterArgs a, SlotList sl) {
+  const int c = sl.s[blockIdx.y];
   const ColInfo& ci = a.cols[c];
   const double* xs = vptr(a, V_X, c);
   const double* ys = vptr(a, V_XT, c);
@@ -836,67 +832,94 @@ void trace_factor_end(morx_ctx ctx, hipStream_t st, void* token) {
 }
 
 // ---------------------------------------------------------------------------
-// host side
+// host side: the slot batch
 
-void workspace_free(Workspace* ws) {
-  if (!ws) return;
-  if (ws->exec) hipGraphExecDestroy(ws->exec);
-  if (ws->graph) hipGraphDestroy(ws->graph);
-  dev_free(ws->vec);
-  dev_free(ws->cols);
-  dev_free(ws->part);
-  if (ws->hcols) hipHostFree(ws->hcols);
-  delete ws;
+void batch_free(KrylovBatch& b) {
+  for (auto& g : b.graphs) {
+    if (g.x) hipGraphExecDestroy(g.x);
+    if (g.g) hipGraphDestroy(g.g);
+  }
+  b.graphs.clear();
+  dev_free(b.vec);
+  dev_free(b.cols);
+  dev_free(b.part);
+  dev_free(b.ftab);
+  if (b.hcols) hipHostFree(b.hcols);
+  if (b.hftab) hipHostFree(b.hftab);
+  b.hcols = nullptr;
+  b.hftab = nullptr;
+  b.cap = b.lcap = 0;
 }
 
-static morx_status workspace_reserve(morx_system sys, int ncol) {
-  Workspace* ws = sys->ws;
-  if (ws && ws->cap >= ncol && ws->ld == sys->n_pad) return MORX_OK;
-  int cap = std::max(ncol, ws ? 2 * ws->cap : 4);
-  if (ws) {
-    MORX_HIP(hipStreamSynchronize(sys->ctx->stream));
-    workspace_free(ws);
-  }
-  sys->ws = nullptr;
-  ws = new Workspace();
-  ws->ld = sys->n_pad;
-  ws->cap = cap;
-  morx_status s = dev_alloc(ws->vec, (size_t)kNumVec * cap * ws->ld * sizeof(double));
-  if (s == MORX_OK) s = dev_alloc(ws->cols, (size_t)cap * sizeof(ColInfo));
-  if (s == MORX_OK) s = dev_alloc(ws->part, (size_t)8 * cap * kMaxBlocks * sizeof(double));
-  if (s == MORX_OK && hipHostMalloc((void**)&ws->hcols, (size_t)cap * sizeof(ColInfo)) != hipSuccess)
+void krylov_batch_delete(KrylovBatch* kb) {
+  if (!kb) return;
+  batch_free(*kb);
+  delete kb;
+}
+
+morx_status batch_alloc(KrylovBatch& b, morx_system sys, int cap, int lcap, int prec,
+                        hipStream_t st) {
+  batch_free(b);
+  b.sys = sys;
+  b.cap = cap;
+  b.lcap = lcap;
+  b.prec = prec;
+  b.ld = sys->n_pad;
+  morx_status s = dev_alloc(b.vec, (size_t)kNumVec * cap * b.ld * sizeof(double));
+  if (s == MORX_OK) s = dev_alloc(b.cols, (size_t)cap * sizeof(ColInfo));
+  if (s == MORX_OK) s = dev_alloc(b.part, (size_t)8 * cap * kMaxBlocks * sizeof(double));
+  if (s == MORX_OK) s = dev_alloc(b.ftab, (size_t)2 * cap * lcap * sizeof(void*));
+  if (s == MORX_OK && hipHostMalloc((void**)&b.hcols, (size_t)cap * sizeof(ColInfo)) != hipSuccess)
+    s = MORX_E_NOMEM;
+  if (s == MORX_OK &&
+      hipHostMalloc((void**)&b.hftab, (size_t)2 * cap * lcap * sizeof(void*)) != hipSuccess)
     s = MORX_E_NOMEM;
   if (s != MORX_OK) {
-    workspace_free(ws);
-    morx_set_error("BiCG workspace allocation failed (%d columns)", ncol);
+    batch_free(b);
+    morx_set_error("BiCG slot allocation failed (%d slots)", cap);
     return MORX_E_NOMEM;
   }
-  hipStream_t st = sys->ctx->stream;
-  const int64_t cnt = (int64_t)(ws->vec.bytes / sizeof(double));
-  k_zero<<<(unsigned)((cnt + 255) / 256), 256, 0, st>>>((double*)ws->vec.p, cnt);
+  for (int c = 0; c < cap; ++c) {
+    ColInfo ci = {};
+    ci.state = COL_IDLE;
+    b.hcols[c] = ci;
+  }
+  memset(b.hftab, 0, (size_t)2 * cap * lcap * sizeof(void*));
+  const int64_t cnt = (int64_t)(b.vec.bytes / sizeof(double));
+  k_zero<<<(unsigned)((cnt + 255) / 256), 256, 0, st>>>((double*)b.vec.p, cnt);
   MORX_HIP(hipGetLastError());
-  sys->ws = ws;
+  MORX_HIP(hipMemcpyAsync(b.cols.p, b.hcols, (size_t)cap * sizeof(ColInfo), hipMemcpyHostToDevice, st));
+  MORX_HIP(hipMemcpyAsync(b.ftab.p, b.hftab, (size_t)2 * cap * lcap * sizeof(void*),
+                          hipMemcpyHostToDevice, st));
   return MORX_OK;
 }
 
-struct BatchCol {
-  double sigma;
-  int L;
-  const double* b;
-  const double* c;
-  double* xout;
-  double* yout;
-  int check_p, check_d, out_x, out_y;
-  morx_col_stats* stats;
-};
+morx_status batch_upload(KrylovBatch& b, int first, int count, hipStream_t st) {
+  if (count <= 0) return MORX_OK;
+  MORX_HIP(hipMemcpyAsync((ColInfo*)b.cols.p + first, b.hcols + first, count * sizeof(ColInfo),
+                          hipMemcpyHostToDevice, st));
+  for (int h = 0; h < 2; ++h) {
+    const size_t off = ((size_t)h * b.cap + first) * b.lcap;
+    MORX_HIP(hipMemcpyAsync((void**)b.ftab.p + off, b.hftab + off, (size_t)count * b.lcap * sizeof(void*),
+                            hipMemcpyHostToDevice, st));
+  }
+  return MORX_OK;
+}
 
-static IterArgs make_args(morx_system sys, Workspace* ws, int nc, int prec, int maxL) {
+morx_status batch_download(KrylovBatch& b, hipStream_t st) {
+  MORX_HIP(hipMemcpyAsync(b.hcols, b.cols.p, (size_t)b.cap * sizeof(ColInfo), hipMemcpyDeviceToHost, st));
+  MORX_HIP(hipStreamSynchronize(st));
+  return MORX_OK;
+}
+
+static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
+  morx_system sys = b.sys;
   IterArgs a;
   a.n = sys->n;
-  a.ld = ws->ld;
+  a.ld = b.ld;
   a.nnzS = sys->nnzS;
   a.nslices = sys->nslice;
-  a.cap = ws->cap;
+  a.cap = b.cap;
   a.nc = nc;
   // slices per wave: as few as the partial-sum budget allows; blocks: a
   // multiple of 8 for the XCD remap
@@ -905,8 +928,9 @@ static IterArgs make_args(morx_system sys, Workspace* ws, int nc, int prec, int 
   int64_t nb = (a.nslices + (int64_t)kWavesPerBlock * a.spw - 1) / ((int64_t)kWavesPerBlock * a.spw);
   nb = std::max<int64_t>(8, (nb + 7) / 8 * 8);
   a.nblk = (int)nb;
-  a.vbytes = (int)prec_bytes(prec);
+  a.vbytes = (int)prec_bytes(b.prec);
   a.maxL = maxL;
+  a.lcap = b.lcap;
   a.off = sys->sell.off;
   a.col = sys->sell.col;
   a.offT = sys->sellT.off;
@@ -914,10 +938,11 @@ static IterArgs make_args(morx_system sys, Workspace* ws, int nc, int prec, int 
   a.valA = sys->sell_val;
   a.valAT = sys->sellT_val;
   a.e = sys->e;
-  a.vec = (double*)ws->vec.p;
-  a.cols = (ColInfo*)ws->cols.p;
-  double* part = (double*)ws->part.p;
-  const int64_t slab = (int64_t)ws->cap * kMaxBlocks;
+  a.vec = (double*)b.vec.p;
+  a.cols = (ColInfo*)b.cols.p;
+  a.ftab = (const void* const*)b.ftab.p;
+  double* part = (double*)b.part.p;
+  const int64_t slab = (int64_t)b.cap * kMaxBlocks;
   a.part_rho = part;
   a.part_delta = part + 3 * slab;
   a.part_norm = part + 6 * slab;
@@ -951,8 +976,7 @@ static dim3 grid_of(const IterArgs& a, int ncv, int halves) {
 // event pair brackets the whole run and counts maxL launches, so the event
 // overhead is spread over the run instead of added to every launch.
 template <typename VT, int NC>
-static void enqueue_chain(const IterArgs& a, const std::vector<morx_factor>& G, hipStream_t st,
-                          TraceState* t) {
+static void enqueue_chain(const IterArgs& a, hipStream_t st, TraceState* t) {
   const dim3 g = grid_of(a, NC, 2);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (t) {
@@ -960,27 +984,24 @@ static void enqueue_chain(const IterArgs& a, const std::vector<morx_factor>& G, 
     e1 = trace_event(t);
     if (e0) hipEventRecord(e0, st);
   }
-  for (int s = 0; s < a.maxL; ++s) {
-    const VT* fv = (const VT*)G[s]->vals.p;
-    const VT* bv = (const VT*)G[a.maxL - 1 - s]->valsT.p;
-    k_chain_step<VT, NC><<<g, kBlock, 0, st>>>(a, fv, bv, s, s == a.maxL - 1 ? 1 : 0);
-  }
+  for (int s = 0; s < a.maxL; ++s)
+    k_chain_step<VT, NC><<<g, kBlock, 0, st>>>(a, s, s == a.maxL - 1 ? 1 : 0);
   if (t && e0 && e1) {
     hipEventRecord(e1, st);
     t->pending.push_back({TR_CHAIN, e0, e1, a.maxL});
   }
 }
 
-static morx_status enqueue_iterations(const IterArgs& a, const std::vector<morx_factor>& G,
-                                      int prec, int iters, hipStream_t st, TraceState* t) {
+static morx_status enqueue_iterations(const IterArgs& a, int prec, int iters, hipStream_t st,
+                                      TraceState* t) {
   const int ncv = pick_nc(a.nc);
   for (int it = 0; it < iters; ++it) {
     const int par = it & 1;
     MORX_NC_DISPATCH(ncv, {
       const dim3 g1 = grid_of(a, NC, 1);
-      if (prec == MORX_F64) enqueue_chain<double, NC>(a, G, st, t);
-      else if (prec == MORX_F32) enqueue_chain<float, NC>(a, G, st, t);
-      else enqueue_chain<uint16_t, NC>(a, G, st, t);
+      if (prec == MORX_F64) enqueue_chain<double, NC>(a, st, t);
+      else if (prec == MORX_F32) enqueue_chain<float, NC>(a, st, t);
+      else enqueue_chain<uint16_t, NC>(a, st, t);
       k_fin_rho<<<1, kFinThreads, 0, st>>>(a);
       launch(t, TR_SPMV, k_spmv_pair<NC>, g1, dim3(kBlock), st, a, par);
       k_fin_delta<<<1, kFinThreads, 0, st>>>(a);
@@ -992,7 +1013,84 @@ static morx_status enqueue_iterations(const IterArgs& a, const std::vector<morx_
   return MORX_OK;
 }
 
-// Solve one batch of columns sharing the factor list G (every chain is a prefix).
+morx_status batch_launch_init(KrylovBatch& b, int nc, hipStream_t st) {
+  const IterArgs a = make_args(b, nc, 1);
+  k_init<1><<<grid_of(a, 1, 1), kBlock, 0, st>>>(a);
+  k_fin_init<<<1, kFinThreads, 0, st>>>(a);
+  MORX_HIP(hipGetLastError());
+  return MORX_OK;
+}
+
+morx_status batch_launch_true(KrylovBatch& b, int nc, hipStream_t st) {
+  const IterArgs a = make_args(b, nc, 1);
+  MORX_NC_DISPATCH(pick_nc(nc), k_true_residual<NC><<<grid_of(a, NC, 1), kBlock, 0, st>>>(a));
+  k_fin_true<<<1, kFinThreads, 0, st>>>(a);
+  MORX_HIP(hipGetLastError());
+  return MORX_OK;
+}
+
+morx_status batch_launch_copy_out(KrylovBatch& b, const int* slots, int count, hipStream_t st) {
+  const IterArgs a = make_args(b, b.cap, 1);
+  for (int k0 = 0; k0 < count; k0 += 64) {
+    SlotList sl;
+    sl.n = std::min(64, count - k0);
+    for (int k = 0; k < sl.n; ++k) sl.s[k] = slots[k0 + k];
+    k_copy_out<<<dim3((unsigned)std::min<int64_t>((a.n + 255) / 256, 1024), sl.n, 1), 256, 0, st>>>(a, sl);
+  }
+  MORX_HIP(hipGetLastError());
+  return MORX_OK;
+}
+
+// one segment of `iters` iterations; graphs are cached per (nc, maxL, iters)
+morx_status batch_launch_segment(KrylovBatch& b, int nc, int maxL, int iters, bool use_graph,
+                                 hipStream_t st, TraceState* t) {
+  const IterArgs a = make_args(b, nc, maxL);
+  if (!use_graph || t) return enqueue_iterations(a, b.prec, iters, st, t);
+  const int key_nc = nc;
+  for (auto& g : b.graphs)
+    if (g.maxL == maxL && g.iters == iters * 1000 + key_nc) {
+      MORX_HIP(hipGraphLaunch(g.x, st));
+      return MORX_OK;
+    }
+  if (b.graphs.size() >= 24) {
+    hipGraphExecDestroy(b.graphs.front().x);
+    hipGraphDestroy(b.graphs.front().g);
+    b.graphs.erase(b.graphs.begin());
+  }
+  MORX_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  morx_status s = enqueue_iterations(a, b.prec, iters, st, nullptr);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(st, &g);
+  MORX_TRY(s);
+  MORX_REQUIRE(e == hipSuccess, MORX_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    morx_set_error("graph instantiation failed: %s", hipGetErrorString(e));
+    return MORX_E_HIP;
+  }
+  b.graphs.push_back({maxL, iters * 1000 + key_nc, g, x});
+  MORX_HIP(hipGraphLaunch(x, st));
+  return MORX_OK;
+}
+
+void trace_collect_pending(TraceState* t) {
+  if (t) trace_collect(t);
+}
+
+struct BatchCol {
+  double sigma;
+  int L;
+  const double* b;
+  const double* c;
+  double* xout;
+  double* yout;
+  int check_p, check_d, out_x, out_y;
+  morx_col_stats* stats;
+};
+
+// Solve a set of columns whose chains are prefixes of one factor list G.
 static morx_status solve_batch(morx_system sys, std::vector<BatchCol>& cols,
                                const std::vector<morx_factor>& G, int prec, const morx_opts& o,
                                hipStream_t st) {
@@ -1001,8 +1099,12 @@ static morx_status solve_batch(morx_system sys, std::vector<BatchCol>& cols,
   int maxL = 0;
   for (auto& c : cols) maxL = std::max(maxL, c.L);
   MORX_REQUIRE(maxL >= 1 && maxL <= (int)G.size(), MORX_E_INVALID, "bad chain length");
-  MORX_TRY(workspace_reserve(sys, nc));
-  Workspace* ws = sys->ws;
+  if (!sys->kb) sys->kb = new KrylovBatch();
+  KrylovBatch& b = *sys->kb;
+  if (b.cap < nc || b.lcap < maxL || b.prec != prec || b.ld != sys->n_pad) {
+    MORX_HIP(hipStreamSynchronize(st));
+    MORX_TRY(batch_alloc(b, sys, std::max(nc, b.cap), std::max(maxL, b.lcap), prec, st));
+  }
   TraceState* t = trace_state_if_on(sys->ctx);
   const int maxit = o.maxit > 0 ? o.maxit : (int)std::min<int64_t>(sys->n, 20000);
   for (int c = 0; c < nc; ++c) {
@@ -1013,7 +1115,7 @@ static morx_status solve_batch(morx_system sys, std::vector<BatchCol>& cols,
     ci.csrc = cols[c].c;
     ci.xout = cols[c].xout;
     ci.yout = cols[c].yout;
-    ci.state = COL_ACTIVE;
+    ci.state = COL_INIT;
     ci.L = cols[c].L;
     ci.first = 1;
     ci.max_restarts = o.max_restarts;
@@ -1023,78 +1125,54 @@ static morx_status solve_batch(morx_system sys, std::vector<BatchCol>& cols,
     ci.out_x = cols[c].out_x;
     ci.out_y = cols[c].out_y;
     ci.status = MORX_E_NOT_CONVERGED;
-    ws->hcols[c] = ci;
+    b.hcols[c] = ci;
+    for (int s = 0; s < b.lcap; ++s) {
+      const bool in = s < cols[c].L;
+      b.hftab[(size_t)c * b.lcap + s] = in ? G[s]->vals.p : nullptr;
+      b.hftab[((size_t)b.cap + c) * b.lcap + s] = in ? G[s]->valsT.p : nullptr;
+    }
   }
-  MORX_HIP(hipMemcpyAsync(ws->cols.p, ws->hcols, nc * sizeof(ColInfo), hipMemcpyHostToDevice, st));
-  const IterArgs a = make_args(sys, ws, nc, prec, maxL);
-  const int ncv = pick_nc(nc);
-  k_init<1><<<grid_of(a, 1, 1), kBlock, 0, st>>>(a);
-  k_fin_init<<<1, kFinThreads, 0, st>>>(a);
-  MORX_HIP(hipGetLastError());
+  MORX_TRY(batch_upload(b, 0, nc, st));
+  MORX_TRY(batch_launch_init(b, nc, st));
 
   int seg = std::max(2, o.poll_iters > 0 ? o.poll_iters : 8);
   seg += seg & 1;  // even: the p buffers alternate by iteration parity
-  if (ws->exec) {
-    hipGraphExecDestroy(ws->exec);
-    ws->exec = nullptr;
-  }
-  if (ws->graph) {
-    hipGraphDestroy(ws->graph);
-    ws->graph = nullptr;
-  }
-  const bool use_graph = o.use_graph && !t;
-  if (use_graph) {
-    MORX_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    morx_status s = enqueue_iterations(a, G, prec, seg, st, nullptr);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(st, &g);
-    MORX_TRY(s);
-    MORX_REQUIRE(e == hipSuccess, MORX_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
-    ws->graph = g;
-    MORX_HIP(hipGraphInstantiate(&ws->exec, g, nullptr, nullptr, 0));
-  }
   const int64_t guard_max = 2 * ((int64_t)(o.max_restarts + 1) * (maxit + seg) / seg + 4);
   for (int64_t guard = 0; guard <= guard_max; ++guard) {
-    MORX_HIP(hipMemcpyAsync(ws->hcols, ws->cols.p, nc * sizeof(ColInfo), hipMemcpyDeviceToHost, st));
-    MORX_HIP(hipStreamSynchronize(st));
+    MORX_TRY(batch_download(b, st));
     if (t) trace_collect(t);
     int active = 0, stop = 0;
     for (int c = 0; c < nc; ++c) {
-      const int s = ws->hcols[c].state;
+      const int s = b.hcols[c].state;
       if (s == COL_ACTIVE) ++active;
       else if (s == COL_CONVERGED || s == COL_BREAKDOWN || s == COL_MAXIT) ++stop;
     }
     if (active == 0 && stop == 0) break;
     if (active == 0) {
-      MORX_NC_DISPATCH(ncv, k_true_residual<NC><<<grid_of(a, NC, 1), kBlock, 0, st>>>(a));
-      k_fin_true<<<1, kFinThreads, 0, st>>>(a);
-      MORX_HIP(hipGetLastError());
+      MORX_TRY(batch_launch_true(b, nc, st));
       continue;
     }
-    if (use_graph) {
-      MORX_HIP(hipGraphLaunch(ws->exec, st));
-    } else {
-      MORX_TRY(enqueue_iterations(a, G, prec, seg, st, t));
-    }
+    MORX_TRY(batch_launch_segment(b, nc, maxL, seg, o.use_graph != 0, st, t));
   }
-  k_copy_out<<<dim3((unsigned)std::min<int64_t>((sys->n + 255) / 256, 1024), nc, 1), 256, 0,
-               st>>>(a);
-  MORX_HIP(hipGetLastError());
-  MORX_HIP(hipMemcpyAsync(ws->hcols, ws->cols.p, nc * sizeof(ColInfo), hipMemcpyDeviceToHost, st));
-  MORX_HIP(hipStreamSynchronize(st));
+  std::vector<int> all(nc);
+  for (int c = 0; c < nc; ++c) all[c] = c;
+  MORX_TRY(batch_launch_copy_out(b, all.data(), nc, st));
+  MORX_TRY(batch_download(b, st));
   if (t) trace_collect(t);
   for (int c = 0; c < nc; ++c) {
-    const ColInfo& ci = ws->hcols[c];
+    ColInfo& ci = b.hcols[c];
     morx_col_stats* out = cols[c].stats;
-    if (!out) continue;
-    out->status = ci.state == COL_DONE ? MORX_OK
-                                       : (ci.state == COL_FAILED ? ci.status : MORX_E_NOT_CONVERGED);
-    out->iters = ci.iters;
-    out->restarts = ci.restarts;
-    out->relres_primal = cols[c].out_x == 2 ? ci.reld : (cols[c].out_x == 1 ? ci.relp : 0.0);
-    out->relres_dual = cols[c].out_y == 2 ? ci.reld : (cols[c].out_y == 1 ? ci.relp : 0.0);
+    if (out) {
+      out->status = ci.state == COL_DONE ? MORX_OK
+                                         : (ci.state == COL_FAILED ? ci.status : MORX_E_NOT_CONVERGED);
+      out->iters = ci.iters;
+      out->restarts = ci.restarts;
+      out->relres_primal = cols[c].out_x == 2 ? ci.reld : (cols[c].out_x == 1 ? ci.relp : 0.0);
+      out->relres_dual = cols[c].out_y == 2 ? ci.reld : (cols[c].out_y == 1 ? ci.relp : 0.0);
+    }
+    ci.state = COL_IDLE;
   }
-  return MORX_OK;
+  return batch_upload(b, 0, nc, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -54,7 +54,8 @@ enum ColState : int32_t {
   COL_MAXIT = 3,       // iteration limit of the cycle reached
   COL_DONE = 4,        // true residuals passed
   COL_FAILED = 5,      // gave up (see host-side status)
-  COL_IDLE = 6         // not part of the current solve
+  COL_IDLE = 6,        // free slot
+  COL_INIT = 7         // filled slot waiting for its first initialisation
 };
 
 // ---------------------------------------------------------------------------
@@ -96,7 +97,7 @@ struct morx_factor_s {
   bool pooled = false;
 };
 
-struct Workspace;  // BiCG workspace (bicg.hip)
+struct KrylovBatch;  // BiCG slots (krylov.h)
 
 struct morx_system_s {
   morx_ctx ctx = nullptr;
@@ -128,7 +129,7 @@ struct morx_system_s {
   int32_t vertical_prec = -1;
   // recycled factor storage and BiCG workspace
   std::vector<morx_factor> factor_pool;
-  Workspace* ws = nullptr;
+  KrylovBatch* kb = nullptr;
   int64_t resident_bytes = 0;
 };
 
@@ -157,7 +158,7 @@ morx_status launch_factor_apply(morx_system sys, morx_factor f, bool trans, int 
                                 hipStream_t st);
 
 // bicg.hip
-void workspace_free(Workspace* ws);
+void krylov_batch_delete(KrylovBatch* kb);
 void trace_factor_begin(morx_ctx ctx, hipStream_t st, void** token);
 void trace_factor_end(morx_ctx ctx, hipStream_t st, void* token);
 

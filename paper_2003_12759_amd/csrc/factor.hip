@@ -368,6 +368,8 @@ morx_status factor_alloc(morx_system sys, int32_t prec, morx_factor* out) {
   k_fill_zero_bytes<<<(unsigned)((w1 + 255) / 256), 256, 0, st>>>((uint32_t*)f->vals.p, w1);
   k_fill_zero_bytes<<<(unsigned)((w2 + 255) / 256), 256, 0, st>>>((uint32_t*)f->valsT.p, w2);
   MORX_HIP(hipGetLastError());
+  // the factor may be built on another stream: the zeros must land first
+  MORX_HIP(hipStreamSynchronize(st));
   *out = f;
   return MORX_OK;
 }

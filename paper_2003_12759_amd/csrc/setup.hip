@@ -442,7 +442,7 @@ extern "C" morx_status morx_system_destroy(morx_system sys) {
     delete f;
   }
   sys->factor_pool.clear();
-  if (sys->ws) workspace_free(sys->ws);
+  if (sys->kb) krylov_batch_delete(sys->kb);
   for (auto& b : sys->owned) dev_free(b);
   delete sys;
   return MORX_OK;

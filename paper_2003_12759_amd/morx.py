@@ -56,6 +56,13 @@ class morx_trace_entry(ctypes.Structure):
                 ("total_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double)]
 
 
+class morx_serve_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("slots_per_system", ctypes.c_int32),
+                ("anchors", ctypes.c_int32), ("anchor_min", ctypes.c_double),
+                ("anchor_max", ctypes.c_double), ("segment_iters", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class MorxError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -87,6 +94,17 @@ _SIG = {
     "morx_project": (_i32, [_p, _i32, _p, _i64, _p, _i64, _i32, _p, _i64, _i32, _p, _i64,
                             ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
                             ctypes.POINTER(_d), _i32, _p]),
+    "morx_serve_config_default": (None, [ctypes.POINTER(morx_serve_config)]),
+    "morx_serve_start": (_i32, [_p, ctypes.POINTER(morx_serve_config), ctypes.POINTER(morx_opts),
+                                ctypes.POINTER(_p)]),
+    "morx_serve_submit": (_i32, [_p, _p, _d, _p, _p, ctypes.POINTER(ctypes.c_uint64)]),
+    "morx_serve_poll": (_i32, [_p, ctypes.c_uint64, ctypes.POINTER(morx_col_stats),
+                               ctypes.POINTER(_d)]),
+    "morx_serve_wait": (_i32, [_p, ctypes.c_uint64, ctypes.POINTER(morx_col_stats),
+                               ctypes.POINTER(_d)]),
+    "morx_serve_info": (_i32, [_p, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                               ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i64)]),
+    "morx_serve_stop": (_i32, [_p]),
     "morx_trace_enable": (_i32, [_p, _i32]),
     "morx_trace_read": (_i32, [_p, ctypes.POINTER(morx_trace_entry), _i32, ctypes.POINTER(_i32)]),
 }
@@ -299,3 +317,61 @@ def morx_trace_read(ctx: int):
     _check(_lib.morx_trace_read(ctx, buf, 16, ctypes.byref(cnt)), "morx_trace_read")
     return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms, buf[i].alg_bytes)
             for i in range(min(cnt.value, 16))}
+
+
+# ---------------------------------------------------------------------------
+# serving
+
+
+def morx_serve_config_default() -> morx_serve_config:
+    c = morx_serve_config()
+    _lib.morx_serve_config_default(ctypes.byref(c))
+    return c
+
+
+def morx_serve_start(ctx: int, cfg: Optional[morx_serve_config] = None,
+                     opts: Optional[morx_opts] = None) -> int:
+    cfg = cfg or morx_serve_config_default()
+    opts = opts or morx_opts_default()
+    h = _p()
+    _check(_lib.morx_serve_start(ctx, ctypes.byref(cfg), ctypes.byref(opts), ctypes.byref(h)),
+           "morx_serve_start")
+    return h.value
+
+
+def morx_serve_submit(srv: int, sys: int, sigma: float, b: torch.Tensor, x: torch.Tensor) -> int:
+    t = ctypes.c_uint64()
+    _check(_lib.morx_serve_submit(srv, sys, float(sigma), _dev(b, torch.float64, "b"),
+                                  _dev(x, torch.float64, "x"), ctypes.byref(t)),
+           "morx_serve_submit")
+    return t.value
+
+
+def _serve_take(fn, srv, ticket):
+    st = morx_col_stats()
+    lat = _d()
+    status = fn(srv, ticket, ctypes.byref(st), ctypes.byref(lat))
+    return status, st, lat.value
+
+
+def morx_serve_poll(srv: int, ticket: int):
+    """(status, morx_col_stats, latency_s); status -10 (pending) while running."""
+    return _serve_take(_lib.morx_serve_poll, srv, ticket)
+
+
+def morx_serve_wait(srv: int, ticket: int):
+    return _serve_take(_lib.morx_serve_wait, srv, ticket)
+
+
+def morx_serve_info(srv: int):
+    a, b = ctypes.c_uint64(), ctypes.c_uint64()
+    c, d = _i32(), _i32()
+    e = _i64()
+    _check(_lib.morx_serve_info(srv, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                ctypes.byref(d), ctypes.byref(e)), "morx_serve_info")
+    return {"submitted": a.value, "completed": b.value, "running": c.value, "queued": d.value,
+            "bytes_in_use": e.value}
+
+
+def morx_serve_stop(srv: int) -> None:
+    _check(_lib.morx_serve_stop(srv), "morx_serve_stop")
