@@ -29,7 +29,6 @@ if ROOT not in sys.path:
 
 METRIC = "shifted solves/sec to rel-res 1e-10 (batched vs plain); HBM GB/s; p99 lat"
 HBM_PEAK_GBPS = 8000.0
-WORKLOAD_INDEX = 1
 DOMINANT = "chain_step"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_chain_step_convdiff3d_n262144.json")
 
@@ -90,6 +89,113 @@ def cpu_baseline(w):
                       "single-threaded NumPy/SciPy"}
 
 
+def serving_bench(args):
+    """Serving workload: 16 resident systems, Poisson request stream.
+
+    First a closed-loop run (every request submitted at once) gives the
+    maximum throughput; then the stream is replayed with Poisson arrivals at
+    0.5, 0.8 and 1.0 of that rate and p50 / p99 latency (submit to result)
+    is reported.  A sample of results is checked against the true residual
+    on the host."""
+    import numpy as np
+    import scipy.sparse as sp
+    import threading
+    import torch
+
+    from paper_2003_12759_amd import api, morx
+    from paper_2003_12759_amd.workloads import make_serving_pool
+
+    pool = make_serving_pool(seed=0, nreq=args.requests)
+    ctx = api.Context(0)
+    systems = [api.System(ctx, A, e) for (A, e) in pool.systems]
+    nreq = args.requests
+    bs, xs = [], []
+    for t in range(nreq):
+        n = systems[pool.req_system[t]].n
+        g = torch.Generator(device="cuda")
+        g.manual_seed(int(pool.req_seed[t]) % (2**63))
+        bs.append(torch.randn(n, dtype=torch.float64, device="cuda", generator=g))
+        xs.append(torch.zeros(n, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    cfg = morx.morx_serve_config_default()
+    cfg.slots_per_system = args.slots
+    srv = morx.morx_serve_start(ctx.handle, cfg)
+    # anchors of every system are built on its first request (not timed)
+    # b and x must stay alive until the request is finished
+    warm_b = [torch.ones(S.n, dtype=torch.float64, device="cuda") for S in systems]
+    warm_x = [torch.zeros(S.n, dtype=torch.float64, device="cuda") for S in systems]
+    warm = [morx.morx_serve_submit(srv, S.handle, 10.0, b, x)
+            for S, b, x in zip(systems, warm_b, warm_x)]
+    for k in warm:
+        morx.morx_serve_wait(srv, k)
+
+    def run(times):
+        tickets = [None] * nreq
+        t0 = time.perf_counter()
+
+        def client():
+            for t in range(nreq):
+                if times is not None:
+                    delay = t0 + times[t] - time.perf_counter()
+                    if delay > 0:
+                        time.sleep(delay)
+                tickets[t] = morx.morx_serve_submit(srv, systems[pool.req_system[t]].handle,
+                                                    pool.req_sigma[t], bs[t], xs[t])
+
+        th = threading.Thread(target=client)
+        th.start()
+        th.join()
+        res = [morx.morx_serve_wait(srv, k) for k in tickets]
+        wall = time.perf_counter() - t0
+        bad = [t for t, r in enumerate(res) if r[0] != 0 or r[1].relres_primal > 1e-10]
+        if bad:
+            raise SystemExit(f"serving: {len(bad)} requests failed, e.g. {bad[:5]}")
+        lat = np.array([r[2] for r in res])
+        its = np.array([r[1].iters for r in res])
+        return wall, lat, its
+
+    wall, lat, its = run(None)
+    lam_max = nreq / wall
+    out = {"closed_loop": {"requests_per_s": round(lam_max, 2), "wall_s": round(wall, 3),
+                           "p50_s": round(float(np.percentile(lat, 50)), 4),
+                           "p99_s": round(float(np.percentile(lat, 99)), 4),
+                           "mean_iters": round(float(its.mean()), 1)}}
+    # host check of a sample of results against their true residuals
+    rng = np.random.default_rng(1)
+    for t in rng.choice(nreq, 16, replace=False):
+        A, e = pool.systems[pool.req_system[t]]
+        M = (pool.req_sigma[t] * sp.diags(e) - A).tocsr()
+        b, x = bs[t].cpu().numpy(), xs[t].cpu().numpy()
+        rr = np.linalg.norm(b - M @ x) / np.linalg.norm(b)
+        if rr > 1.01e-10:
+            raise SystemExit(f"serving: request {t} true residual {rr}")
+    loads = {}
+    for rho in args.loads:
+        times = np.cumsum(pool.gaps) / (rho * lam_max)
+        wall, lat, its = run(times)
+        loads[str(rho)] = {"offered_per_s": round(rho * lam_max, 2),
+                           "achieved_per_s": round(nreq / wall, 2),
+                           "p50_s": round(float(np.percentile(lat, 50)), 4),
+                           "p99_s": round(float(np.percentile(lat, 99)), 4)}
+    info = morx.morx_serve_info(srv)
+    morx.morx_serve_stop(srv)
+    hi = loads.get("0.8") or next(iter(loads.values()), out["closed_loop"])
+    line = {"metric": METRIC, "value": round(lam_max, 3), "unit": "solves/s", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": round(1e3 * out["closed_loop"]["wall_s"], 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "serving_pool16", "systems": len(systems),
+                       "n_range": [min(S.n for S in systems), max(S.n for S in systems)],
+                       "requests": nreq, "slots_per_system": args.slots, "anchors": cfg.anchors,
+                       "precond_storage": "f64", "tol": 1e-10, "mode": "continuous batching"},
+            "p50_s": hi["p50_s"], "p99_s": hi["p99_s"], "serving": out, "loads": loads,
+            "server_bytes": info["bytes_in_use"], "roofline": None, "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+    for S in systems:
+        S.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +206,15 @@ def main():
     ap.add_argument("--no-trace", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--workload", default="convdiff3d_n262144",
+                    choices=["convdiff3d_n262144", "laplace2d_n2025", "varcoef3d_n1191016_mimo4",
+                             "varcoef27_n2097152", "serving_pool16"])
+    ap.add_argument("--prec", default=None, choices=[None, "f64", "f32", "bf16"],
+                    help="factor storage precision (default: the workload's)")
+    ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
+    ap.add_argument("--slots", type=int, default=16, help="serving: slots per system")
+    ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 1.0],
+                    help="serving: offered loads as fractions of the closed-loop rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the path is one system per GPU); --gpus {args.gpus} "
@@ -111,7 +226,12 @@ def main():
     from paper_2003_12759_amd import api, morx
     from paper_2003_12759_amd.workloads import make_workload
 
-    w = make_workload(WORKLOAD_INDEX)
+    if args.workload == "serving_pool16":
+        serving_bench(args)
+        return
+    index = {"laplace2d_n2025": 0, "convdiff3d_n262144": 1, "varcoef3d_n1191016_mimo4": 2,
+             "varcoef27_n2097152": 4}[args.workload]
+    w = make_workload(index, prec=args.prec)
     nsolves = sum(len(r) for r in w.rounds) * w.B.shape[1]
     ctx = api.Context(0)
     S = api.System(ctx, w.A, w.e)
