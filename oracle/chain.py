@@ -16,9 +16,17 @@ factors.  The product is never formed (Section III-B): applying it to a
 vector means applying ``P_1^(1)`` first and ``Q_i^(z)`` last; its transpose
 applies the transposed factors in the reverse order.
 
-Pinned by: a hand-written expected schedule for three rounds, and the chain
-apply against the explicitly formed dense product on small matrices
-(tests/test_oracle_pins.py).
+Applying in FP32 (the mixed-precision form of the method's preconditioner,
+whose storage may already be FP32 or BF16) is defined here as: the input
+vector rounded to FP32, then every factor product formed in FP64 and its
+result rounded to FP32 before the next factor; the output is the last rounded
+vector.  The Krylov recurrences that consume it stay FP64.
+
+Pinned by: a hand-written expected schedule for three rounds, the chain
+apply against the explicitly formed dense product on small matrices, and for
+the FP32 apply: exact agreement with the FP64 apply when every intermediate
+is an FP32 number, a rounding-error bound per pass, and FP32-representable
+outputs (tests/test_oracle_pins.py).
 """
 from __future__ import annotations
 
@@ -55,17 +63,28 @@ def schedule(rounds: Sequence[Sequence[float]]):
     return specs, chains
 
 
-def apply(factors, chain: Sequence[int], v: np.ndarray) -> np.ndarray:
-    """``F_chain[-1] ( ... F_chain[1] (F_chain[0] v))``, factors never multiplied together."""
-    out = np.asarray(v, dtype=np.float64)
+def _to_apply(v: np.ndarray, apply_prec: str) -> np.ndarray:
+    if apply_prec == "f64":
+        return v
+    if apply_prec != "f32":
+        raise ValueError(apply_prec)
+    return v.astype(np.float32).astype(np.float64)
+
+
+def apply(factors, chain: Sequence[int], v: np.ndarray, apply_prec: str = "f64") -> np.ndarray:
+    """``F_chain[-1] ( ... F_chain[1] (F_chain[0] v))``, factors never multiplied together.
+
+    ``apply_prec="f32"`` rounds the input and every pass result to FP32."""
+    out = _to_apply(np.asarray(v, dtype=np.float64), apply_prec)
     for f in chain:
-        out = factors[f] @ out
+        out = _to_apply(factors[f] @ out, apply_prec)
     return out
 
 
-def apply_transpose(factors, chain: Sequence[int], v: np.ndarray) -> np.ndarray:
+def apply_transpose(factors, chain: Sequence[int], v: np.ndarray,
+                    apply_prec: str = "f64") -> np.ndarray:
     """Transpose of :func:`apply`: ``F_chain[0]^T ( ... (F_chain[-1]^T v))``."""
-    out = np.asarray(v, dtype=np.float64)
+    out = _to_apply(np.asarray(v, dtype=np.float64), apply_prec)
     for f in reversed(chain):
-        out = factors[f].T @ out
+        out = _to_apply(factors[f].T @ out, apply_prec)
     return out

@@ -33,9 +33,13 @@ def build_factors(A, e, specs, prec: str = "f64", columns=None):
 
 
 def run(A, e, B, C, rounds, prec: str = "f64", tol: float = 1e-10, want_dual: bool = True,
-        maxit=None, max_restarts: int = 3, project: bool = True, factors=None):
+        maxit=None, max_restarts: int = 3, project: bool = True, factors=None,
+        apply_prec: str = "f64"):
     """Return a dict with factor specs, factors, per-(round, shift, column)
-    solutions and stats, and the reduced model of each round."""
+    solutions and stats, and the reduced model of each round.
+
+    ``prec`` is the storage precision of the factor values, ``apply_prec``
+    the precision of the preconditioner apply (:func:`oracle.chain.apply`)."""
     A = sp.csr_matrix(A)
     n = A.shape[0]
     e = np.asarray(e, dtype=np.float64)
@@ -54,8 +58,8 @@ def run(A, e, B, C, rounds, prec: str = "f64", tol: float = 1e-10, want_dual: bo
             As = (float(s) * E - A).tocsr()
             AsT = As.T.tocsr()
             ch = chains[z][i]
-            P = lambda v, ch=ch: chain.apply(factors, ch, v)
-            PT = lambda v, ch=ch: chain.apply_transpose(factors, ch, v)
+            P = lambda v, ch=ch: chain.apply(factors, ch, v, apply_prec)
+            PT = lambda v, ch=ch: chain.apply_transpose(factors, ch, v, apply_prec)
             for j in range(B.shape[1]):
                 res = bicg.solve(lambda v: As @ v, lambda v: AsT @ v, B[:, j],
                                  C[:, j] if want_dual else None, P, PT, tol=tol,

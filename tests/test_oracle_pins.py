@@ -150,11 +150,76 @@ def test_chain_apply_matches_formed_product():
     assert np.allclose(chain.apply_transpose(fs, ch, v), dense.T @ v, rtol=1e-13, atol=1e-13)
 
 
-def test_bicg_matches_dense_lu_on_laplace2d_n2025():
+def test_chain_apply_f32_exact_when_every_pass_is_representable():
+    """Small-integer factors and input: every pass result is an FP32 number,
+    so the FP32 apply equals the FP64 apply bit for bit (both directions)."""
+    n = 20
+    rng = np.random.default_rng(31)
+    fs = []
+    for k in range(3):
+        F = sp.random(n, n, density=0.2, random_state=rng, format="csr")
+        F.data = rng.integers(-3, 4, F.nnz).astype(np.float64)
+        fs.append((F + sp.eye(n)).tocsr())
+    v = rng.integers(-5, 6, n).astype(np.float64)
+    ch = [1, 2, 0]
+    assert np.array_equal(chain.apply(fs, ch, v, "f32"), chain.apply(fs, ch, v))
+    assert np.array_equal(chain.apply_transpose(fs, ch, v, "f32"), chain.apply_transpose(fs, ch, v))
+
+
+def test_chain_apply_f32_rounds_input_each_pass_and_output():
+    """Hand-worked cases: 1 + 2^-30 is not an FP32 number and rounds to 1.
+    A difference of two such values scaled by 2^30 exposes where rounding
+    happens: at the input, after each pass, and after the last pass."""
+    t = 2.0 ** -30
+    I2 = sp.identity(2, format="csr")
+    D = sp.csr_matrix(sp.diags([1.0 + t, 1.0]))
+    K = sp.csr_matrix(np.array([[2.0 ** 30, -(2.0 ** 30)], [0.0, 1.0]]))
+    # input rounding: [1 + t, 1] -> [1, 1]
+    v = np.array([1.0 + t, 1.0])
+    assert np.array_equal(chain.apply([I2, K], [0, 1], v, "f32"), [0.0, 1.0])
+    assert np.array_equal(chain.apply([I2, K], [0, 1], v), [1.0, 1.0])
+    # rounding after an intermediate pass: D [1, 1] = [1 + t, 1] -> [1, 1]
+    one = np.array([1.0, 1.0])
+    assert np.array_equal(chain.apply([D, K], [0, 1], one, "f32"), [0.0, 1.0])
+    assert np.array_equal(chain.apply([D, K], [0, 1], one), [1.0, 1.0])
+    # and in the transposed chain, which applies K^T first and D^T last
+    KT = sp.csr_matrix(K.toarray().T)
+    assert np.array_equal(chain.apply_transpose([D, KT], [1, 0], one, "f32"), [0.0, 1.0])
+    # rounding of the last pass
+    assert np.array_equal(chain.apply([D], [0], one, "f32"), [1.0, 1.0])
+    assert chain.apply([D], [0], one)[0] == 1.0 + t
+
+
+def test_chain_apply_f32_error_bound():
+    """Random factors: each pass adds at most one FP32 rounding (relative
+    2^-24) on top of the propagated error, so the gap to the FP64 apply is
+    bounded by |F_k| applied to the previous bound plus 2^-24 |result|."""
+    n = 40
+    fs = [_rand_sparse(n, 0.1, 40 + k) for k in range(3)]
+    v = np.random.default_rng(41).standard_normal(n)
+    ch = [0, 1, 2]
+    u = 2.0 ** -24
+    got = chain.apply(fs, ch, v, "f32")
+    exact = chain.apply(fs, ch, v)
+    t = np.asarray(v, dtype=np.float64)
+    bound = u * np.abs(t)
+    for f in ch:
+        t = fs[f] @ t
+        bound = abs(fs[f]) @ bound + u * (np.abs(t) + abs(fs[f]) @ bound) + 1e-300
+    assert np.all(np.abs(got - exact) <= bound * 1.0001)
+    assert np.all(got.astype(np.float32).astype(np.float64) == got)
+    assert np.max(np.abs(got - exact)) > 0.0  # the rounding is really there
+
+
+@pytest.mark.parametrize("apply_prec", ["f64", "f32"])
+def test_bicg_matches_dense_lu_on_laplace2d_n2025(apply_prec):
     """All six shifts of the 45x45 workload, SPAI chain, tolerance 1e-10:
-    true residuals pass and ||x - x_LU|| <= ||A_s^{-1}|| (||r|| + rounding)."""
+    true residuals pass and ||x - x_LU|| <= ||A_s^{-1}|| (||r|| + rounding).
+    With an FP32-applied preconditioner the FP64 recurrences and the
+    true-residual refinement still reach the same bound."""
     w = make_workload(0)
-    out = job.run(w.A, w.e, w.B, w.C, w.rounds, prec="f64", tol=1e-10, project=False)
+    out = job.run(w.A, w.e, w.B, w.C, w.rounds, prec="f64", tol=1e-10, project=False,
+                  apply_prec=apply_prec)
     Ad = w.A.toarray()
     for i, s in enumerate(w.rounds[0]):
         st = out["rounds"][0]["stats"][i]
