@@ -44,11 +44,19 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def run_job(S, w, Bd, Cd, batched: bool, use_graph: bool = True):
+def default_apply(prec: str) -> str:
+    """Apply precision used unless --apply says otherwise: FP64 vectors for
+    every storage precision (FP32 and BF16 factor values are widened as they
+    are loaded).  Rounding the chain's vectors to FP32 costs far more BiCG
+    iterations at 64^3 than it saves in bytes."""
+    return "f64"
+
+
+def run_job(S, w, Bd, Cd, batched: bool, apply: str, use_graph: bool = True):
     stats_all = []
     for z, sig in enumerate(w.rounds):
         X, Y, st, stats = S.solve_shifts(sig, Bd, Cd, prec=w.prec, tol=w.tol, batched=batched,
-                                         next_round=z > 0, use_graph=use_graph)
+                                         next_round=z > 0, use_graph=use_graph, apply=apply)
         S.project(X, Y, Bd, Cd)
         stats_all.extend(stats)
     return stats_all
@@ -61,7 +69,7 @@ def check(stats, tol):
         raise SystemExit(f"accuracy check failed: {bad[:5]}")
 
 
-def cpu_baseline(w):
+def cpu_baseline(w, apply):
     """Oracle on one factor build + one pair solve (round 1, shift 1)."""
     import numpy as np
     import scipy.sparse as sp
@@ -79,12 +87,13 @@ def cpu_baseline(w):
         As = (s * sp.diags(w.e) - w.A).tocsr()
         AsT = As.T.tocsr()
         res = obicg.solve(lambda v: As @ v, lambda v: AsT @ v, w.B[:, 0], w.C[:, 0],
-                          lambda v: ochain.apply(factors, [0], v),
-                          lambda v: ochain.apply_transpose(factors, [0], v), tol=w.tol)
+                          lambda v: ochain.apply(factors, [0], v, apply),
+                          lambda v: ochain.apply_transpose(factors, [0], v, apply), tol=w.tol)
         dt = time.perf_counter() - t0
     assert res.status == "ok"
     return {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"one SPAI factor build (n={w.n}, FP32 storage) + one primal+dual "
+            "sample": f"one SPAI factor build (n={w.n}, {w.prec.upper()} storage, "
+                      f"{apply.upper()} apply) + one primal+dual "
                       f"BiCG pair solve to 1e-10 ({res.iters} iterations), {dt:.1f} s, "
                       "single-threaded NumPy/SciPy"}
 
@@ -119,7 +128,12 @@ def serving_bench(args):
     torch.cuda.synchronize()
     cfg = morx.morx_serve_config_default()
     cfg.slots_per_system = args.slots
-    srv = morx.morx_serve_start(ctx.handle, cfg)
+    prec = args.prec or "f32"
+    apply = args.apply or default_apply(prec)
+    opts = morx.morx_opts_default()
+    opts.precond_prec = morx.PREC[prec]
+    opts.apply_prec = morx.PREC[apply]
+    srv = morx.morx_serve_start(ctx.handle, cfg, opts)
     # anchors of every system are built on its first request (not timed)
     # b and x must stay alive until the request is finished
     warm_b = [torch.ones(S.n, dtype=torch.float64, device="cuda") for S in systems]
@@ -187,7 +201,8 @@ def serving_bench(args):
             "config": {"workload": "serving_pool16", "systems": len(systems),
                        "n_range": [min(S.n for S in systems), max(S.n for S in systems)],
                        "requests": nreq, "slots_per_system": args.slots, "anchors": cfg.anchors,
-                       "precond_storage": "f64", "tol": 1e-10, "mode": "continuous batching"},
+                       "precond_storage": prec, "precond_apply": apply, "krylov": "f64",
+                       "tol": 1e-10, "mode": "continuous batching"},
             "p50_s": hi["p50_s"], "p99_s": hi["p99_s"], "serving": out, "loads": loads,
             "server_bytes": info["bytes_in_use"], "roofline": None, "cpu_baseline": None}
     print(json.dumps(line), flush=True)
@@ -211,6 +226,8 @@ def main():
                              "varcoef27_n2097152", "serving_pool16"])
     ap.add_argument("--prec", default=None, choices=[None, "f64", "f32", "bf16"],
                     help="factor storage precision (default: the workload's)")
+    ap.add_argument("--apply", default=None, choices=[None, "f64", "f32"],
+                    help="preconditioner apply precision (default: FP64)")
     ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=16, help="serving: slots per system")
     ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 1.0],
@@ -232,6 +249,7 @@ def main():
     index = {"laplace2d_n2025": 0, "convdiff3d_n262144": 1, "varcoef3d_n1191016_mimo4": 2,
              "varcoef27_n2097152": 4}[args.workload]
     w = make_workload(index, prec=args.prec)
+    apply = args.apply or default_apply(w.prec)
     nsolves = sum(len(r) for r in w.rounds) * w.B.shape[1]
     ctx = api.Context(0)
     S = api.System(ctx, w.A, w.e)
@@ -240,31 +258,43 @@ def main():
     torch.cuda.synchronize()
 
     for _ in range(args.warmup):
-        check(run_job(S, w, Bd, Cd, batched=True), w.tol)
+        check(run_job(S, w, Bd, Cd, batched=True, apply=apply), w.tol)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     last = None
     for _ in range(args.steps):
-        last = run_job(S, w, Bd, Cd, batched=True)
+        last = run_job(S, w, Bd, Cd, batched=True, apply=apply)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     check(last, w.tol)
     value = nsolves * args.steps / dt
+    iters = sum(st.iters for st in last)
+
+    def timed(batched, ap_, steps):
+        run_job(S, w, Bd, Cd, batched=batched, apply=ap_)  # first call sizes the slot batch
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            st_ = run_job(S, w, Bd, Cd, batched=batched, apply=ap_)
+        torch.cuda.synchronize()
+        check(st_, w.tol)
+        return nsolves * steps / (time.perf_counter() - t1), sum(x.iters for x in st_)
+
+    # the same batched job with the preconditioner applied in FP64
+    f64_apply = None
+    if apply != "f64" and args.plain_steps > 0:
+        v64, it64 = timed(True, "f64", 1)
+        f64_apply = {"value": round(v64, 3), "unit": "solves/s", "iters_per_step": it64,
+                     "mode": "batched multi-shift, preconditioner applied in FP64"}
 
     plain_value = None
     if args.plain_steps > 0:
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.plain_steps):
-            pst = run_job(S, w, Bd, Cd, batched=False)
-        torch.cuda.synchronize()
-        check(pst, w.tol)
-        plain_value = nsolves * args.plain_steps / (time.perf_counter() - t1)
+        plain_value, plain_iters = timed(False, "f64", args.plain_steps)
 
     roofline, kernels = None, None
     if not args.no_trace:
         morx.morx_trace_enable(ctx.handle, True)
-        check(run_job(S, w, Bd, Cd, batched=True), w.tol)
+        check(run_job(S, w, Bd, Cd, batched=True, apply=apply), w.tol)
         tr = morx.morx_trace_read(ctx.handle)
         morx.morx_trace_enable(ctx.handle, False)
         kernels = {}
@@ -284,11 +314,12 @@ def main():
             if tf.get("source_sha256") == kernel_source_hash():
                 traffic = tf.get("bytes_per_launch")
         ncol = len(w.rounds[0]) * w.B.shape[1]
+        ctype = {"f64": "double", "f32": "float", "bf16": "unsigned short"}
         chunks = -(-ncol // 8)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                     "traffic": traffic,
-                    "kernel": f"k_chain_step<{ {'f64': 'double', 'f32': 'float', 'bf16': 'unsigned short'}[w.prec]}, {-(-ncol // chunks)}>",
+                    "kernel": f"k_chain_step<{ctype[w.prec]}, {ctype[apply]}, {-(-ncol // chunks)}>",
                     "avg_launch_us": round(1e3 * ms / launches, 2),
                     "alg_bytes_per_launch": byts / launches}
 
@@ -301,7 +332,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(w)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(w, apply)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1,
@@ -310,10 +341,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "nnz": w.nnz, "shifts_per_round": len(w.rounds[0]),
                    "rounds": len(w.rounds), "solves_per_step": nsolves, "precond_storage": w.prec,
-                   "tol": w.tol, "mode": "batched multi-shift", "parallelism": "single GPU"},
+                   "precond_apply": apply, "krylov": "f64", "tol": w.tol,
+                   "mode": "batched multi-shift", "parallelism": "single GPU"},
+        "iters_per_step": iters,
+        "batched_f64_apply": f64_apply,
         "plain": None if plain_value is None else {"value": round(plain_value, 3),
                                                     "unit": "solves/s",
-                                                    "mode": "one shift, one column at a time"},
+                                                    "iters_per_step": plain_iters,
+                                                    "mode": "one shift, one column at a time, "
+                                                            "preconditioner applied in FP64"},
         "batched_over_plain": None if plain_value is None else round(value / plain_value, 3),
         "roofline": roofline,
         "kernels": kernels,

@@ -83,7 +83,12 @@ typedef struct {
                             0: one shift and one column at a time (1)              */
   int32_t poll_iters;    /* iterations between host convergence checks (8)          */
   int32_t use_graph;     /* 1: replay the iteration segment as a HIP graph (1)      */
-  int32_t reserved;
+  int32_t apply_prec;    /* morx_prec of the preconditioner apply (MORX_F64):
+                            MORX_F32 rounds the input of the chain and the result
+                            of every factor pass to FP32 (each pass sums in FP64);
+                            the operator, the BiCG recurrences, the residual
+                            tests and the refinement stay FP64.  MORX_BF16 is
+                            rejected with MORX_E_INVALID.                          */
 } morx_opts;
 
 /* Per-column result.  status is a morx_status. */

@@ -75,8 +75,11 @@ class System:
     def solve_shifts(self, sigmas: Sequence[float], B, C=None, prec: str = "f64", tol: float = 1e-10,
                      batched: bool = True, next_round: bool = False, use_graph: bool = True,
                      poll_iters: int = 8, maxit: int = 0, max_restarts: int = 3,
-                     raise_on_error: bool = True):
-        """Returns (X, Y, status, stats); X, Y are column-major (n, m*nshift) tensors."""
+                     raise_on_error: bool = True, apply: str = "f64"):
+        """Returns (X, Y, status, stats); X, Y are column-major (n, m*nshift) tensors.
+
+        ``prec`` is the storage precision of the factor values, ``apply`` the
+        precision of the preconditioner apply ("f64" or "f32")."""
         Bd = B if isinstance(B, torch.Tensor) else block_to_dev(B, self.device)
         Cd = None
         if C is not None:
@@ -95,6 +98,7 @@ class System:
         o.poll_iters = poll_iters
         o.maxit = maxit
         o.max_restarts = max_restarts
+        o.apply_prec = morx.PREC[apply]
         st, stats = morx.morx_solve_shifts(self.handle, sigmas, Bd, Cd, X, Y, o,
                                            raise_on_error=raise_on_error)
         return X, Y, st, stats

@@ -31,10 +31,13 @@
 
 #include "krylov.h"
 
-enum Vec : int {
-  V_X, V_XT, V_R, V_RT, V_P0, V_P1, V_PT0, V_PT1, V_Z, V_ZT, V_Q, V_QT,
-  V_T0, V_T1, V_TT0, V_TT1, kNumVec
-};
+// FP64 Krylov vectors of a slot
+enum Vec : int { V_X, V_XT, V_R, V_RT, V_P0, V_P1, V_PT0, V_PT1, V_Q, V_QT, kNumVec };
+// vectors of the preconditioner apply, in the apply precision: z, z~, the
+// ping-pong intermediates of both chains and (FP32 apply only) the rounded
+// copies of r, r~ that the first factor pass reads
+enum ApplyVec : int { A_Z, A_ZT, A_T0, A_T1, A_TT0, A_TT1, A_R, A_RT };
+static int apply_vecs(int aprec) { return aprec == MORX_F64 ? 6 : 8; }
 
 // trace counters (algorithmic bytes per kernel class)
 enum TraceClass : int { TR_CHAIN = 0, TR_SPMV = 1, TR_UPDATE = 2, TR_FACTOR = 3, kTraceClasses = 8 };
@@ -60,6 +63,8 @@ struct IterArgs {
   const int32_t *off, *col, *offT, *colT;
   const double *valA, *valAT, *e;
   double* vec;
+  void* avec;    // apply vectors (element type double or float)
+  int abytes;    // 8 or 4
   ColInfo* cols;
   const void* const* ftab;  // [2][cap][lcap]: factor values, forward then transposed order
   double* part_rho;    // [3][cap][nblk]
@@ -70,6 +75,20 @@ struct IterArgs {
 
 __device__ __forceinline__ double* vptr(const IterArgs& a, int slot, int c) {
   return a.vec + ((int64_t)slot * a.cap + c) * a.ld;
+}
+
+template <typename AT>
+__device__ __forceinline__ AT* aptr(const IterArgs& a, int slot, int c) {
+  return (AT*)a.avec + ((int64_t)slot * a.cap + c) * a.ld;
+}
+
+// the FP32 copies of r and r~ (apply precision FP32 only)
+__device__ __forceinline__ void store_rcopy(const IterArgs& a, int c, int64_t i, double ri,
+                                            double rti) {
+  if (a.abytes == 4) {
+    aptr<float>(a, A_R, c)[i] = (float)ri;
+    aptr<float>(a, A_RT, c)[i] = (float)rti;
+  }
 }
 
 struct WaveCtx {
@@ -171,29 +190,31 @@ __device__ __forceinline__ void load_chunk(const int32_t* __restrict__ col,
   }
 }
 
+template <typename XT>
 __device__ __forceinline__ double chunk_dot(const SliceChunk& ch, const double (&v)[kUnroll],
-                                            int32_t m0, int32_t w, const double* __restrict__ x,
+                                            int32_t m0, int32_t w, const XT* __restrict__ x,
                                             double acc) {
   double g[kUnroll];
 #pragma unroll
-  for (int u = 0; u < kUnroll; ++u) g[u] = x[ch.c[u]];
+  for (int u = 0; u < kUnroll; ++u) g[u] = (double)x[ch.c[u]];
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) acc = (m0 + u < w) ? fma(v[u], g[u], acc) : acc;
   return acc;
 }
 
 // the same with p = z + beta * p_old formed at every gathered index
+template <typename AT>
 __device__ __forceinline__ double chunk_dot_p(const SliceChunk& ch, const double (&v)[kUnroll],
-                                              int32_t m0, int32_t w, const double* __restrict__ z,
+                                              int32_t m0, int32_t w, const AT* __restrict__ z,
                                               const double* __restrict__ po, double beta,
                                               bool first, double acc) {
   double g[kUnroll];
   if (first) {
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) g[u] = z[ch.c[u]];
+    for (int u = 0; u < kUnroll; ++u) g[u] = (double)z[ch.c[u]];
   } else {
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) g[u] = fma(beta, po[ch.c[u]], z[ch.c[u]]);
+    for (int u = 0; u < kUnroll; ++u) g[u] = fma(beta, po[ch.c[u]], (double)z[ch.c[u]]);
   }
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) acc = (m0 + u < w) ? fma(v[u], g[u], acc) : acc;
@@ -227,6 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_init(IterArgs a) {
       vptr(a, V_XT, c)[i] = 0.0;
       vptr(a, V_R, c)[i] = bi;
       vptr(a, V_RT, c)[i] = cv;
+      store_rcopy(a, c, i, bi, cv);
       v[j][0] = fma(bi, bi, v[j][0]);
       v[j][1] = fma(cv, cv, v[j][1]);
     }
@@ -255,7 +277,17 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_init(IterArgs a) {
 // maxL-1-s transposed on the rows of S^T; the last step also forms the
 // partial sums of rho = z~^T r, ||z~||^2, ||r||^2.  Columns whose chains
 // share a factor share its value loads.
-template <typename VT, int NC>
+// AT is the apply precision: each pass sums in FP64 and stores its result
+// rounded to AT; with AT = float the first pass reads the FP32 copy of r.
+template <typename AT>
+__device__ __forceinline__ const AT* chain_input(const IterArgs& a, int c, bool bwd) {
+  if constexpr (sizeof(AT) == 8)
+    return (const AT*)vptr(a, bwd ? V_RT : V_R, c);
+  else
+    return aptr<AT>(a, bwd ? A_RT : A_R, c);
+}
+
+template <typename VT, typename AT, int NC>
 __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s, int do_rho) {
   const WaveCtx t = wave_ctx(a);
   const int c0 = blockIdx.y * NC;
@@ -263,8 +295,8 @@ __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s, int do
   const int jf = bwd ? a.maxL - 1 - s : s;  // chain position applied by this half
   const bool rho_half = bwd && do_rho;
   unsigned valid = 0;
-  const double* src[NC];
-  double* dst[NC];
+  const AT* src[NC];
+  AT* dst[NC];
   const VT* fv[NC];
 #pragma unroll
   for (int j = 0; j < NC; ++j) {
@@ -275,12 +307,12 @@ __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s, int do
     if (on) valid |= 1u << j;
     fv[j] = on ? (const VT*)a.ftab[((int64_t)(bwd ? a.cap : 0) + c) * a.lcap + jf] : nullptr;
     if (!bwd) {
-      src[j] = (jf == 0) ? vptr(a, V_R, c) : vptr(a, V_T0 + ((jf - 1) & 1), c);
-      dst[j] = (jf == L - 1) ? vptr(a, V_Z, c) : vptr(a, V_T0 + (jf & 1), c);
+      src[j] = (jf == 0) ? chain_input<AT>(a, c, false) : aptr<AT>(a, A_T0 + ((jf - 1) & 1), c);
+      dst[j] = (jf == L - 1) ? aptr<AT>(a, A_Z, c) : aptr<AT>(a, A_T0 + (jf & 1), c);
     } else {
       const int k = max(L - 1 - jf, 0);  // transposed factors this column applied before
-      src[j] = (k == 0) ? vptr(a, V_RT, c) : vptr(a, V_TT0 + ((k - 1) & 1), c);
-      dst[j] = (jf == 0) ? vptr(a, V_ZT, c) : vptr(a, V_TT0 + (k & 1), c);
+      src[j] = (k == 0) ? chain_input<AT>(a, c, true) : aptr<AT>(a, A_TT0 + ((k - 1) & 1), c);
+      dst[j] = (jf == 0) ? aptr<AT>(a, A_ZT, c) : aptr<AT>(a, A_TT0 + (k & 1), c);
     }
   }
   double v[NC][3];
@@ -322,11 +354,13 @@ __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s, int do
 #pragma unroll
         for (int j = 0; j < NC; ++j)
           if (valid & (1u << j)) {
-            dst[j][i] = acc[j];
+            const AT zs = (AT)acc[j];
+            dst[j][i] = zs;
             if (rho_half) {
+              const double zi = (double)zs;
               const double ri = vptr(a, V_R, c0 + j)[i];
-              v[j][0] = fma(acc[j], ri, v[j][0]);
-              v[j][1] = fma(acc[j], acc[j], v[j][1]);
+              v[j][0] = fma(zi, ri, v[j][0]);
+              v[j][1] = fma(zi, zi, v[j][1]);
               v[j][2] = fma(ri, ri, v[j][2]);
             }
           }
@@ -379,14 +413,17 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(IterArgs a) {
     // algorithmic bytes of this iteration's chain launches and of spmv_pair
     const double n = (double)a.n, nnz = (double)a.nnzS;
     const double mat = (double)(a.vbytes + 4) * nnz + 4.0 * (n + 1.0);
+    const double ab = (double)a.abytes;
     if (chain_cols > 0.0) {
       // maxL factor passes per direction; per (column, factor, direction) one
       // n-vector read and one written; r read once per column for rho
-      a.trace[TR_CHAIN] += 2.0 * a.maxL * mat + 2.0 * 16.0 * n * chain_cols + 8.0 * n * act_cols;
+      a.trace[TR_CHAIN] += 2.0 * a.maxL * mat + 2.0 * 2.0 * ab * n * chain_cols + 8.0 * n * act_cols;
     }
     if (vec_cols > 0.0) {
+      // per column: z, z~ read; p, p~ read (not on a cycle's first step) and
+      // written; q, q~ written
       const double amat = 2.0 * (12.0 * nnz + 4.0 * (n + 1.0)) + 8.0 * n;
-      a.trace[TR_SPMV] += amat + 64.0 * n * vec_cols - 16.0 * n * first_cols;
+      a.trace[TR_SPMV] += amat + (2.0 * ab + 48.0) * n * vec_cols - 16.0 * n * first_cols;
     }
   }
 }
@@ -394,7 +431,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(IterArgs a) {
 // p = z + beta p, p~ = z~ + beta p~ (formed on the fly at every gathered
 // index), q = (sigma E - A) p, q~ = (sigma E - A)^T p~, partial sums of
 // delta = p~^T q, ||p~||^2, ||q||^2
-template <int NC>
+template <typename AT, int NC>
 __global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
   const WaveCtx t = wave_ctx(a);
   const int c0 = blockIdx.y * NC;
@@ -429,7 +466,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
 #pragma unroll
           for (int j = 0; j < NC; ++j)
             if (valid & (1u << j))
-              acc[j] = chunk_dot_p(ch, vv, m0, w, vptr(a, V_Z, c0 + j),
+              acc[j] = chunk_dot_p(ch, vv, m0, w, aptr<AT>(a, A_Z, c0 + j),
                                    vptr(a, V_P0 + (par ^ 1), c0 + j), beta[j], first[j], acc[j]);
         }
       }
@@ -443,7 +480,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
 #pragma unroll
           for (int j = 0; j < NC; ++j)
             if (valid & (1u << j))
-              acct[j] = chunk_dot_p(ch, vv, m0, w, vptr(a, V_ZT, c0 + j),
+              acct[j] = chunk_dot_p(ch, vv, m0, w, aptr<AT>(a, A_ZT, c0 + j),
                                     vptr(a, V_PT0 + (par ^ 1), c0 + j), beta[j], first[j], acct[j]);
         }
       }
@@ -453,7 +490,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
         for (int j = 0; j < NC; ++j)
           if (valid & (1u << j)) {
             const int c = c0 + j;
-            const double zi = vptr(a, V_Z, c)[i], zti = vptr(a, V_ZT, c)[i];
+            const double zi = (double)aptr<AT>(a, A_Z, c)[i];
+            const double zti = (double)aptr<AT>(a, A_ZT, c)[i];
             const double pi = first[j] ? zi : fma(beta[j], vptr(a, V_P0 + (par ^ 1), c)[i], zi);
             const double pti = first[j] ? zti : fma(beta[j], vptr(a, V_PT0 + (par ^ 1), c)[i], zti);
             const double se = sig[j] * ei;
@@ -500,7 +538,9 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_delta(IterArgs a) {
   }
   if (!a.trace) return;
   __syncthreads();
-  if (threadIdx.x == 0) a.trace[TR_UPDATE] += 96.0 * (double)a.n * upd_cols;
+  // x, x~, r, r~ read and written, p, p~, q, q~ read (+ the FP32 copies of r, r~)
+  const double rcopy = a.abytes == 4 ? 8.0 : 0.0;
+  if (threadIdx.x == 0) a.trace[TR_UPDATE] += (96.0 + rcopy) * (double)a.n * upd_cols;
 }
 
 // x += alpha p, x~ += alpha p~, r -= alpha q, r~ -= alpha q~; partial norms
@@ -536,6 +576,7 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a, int par) {
       const double rti = fma(-al[j], vptr(a, V_QT, c)[i], rt[i]);
       r[i] = ri;
       rt[i] = rti;
+      store_rcopy(a, c, i, ri, rti);
       v[j][0] = fma(ri, ri, v[j][0]);
       v[j][1] = fma(rti, rti, v[j][1]);
     }
@@ -598,6 +639,7 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(IterArgs a) {
           const double rti = ci.csrc[i] - fma(se, vptr(a, V_XT, c)[i], -acct[j]);
           vptr(a, V_R, c)[i] = ri;
           vptr(a, V_RT, c)[i] = rti;
+          store_rcopy(a, c, i, ri, rti);
           v[j][0] = fma(ri, ri, v[j][0]);
           v[j][1] = fma(rti, rti, v[j][1]);
         }
@@ -841,6 +883,7 @@ void batch_free(KrylovBatch& b) {
   }
   b.graphs.clear();
   dev_free(b.vec);
+  dev_free(b.avec);
   dev_free(b.cols);
   dev_free(b.part);
   dev_free(b.ftab);
@@ -857,15 +900,25 @@ void krylov_batch_delete(KrylovBatch* kb) {
   delete kb;
 }
 
-morx_status batch_alloc(KrylovBatch& b, morx_system sys, int cap, int lcap, int prec,
+size_t batch_bytes(morx_system sys, int cap, int aprec) {
+  const size_t ld = (size_t)sys->n_pad;
+  return (size_t)kNumVec * cap * ld * sizeof(double) +
+         (size_t)apply_vecs(aprec) * cap * ld * prec_bytes(aprec) +
+         (size_t)8 * cap * kMaxBlocks * sizeof(double);
+}
+
+morx_status batch_alloc(KrylovBatch& b, morx_system sys, int cap, int lcap, int prec, int aprec,
                         hipStream_t st) {
   batch_free(b);
   b.sys = sys;
   b.cap = cap;
   b.lcap = lcap;
   b.prec = prec;
+  b.aprec = aprec;
   b.ld = sys->n_pad;
   morx_status s = dev_alloc(b.vec, (size_t)kNumVec * cap * b.ld * sizeof(double));
+  if (s == MORX_OK)
+    s = dev_alloc(b.avec, (size_t)apply_vecs(aprec) * cap * b.ld * prec_bytes(aprec));
   if (s == MORX_OK) s = dev_alloc(b.cols, (size_t)cap * sizeof(ColInfo));
   if (s == MORX_OK) s = dev_alloc(b.part, (size_t)8 * cap * kMaxBlocks * sizeof(double));
   if (s == MORX_OK) s = dev_alloc(b.ftab, (size_t)2 * cap * lcap * sizeof(void*));
@@ -887,6 +940,8 @@ morx_status batch_alloc(KrylovBatch& b, morx_system sys, int cap, int lcap, int 
   memset(b.hftab, 0, (size_t)2 * cap * lcap * sizeof(void*));
   const int64_t cnt = (int64_t)(b.vec.bytes / sizeof(double));
   k_zero<<<(unsigned)((cnt + 255) / 256), 256, 0, st>>>((double*)b.vec.p, cnt);
+  const int64_t acnt = (int64_t)(b.avec.bytes / sizeof(double));
+  k_zero<<<(unsigned)((acnt + 255) / 256), 256, 0, st>>>((double*)b.avec.p, acnt);
   MORX_HIP(hipGetLastError());
   MORX_HIP(hipMemcpyAsync(b.cols.p, b.hcols, (size_t)cap * sizeof(ColInfo), hipMemcpyHostToDevice, st));
   MORX_HIP(hipMemcpyAsync(b.ftab.p, b.hftab, (size_t)2 * cap * lcap * sizeof(void*),
@@ -939,6 +994,8 @@ static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   a.valAT = sys->sellT_val;
   a.e = sys->e;
   a.vec = (double*)b.vec.p;
+  a.avec = b.avec.p;
+  a.abytes = (int)prec_bytes(b.aprec);
   a.cols = (ColInfo*)b.cols.p;
   a.ftab = (const void* const*)b.ftab.p;
   double* part = (double*)b.part.p;
@@ -975,7 +1032,7 @@ static dim3 grid_of(const IterArgs& a, int ncv, int halves) {
 // The maxL chain launches of an iteration run back to back; when tracing, one
 // event pair brackets the whole run and counts maxL launches, so the event
 // overhead is spread over the run instead of added to every launch.
-template <typename VT, int NC>
+template <typename VT, typename AT, int NC>
 static void enqueue_chain(const IterArgs& a, hipStream_t st, TraceState* t) {
   const dim3 g = grid_of(a, NC, 2);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -985,25 +1042,33 @@ static void enqueue_chain(const IterArgs& a, hipStream_t st, TraceState* t) {
     if (e0) hipEventRecord(e0, st);
   }
   for (int s = 0; s < a.maxL; ++s)
-    k_chain_step<VT, NC><<<g, kBlock, 0, st>>>(a, s, s == a.maxL - 1 ? 1 : 0);
+    k_chain_step<VT, AT, NC><<<g, kBlock, 0, st>>>(a, s, s == a.maxL - 1 ? 1 : 0);
   if (t && e0 && e1) {
     hipEventRecord(e1, st);
     t->pending.push_back({TR_CHAIN, e0, e1, a.maxL});
   }
 }
 
+template <typename AT, int NC>
+static void enqueue_chain_prec(const IterArgs& a, int prec, hipStream_t st, TraceState* t) {
+  if (prec == MORX_F64) enqueue_chain<double, AT, NC>(a, st, t);
+  else if (prec == MORX_F32) enqueue_chain<float, AT, NC>(a, st, t);
+  else enqueue_chain<uint16_t, AT, NC>(a, st, t);
+}
+
 static morx_status enqueue_iterations(const IterArgs& a, int prec, int iters, hipStream_t st,
                                       TraceState* t) {
   const int ncv = pick_nc(a.nc);
+  const bool f32 = a.abytes == 4;
   for (int it = 0; it < iters; ++it) {
     const int par = it & 1;
     MORX_NC_DISPATCH(ncv, {
       const dim3 g1 = grid_of(a, NC, 1);
-      if (prec == MORX_F64) enqueue_chain<double, NC>(a, st, t);
-      else if (prec == MORX_F32) enqueue_chain<float, NC>(a, st, t);
-      else enqueue_chain<uint16_t, NC>(a, st, t);
+      if (f32) enqueue_chain_prec<float, NC>(a, prec, st, t);
+      else enqueue_chain_prec<double, NC>(a, prec, st, t);
       k_fin_rho<<<1, kFinThreads, 0, st>>>(a);
-      launch(t, TR_SPMV, k_spmv_pair<NC>, g1, dim3(kBlock), st, a, par);
+      if (f32) launch(t, TR_SPMV, k_spmv_pair<float, NC>, g1, dim3(kBlock), st, a, par);
+      else launch(t, TR_SPMV, k_spmv_pair<double, NC>, g1, dim3(kBlock), st, a, par);
       k_fin_delta<<<1, kFinThreads, 0, st>>>(a);
       // elementwise: one column per wave, nothing to share between columns
       launch(t, TR_UPDATE, k_update<1>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
@@ -1094,6 +1159,7 @@ struct BatchCol {
 static morx_status solve_batch(morx_system sys, std::vector<BatchCol>& cols,
                                const std::vector<morx_factor>& G, int prec, const morx_opts& o,
                                hipStream_t st) {
+  const int aprec = o.apply_prec;
   const int nc = (int)cols.size();
   if (nc == 0) return MORX_OK;
   int maxL = 0;
@@ -1101,9 +1167,9 @@ static morx_status solve_batch(morx_system sys, std::vector<BatchCol>& cols,
   MORX_REQUIRE(maxL >= 1 && maxL <= (int)G.size(), MORX_E_INVALID, "bad chain length");
   if (!sys->kb) sys->kb = new KrylovBatch();
   KrylovBatch& b = *sys->kb;
-  if (b.cap < nc || b.lcap < maxL || b.prec != prec || b.ld != sys->n_pad) {
+  if (b.cap < nc || b.lcap < maxL || b.prec != prec || b.aprec != aprec || b.ld != sys->n_pad) {
     MORX_HIP(hipStreamSynchronize(st));
-    MORX_TRY(batch_alloc(b, sys, std::max(nc, b.cap), std::max(maxL, b.lcap), prec, st));
+    MORX_TRY(batch_alloc(b, sys, std::max(nc, b.cap), std::max(maxL, b.lcap), prec, aprec, st));
   }
   TraceState* t = trace_state_if_on(sys->ctx);
   const int maxit = o.maxit > 0 ? o.maxit : (int)std::min<int64_t>(sys->n, 20000);
@@ -1367,6 +1433,8 @@ extern "C" morx_status morx_solve_shifts(morx_system sys, int32_t nshift, const 
                "morx_solve_shifts: want_dual needs C and Y");
   MORX_REQUIRE(o.precond_prec >= MORX_F64 && o.precond_prec <= MORX_BF16, MORX_E_INVALID,
                "morx_solve_shifts: bad precision");
+  MORX_REQUIRE(o.apply_prec == MORX_F64 || o.apply_prec == MORX_F32, MORX_E_INVALID,
+               "morx_solve_shifts: apply precision must be MORX_F64 or MORX_F32");
   MORX_REQUIRE(o.tol >= 0.0 && o.max_restarts >= 0, MORX_E_INVALID,
                "morx_solve_shifts: bad tolerance or restart limit");
   for (int i = 0; i < nshift; ++i)

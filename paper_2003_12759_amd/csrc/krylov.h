@@ -33,9 +33,10 @@ struct KrylovBatch {
   morx_system sys = nullptr;
   int cap = 0;        // column slots
   int lcap = 0;       // longest chain a slot may hold
-  int prec = MORX_F64;
+  int prec = MORX_F64;   // factor storage
+  int aprec = MORX_F64;  // preconditioner apply (MORX_F64 or MORX_F32)
   int64_t ld = 0;
-  DevBuf vec, cols, part, ftab;
+  DevBuf vec, avec, cols, part, ftab;
   ColInfo* hcols = nullptr;     // pinned host mirror of the slots
   const void** hftab = nullptr;  // pinned host mirror: [2][cap][lcap]
   // graphs of one iteration segment, cached per (chain length, segment length)
@@ -47,8 +48,10 @@ struct KrylovBatch {
   std::vector<Seg> graphs;
 };
 
-morx_status batch_alloc(KrylovBatch& b, morx_system sys, int cap, int lcap, int prec,
+morx_status batch_alloc(KrylovBatch& b, morx_system sys, int cap, int lcap, int prec, int aprec,
                         hipStream_t st);
+// device bytes batch_alloc takes for `cap` slots
+size_t batch_bytes(morx_system sys, int cap, int aprec);
 void batch_free(KrylovBatch& b);
 // copy slot descriptors and factor tables (host mirrors) to the device
 morx_status batch_upload(KrylovBatch& b, int first, int count, hipStream_t st);

@@ -65,9 +65,6 @@ size_t factor_bytes(morx_system sys, int prec) {
   return (size_t)(sys->sell.nnz_sell + sys->sellT.nnz_sell) * prec_bytes(prec);
 }
 
-size_t batch_bytes(morx_system sys, int slots) {
-  return (size_t)16 * slots * sys->n_pad * sizeof(double) + (size_t)8 * slots * 1024 * sizeof(double);
-}
 
 }  // namespace
 
@@ -128,7 +125,7 @@ morx_status build_anchors(morx_server srv, SysServe* ss) {
 morx_status make_system(morx_server srv, morx_system sys, SysServe** out) {
   *out = nullptr;
   const int slots = srv->cfg.slots_per_system;
-  const size_t need = batch_bytes(sys, slots) +
+  const size_t need = batch_bytes(sys, slots, srv->opts.apply_prec) +
                       (size_t)srv->cfg.anchors * factor_bytes(sys, srv->opts.precond_prec);
   if (srv->used + need > srv->cfg.hbm_budget_bytes) return MORX_E_ADMISSION;
   SysServe* ss = new SysServe();
@@ -139,7 +136,7 @@ morx_status make_system(morx_server srv, morx_system sys, SysServe** out) {
     return MORX_E_HIP;
   }
   morx_status s = batch_alloc(ss->kb, sys, slots, srv->cfg.anchors + 1, srv->opts.precond_prec,
-                              ss->stream);
+                              srv->opts.apply_prec, ss->stream);
   if (s == MORX_OK) s = build_anchors(srv, ss);
   if (s != MORX_OK) {
     hipStreamSynchronize(ss->stream);
@@ -389,7 +386,8 @@ extern "C" morx_status morx_serve_start(morx_ctx ctx, const morx_serve_config* c
   const morx_serve_config& c = srv->cfg;
   if (!(c.slots_per_system >= 1 && c.slots_per_system <= 64 && c.anchors >= 1 && c.anchors <= 31 &&
         c.anchor_min > 0.0 && c.anchor_max >= c.anchor_min && std::isfinite(c.anchor_max) &&
-        srv->opts.precond_prec >= MORX_F64 && srv->opts.precond_prec <= MORX_BF16)) {
+        srv->opts.precond_prec >= MORX_F64 && srv->opts.precond_prec <= MORX_BF16 &&
+        (srv->opts.apply_prec == MORX_F64 || srv->opts.apply_prec == MORX_F32))) {
     delete srv;
     morx_set_error("morx_serve_start: bad configuration");
     return MORX_E_INVALID;

@@ -42,7 +42,7 @@ class morx_opts(ctypes.Structure):
                 ("max_restarts", ctypes.c_int32), ("precond_prec", ctypes.c_int32),
                 ("chain", ctypes.c_int32), ("want_dual", ctypes.c_int32),
                 ("batched", ctypes.c_int32), ("poll_iters", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("apply_prec", ctypes.c_int32)]
 
 
 class morx_col_stats(ctypes.Structure):

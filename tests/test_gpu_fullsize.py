@@ -1,5 +1,6 @@
 """Full-size checks of the benchmark job (64^3 convection-diffusion, n = 262,144),
-in the launch configuration bench.py times (batched, FP32 factors, 3 rounds).
+in the launch configurations bench.py times (batched, FP32 factors, 3 rounds,
+preconditioner applied in FP64 and in FP32).
 
 At this size the oracle cannot solve every system, so the checks are:
 * sampled factor columns against the oracle's column least squares;
@@ -35,15 +36,16 @@ def setup():
     ctx.close()
 
 
-def test_bench_job_fullsize_residuals_and_interpolation(setup):
+@pytest.mark.parametrize("apply", ["f64", "f32"])
+def test_bench_job_fullsize_residuals_and_interpolation(setup, apply):
     from paper_2003_12759_amd import api
 
     w, ctx, S = setup
     Bd, Cd = api.block_to_dev(w.B), api.block_to_dev(w.C)
     E = sp.diags(w.e)
     for z, sig in enumerate(w.rounds):
-        print(f"[case] full-size round {z}", flush=True)
-        X, Y, st, stats = S.solve_shifts(sig, Bd, Cd, prec="f32", next_round=z > 0)
+        print(f"[case] full-size round {z} apply={apply}", flush=True)
+        X, Y, st, stats = S.solve_shifts(sig, Bd, Cd, prec="f32", next_round=z > 0, apply=apply)
         Ar, Er, Br, Cr = S.project(X, Y, Bd, Cd)
         Xg, Yg = X.cpu().numpy(), Y.cpu().numpy()
         for i, s in enumerate(sig):

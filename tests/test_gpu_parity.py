@@ -175,6 +175,20 @@ def test_chain_apply_matches_oracle(ctx):
     S.close()
 
 
+def _iter_allowance(apply, iters):
+    """How far the GPU's BiCG iteration count may sit from the oracle's.
+
+    With the preconditioner applied in FP64, FP64 rounding differences leave
+    the count almost unchanged (5%).  With the FP32 apply the recurrence is
+    far more sensitive: changing only the FP64 summation order of the
+    operator products (the oracle rerun with the columns of A_s permuted)
+    moves the oracle's own count by up to 7% on the 45x45 Laplacian shifts
+    and 8% on the 12^3 convection-diffusion rounds; the GPU changes several
+    such orders at once (fused multiply-adds, block-partial dot products),
+    so the allowance is 20%."""
+    return max(3, (0.2 if apply == "f32" else 0.05) * iters)
+
+
 def _true_relres(A, e, s, x, b, trans=False):
     M = (s * sp.diags(e) - A)
     if trans:
@@ -183,15 +197,18 @@ def _true_relres(A, e, s, x, b, trans=False):
     return np.linalg.norm(b - M @ x) / nb if nb > 0 else np.linalg.norm(M @ x)
 
 
+@pytest.mark.parametrize("apply", ["f64", "f32"])
 @pytest.mark.parametrize("batched", [True, False])
-def test_solve_laplace2d_n2025_matches_oracle(ctx, batched):
+def test_solve_laplace2d_n2025_matches_oracle(ctx, batched, apply):
     from paper_2003_12759_amd import api
 
     w = make_workload(0)
     S = api.System(ctx, w.A, w.e)
-    _say(f"solve laplace2d_n2025 batched={batched}")
-    X, Y, st, stats = S.solve_shifts(w.rounds[0], w.B, w.C, prec="f64", batched=batched)
-    ref = ojob.run(w.A, w.e, w.B, w.C, w.rounds, prec="f64", tol=1e-10, project=False)
+    _say(f"solve laplace2d_n2025 batched={batched} apply={apply}")
+    X, Y, st, stats = S.solve_shifts(w.rounds[0], w.B, w.C, prec="f64", batched=batched,
+                                     apply=apply)
+    ref = ojob.run(w.A, w.e, w.B, w.C, w.rounds, prec="f64", tol=1e-10, project=False,
+                   apply_prec=apply)
     Xg, Yg = X.cpu().numpy(), Y.cpu().numpy()
     Ad = w.A.toarray()
     for i, s in enumerate(w.rounds[0]):
@@ -205,20 +222,24 @@ def test_solve_laplace2d_n2025_matches_oracle(ctx, batched):
         by = (rd + ro.relres_dual) * np.linalg.norm(w.C) / smin * 1.01
         assert np.linalg.norm(Xg[:, i] - ref["rounds"][0]["X"][:, i]) <= bx
         assert np.linalg.norm(Yg[:, i] - ref["rounds"][0]["Y"][:, i]) <= by
-        assert abs(stats[i].iters - ro.iters) <= max(3, 0.05 * ro.iters), (stats[i].iters, ro.iters)
+        assert abs(stats[i].iters - ro.iters) <= _iter_allowance(apply, ro.iters), \
+            (stats[i].iters, ro.iters)
     S.close()
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16", "f64"])
-def test_solve_convdiff_three_rounds_vertical_reuse(ctx, prec):
+@pytest.mark.parametrize("prec,apply", [("f32", "f64"), ("bf16", "f64"), ("f64", "f64"),
+                                        ("f32", "f32"), ("bf16", "f32")])
+def test_solve_convdiff_three_rounds_vertical_reuse(ctx, prec, apply):
     from paper_2003_12759_amd import api
 
     w = make_workload(1, N=12, nshift=5, nrounds=3)
     S = api.System(ctx, w.A, w.e)
-    ref = ojob.run(w.A, w.e, w.B, w.C, w.rounds, prec=prec, tol=1e-10, project=False)
+    ref = ojob.run(w.A, w.e, w.B, w.C, w.rounds, prec=prec, tol=1e-10, project=False,
+                   apply_prec=apply)
     for z, sig in enumerate(w.rounds):
-        _say(f"solve convdiff n={w.n} round {z} prec={prec}")
-        X, Y, st, stats = S.solve_shifts(sig, w.B, w.C, prec=prec, next_round=(z > 0))
+        _say(f"solve convdiff n={w.n} round {z} prec={prec} apply={apply}")
+        X, Y, st, stats = S.solve_shifts(sig, w.B, w.C, prec=prec, next_round=(z > 0),
+                                         apply=apply)
         Xg, Yg = X.cpu().numpy(), Y.cpu().numpy()
         for i, s in enumerate(sig):
             assert stats[i].status == 0
@@ -231,7 +252,8 @@ def test_solve_convdiff_three_rounds_vertical_reuse(ctx, prec):
             assert np.linalg.norm(Xg[:, i] - x) <= 1e-8 * np.linalg.norm(x)
             assert np.linalg.norm(Yg[:, i] - y) <= 1e-8 * np.linalg.norm(y)
             ro = ref["rounds"][z]["stats"][i]
-            assert abs(stats[i].iters - ro.iters) <= max(3, 0.1 * ro.iters), (stats[i].iters, ro.iters)
+            assert abs(stats[i].iters - ro.iters) <= max(3, 0.1 * ro.iters, _iter_allowance(apply, ro.iters)), \
+                (stats[i].iters, ro.iters)
     S.close()
 
 
@@ -251,7 +273,21 @@ def test_batched_equals_plain_mimo(ctx):
     S.close()
 
 
-def test_zero_right_hand_sides(ctx):
+def test_apply_precision_rejected_values(ctx):
+    from paper_2003_12759_amd import api, morx
+
+    w = make_workload(0, N=10, nshift=2)
+    S = api.System(ctx, w.A, w.e)
+    with pytest.raises(morx.MorxError):
+        S.solve_shifts(w.rounds[0], w.B, w.C, apply="bf16")
+    # the system still solves afterwards
+    _, _, st, stats = S.solve_shifts(w.rounds[0], w.B, w.C, apply="f32")
+    assert all(c.status == 0 for c in stats)
+    S.close()
+
+
+@pytest.mark.parametrize("apply", ["f64", "f32"])
+def test_zero_right_hand_sides(ctx, apply):
     from paper_2003_12759_amd import api
 
     w = make_workload(0, N=20, nshift=2)
@@ -263,8 +299,8 @@ def test_zero_right_hand_sides(ctx):
     C[:, 1] = rng.standard_normal(n)      # b = 0: transposed only
     # column 2: both zero
     S = api.System(ctx, w.A, w.e)
-    _say("solve zero right-hand sides")
-    X, Y, st, stats = S.solve_shifts(w.rounds[0], B, C)
+    _say(f"solve zero right-hand sides apply={apply}")
+    X, Y, st, stats = S.solve_shifts(w.rounds[0], B, C, apply=apply)
     Xg, Yg = X.cpu().numpy(), Y.cpu().numpy()
     for i, s in enumerate(w.rounds[0]):
         k0, k1, k2 = 3 * i, 3 * i + 1, 3 * i + 2

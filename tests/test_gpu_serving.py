@@ -35,10 +35,10 @@ def pool():
     ctx.close()
 
 
-def _serve(ctx, systems, p, reqs, cfg=None, threads=1, gap=0.0):
+def _serve(ctx, systems, p, reqs, cfg=None, threads=1, gap=0.0, opts=None):
     from paper_2003_12759_amd import morx
 
-    srv = morx.morx_serve_start(ctx.handle, cfg)
+    srv = morx.morx_serve_start(ctx.handle, cfg, opts)
     bs, xs, tickets = {}, {}, {}
     for t in reqs:
         n = systems[p.req_system[t]].n
@@ -89,6 +89,22 @@ def test_serving_results_match_direct_solves(pool):
         status, st, lat = out[t]
         assert status == 0 and st.status == 0, (t, status)
         assert st.relres_primal <= 1e-10 and lat > 0
+        _check_exact(p, t, xs[t])
+
+
+def test_serving_fp32_storage_and_apply(pool):
+    from paper_2003_12759_amd import morx
+
+    p, ctx, systems = pool
+    o = morx.morx_opts_default()
+    o.precond_prec = morx.PREC["f32"]
+    o.apply_prec = morx.PREC["f32"]
+    reqs = list(range(20))
+    print("[case] serving 20 requests, FP32 factors applied in FP32", flush=True)
+    xs, out, info = _serve(ctx, systems, p, reqs, threads=2, opts=o)
+    for t in reqs:
+        status, st, lat = out[t]
+        assert status == 0 and st.status == 0, (t, status)
         _check_exact(p, t, xs[t])
 
 
