@@ -52,14 +52,62 @@ def default_apply(prec: str) -> str:
     return "f64"
 
 
-def run_job(S, w, Bd, Cd, batched: bool, apply: str, use_graph: bool = True):
+def run_job(S, w, Bd, Cd, batched: bool, apply: str, use_graph: bool = True, prec=None,
+            keep=None):
+    """One step: every round's shifted solves and projection.  ``keep`` (a
+    list) receives the last round's (X, Y)."""
     stats_all = []
     for z, sig in enumerate(w.rounds):
-        X, Y, st, stats = S.solve_shifts(sig, Bd, Cd, prec=w.prec, tol=w.tol, batched=batched,
-                                         next_round=z > 0, use_graph=use_graph, apply=apply)
+        X, Y, st, stats = S.solve_shifts(sig, Bd, Cd, prec=prec or w.prec, tol=w.tol,
+                                         batched=batched, next_round=z > 0, use_graph=use_graph,
+                                         apply=apply)
         S.project(X, Y, Bd, Cd)
         stats_all.extend(stats)
+    if keep is not None:
+        keep[:] = [X, Y]
     return stats_all
+
+
+def ladder(S, w, Bd, Cd, nsolves):
+    """Precision ladder: the same job with FP64, FP32 and BF16 factor storage
+    (chain applied with FP64 vectors, FP64 Krylov and refinement).  Per
+    precision: one timed step after one untimed one, iterations per shift,
+    the largest true relative residual recomputed on the host in FP64, and
+    the largest relative distance of x and y from the FP64-storage solution."""
+    import numpy as np
+    import scipy.sparse as sp
+    import torch
+
+    E = sp.diags(w.e)
+    out, ref = {}, None
+    for prec in ("f64", "f32", "bf16"):
+        keep = []
+        run_job(S, w, Bd, Cd, batched=True, apply="f64", prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = run_job(S, w, Bd, Cd, batched=True, apply="f64", prec=prec, keep=keep)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        check(st, w.tol)
+        X, Y = keep[0].cpu().numpy(), keep[1].cpu().numpy()
+        m = w.B.shape[1]
+        res = 0.0
+        for i, sig in enumerate(w.rounds[-1]):
+            M = (sig * E - w.A).tocsr()
+            for j in range(m):
+                k = i * m + j
+                res = max(res, np.linalg.norm(w.B[:, j] - M @ X[:, k]) / np.linalg.norm(w.B[:, j]),
+                          np.linalg.norm(w.C[:, j] - M.T @ Y[:, k]) / np.linalg.norm(w.C[:, j]))
+        if ref is None:
+            ref = (X, Y)
+        err = max(float(np.max(np.linalg.norm(X - ref[0], axis=0) / np.linalg.norm(ref[0], axis=0))),
+                  float(np.max(np.linalg.norm(Y - ref[1], axis=0) / np.linalg.norm(ref[1], axis=0))))
+        its = [x.iters for x in st[-len(w.rounds[-1]) * m:]]
+        out[prec] = {"value": round(nsolves / dt, 3), "unit": "solves/s",
+                     "iters_per_shift": its, "iters_total": sum(its),
+                     "max_true_relres": float(f"{res:.3e}"),
+                     "max_rel_diff_vs_f64_storage": float(f"{err:.3e}")}
+    return out
 
 
 def check(stats, tol):
@@ -133,6 +181,11 @@ def serving_bench(args):
     opts = morx.morx_opts_default()
     opts.precond_prec = morx.PREC[prec]
     opts.apply_prec = morx.PREC[apply]
+    if not args.no_autotune:
+        # per system: slots columns, chains up to anchors + 1 factors
+        for S in systems:
+            S.autotune(float(cfg.anchor_min * (cfg.anchor_max / cfg.anchor_min) ** 0.5),
+                       ncols=cfg.slots_per_system, chain_len=cfg.anchors + 1, prec=prec)
     srv = morx.morx_serve_start(ctx.handle, cfg, opts)
     # anchors of every system are built on its first request (not timed)
     # b and x must stay alive until the request is finished
@@ -202,7 +255,8 @@ def serving_bench(args):
                        "n_range": [min(S.n for S in systems), max(S.n for S in systems)],
                        "requests": nreq, "slots_per_system": args.slots, "anchors": cfg.anchors,
                        "precond_storage": prec, "precond_apply": apply, "krylov": "f64",
-                       "tol": 1e-10, "mode": "continuous batching"},
+                       "tol": 1e-10, "mode": "continuous batching",
+                       "launch_shapes": "built-in" if args.no_autotune else "autotuned per system"},
             "p50_s": hi["p50_s"], "p99_s": hi["p99_s"], "serving": out, "loads": loads,
             "server_bytes": info["bytes_in_use"], "roofline": None, "cpu_baseline": None}
     print(json.dumps(line), flush=True)
@@ -228,6 +282,8 @@ def main():
                     help="factor storage precision (default: the workload's)")
     ap.add_argument("--apply", default=None, choices=[None, "f64", "f32"],
                     help="preconditioner apply precision (default: FP64)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in launch shapes instead of timing candidates first")
     ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=16, help="serving: slots per system")
     ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 1.0],
@@ -256,6 +312,15 @@ def main():
     Bd = api.block_to_dev(w.B)
     Cd = api.block_to_dev(w.C)
     torch.cuda.synchronize()
+
+    # launch shapes: timed on this system before the clock starts (a
+    # one-time cost per system, like building it)
+    tuned = None
+    if not args.no_autotune:
+        t_tune = time.perf_counter()
+        tuned = S.autotune(float(w.rounds[0][0]), ncols=len(w.rounds[0]) * w.B.shape[1],
+                           chain_len=len(w.rounds[0]) + len(w.rounds) - 1, prec=w.prec)
+        tuned["seconds"] = round(time.perf_counter() - t_tune, 3)
 
     for _ in range(args.warmup):
         check(run_job(S, w, Bd, Cd, batched=True, apply=apply), w.tol)
@@ -315,7 +380,8 @@ def main():
                 traffic = tf.get("bytes_per_launch")
         ncol = len(w.rounds[0]) * w.B.shape[1]
         ctype = {"f64": "double", "f32": "float", "bf16": "unsigned short"}
-        chunks = -(-ncol // 8)
+        ncmax = S.get_tune()["cols_per_wave"]
+        chunks = -(-ncol // (ncmax if ncmax > 0 else 8))
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                     "traffic": traffic,
@@ -332,6 +398,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    lad = ladder(S, w, Bd, Cd, nsolves) if index == 4 and args.prec is None else None
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, apply)
 
     out = {
@@ -342,7 +410,8 @@ def main():
         "config": {"workload": w.name, "n": w.n, "nnz": w.nnz, "shifts_per_round": len(w.rounds[0]),
                    "rounds": len(w.rounds), "solves_per_step": nsolves, "precond_storage": w.prec,
                    "precond_apply": apply, "krylov": "f64", "tol": w.tol,
-                   "mode": "batched multi-shift", "parallelism": "single GPU"},
+                   "mode": "batched multi-shift", "parallelism": "single GPU",
+                   "launch_shapes": tuned or "built-in"},
         "iters_per_step": iters,
         "batched_f64_apply": f64_apply,
         "plain": None if plain_value is None else {"value": round(plain_value, 3),
@@ -355,6 +424,8 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
     }
+    if lad is not None:
+        out["ladder"] = lad
     print(json.dumps(out), flush=True)
     S.close()
     ctx.close()

@@ -194,6 +194,43 @@ morx_status morx_project(morx_system sys, int32_t r, const double* V, int64_t ld
                          double* Br, double* Cr, int32_t orthonormalize, void* stream);
 
 /*
+ * Launch shapes of a system's kernels (the batching extension: the tile and
+ * row-block shapes of the multi-column iteration kernels and of the
+ * least-squares factor kernel); -1 selects the built-in choice.
+ *   factor_kernel    0: one wave per column; 8 or 16: one block of 32 x 8 or
+ *                    32 x 16 threads per column, the local matrix in
+ *                    registers (patterns with |J_k| < 32 and |I_k| <= 256);
+ *   cols_per_wave    iteration kernels: most right-hand-side columns one wave
+ *                    carries over its rows, sharing every matrix and factor
+ *                    load among them (1..8);
+ *   slices_per_wave  iteration kernels: 64-row slices per wave (1..64; raised
+ *                    to the least value that keeps <= 1024 row blocks).
+ * morx_system_set_tune checks the values (MORX_E_INVALID) and they apply from
+ * the next call on the system.  morx_autotune times the candidates on the
+ * system itself: one SPAI factor build at `sigma` (storage prec) per factor
+ * kernel, then a few BiCG iterations of ncols column pairs per iteration
+ * shape (HIP events), column c preconditioned by 1 + c * chain_len / ncols
+ * distinct factors of one list, as the chains of one round are
+ * (chain_len 1..64: the longest chain of the solves to come).  It keeps the
+ * fastest, fills *out (factor_ms and iter_ms: the chosen build and one
+ * iteration) and returns MORX_OK.  Shapes change rounding order only.  It
+ * allocates its own scratch on the device.
+ */
+typedef struct {
+  int32_t factor_kernel;
+  int32_t cols_per_wave;
+  int32_t slices_per_wave;
+  int32_t reserved;
+  double factor_ms;
+  double iter_ms;
+} morx_tune;
+
+morx_status morx_system_get_tune(morx_system sys, morx_tune* out);
+morx_status morx_system_set_tune(morx_system sys, const morx_tune* tune);
+morx_status morx_autotune(morx_system sys, double sigma, int32_t ncols, int32_t chain_len,
+                          int32_t prec, morx_tune* out, void* stream);
+
+/*
  * Serving (continuous batching).  A server owns one scheduler thread on the
  * context's device.  Requests ask for the primal solve (sigma E - A) x = b on
  * a resident system; they are admitted while their device memory fits the

@@ -103,5 +103,16 @@ class System:
                                            raise_on_error=raise_on_error)
         return X, Y, st, stats
 
+    def autotune(self, sigma: float, ncols: int, chain_len: int = 1, prec: str = "f64") -> dict:
+        """Time the launch-shape candidates on this system and keep the fastest."""
+        return morx.morx_autotune(self.handle, sigma, ncols, chain_len, prec)
+
+    def set_tune(self, factor_kernel: int = -1, cols_per_wave: int = -1,
+                 slices_per_wave: int = -1) -> None:
+        morx.morx_system_set_tune(self.handle, factor_kernel, cols_per_wave, slices_per_wave)
+
+    def get_tune(self) -> dict:
+        return morx.morx_system_get_tune(self.handle)
+
     def project(self, V, W, B=None, C=None, orthonormalize=True):
         return morx.morx_project(self.handle, V, W, B, C, orthonormalize)

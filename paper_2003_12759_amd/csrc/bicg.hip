@@ -60,6 +60,7 @@ constexpr double kBreakdown = 1e-14;
 struct IterArgs {
   int64_t n, ld, nnzS, nslices;
   int cap, nc, nblk, spw, vbytes, maxL, lcap;
+  int ncmax;  // most columns per wave
   const int32_t *off, *col, *offT, *colT;
   const double *valA, *valAT, *e;
   double* vec;
@@ -976,10 +977,12 @@ static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   a.nslices = sys->nslice;
   a.cap = b.cap;
   a.nc = nc;
-  // slices per wave: as few as the partial-sum budget allows; blocks: a
-  // multiple of 8 for the XCD remap
+  // slices per wave: as few as the partial-sum budget allows (or the tuned
+  // value); blocks: a multiple of 8 for the XCD remap
   const int64_t per_blk_min = (a.nslices + kMaxBlocks - 1) / kMaxBlocks;
   a.spw = (int)std::max<int64_t>(1, (per_blk_min + kWavesPerBlock - 1) / kWavesPerBlock);
+  if (sys->tune_spw > 0) a.spw = std::max(a.spw, (int)sys->tune_spw);
+  a.ncmax = sys->tune_nc > 0 ? (int)sys->tune_nc : kMaxNC;
   int64_t nb = (a.nslices + (int64_t)kWavesPerBlock * a.spw - 1) / ((int64_t)kWavesPerBlock * a.spw);
   nb = std::max<int64_t>(8, (nb + 7) / 8 * 8);
   a.nblk = (int)nb;
@@ -1007,9 +1010,9 @@ static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   return a;
 }
 
-// columns per wave: the batch split into equal chunks of at most kMaxNC
-static int pick_nc(int nc) {
-  const int chunks = (nc + kMaxNC - 1) / kMaxNC;
+// columns per wave: the batch split into equal chunks of at most ncmax
+static int pick_nc(int nc, int ncmax) {
+  const int chunks = (nc + ncmax - 1) / ncmax;
   return (nc + chunks - 1) / chunks;
 }
 
@@ -1058,7 +1061,7 @@ static void enqueue_chain_prec(const IterArgs& a, int prec, hipStream_t st, Trac
 
 static morx_status enqueue_iterations(const IterArgs& a, int prec, int iters, hipStream_t st,
                                       TraceState* t) {
-  const int ncv = pick_nc(a.nc);
+  const int ncv = pick_nc(a.nc, a.ncmax);
   const bool f32 = a.abytes == 4;
   for (int it = 0; it < iters; ++it) {
     const int par = it & 1;
@@ -1088,7 +1091,8 @@ morx_status batch_launch_init(KrylovBatch& b, int nc, hipStream_t st) {
 
 morx_status batch_launch_true(KrylovBatch& b, int nc, hipStream_t st) {
   const IterArgs a = make_args(b, nc, 1);
-  MORX_NC_DISPATCH(pick_nc(nc), k_true_residual<NC><<<grid_of(a, NC, 1), kBlock, 0, st>>>(a));
+  MORX_NC_DISPATCH(pick_nc(nc, a.ncmax),
+                   k_true_residual<NC><<<grid_of(a, NC, 1), kBlock, 0, st>>>(a));
   k_fin_true<<<1, kFinThreads, 0, st>>>(a);
   MORX_HIP(hipGetLastError());
   return MORX_OK;
@@ -1107,13 +1111,14 @@ morx_status batch_launch_copy_out(KrylovBatch& b, const int* slots, int count, h
 }
 
 // one segment of `iters` iterations; graphs are cached per (nc, maxL, iters)
+// and launch shape
 morx_status batch_launch_segment(KrylovBatch& b, int nc, int maxL, int iters, bool use_graph,
                                  hipStream_t st, TraceState* t) {
   const IterArgs a = make_args(b, nc, maxL);
   if (!use_graph || t) return enqueue_iterations(a, b.prec, iters, st, t);
-  const int key_nc = nc;
+  const int64_t key = (((int64_t)iters * 1024 + nc) * 128 + a.spw) * 16 + a.ncmax;
   for (auto& g : b.graphs)
-    if (g.maxL == maxL && g.iters == iters * 1000 + key_nc) {
+    if (g.maxL == maxL && g.key == key) {
       MORX_HIP(hipGraphLaunch(g.x, st));
       return MORX_OK;
     }
@@ -1135,7 +1140,7 @@ morx_status batch_launch_segment(KrylovBatch& b, int nc, int maxL, int iters, bo
     morx_set_error("graph instantiation failed: %s", hipGetErrorString(e));
     return MORX_E_HIP;
   }
-  b.graphs.push_back({maxL, iters * 1000 + key_nc, g, x});
+  b.graphs.push_back({maxL, key, g, x});
   MORX_HIP(hipGraphLaunch(x, st));
   return MORX_OK;
 }
@@ -1452,6 +1457,222 @@ extern "C" morx_status morx_solve_shifts(morx_system sys, int32_t nshift, const 
   hipStreamSynchronize(ctx->stream);
   for (morx_factor f : horizontal) factor_release(f);
   for (morx_factor f : fresh) factor_release(f);
+  morx_status s2 = stream_leave(ctx, caller);
+  return s != MORX_OK ? s : s2;
+}
+
+// ---------------------------------------------------------------------------
+// launch shapes: get, set, autotune
+
+extern "C" morx_status morx_system_get_tune(morx_system sys, morx_tune* out) {
+  MORX_REQUIRE(sys && out, MORX_E_INVALID, "morx_system_get_tune: null argument");
+  memset(out, 0, sizeof(*out));
+  out->factor_kernel = sys->tune_factor_rows;
+  out->cols_per_wave = sys->tune_nc;
+  out->slices_per_wave = sys->tune_spw;
+  return MORX_OK;
+}
+
+extern "C" morx_status morx_system_set_tune(morx_system sys, const morx_tune* t) {
+  MORX_REQUIRE(sys && t, MORX_E_INVALID, "morx_system_set_tune: null argument");
+  MORX_REQUIRE(t->factor_kernel == -1 || factor_kernel_supported(sys, t->factor_kernel),
+               MORX_E_INVALID, "morx_system_set_tune: factor kernel %d does not fit the pattern",
+               t->factor_kernel);
+  MORX_REQUIRE(t->cols_per_wave == -1 || (t->cols_per_wave >= 1 && t->cols_per_wave <= kMaxNC),
+               MORX_E_INVALID, "morx_system_set_tune: cols_per_wave must be -1 or 1..%d", kMaxNC);
+  MORX_REQUIRE(t->slices_per_wave == -1 || (t->slices_per_wave >= 1 && t->slices_per_wave <= 64),
+               MORX_E_INVALID, "morx_system_set_tune: slices_per_wave must be -1 or 1..64");
+  std::lock_guard<std::mutex> lk(sys->ctx->mu);
+  sys->tune_factor_rows = t->factor_kernel;
+  sys->tune_nc = t->cols_per_wave;
+  sys->tune_spw = t->slices_per_wave;
+  return MORX_OK;
+}
+
+namespace {
+
+// deterministic, nonzero right-hand sides for timing runs
+__global__ void k_tune_rhs(double* p, int64_t n, int64_t ld, int ncol) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int c = 0; c < ncol; ++c) {
+    const uint32_t h = (uint32_t)(i * 2654435761u) ^ (uint32_t)(c * 40503u + 17u);
+    p[(int64_t)c * ld + i] = 0.5 + (double)(h & 0xffffu) / 65536.0;
+  }
+}
+
+}  // namespace
+
+static morx_status time_events(hipEvent_t a, hipEvent_t b, hipStream_t st, double* ms) {
+  MORX_HIP(hipStreamSynchronize(st));
+  float f = 0.f;
+  MORX_HIP(hipEventElapsedTime(&f, a, b));
+  *ms = f;
+  return MORX_OK;
+}
+
+static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int chain_len,
+                                 int prec, morx_tune* out, hipStream_t st, hipEvent_t e0,
+                                 hipEvent_t e1, std::vector<morx_factor>& keep) {
+  // 1. least-squares kernel: one SPAI build per candidate
+  double best_f = 1e300;
+  int best_rows = -1;
+  FactorJob job{sigma, 0.0, 1, nullptr, nullptr};
+  morx_factor f = nullptr;
+  MORX_TRY(factor_alloc(sys, prec, &f));
+  keep.push_back(f);
+  job.vals = f->vals.p;
+  job.valsT = f->valsT.p;
+  const int saved_rows = sys->tune_factor_rows;
+  for (int rows : {0, 8, 16}) {
+    if (!factor_kernel_supported(sys, rows)) continue;
+    sys->tune_factor_rows = rows;
+    MORX_HIP(hipEventRecord(e0, st));
+    morx_status s = factor_build_many(sys, prec, &job, 1, st);
+    MORX_HIP(hipEventRecord(e1, st));
+    double ms = 0.0;
+    MORX_TRY(time_events(e0, e1, st, &ms));
+    if (s != MORX_OK) {
+      sys->tune_factor_rows = saved_rows;
+      return s;
+    }
+    if (ms < best_f) {
+      best_f = ms;
+      best_rows = rows;
+    }
+  }
+  sys->tune_factor_rows = best_rows;
+  f->is_spai = true;
+  f->sigma_new = sigma;
+
+  // 2. iteration shapes: BiCG iterations of ncols pairs preconditioned by
+  // prefixes of one list of chain_len distinct copies of f, column c taking
+  // 1 + c * chain_len / ncols factors (the chains of one round of
+  // Algorithm 4; a single factor reused would stay in the last-level cache)
+  std::vector<morx_factor> chain{f};
+  for (int j = 1; j < chain_len; ++j) {
+    morx_factor g = nullptr;
+    MORX_TRY(factor_alloc(sys, prec, &g));
+    keep.push_back(g);
+    MORX_HIP(hipMemcpyAsync(g->vals.p, f->vals.p, f->vals.bytes, hipMemcpyDeviceToDevice, st));
+    MORX_HIP(hipMemcpyAsync(g->valsT.p, f->valsT.p, f->valsT.bytes, hipMemcpyDeviceToDevice, st));
+    chain.push_back(g);
+  }
+  KrylovBatch kb;
+  MORX_TRY(batch_alloc(kb, sys, ncols, chain_len, prec, MORX_F64, st));
+  DevBuf rhs;
+  morx_status s = dev_alloc(rhs, (size_t)ncols * sys->n_pad * sizeof(double));
+  if (s != MORX_OK) {
+    batch_free(kb);
+    return s;
+  }
+  k_tune_rhs<<<(unsigned)((sys->n + 255) / 256), 256, 0, st>>>((double*)rhs.p, sys->n, sys->n_pad,
+                                                                ncols);
+  const int saved_nc = sys->tune_nc, saved_spw = sys->tune_spw;
+  sys->tune_nc = -1;
+  sys->tune_spw = -1;
+  const IterArgs a0 = make_args(kb, ncols, chain_len);
+  const int spw0 = a0.spw;
+  double best_i = 1e300;
+  int best_nc = -1, best_spw = -1;
+  std::vector<int> seen_nc;
+  constexpr int kWarm = 2, kTimed = 6;
+  for (int ncmax : {8, 4, 2, 1}) {
+    const int ncv = pick_nc(ncols, ncmax);
+    if (std::find(seen_nc.begin(), seen_nc.end(), ncv) != seen_nc.end()) continue;
+    seen_nc.push_back(ncv);
+    for (int mult : {1, 2, 4}) {
+      const int spw = spw0 * mult;
+      if (mult > 1 && (sys->nslice + (int64_t)kWavesPerBlock * spw - 1) /
+                              ((int64_t)kWavesPerBlock * spw) < 256)
+        break;  // too few row blocks to fill the chip
+      sys->tune_nc = ncmax;
+      sys->tune_spw = spw;
+      for (int c = 0; c < ncols; ++c) {
+        ColInfo ci = {};
+        ci.sigma = sigma;
+        ci.tol = 0.0;  // never converges: every timed iteration does full work
+        ci.bsrc = (const double*)rhs.p + (int64_t)c * sys->n_pad;
+        ci.csrc = ci.bsrc;
+        ci.state = COL_INIT;
+        ci.L = 1 + (int)(((int64_t)c * chain_len) / ncols);
+        ci.first = 1;
+        ci.maxit = 1 << 20;
+        ci.check_p = ci.check_d = 1;
+        kb.hcols[c] = ci;
+        for (int j = 0; j < chain_len; ++j) {
+          const bool in = j < ci.L;
+          kb.hftab[(size_t)c * kb.lcap + j] = in ? chain[j]->vals.p : nullptr;
+          kb.hftab[((size_t)kb.cap + c) * kb.lcap + j] = in ? chain[j]->valsT.p : nullptr;
+        }
+      }
+      s = batch_upload(kb, 0, ncols, st);
+      if (s == MORX_OK) s = batch_launch_init(kb, ncols, st);
+      const IterArgs a = make_args(kb, ncols, chain_len);
+      if (s == MORX_OK) s = enqueue_iterations(a, prec, kWarm, st, nullptr);
+      if (s == MORX_OK && hipEventRecord(e0, st) != hipSuccess) s = MORX_E_HIP;
+      if (s == MORX_OK) s = enqueue_iterations(a, prec, kTimed, st, nullptr);
+      if (s == MORX_OK && hipEventRecord(e1, st) != hipSuccess) s = MORX_E_HIP;
+      double ms = 0.0;
+      if (s == MORX_OK) s = time_events(e0, e1, st, &ms);
+      if (s != MORX_OK) break;
+      ms /= kTimed;
+      if (ms < best_i) {
+        best_i = ms;
+        best_nc = ncmax;
+        best_spw = spw;
+      }
+    }
+    if (s != MORX_OK) break;
+  }
+  hipStreamSynchronize(st);
+  dev_free(rhs);
+  batch_free(kb);
+  if (s != MORX_OK) {
+    sys->tune_nc = saved_nc;
+    sys->tune_spw = saved_spw;
+    return s;
+  }
+  sys->tune_nc = best_nc;
+  sys->tune_spw = best_spw;
+  memset(out, 0, sizeof(*out));
+  out->factor_kernel = best_rows;
+  out->cols_per_wave = best_nc;
+  out->slices_per_wave = best_spw;
+  out->factor_ms = best_f;
+  out->iter_ms = best_i;
+  return MORX_OK;
+}
+
+extern "C" morx_status morx_autotune(morx_system sys, double sigma, int32_t ncols,
+                                     int32_t chain_len, int32_t prec, morx_tune* out,
+                                     void* stream) {
+  MORX_REQUIRE(sys && out, MORX_E_INVALID, "morx_autotune: null argument");
+  MORX_REQUIRE(ncols >= 1 && ncols <= 1024, MORX_E_INVALID, "morx_autotune: ncols must be 1..1024");
+  MORX_REQUIRE(chain_len >= 1 && chain_len <= 64, MORX_E_INVALID,
+               "morx_autotune: chain_len must be 1..64");
+  MORX_REQUIRE(prec >= MORX_F64 && prec <= MORX_BF16, MORX_E_INVALID, "morx_autotune: bad precision");
+  MORX_REQUIRE(std::isfinite(sigma), MORX_E_NONFINITE, "morx_autotune: shift not finite");
+  MORX_REQUIRE(sys->ls_supported, MORX_E_UNSUPPORTED,
+               "factor pattern exceeds the local least-squares limits");
+  morx_ctx ctx = sys->ctx;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  MORX_HIP(hipSetDevice(ctx->device));
+  hipStream_t caller = (hipStream_t)stream;
+  MORX_TRY(stream_enter(ctx, caller));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  morx_status s = MORX_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    morx_set_error("morx_autotune: event creation failed");
+    s = MORX_E_HIP;
+  }
+  std::vector<morx_factor> fs;
+  if (s == MORX_OK)
+    s = autotune_impl(sys, sigma, ncols, chain_len, prec, out, ctx->stream, e0, e1, fs);
+  hipStreamSynchronize(ctx->stream);
+  for (morx_factor f : fs) factor_release(f);
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
   morx_status s2 = stream_leave(ctx, caller);
   return s != MORX_OK ? s : s2;
 }

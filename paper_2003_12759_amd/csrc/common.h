@@ -122,6 +122,10 @@ struct morx_system_s {
   // local least-squares sizes
   int32_t max_J = 0, max_T = 0, max_I = 0;
   bool ls_supported = true;
+  // launch shapes (morx_tune): -1 means the built-in heuristic
+  int32_t tune_factor_rows = -1;  // least-squares kernel: 0 per wave, 8 or 16 row groups
+  int32_t tune_nc = -1;           // iteration kernels: most columns per wave (1..8)
+  int32_t tune_spw = -1;          // iteration kernels: 64-row slices per wave
   std::vector<DevBuf> owned;
   // chain state between morx_solve_shifts calls (Algorithm 4)
   std::vector<morx_factor> vertical;  // P_1^(1), Q_1^(2), ..., Q_1^(z)
@@ -145,6 +149,8 @@ struct FactorJob {
   void* valsT;
 };
 morx_status factor_alloc(morx_system sys, int32_t prec, morx_factor* out);
+// whether the least-squares kernel variant (0, 8 or 16 row groups) handles the pattern
+bool factor_kernel_supported(morx_system sys, int rows);
 void factor_release(morx_factor f);
 morx_status factor_build_many(morx_system sys, int32_t prec, const FactorJob* jobs, int njobs,
                               hipStream_t st);

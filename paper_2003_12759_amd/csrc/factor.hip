@@ -294,12 +294,309 @@ __global__ void k_factor_to_csr(const VT* __restrict__ vals, const int32_t* __re
   if (p < nnz) out[p] = load_val<VT>(vals + csr2sell[p]);
 }
 
+// ---- block kernel for larger local problems ------------------------------------
+//
+// One block of 32 x BR threads per column.  The dense |I_k| x (|J_k| + 1)
+// matrix is held in registers: thread (cc, g) = (tid % 32, tid / 32) owns
+// column cc (column |J_k| is the right-hand side) at the local rows
+// r = s * BR + g, s < S.  A Householder step stages only the reflector column, row c of
+// every column and the per-row-group partial dot products in LDS (double
+// buffered by step parity, two barriers per step); the gathered triples stay
+// in LDS so every shift rebuilds its matrix without touching global memory.
+constexpr int kBC = 32;         // column lanes: |J_k| + 1 <= 32
+constexpr int kRld = kBC + 1;   // row stride of the R staging buffer
+
+struct BlkLayout {
+  int Tpad, Tmax, maxI, S, BR;
+  size_t off_keys, off_trow, off_tv, off_uniq, off_col, off_v, off_rowc, off_part, bytes;
+};
+
+BlkLayout blk_layout(int maxT, int maxI, int S, int BR) {
+  BlkLayout L;
+  L.Tmax = std::max(maxT, 1);
+  L.Tpad = 256;
+  while (L.Tpad < L.Tmax) L.Tpad <<= 1;
+  L.maxI = std::max(maxI, 1);
+  L.S = S;
+  L.BR = BR;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o += (bytes + 15) / 16 * 16;
+    return r;
+  };
+  // sort keys, then the R staging buffer of the back substitution
+  L.off_keys = take(std::max((size_t)L.Tpad * 4, (size_t)kBC * kRld * 8));
+  L.off_trow = take((size_t)L.Tmax * 4);
+  L.off_tv = take((size_t)L.Tmax * 8);
+  L.off_uniq = take((size_t)L.maxI * 4);
+  L.off_col = take((size_t)(3 * kBC + 8) * 4);  // J, triple offsets (+1), diagonal rows, misc
+  L.off_v = take((size_t)2 * S * BR * 8);
+  L.off_rowc = take((size_t)2 * kBC * 8);
+  L.off_part = take((size_t)2 * BR * kBC * 8);
+  L.bytes = o;
+  return L;
+}
+
+// (up to 16 slots: at least 3 blocks per CU; the steps are latency bound, so
+// blocks in flight matter more than registers)
+template <typename VT, int S, int BR>
+__global__ __launch_bounds__(kBC * BR, (S <= 16 ? 3 : 1)) void k_factor_ls_blk(
+    const int32_t* __restrict__ trowptr, const int32_t* __restrict__ tcol,
+    const double* __restrict__ tval, const double* __restrict__ e,
+    const int32_t* __restrict__ tp2s, const int32_t* __restrict__ sellT_off, int64_t n,
+    const FactorJob* __restrict__ jobs, int njobs, BlkLayout L, int* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  int* keys = (int*)(lds + L.off_keys);
+  double* R = (double*)(lds + L.off_keys);
+  int* trow = (int*)(lds + L.off_trow);
+  double* tv = (double*)(lds + L.off_tv);
+  int* uniq = (int*)(lds + L.off_uniq);
+  int* colJ = (int*)(lds + L.off_col);
+  int* coloff = colJ + kBC;        // kBC + 1 entries
+  int* coldiag = colJ + 2 * kBC + 1;
+  int* misc = colJ + 3 * kBC + 1;  // T, nI, kloc, ak
+  double* vbuf = (double*)(lds + L.off_v);
+  double* rowc = (double*)(lds + L.off_rowc);
+  double* part = (double*)(lds + L.off_part);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cc = tid % kBC, g = tid / kBC;
+  constexpr int kBR = BR;
+  constexpr int kBT = kBC * BR;
+  constexpr int VS = S * kBR;  // rows held per column (>= |I_k|)
+
+  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+    const int lo = trowptr[k];
+    const int m = trowptr[k + 1] - lo;
+    // gather the nonzeros of S[:, J_k] in column order (wave 0)
+    if (wave == 0) {
+      int len = 0, j = 0;
+      if (lane < m) {
+        j = tcol[lo + lane];
+        colJ[lane] = j;
+        len = trowptr[j + 1] - trowptr[j];
+      }
+      int T;
+      const int off = wave_excl_scan(len, lane, &T);
+      if (lane < m) {
+        coloff[lane] = off;
+        const int b = trowptr[j];
+        for (int u = 0; u < len; ++u) {
+          const int row = tcol[b + u];
+          trow[off + u] = row;
+          keys[off + u] = row;
+          tv[off + u] = tval[b + u];
+        }
+      }
+      if (lane == 0) {
+        coloff[m] = T;
+        misc[0] = T;
+      }
+    }
+    __syncthreads();
+    const int T = misc[0];
+    for (int t = T + tid; t < L.Tpad; t += kBT) keys[t] = 0x7fffffff;
+    __syncthreads();
+    // bitonic sort of the row indices
+    for (int size = 2; size <= L.Tpad; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int t = tid; t < L.Tpad; t += kBT) {
+          const int p = t ^ stride;
+          if (p > t) {
+            const int a = keys[t], b = keys[p];
+            const bool up = ((t & size) == 0);
+            if ((a > b) == up) {
+              keys[t] = b;
+              keys[p] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // unique rows I_k (wave 0)
+    if (wave == 0) {
+      int base = 0;
+      for (int t0 = 0; t0 < T; t0 += 64) {
+        const int t = t0 + lane;
+        const bool first = (t < T) && (t == 0 || keys[t] != keys[t - 1]);
+        const unsigned long long mask = __ballot(first);
+        const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+        if (first) uniq[pos] = keys[t];
+        base += __popcll(mask);
+      }
+      if (lane == 0) misc[1] = base;
+    }
+    __syncthreads();
+    const int nI = misc[1];
+    // every triple as (local row << 5) | local column, in column order (rows
+    // ascending within a column); the local row of every column's own index
+    for (int t = tid; t < T; t += kBT) {
+      int a = 0;
+      while (a + 1 < m && coloff[a + 1] <= t) ++a;
+      trow[t] = (find_row(uniq, nI, trow[t]) << 5) | a;
+    }
+    if (tid < m) {
+      coldiag[tid] = find_row(uniq, nI, colJ[tid]);
+      if (colJ[tid] == (int)k) misc[3] = tid;
+    }
+    if (tid == 0) misc[2] = find_row(uniq, nI, (int)k);
+    __syncthreads();
+    const int kloc = misc[2], ak = misc[3];
+
+    for (int jb = 0; jb < njobs; ++jb) {
+      const FactorJob job = jobs[jb];
+      // this thread's column of [A_new(I_k, J_k) | rhs]
+      double M[S];
+      const bool rhs = (cc == m);
+      if (cc < m || (rhs && !job.is_spai)) {
+        // column cc of A_new, or for an update the right-hand side
+        // A_prev(I_k, k) = column ak with the previous shift
+        const int a = rhs ? ak : cc;
+        const double sh = rhs ? job.sigma_prev : job.sigma_new;
+        const int dl = coldiag[a];
+        const double dv = sh * e[colJ[a]];
+        int p = coloff[a];
+        const int pe = coloff[a + 1];
+#pragma unroll
+        for (int s2 = 0; s2 < S; ++s2) {
+          const int r = s2 * kBR + g;
+          double x = 0.0;
+          while (p < pe && (trow[p] >> 5) < r) ++p;
+          if (p < pe && (trow[p] >> 5) == r) x = -tv[p];
+          if (r == dl) x += dv;
+          M[s2] = x;
+        }
+      } else {
+#pragma unroll
+        for (int s2 = 0; s2 < S; ++s2) M[s2] = (rhs && s2 * kBR + g == kloc) ? 1.0 : 0.0;
+      }
+      // Householder QR of the m columns, applied to the right-hand side too
+      bool singular = false;
+      double rmax = 0.0;  // largest |R_aa| so far
+      for (int c = 0; c < m; ++c) {
+        const int buf = c & 1;
+        double* vb = vbuf + buf * VS;
+        if (cc == c) {
+#pragma unroll
+          for (int s2 = 0; s2 < S; ++s2) vb[s2 * kBR + g] = M[s2];
+        }
+        if (g == c % kBR) {
+          double x = 0.0;
+#pragma unroll
+          for (int s2 = 0; s2 < S; ++s2) x = (s2 == c / kBR) ? M[s2] : x;
+          rowc[buf * kBC + cc] = x;
+        }
+        __syncthreads();
+        const double x0 = vb[c];
+        double pp[2] = {0.0, 0.0};  // two chains: even and odd slots
+#pragma unroll
+        for (int s2 = 0; s2 < S; ++s2) {
+          const int r = s2 * kBR + g;
+          const double x = (r >= c) ? vb[r] : 0.0;
+          pp[s2 & 1] = fma(x, M[s2], pp[s2 & 1]);
+        }
+        part[(buf * kBR + g) * kBC + cc] = pp[0] + pp[1];
+        __syncthreads();
+        double sc = 0.0, n2 = 0.0;
+        {
+          double a4[4] = {0.0, 0.0, 0.0, 0.0}, b4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int g2 = 0; g2 < kBR; ++g2) {
+            a4[g2 & 3] += part[(buf * kBR + g2) * kBC + cc];
+            b4[g2 & 3] += part[(buf * kBR + g2) * kBC + c];
+          }
+          sc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+          n2 = (b4[0] + b4[1]) + (b4[2] + b4[3]);
+        }
+        const double scale = fmax(rmax, fabs(x0));
+        if (!(n2 > 0.0) || sqrt(n2) <= 1e-14 * fmax(scale, 1e-300)) singular = true;
+        const double alpha = (x0 > 0.0) ? -sqrt(n2) : sqrt(n2);
+        const double vtv = 2.0 * alpha * (alpha - x0);
+        if (cc > c && cc <= m && vtv > 0.0) {
+          const double d = sc - alpha * rowc[buf * kBC + cc];
+          const double tau = 2.0 * d / vtv;
+#pragma unroll
+          for (int s2 = 0; s2 < S; ++s2) {
+            const int r = s2 * kBR + g;
+            const double w = (r == c) ? (x0 - alpha) : ((r > c) ? vb[r] : 0.0);
+            M[s2] = fma(-tau, w, M[s2]);
+          }
+        }
+        if (cc == c) {
+#pragma unroll
+          for (int s2 = 0; s2 < S; ++s2) M[s2] = (s2 * kBR + g == c) ? alpha : M[s2];
+        }
+        rmax = fmax(rmax, fabs(alpha));
+      }
+      // back substitution R q = (Q^T rhs)(0:m), one wave, column by column
+      __syncthreads();
+      if (cc <= m) {
+#pragma unroll
+        for (int s2 = 0; s2 < S; ++s2) {
+          const int r = s2 * kBR + g;
+          if (r < m) R[r * kRld + cc] = M[s2];
+        }
+      }
+      __syncthreads();
+      if (wave == 0) {
+        double y = (lane < m) ? R[lane * kRld + m] : 0.0;
+        double q = 0.0;
+        for (int i = m - 1; i >= 0; --i) {
+          const double qi = __shfl(y, i, 64) / R[i * kRld + i];
+          if (lane == i) q = qi;
+          if (lane < i) y = fma(-R[lane * kRld + i], qi, y);
+        }
+        if (lane < m) {
+          const double v = singular ? 0.0 : q;
+          const int64_t posT =
+              (int64_t)sellT_off[k / kSlice] + (int64_t)lane * kSlice + (k % kSlice);
+          store_val<VT>((VT*)job.valsT + posT, v);
+          store_val<VT>((VT*)job.vals + tp2s[trowptr[k] + lane], v);
+        }
+        if (singular && lane == 0) atomicOr(status, 1);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Register slots per thread of the block kernel: rows per column / BR.
+int blk_slots(int maxI, int BR) {
+  int S = 4;
+  while (S * BR < maxI) S <<= 1;
+  return S;
+}
+
+// Row groups of the block kernel (8 or 16), or 0 when the per-wave kernel
+// handles the pattern: small column patterns keep the per-wave kernel, whose
+// lane groups match them.  The system's tuned choice wins when it is set.
+int blk_rows(morx_system sys) {
+  if (sys->max_J + 1 > kBC || sys->max_I > 32 * 8) return 0;
+  int BR = sys->tune_factor_rows;
+  if (BR < 0) BR = sys->max_J < 12 ? 0 : 16;
+  if (BR == 0) return 0;
+  if (BR == 16 && blk_slots(sys->max_I, 16) > 16) BR = 8;
+  const int S = blk_slots(sys->max_I, BR);
+  return blk_layout(sys->max_T, sys->max_I, S, BR).bytes <= (size_t)kLdsBudget ? BR : 0;
+}
+
 int ls_grid(morx_system sys) {
   int64_t cap = (int64_t)std::max(sys->ctx->num_cu, 1) * 64;
   return (int)std::min<int64_t>(sys->n, std::max<int64_t>(cap, 1));
 }
 
 }  // namespace
+
+bool factor_kernel_supported(morx_system sys, int rows) {
+  if (!sys->ls_supported) return false;
+  if (rows == 0) return true;
+  if (rows != 8 && rows != 16) return false;
+  if (sys->max_J + 1 > kBC || sys->max_I > 32 * 8) return false;
+  const int S = blk_slots(sys->max_I, rows);
+  if (S > (rows == 16 ? 16 : 32)) return false;
+  return blk_layout(sys->max_T, sys->max_I, S, rows).bytes <= (size_t)kLdsBudget;
+}
 
 morx_status ls_pattern_stats(morx_system sys, hipStream_t st) {
   DevBuf sb;
@@ -395,7 +692,36 @@ morx_status factor_build_many(morx_system sys, int32_t prec, const FactorJob* jo
   const int grid = ls_grid(sys);
   void* token = nullptr;
   trace_factor_begin(sys->ctx, st, &token);
-  switch (prec) {
+  const int BR = blk_rows(sys);
+  if (BR > 0) {
+    const int S = blk_slots(sys->max_I, BR);
+    const BlkLayout B = blk_layout(sys->max_T, sys->max_I, S, BR);
+    const int bgrid = (int)std::min<int64_t>(sys->n, (int64_t)std::max(sys->ctx->num_cu, 1) * 8);
+#define MORX_BLK_LAUNCH(VT, SV, BRV)                                                      \
+  k_factor_ls_blk<VT, SV, BRV><<<bgrid, kBC * BRV, B.bytes, st>>>(                         \
+      sys->trowptr, sys->tcol, sys->tval, sys->e, sys->tp2s, sys->sellT.off, sys->n,      \
+      (FactorJob*)jb.p, njobs, B, (int*)sb.p)
+#define MORX_BLK_S(VT)                                                   \
+  if (BR == 8) {                                                         \
+    switch (S) {                                                         \
+      case 4: MORX_BLK_LAUNCH(VT, 4, 8); break;                          \
+      case 8: MORX_BLK_LAUNCH(VT, 8, 8); break;                          \
+      case 16: MORX_BLK_LAUNCH(VT, 16, 8); break;                        \
+      default: MORX_BLK_LAUNCH(VT, 32, 8); break;                        \
+    }                                                                    \
+  } else {                                                               \
+    switch (S) {                                                         \
+      case 4: MORX_BLK_LAUNCH(VT, 4, 16); break;                         \
+      case 8: MORX_BLK_LAUNCH(VT, 8, 16); break;                         \
+      default: MORX_BLK_LAUNCH(VT, 16, 16); break;                       \
+    }                                                                    \
+  }
+    if (prec == MORX_F64) { MORX_BLK_S(double) }
+    else if (prec == MORX_F32) { MORX_BLK_S(float) }
+    else { MORX_BLK_S(uint16_t) }
+#undef MORX_BLK_S
+#undef MORX_BLK_LAUNCH
+  } else switch (prec) {
     case MORX_F64:
       k_factor_ls<double><<<grid, 64, L.bytes, st>>>(sys->trowptr, sys->tcol, sys->tval, sys->e,
                                                      sys->tp2s, sys->sellT.off, sys->n,

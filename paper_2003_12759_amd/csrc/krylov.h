@@ -39,9 +39,11 @@ struct KrylovBatch {
   DevBuf vec, avec, cols, part, ftab;
   ColInfo* hcols = nullptr;     // pinned host mirror of the slots
   const void** hftab = nullptr;  // pinned host mirror: [2][cap][lcap]
-  // graphs of one iteration segment, cached per (chain length, segment length)
+  // graphs of one iteration segment, cached per (chain length, segment
+  // length, columns, launch shape)
   struct Seg {
-    int maxL, iters;
+    int maxL;
+    int64_t key;
     hipGraph_t g;
     hipGraphExec_t x;
   };

@@ -63,6 +63,12 @@ class morx_serve_config(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class morx_tune(ctypes.Structure):
+    _fields_ = [("factor_kernel", ctypes.c_int32), ("cols_per_wave", ctypes.c_int32),
+                ("slices_per_wave", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("factor_ms", ctypes.c_double), ("iter_ms", ctypes.c_double)]
+
+
 class MorxError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -94,6 +100,9 @@ _SIG = {
     "morx_project": (_i32, [_p, _i32, _p, _i64, _p, _i64, _i32, _p, _i64, _i32, _p, _i64,
                             ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
                             ctypes.POINTER(_d), _i32, _p]),
+    "morx_system_get_tune": (_i32, [_p, ctypes.POINTER(morx_tune)]),
+    "morx_system_set_tune": (_i32, [_p, ctypes.POINTER(morx_tune)]),
+    "morx_autotune": (_i32, [_p, _d, _i32, _i32, _i32, ctypes.POINTER(morx_tune), _p]),
     "morx_serve_config_default": (None, [ctypes.POINTER(morx_serve_config)]),
     "morx_serve_start": (_i32, [_p, ctypes.POINTER(morx_serve_config), ctypes.POINTER(morx_opts),
                                 ctypes.POINTER(_p)]),
@@ -206,6 +215,31 @@ def morx_system_info(sys: int):
     a, b = _i64(), _i64()
     _check(_lib.morx_system_info(sys, ctypes.byref(a), ctypes.byref(b)), "morx_system_info")
     return a.value, b.value
+
+
+def _tune_dict(t: morx_tune) -> dict:
+    return {"factor_kernel": t.factor_kernel, "cols_per_wave": t.cols_per_wave,
+            "slices_per_wave": t.slices_per_wave, "factor_ms": t.factor_ms, "iter_ms": t.iter_ms}
+
+
+def morx_system_get_tune(sys: int) -> dict:
+    t = morx_tune()
+    _check(_lib.morx_system_get_tune(sys, ctypes.byref(t)), "morx_system_get_tune")
+    return _tune_dict(t)
+
+
+def morx_system_set_tune(sys: int, factor_kernel: int = -1, cols_per_wave: int = -1,
+                         slices_per_wave: int = -1) -> None:
+    t = morx_tune(factor_kernel, cols_per_wave, slices_per_wave, 0, 0.0, 0.0)
+    _check(_lib.morx_system_set_tune(sys, ctypes.byref(t)), "morx_system_set_tune")
+
+
+def morx_autotune(sys: int, sigma: float, ncols: int, chain_len: int = 1, prec: str = "f64",
+                  stream=None) -> dict:
+    t = morx_tune()
+    _check(_lib.morx_autotune(sys, float(sigma), int(ncols), int(chain_len), PREC[prec],
+                              ctypes.byref(t), _stream(stream)), "morx_autotune")
+    return _tune_dict(t)
 
 
 def morx_system_pattern(sys: int, rowptr: torch.Tensor, colind: torch.Tensor, stream=None) -> None:

@@ -10,6 +10,8 @@ Tolerances:
   CPU) and ||x - x_ref|| <= ||A_s^{-1}|| (||r|| + ||r_ref||), or <= 1e-8 ||x||
   against a sparse direct solve where ||A_s^{-1}|| is not computed.
 """
+import functools
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -108,24 +110,39 @@ def _oracle_csr_values(F_csc, A):
     return S, out
 
 
+@functools.lru_cache(maxsize=None)
+def _oracle_factor(name, kind, args):
+    A, e = CASES[name]()
+    if kind == "spai":
+        return ospai.spai(A, e, args[0])
+    return ospai.update(A, e, args[0], args[1])
+
+
+# least-squares kernel variants: -1 the built-in choice, 0 one wave per
+# column, 8 / 16 one block per column with that many row groups
+@pytest.mark.parametrize("kernel", [-1, 0, 8, 16])
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
-def test_factor_columns_match_oracle(ctx, name, prec):
+def test_factor_columns_match_oracle(ctx, name, prec, kernel):
     from paper_2003_12759_amd import morx
 
     A, e, S = _system(ctx, name)
+    try:
+        S.set_tune(factor_kernel=kernel)
+    except morx.MorxError:
+        S.close()
+        pytest.skip(f"factor kernel {kernel} does not fit the {name} pattern")
     rp, ci = S.pattern()
     Sref = opattern.pattern(A).tocsr()
     Sref.sort_indices()
     assert np.array_equal(rp, Sref.indptr) and np.array_equal(ci, Sref.indices)
     for kind, args in (("spai", (2.5,)), ("update", (2.5, 40.0)), ("update", (40.0, 0.3))):
-        _say(f"factor {kind}{args} {name} {prec}")
+        _say(f"factor {kind}{args} {name} {prec} kernel={kernel}")
         if kind == "spai":
             f = morx.morx_factor_spai(S.handle, args[0], prec)
-            ref = ospai.spai(A, e, args[0])
         else:
             f = morx.morx_factor_update(S.handle, args[0], args[1], prec)
-            ref = ospai.update(A, e, args[0], args[1])
+        ref = _oracle_factor(name, kind, args)
         vals = torch.empty(S.nnz_pattern, dtype=torch.float64, device="cuda")
         morx.morx_factor_values(f, vals)
         got = vals.cpu().numpy()
@@ -270,6 +287,67 @@ def test_batched_equals_plain_mimo(ctx):
         assert sb[k].status == 0 and spl[k].status == 0
         assert np.linalg.norm(Xb[:, k] - Xp[:, k]) <= 1e-8 * np.linalg.norm(Xp[:, k])
         assert np.linalg.norm(Yb[:, k] - Yp[:, k]) <= 1e-8 * np.linalg.norm(Yp[:, k])
+    S.close()
+
+
+@pytest.mark.parametrize("shape", [(1, -1), (2, -1), (8, -1), (-1, 2), (3, 4)])
+def test_solve_under_forced_launch_shapes(ctx, shape):
+    """Columns per wave and slices per wave change the launch, not the method:
+    every shape meets the oracle's accuracy on the three-round job."""
+    from paper_2003_12759_amd import api
+
+    ncw, spw = shape
+    w = make_workload(1, N=12, nshift=5, nrounds=2)
+    S = api.System(ctx, w.A, w.e)
+    S.set_tune(cols_per_wave=ncw, slices_per_wave=spw)
+    assert S.get_tune()["cols_per_wave"] == ncw and S.get_tune()["slices_per_wave"] == spw
+    ref = ojob.run(w.A, w.e, w.B, w.C, w.rounds, prec="f32", tol=1e-10, project=False)
+    for z, sig in enumerate(w.rounds):
+        _say(f"solve convdiff n={w.n} round {z} shape={shape}")
+        X, Y, st, stats = S.solve_shifts(sig, w.B, w.C, prec="f32", next_round=(z > 0))
+        Xg, Yg = X.cpu().numpy(), Y.cpu().numpy()
+        for i, s in enumerate(sig):
+            assert stats[i].status == 0
+            assert _true_relres(w.A, w.e, s, Xg[:, i], w.B[:, 0]) <= 1.01e-10
+            assert _true_relres(w.A, w.e, s, Yg[:, i], w.C[:, 0], trans=True) <= 1.01e-10
+            xr = ref["rounds"][z]["X"][:, i]
+            assert np.linalg.norm(Xg[:, i] - xr) <= 1e-8 * np.linalg.norm(xr)
+            ro = ref["rounds"][z]["stats"][i]
+            assert abs(stats[i].iters - ro.iters) <= max(3, 0.1 * ro.iters)
+    S.close()
+
+
+@pytest.mark.parametrize("name", ["laplace2d_n2025", "varcoef27_n343"])
+def test_autotune_then_solve(ctx, name):
+    from paper_2003_12759_amd import api
+
+    idx = {"laplace2d_n2025": 0, "varcoef27_n343": 4}[name]
+    w = make_workload(idx, N=45 if idx == 0 else 7, nshift=4)
+    S = api.System(ctx, w.A, w.e)
+    _say(f"autotune {name}")
+    t = S.autotune(float(w.rounds[0][0]), ncols=len(w.rounds[0]), chain_len=len(w.rounds[0]),
+                   prec="f32")
+    assert t["factor_kernel"] in (0, 8, 16)
+    assert 1 <= t["cols_per_wave"] <= 8 and t["slices_per_wave"] >= 1
+    assert t["factor_ms"] > 0 and t["iter_ms"] > 0
+    assert S.get_tune()["cols_per_wave"] == t["cols_per_wave"]
+    X, Y, st, stats = S.solve_shifts(w.rounds[0], w.B, w.C, prec="f32")
+    Xg = X.cpu().numpy()
+    for i, s in enumerate(w.rounds[0]):
+        assert stats[i].status == 0
+        assert _true_relres(w.A, w.e, s, Xg[:, i], w.B[:, 0]) <= 1.01e-10
+    S.close()
+
+
+def test_tune_rejects_bad_values(ctx):
+    from paper_2003_12759_amd import api, morx
+
+    w = make_workload(0, N=10, nshift=2)
+    S = api.System(ctx, w.A, w.e)
+    for bad in ({"cols_per_wave": 9}, {"cols_per_wave": 0}, {"slices_per_wave": 65},
+                {"factor_kernel": 4}):
+        with pytest.raises(morx.MorxError):
+            S.set_tune(**bad)
     S.close()
 
 
