@@ -284,6 +284,9 @@ def main():
                     help="preconditioner apply precision (default: FP64)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch shapes instead of timing candidates first")
+    ap.add_argument("--shapes", default=None,
+                    help="pin the launch shapes instead of autotuning: "
+                         "factor_kernel,cols_per_wave,slices_per_wave (e.g. 0,2,2)")
     ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=16, help="serving: slots per system")
     ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 1.0],
@@ -316,7 +319,11 @@ def main():
     # launch shapes: timed on this system before the clock starts (a
     # one-time cost per system, like building it)
     tuned = None
-    if not args.no_autotune:
+    if args.shapes:
+        fk, ncw, spw = (int(x) for x in args.shapes.split(","))
+        S.set_tune(factor_kernel=fk, cols_per_wave=ncw, slices_per_wave=spw)
+        tuned = dict(S.get_tune(), pinned=True)
+    elif not args.no_autotune:
         t_tune = time.perf_counter()
         tuned = S.autotune(float(w.rounds[0][0]), ncols=len(w.rounds[0]) * w.B.shape[1],
                            chain_len=len(w.rounds[0]) + len(w.rounds) - 1, prec=w.prec)
@@ -371,21 +378,24 @@ def main():
                              "GBps": (byts / (ms * 1e-3) / 1e9) if byts > 0 else None}
         launches, ms, byts = tr[DOMINANT]
         achieved = byts / (ms * 1e-3) / 1e9
-        traffic = None
-        if os.path.exists(TRAFFIC_FILE):
-            with open(TRAFFIC_FILE) as f:
-                tf = json.load(f)
-            # counters describe the kernel source they were taken on
-            if tf.get("source_sha256") == kernel_source_hash():
-                traffic = tf.get("bytes_per_launch")
         ncol = len(w.rounds[0]) * w.B.shape[1]
         ctype = {"f64": "double", "f32": "float", "bf16": "unsigned short"}
         ncmax = S.get_tune()["cols_per_wave"]
         chunks = -(-ncol // (ncmax if ncmax > 0 else 8))
+        roof_kernel = f"k_chain_step<{ctype[w.prec]}, {ctype[apply]}, {-(-ncol // chunks)}>"
+        traffic = None
+        if os.path.exists(TRAFFIC_FILE):
+            with open(TRAFFIC_FILE) as f:
+                tf = json.load(f)
+            # counters describe the kernel source and instance they were taken on
+            entry = tf.get("kernels", {}).get(roof_kernel)
+            if (tf.get("source_sha256") == kernel_source_hash() and entry
+                    and w.name in tf.get("workload", "")):
+                traffic = entry.get("bytes_per_launch")
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                     "traffic": traffic,
-                    "kernel": f"k_chain_step<{ctype[w.prec]}, {ctype[apply]}, {-(-ncol // chunks)}>",
+                    "kernel": roof_kernel,
                     "avg_launch_us": round(1e3 * ms / launches, 2),
                     "alg_bytes_per_launch": byts / launches}
 
