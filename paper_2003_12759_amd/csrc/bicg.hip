@@ -288,8 +288,17 @@ __device__ __forceinline__ const AT* chain_input(const IterArgs& a, int c, bool 
     return aptr<AT>(a, bwd ? A_RT : A_R, c);
 }
 
+// Slots per chunk of the product loops: every index, value and gather load of
+// a chunk is issued before its first use; wide tiles take shorter chunks to
+// stay within the register budget.
+template <int NC>
+struct ChunkLen {
+  static constexpr int value = NC <= 4 ? 8 : 4;
+};
+
 template <typename VT, typename AT, int NC>
 __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s, int do_rho) {
+  constexpr int kU = ChunkLen<NC>::value;
   const WaveCtx t = wave_ctx(a);
   const int c0 = blockIdx.y * NC;
   const bool bwd = blockIdx.z == 1;
@@ -316,56 +325,97 @@ __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s, int do
       dst[j] = (jf == 0) ? aptr<AT>(a, A_ZT, c) : aptr<AT>(a, A_TT0 + (k & 1), c);
     }
   }
+  // valid is the same for the whole block (one column chunk per block)
+  if (!valid) return;
+  // Inactive columns of the chunk run along with the first active one's
+  // source and factor (cache hits, results dropped), so the chunk loop has no
+  // per-column branch and every load of a chunk is in flight at once.
+  const AT* src0 = nullptr;
+  const VT* fv0 = nullptr;
+#pragma unroll
+  for (int j = NC - 1; j >= 0; --j)
+    if (valid & (1u << j)) {
+      src0 = src[j];
+      fv0 = fv[j];
+    }
+  bool shared = true;  // every column applies the same factor (batched solves)
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    if (!(valid & (1u << j))) {
+      src[j] = src0;
+      fv[j] = fv0;
+    }
+    shared = shared && fv[j] == fv0;
+  }
   double v[NC][3];
 #pragma unroll
   for (int j = 0; j < NC; ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
-  if (valid) {
-    const int32_t* off = bwd ? a.offT : a.off;
-    const int32_t* col = bwd ? a.colT : a.col;
-    for (int64_t sl = t.s_begin; sl < t.s_end; ++sl) {
-      const int32_t base = off[sl];
-      const int32_t w = (off[sl + 1] - base) >> 6;
-      const int32_t p0 = base + t.lane;
-      const int64_t i = sl * kSlice + t.lane;
-      double acc[NC];
+  const int32_t* off = bwd ? a.offT : a.off;
+  const int32_t* col = bwd ? a.colT : a.col;
+  for (int64_t sl = t.s_begin; sl < t.s_end; ++sl) {
+    const int32_t base = gld(off + sl);
+    const int32_t w = (gld(off + sl + 1) - base) >> 6;
+    const int32_t p0 = base + t.lane;
+    const int64_t i = sl * kSlice + t.lane;
+    double acc[NC];
 #pragma unroll
-      for (int j = 0; j < NC; ++j) acc[j] = 0.0;
-      for (int32_t m0 = 0; m0 < w; m0 += kUnroll) {
-        SliceChunk ch;
-        int32_t pp[kUnroll];
+    for (int j = 0; j < NC; ++j) acc[j] = 0.0;
+    // column indices of the next chunk are loaded while the current chunk's
+    // values and gathers are in flight
+    int32_t nix[kU];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          pp[u] = p0 + ((m0 + u < w) ? (m0 + u) * kSlice : 0);
-          ch.c[u] = col[pp[u]];
-        }
-        const VT* loaded = nullptr;
-        double vv[kUnroll];
+    for (int u = 0; u < kU; ++u) nix[u] = gld(col + p0 + (u < w ? u * kSlice : 0));
+    for (int32_t m0 = 0; m0 < w; m0 += kU) {
+      int32_t pp[kU], cix[kU];
+      bool ok[kU];
 #pragma unroll
-        for (int j = 0; j < NC; ++j) {
-          if (!(valid & (1u << j))) continue;
-          if (fv[j] != loaded) {
-            loaded = fv[j];
+      for (int u = 0; u < kU; ++u) {
+        ok[u] = m0 + u < w;
+        pp[u] = p0 + (ok[u] ? (m0 + u) * kSlice : 0);  // past the row: slot 0, value dropped
+        cix[u] = nix[u];
+      }
+      if (m0 + kU < w) {
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) vv[u] = (m0 + u < w) ? load_val<VT>(loaded + pp[u]) : 0.0;
-          }
-          acc[j] = chunk_dot(ch, vv, m0, w, src[j], acc[j]);
+        for (int u = 0; u < kU; ++u) {
+          const int32_t mn = m0 + kU + u;
+          nix[u] = gld(col + p0 + (mn < w ? mn * kSlice : 0));
         }
       }
-      if (i < a.n) {
+      if (shared) {
+        double vv[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const double raw = gload_val<VT>(fv0 + pp[u]);
+          vv[u] = ok[u] ? raw : 0.0;
+        }
 #pragma unroll
         for (int j = 0; j < NC; ++j)
-          if (valid & (1u << j)) {
-            const AT zs = (AT)acc[j];
-            dst[j][i] = zs;
-            if (rho_half) {
-              const double zi = (double)zs;
-              const double ri = vptr(a, V_R, c0 + j)[i];
-              v[j][0] = fma(zi, ri, v[j][0]);
-              v[j][1] = fma(zi, zi, v[j][1]);
-              v[j][2] = fma(ri, ri, v[j][2]);
-            }
+#pragma unroll
+          for (int u = 0; u < kU; ++u) acc[j] = fma(vv[u], (double)gld(src[j] + cix[u]), acc[j]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const double raw = gload_val<VT>(fv[j] + pp[u]);
+            acc[j] = fma(ok[u] ? raw : 0.0, (double)gld(src[j] + cix[u]), acc[j]);
           }
       }
+    }
+    if (i < a.n) {
+#pragma unroll
+      for (int j = 0; j < NC; ++j)
+        if (valid & (1u << j)) {
+          const AT zs = (AT)acc[j];
+          gst(dst[j] + i, zs);
+          if (rho_half) {
+            const double zi = (double)zs;
+            const double ri = gld(vptr(a, V_R, c0 + j) + i);
+            v[j][0] = fma(zi, ri, v[j][0]);
+            v[j][1] = fma(zi, zi, v[j][1]);
+            v[j][2] = fma(ri, ri, v[j][2]);
+          }
+        }
     }
   }
   if (rho_half) block_partials<NC, 3>(a, t, c0, valid, v, a.part_rho);
@@ -434,11 +484,14 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(IterArgs a) {
 // delta = p~^T q, ||p~||^2, ||q||^2
 template <typename AT, int NC>
 __global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
+  constexpr int kU = ChunkLen<NC>::value;
   const WaveCtx t = wave_ctx(a);
   const int c0 = blockIdx.y * NC;
   unsigned valid = 0;
   double beta[NC], sig[NC];
   bool first[NC];
+  const AT *z[NC], *zt[NC];
+  const double *po[NC], *pto[NC];
 #pragma unroll
   for (int j = 0; j < NC; ++j) {
     const int c = min(c0 + j, a.nc - 1);
@@ -447,66 +500,90 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
     beta[j] = ci.beta;
     sig[j] = ci.sigma;
     first[j] = ci.first != 0;
+    z[j] = aptr<AT>(a, A_Z, c);
+    zt[j] = aptr<AT>(a, A_ZT, c);
+    po[j] = vptr(a, V_P0 + (par ^ 1), c);
+    pto[j] = vptr(a, V_PT0 + (par ^ 1), c);
   }
+  // valid is the same for the whole block; columns past the batch read the
+  // last column's vectors and their results are dropped
+  if (!valid) return;
   double v[NC][3];
 #pragma unroll
   for (int j = 0; j < NC; ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
-  if (valid) {
-    for (int64_t sl = t.s_begin; sl < t.s_end; ++sl) {
-      const int64_t i = sl * kSlice + t.lane;
-      double acc[NC], acct[NC];
+  for (int64_t sl = t.s_begin; sl < t.s_end; ++sl) {
+    const int64_t i = sl * kSlice + t.lane;
+    double acc[NC], acct[NC];
 #pragma unroll
-      for (int j = 0; j < NC; ++j) acc[j] = acct[j] = 0.0;
-      {
-        const int32_t base = a.off[sl];
-        const int32_t w = (a.off[sl + 1] - base) >> 6;
-        for (int32_t m0 = 0; m0 < w; m0 += kUnroll) {
-          SliceChunk ch;
-          double vv[kUnroll];
-          load_chunk<double>(a.col, a.valA, base + t.lane, w, m0, ch, vv);
+    for (int j = 0; j < NC; ++j) acc[j] = acct[j] = 0.0;
+    // p = z + beta p_old is formed at every gathered index (first step of a
+    // cycle: p = z)
 #pragma unroll
-          for (int j = 0; j < NC; ++j)
-            if (valid & (1u << j))
-              acc[j] = chunk_dot_p(ch, vv, m0, w, aptr<AT>(a, A_Z, c0 + j),
-                                   vptr(a, V_P0 + (par ^ 1), c0 + j), beta[j], first[j], acc[j]);
+    for (int h = 0; h < 2; ++h) {
+      const int32_t* off = h ? a.offT : a.off;
+      const int32_t* col = h ? a.colT : a.col;
+      const double* val = h ? a.valAT : a.valA;
+      const int32_t base = gld(off + sl);
+      const int32_t w = (gld(off + sl + 1) - base) >> 6;
+      const int32_t p0 = base + t.lane;
+      int32_t nix[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) nix[u] = gld(col + p0 + (u < w ? u * kSlice : 0));
+      for (int32_t m0 = 0; m0 < w; m0 += kU) {
+        int32_t cix[kU];
+        double vv[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const bool ok = m0 + u < w;
+          const int32_t pp = p0 + (ok ? (m0 + u) * kSlice : 0);
+          cix[u] = nix[u];
+          const double raw = gld(val + pp);
+          vv[u] = ok ? raw : 0.0;
         }
-      }
-      {
-        const int32_t base = a.offT[sl];
-        const int32_t w = (a.offT[sl + 1] - base) >> 6;
-        for (int32_t m0 = 0; m0 < w; m0 += kUnroll) {
-          SliceChunk ch;
-          double vv[kUnroll];
-          load_chunk<double>(a.colT, a.valAT, base + t.lane, w, m0, ch, vv);
+        if (m0 + kU < w) {
 #pragma unroll
-          for (int j = 0; j < NC; ++j)
-            if (valid & (1u << j))
-              acct[j] = chunk_dot_p(ch, vv, m0, w, aptr<AT>(a, A_ZT, c0 + j),
-                                    vptr(a, V_PT0 + (par ^ 1), c0 + j), beta[j], first[j], acct[j]);
-        }
-      }
-      if (i < a.n) {
-        const double ei = a.e[i];
-#pragma unroll
-        for (int j = 0; j < NC; ++j)
-          if (valid & (1u << j)) {
-            const int c = c0 + j;
-            const double zi = (double)aptr<AT>(a, A_Z, c)[i];
-            const double zti = (double)aptr<AT>(a, A_ZT, c)[i];
-            const double pi = first[j] ? zi : fma(beta[j], vptr(a, V_P0 + (par ^ 1), c)[i], zi);
-            const double pti = first[j] ? zti : fma(beta[j], vptr(a, V_PT0 + (par ^ 1), c)[i], zti);
-            const double se = sig[j] * ei;
-            const double qi = fma(se, pi, -acc[j]);
-            const double qti = fma(se, pti, -acct[j]);
-            vptr(a, V_P0 + par, c)[i] = pi;
-            vptr(a, V_PT0 + par, c)[i] = pti;
-            vptr(a, V_Q, c)[i] = qi;
-            vptr(a, V_QT, c)[i] = qti;
-            v[j][0] = fma(pti, qi, v[j][0]);
-            v[j][1] = fma(pti, pti, v[j][1]);
-            v[j][2] = fma(qi, qi, v[j][2]);
+          for (int u = 0; u < kU; ++u) {
+            const int32_t mn = m0 + kU + u;
+            nix[u] = gld(col + p0 + (mn < w ? mn * kSlice : 0));
           }
+        }
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const AT* zz = h ? zt[j] : z[j];
+          const double* pp_old = h ? pto[j] : po[j];
+          double sacc = h ? acct[j] : acc[j];
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const double zv = (double)gld(zz + cix[u]);
+            const double pv = fma(beta[j], gld(pp_old + cix[u]), zv);
+            sacc = fma(vv[u], first[j] ? zv : pv, sacc);
+          }
+          if (h) acct[j] = sacc;
+          else acc[j] = sacc;
+        }
       }
+    }
+    if (i < a.n) {
+      const double ei = gld(a.e + i);
+#pragma unroll
+      for (int j = 0; j < NC; ++j)
+        if (valid & (1u << j)) {
+          const int c = c0 + j;
+          const double zi = (double)gld(z[j] + i);
+          const double zti = (double)gld(zt[j] + i);
+          const double pi = first[j] ? zi : fma(beta[j], gld(po[j] + i), zi);
+          const double pti = first[j] ? zti : fma(beta[j], gld(pto[j] + i), zti);
+          const double se = sig[j] * ei;
+          const double qi = fma(se, pi, -acc[j]);
+          const double qti = fma(se, pti, -acct[j]);
+          gst(vptr(a, V_P0 + par, c) + i, pi);
+          gst(vptr(a, V_PT0 + par, c) + i, pti);
+          gst(vptr(a, V_Q, c) + i, qi);
+          gst(vptr(a, V_QT, c) + i, qti);
+          v[j][0] = fma(pti, qi, v[j][0]);
+          v[j][1] = fma(pti, pti, v[j][1]);
+          v[j][2] = fma(qi, qi, v[j][2]);
+        }
     }
   }
   block_partials<NC, 3>(a, t, c0, valid, v, a.part_delta);

@@ -212,6 +212,29 @@ __device__ __forceinline__ void store_val<uint16_t>(uint16_t* p, double v) {
   *p = f32_to_bf16_rne((float)v);
 }
 
+// Loads and stores through the global address space.  Pointers that come out
+// of device memory (factor tables, slot descriptors) or out of selects are
+// generic to the compiler, which then emits flat instructions that also count
+// against the LDS wait counter; these casts keep them global.
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+template <typename T>
+__device__ __forceinline__ double gload_val(const T* p);
+template <>
+__device__ __forceinline__ double gload_val<double>(const double* p) { return gld(p); }
+template <>
+__device__ __forceinline__ double gload_val<float>(const float* p) { return (double)gld(p); }
+template <>
+__device__ __forceinline__ double gload_val<uint16_t>(const uint16_t* p) {
+  return (double)__uint_as_float(((uint32_t)gld(p)) << 16);
+}
+
 inline size_t prec_bytes(int32_t prec) { return prec == MORX_F64 ? 8 : (prec == MORX_F32 ? 4 : 2); }
 
 // One row of a sliced-ELL product for up to NC columns: acc[j] += sum_m v_m * x_j[col_m].
