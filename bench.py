@@ -286,7 +286,7 @@ def main():
                     help="keep the built-in launch shapes instead of timing candidates first")
     ap.add_argument("--shapes", default=None,
                     help="pin the launch shapes instead of autotuning: "
-                         "factor_kernel,cols_per_wave,slices_per_wave (e.g. 0,2,2)")
+                         "factor_kernel,cols_per_wave,slices_per_wave[,spmv_cols_per_wave]")
     ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=16, help="serving: slots per system")
     ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 1.0],
@@ -324,8 +324,9 @@ def main():
     # one-time cost per system, like building it)
     tuned = None
     if args.shapes:
-        fk, ncw, spw = (int(x) for x in args.shapes.split(","))
-        S.set_tune(factor_kernel=fk, cols_per_wave=ncw, slices_per_wave=spw)
+        sh = [int(x) for x in args.shapes.split(",")] + [-1]
+        S.set_tune(factor_kernel=sh[0], cols_per_wave=sh[1], slices_per_wave=sh[2],
+                   spmv_cols_per_wave=sh[3])
         tuned = dict(S.get_tune(), pinned=True)
     elif not args.no_autotune:
         t_tune = time.perf_counter()

@@ -200,18 +200,22 @@ morx_status morx_project(morx_system sys, int32_t r, const double* V, int64_t ld
  *   factor_kernel    0: one wave per column; 8 or 16: one block of 32 x 8 or
  *                    32 x 16 threads per column, the local matrix in
  *                    registers (patterns with |J_k| < 32 and |I_k| <= 256);
- *   cols_per_wave    iteration kernels: most right-hand-side columns one wave
- *                    carries over its rows, sharing every matrix and factor
- *                    load among them (1..8);
+ *   cols_per_wave    chain step: most right-hand-side columns one wave
+ *                    carries over its rows, sharing every factor load among
+ *                    them (1..8);
  *   slices_per_wave  iteration kernels: 64-row slices per wave (1..64; raised
- *                    to the least value that keeps <= 1024 row blocks).
+ *                    to the least value that keeps <= 1024 row blocks);
+ *   spmv_cols_per_wave  shifted pair and true residual: the same as
+ *                    cols_per_wave for the operator's loads (1..8; -1 follows
+ *                    cols_per_wave).
  * morx_system_set_tune checks the values (MORX_E_INVALID) and they apply from
  * the next call on the system.  morx_autotune times the candidates on the
  * system itself: one SPAI factor build at `sigma` (storage prec) per factor
  * kernel, then a few BiCG iterations of ncols column pairs per iteration
  * shape (HIP events), column c preconditioned by 1 + c * chain_len / ncols
  * distinct factors of one list, as the chains of one round are
- * (chain_len 1..64: the longest chain of the solves to come).  It keeps the
+ * (chain_len 1..64: the longest chain of the solves to come); chain tile and
+ * row block first, then the shifted pair's tile.  It keeps the
  * fastest, fills *out (factor_ms and iter_ms: the chosen build and one
  * iteration) and returns MORX_OK.  Shapes change rounding order only.  It
  * allocates its own scratch on the device.
@@ -220,7 +224,7 @@ typedef struct {
   int32_t factor_kernel;
   int32_t cols_per_wave;
   int32_t slices_per_wave;
-  int32_t reserved;
+  int32_t spmv_cols_per_wave;
   double factor_ms;
   double iter_ms;
 } morx_tune;

@@ -60,7 +60,8 @@ constexpr double kBreakdown = 1e-14;
 struct IterArgs {
   int64_t n, ld, nnzS, nslices;
   int cap, nc, nblk, spw, vbytes, maxL, lcap;
-  int ncmax;  // most columns per wave
+  int ncmax;       // most columns per wave, chain step
+  int ncmax_spmv;  // most columns per wave, shifted pair and true residual
   const int32_t *off, *col, *offT, *colT;
   const double *valA, *valAT, *e;
   double* vec;
@@ -1060,6 +1061,7 @@ static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   a.spw = (int)std::max<int64_t>(1, (per_blk_min + kWavesPerBlock - 1) / kWavesPerBlock);
   if (sys->tune_spw > 0) a.spw = std::max(a.spw, (int)sys->tune_spw);
   a.ncmax = sys->tune_nc > 0 ? (int)sys->tune_nc : kMaxNC;
+  a.ncmax_spmv = sys->tune_nc_spmv > 0 ? (int)sys->tune_nc_spmv : a.ncmax;
   int64_t nb = (a.nslices + (int64_t)kWavesPerBlock * a.spw - 1) / ((int64_t)kWavesPerBlock * a.spw);
   nb = std::max<int64_t>(8, (nb + 7) / 8 * 8);
   a.nblk = (int)nb;
@@ -1139,20 +1141,23 @@ static void enqueue_chain_prec(const IterArgs& a, int prec, hipStream_t st, Trac
 static morx_status enqueue_iterations(const IterArgs& a, int prec, int iters, hipStream_t st,
                                       TraceState* t) {
   const int ncv = pick_nc(a.nc, a.ncmax);
+  const int ncs = pick_nc(a.nc, a.ncmax_spmv);
   const bool f32 = a.abytes == 4;
   for (int it = 0; it < iters; ++it) {
     const int par = it & 1;
     MORX_NC_DISPATCH(ncv, {
-      const dim3 g1 = grid_of(a, NC, 1);
       if (f32) enqueue_chain_prec<float, NC>(a, prec, st, t);
       else enqueue_chain_prec<double, NC>(a, prec, st, t);
-      k_fin_rho<<<1, kFinThreads, 0, st>>>(a);
+    });
+    k_fin_rho<<<1, kFinThreads, 0, st>>>(a);
+    MORX_NC_DISPATCH(ncs, {
+      const dim3 g1 = grid_of(a, NC, 1);
       if (f32) launch(t, TR_SPMV, k_spmv_pair<float, NC>, g1, dim3(kBlock), st, a, par);
       else launch(t, TR_SPMV, k_spmv_pair<double, NC>, g1, dim3(kBlock), st, a, par);
-      k_fin_delta<<<1, kFinThreads, 0, st>>>(a);
-      // elementwise: one column per wave, nothing to share between columns
-      launch(t, TR_UPDATE, k_update<1>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
     });
+    k_fin_delta<<<1, kFinThreads, 0, st>>>(a);
+    // elementwise: one column per wave, nothing to share between columns
+    launch(t, TR_UPDATE, k_update<1>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
   }
   MORX_HIP(hipGetLastError());
   return MORX_OK;
@@ -1168,7 +1173,7 @@ morx_status batch_launch_init(KrylovBatch& b, int nc, hipStream_t st) {
 
 morx_status batch_launch_true(KrylovBatch& b, int nc, hipStream_t st) {
   const IterArgs a = make_args(b, nc, 1);
-  MORX_NC_DISPATCH(pick_nc(nc, a.ncmax),
+  MORX_NC_DISPATCH(pick_nc(nc, a.ncmax_spmv),
                    k_true_residual<NC><<<grid_of(a, NC, 1), kBlock, 0, st>>>(a));
   k_fin_true<<<1, kFinThreads, 0, st>>>(a);
   MORX_HIP(hipGetLastError());
@@ -1193,7 +1198,8 @@ morx_status batch_launch_segment(KrylovBatch& b, int nc, int maxL, int iters, bo
                                  hipStream_t st, TraceState* t) {
   const IterArgs a = make_args(b, nc, maxL);
   if (!use_graph || t) return enqueue_iterations(a, b.prec, iters, st, t);
-  const int64_t key = (((int64_t)iters * 1024 + nc) * 128 + a.spw) * 16 + a.ncmax;
+  const int64_t key =
+      ((((int64_t)iters * 1024 + nc) * 128 + a.spw) * 16 + a.ncmax) * 16 + a.ncmax_spmv;
   for (auto& g : b.graphs)
     if (g.maxL == maxL && g.key == key) {
       MORX_HIP(hipGraphLaunch(g.x, st));
@@ -1547,6 +1553,7 @@ extern "C" morx_status morx_system_get_tune(morx_system sys, morx_tune* out) {
   out->factor_kernel = sys->tune_factor_rows;
   out->cols_per_wave = sys->tune_nc;
   out->slices_per_wave = sys->tune_spw;
+  out->spmv_cols_per_wave = sys->tune_nc_spmv;
   return MORX_OK;
 }
 
@@ -1559,10 +1566,15 @@ extern "C" morx_status morx_system_set_tune(morx_system sys, const morx_tune* t)
                MORX_E_INVALID, "morx_system_set_tune: cols_per_wave must be -1 or 1..%d", kMaxNC);
   MORX_REQUIRE(t->slices_per_wave == -1 || (t->slices_per_wave >= 1 && t->slices_per_wave <= 64),
                MORX_E_INVALID, "morx_system_set_tune: slices_per_wave must be -1 or 1..64");
+  MORX_REQUIRE(t->spmv_cols_per_wave == -1 ||
+                   (t->spmv_cols_per_wave >= 1 && t->spmv_cols_per_wave <= kMaxNC),
+               MORX_E_INVALID, "morx_system_set_tune: spmv_cols_per_wave must be -1 or 1..%d",
+               kMaxNC);
   std::lock_guard<std::mutex> lk(sys->ctx->mu);
   sys->tune_factor_rows = t->factor_kernel;
   sys->tune_nc = t->cols_per_wave;
   sys->tune_spw = t->slices_per_wave;
+  sys->tune_nc_spmv = t->spmv_cols_per_wave;
   return MORX_OK;
 }
 
@@ -1645,55 +1657,63 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
   }
   k_tune_rhs<<<(unsigned)((sys->n + 255) / 256), 256, 0, st>>>((double*)rhs.p, sys->n, sys->n_pad,
                                                                 ncols);
-  const int saved_nc = sys->tune_nc, saved_spw = sys->tune_spw;
+  const int saved_nc = sys->tune_nc, saved_spw = sys->tune_spw, saved_ncs = sys->tune_nc_spmv;
   sys->tune_nc = -1;
   sys->tune_spw = -1;
+  sys->tune_nc_spmv = -1;
   const IterArgs a0 = make_args(kb, ncols, chain_len);
   const int spw0 = a0.spw;
-  double best_i = 1e300;
-  int best_nc = -1, best_spw = -1;
-  std::vector<int> seen_nc;
   constexpr int kWarm = 2, kTimed = 6;
+  // ms per iteration at one shape (fresh recurrences every time)
+  auto time_shape = [&](int ncmax, int spw, int ncs, double* ms) -> morx_status {
+    sys->tune_nc = ncmax;
+    sys->tune_spw = spw;
+    sys->tune_nc_spmv = ncs;
+    for (int c = 0; c < ncols; ++c) {
+      ColInfo ci = {};
+      ci.sigma = sigma;
+      ci.tol = 0.0;  // never converges: every timed iteration does full work
+      ci.bsrc = (const double*)rhs.p + (int64_t)c * sys->n_pad;
+      ci.csrc = ci.bsrc;
+      ci.state = COL_INIT;
+      ci.L = 1 + (int)(((int64_t)c * chain_len) / ncols);
+      ci.first = 1;
+      ci.maxit = 1 << 20;
+      ci.check_p = ci.check_d = 1;
+      kb.hcols[c] = ci;
+      for (int j = 0; j < chain_len; ++j) {
+        const bool in = j < ci.L;
+        kb.hftab[(size_t)c * kb.lcap + j] = in ? chain[j]->vals.p : nullptr;
+        kb.hftab[((size_t)kb.cap + c) * kb.lcap + j] = in ? chain[j]->valsT.p : nullptr;
+      }
+    }
+    MORX_TRY(batch_upload(kb, 0, ncols, st));
+    MORX_TRY(batch_launch_init(kb, ncols, st));
+    const IterArgs a = make_args(kb, ncols, chain_len);
+    MORX_TRY(enqueue_iterations(a, prec, kWarm, st, nullptr));
+    MORX_HIP(hipEventRecord(e0, st));
+    MORX_TRY(enqueue_iterations(a, prec, kTimed, st, nullptr));
+    MORX_HIP(hipEventRecord(e1, st));
+    MORX_TRY(time_events(e0, e1, st, ms));
+    *ms /= kTimed;
+    return MORX_OK;
+  };
+  double best_i = 1e300;
+  int best_nc = -1, best_spw = -1, best_ncs = -1;
+  // chain tile and row block (the shifted pair follows the chain tile) ...
+  std::vector<int> seen;
   for (int ncmax : {8, 4, 2, 1}) {
     const int ncv = pick_nc(ncols, ncmax);
-    if (std::find(seen_nc.begin(), seen_nc.end(), ncv) != seen_nc.end()) continue;
-    seen_nc.push_back(ncv);
+    if (std::find(seen.begin(), seen.end(), ncv) != seen.end()) continue;
+    seen.push_back(ncv);
     for (int mult : {1, 2, 4}) {
       const int spw = spw0 * mult;
       if (mult > 1 && (sys->nslice + (int64_t)kWavesPerBlock * spw - 1) /
                               ((int64_t)kWavesPerBlock * spw) < 256)
         break;  // too few row blocks to fill the chip
-      sys->tune_nc = ncmax;
-      sys->tune_spw = spw;
-      for (int c = 0; c < ncols; ++c) {
-        ColInfo ci = {};
-        ci.sigma = sigma;
-        ci.tol = 0.0;  // never converges: every timed iteration does full work
-        ci.bsrc = (const double*)rhs.p + (int64_t)c * sys->n_pad;
-        ci.csrc = ci.bsrc;
-        ci.state = COL_INIT;
-        ci.L = 1 + (int)(((int64_t)c * chain_len) / ncols);
-        ci.first = 1;
-        ci.maxit = 1 << 20;
-        ci.check_p = ci.check_d = 1;
-        kb.hcols[c] = ci;
-        for (int j = 0; j < chain_len; ++j) {
-          const bool in = j < ci.L;
-          kb.hftab[(size_t)c * kb.lcap + j] = in ? chain[j]->vals.p : nullptr;
-          kb.hftab[((size_t)kb.cap + c) * kb.lcap + j] = in ? chain[j]->valsT.p : nullptr;
-        }
-      }
-      s = batch_upload(kb, 0, ncols, st);
-      if (s == MORX_OK) s = batch_launch_init(kb, ncols, st);
-      const IterArgs a = make_args(kb, ncols, chain_len);
-      if (s == MORX_OK) s = enqueue_iterations(a, prec, kWarm, st, nullptr);
-      if (s == MORX_OK && hipEventRecord(e0, st) != hipSuccess) s = MORX_E_HIP;
-      if (s == MORX_OK) s = enqueue_iterations(a, prec, kTimed, st, nullptr);
-      if (s == MORX_OK && hipEventRecord(e1, st) != hipSuccess) s = MORX_E_HIP;
       double ms = 0.0;
-      if (s == MORX_OK) s = time_events(e0, e1, st, &ms);
+      s = time_shape(ncmax, spw, -1, &ms);
       if (s != MORX_OK) break;
-      ms /= kTimed;
       if (ms < best_i) {
         best_i = ms;
         best_nc = ncmax;
@@ -1702,20 +1722,40 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
     }
     if (s != MORX_OK) break;
   }
+  // ... then the shifted pair's own tile with the chain shape fixed
+  if (s == MORX_OK) {
+    seen.clear();
+    seen.push_back(pick_nc(ncols, best_nc));
+    for (int ncs : {8, 4, 2, 1}) {
+      const int ncv = pick_nc(ncols, ncs);
+      if (std::find(seen.begin(), seen.end(), ncv) != seen.end()) continue;
+      seen.push_back(ncv);
+      double ms = 0.0;
+      s = time_shape(best_nc, best_spw, ncs, &ms);
+      if (s != MORX_OK) break;
+      if (ms < best_i) {
+        best_i = ms;
+        best_ncs = ncs;
+      }
+    }
+  }
   hipStreamSynchronize(st);
   dev_free(rhs);
   batch_free(kb);
   if (s != MORX_OK) {
     sys->tune_nc = saved_nc;
     sys->tune_spw = saved_spw;
+    sys->tune_nc_spmv = saved_ncs;
     return s;
   }
   sys->tune_nc = best_nc;
   sys->tune_spw = best_spw;
+  sys->tune_nc_spmv = best_ncs;
   memset(out, 0, sizeof(*out));
   out->factor_kernel = best_rows;
   out->cols_per_wave = best_nc;
   out->slices_per_wave = best_spw;
+  out->spmv_cols_per_wave = best_ncs;
   out->factor_ms = best_f;
   out->iter_ms = best_i;
   return MORX_OK;

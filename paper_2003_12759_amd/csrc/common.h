@@ -124,7 +124,8 @@ struct morx_system_s {
   bool ls_supported = true;
   // launch shapes (morx_tune): -1 means the built-in heuristic
   int32_t tune_factor_rows = -1;  // least-squares kernel: 0 per wave, 8 or 16 row groups
-  int32_t tune_nc = -1;           // iteration kernels: most columns per wave (1..8)
+  int32_t tune_nc = -1;           // chain step: most columns per wave (1..8)
+  int32_t tune_nc_spmv = -1;      // shifted pair, true residual: the same (-1: tune_nc)
   int32_t tune_spw = -1;          // iteration kernels: 64-row slices per wave
   std::vector<DevBuf> owned;
   // chain state between morx_solve_shifts calls (Algorithm 4)

@@ -290,17 +290,19 @@ def test_batched_equals_plain_mimo(ctx):
     S.close()
 
 
-@pytest.mark.parametrize("shape", [(1, -1), (2, -1), (8, -1), (-1, 2), (3, 4)])
+@pytest.mark.parametrize("shape", [(1, -1, -1), (2, -1, -1), (8, -1, -1), (-1, 2, -1),
+                                   (3, 4, -1), (1, 2, 5), (5, -1, 1)])
 def test_solve_under_forced_launch_shapes(ctx, shape):
     """Columns per wave and slices per wave change the launch, not the method:
     every shape meets the oracle's accuracy on the three-round job."""
     from paper_2003_12759_amd import api
 
-    ncw, spw = shape
+    ncw, spw, ncs = shape
     w = make_workload(1, N=12, nshift=5, nrounds=2)
     S = api.System(ctx, w.A, w.e)
-    S.set_tune(cols_per_wave=ncw, slices_per_wave=spw)
-    assert S.get_tune()["cols_per_wave"] == ncw and S.get_tune()["slices_per_wave"] == spw
+    S.set_tune(cols_per_wave=ncw, slices_per_wave=spw, spmv_cols_per_wave=ncs)
+    t = S.get_tune()
+    assert (t["cols_per_wave"], t["slices_per_wave"], t["spmv_cols_per_wave"]) == shape
     ref = ojob.run(w.A, w.e, w.B, w.C, w.rounds, prec="f32", tol=1e-10, project=False)
     for z, sig in enumerate(w.rounds):
         _say(f"solve convdiff n={w.n} round {z} shape={shape}")
@@ -345,7 +347,7 @@ def test_tune_rejects_bad_values(ctx):
     w = make_workload(0, N=10, nshift=2)
     S = api.System(ctx, w.A, w.e)
     for bad in ({"cols_per_wave": 9}, {"cols_per_wave": 0}, {"slices_per_wave": 65},
-                {"factor_kernel": 4}):
+                {"factor_kernel": 4}, {"spmv_cols_per_wave": 9}):
         with pytest.raises(morx.MorxError):
             S.set_tune(**bad)
     S.close()
