@@ -197,9 +197,11 @@ morx_status morx_project(morx_system sys, int32_t r, const double* V, int64_t ld
  * Launch shapes of a system's kernels (the batching extension: the tile and
  * row-block shapes of the multi-column iteration kernels and of the
  * least-squares factor kernel); -1 selects the built-in choice.
- *   factor_kernel    0: one wave per column; 8 or 16: one block of 32 x 8 or
- *                    32 x 16 threads per column, the local matrix in
- *                    registers (patterns with |J_k| < 32 and |I_k| <= 256);
+ *   factor_kernel    0: one wave per column, the local matrix in LDS;
+ *                    1: one wave per column, the local matrix in registers
+ *                    (8 or 16 column lanes; patterns with |J_k| < 16);
+ *                    8 or 16: one block of 32 x 8 or 32 x 16 threads per
+ *                    column, the local matrix in registers (|J_k| < 32);
  *   cols_per_wave    chain step: most right-hand-side columns one wave
  *                    carries over its rows, sharing every factor load among
  *                    them (1..8);

@@ -1613,7 +1613,7 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
   job.vals = f->vals.p;
   job.valsT = f->valsT.p;
   const int saved_rows = sys->tune_factor_rows;
-  for (int rows : {0, 8, 16}) {
+  for (int rows : {0, 1, 8, 16}) {
     if (!factor_kernel_supported(sys, rows)) continue;
     sys->tune_factor_rows = rows;
     MORX_HIP(hipEventRecord(e0, st));

@@ -296,29 +296,30 @@ __global__ void k_factor_to_csr(const VT* __restrict__ vals, const int32_t* __re
 
 // ---- block kernel for larger local problems ------------------------------------
 //
-// One block of 32 x BR threads per column.  The dense |I_k| x (|J_k| + 1)
-// matrix is held in registers: thread (cc, g) = (tid % 32, tid / 32) owns
-// column cc (column |J_k| is the right-hand side) at the local rows
-// r = s * BR + g, s < S.  A Householder step stages only the reflector column, row c of
+// One block of BC x BR threads per column (BC = 32: four or eight waves; BC
+// = 8 or 16: one wave, for small column patterns).  The dense
+// |I_k| x (|J_k| + 1) matrix is held in registers: thread (cc, g) =
+// (tid % BC, tid / BC) owns column cc (column |J_k| is the right-hand side)
+// at the local rows r = s * BR + g, s < S.  A Householder step stages only the reflector column, row c of
 // every column and the per-row-group partial dot products in LDS (double
 // buffered by step parity, two barriers per step); the gathered triples stay
 // in LDS so every shift rebuilds its matrix without touching global memory.
-constexpr int kBC = 32;         // column lanes: |J_k| + 1 <= 32
-constexpr int kRld = kBC + 1;   // row stride of the R staging buffer
+constexpr int kBCmax = 32;  // column lanes: |J_k| + 1 <= 32
 
 struct BlkLayout {
-  int Tpad, Tmax, maxI, S, BR;
+  int Tpad, Tmax, maxI, S, BR, BC;
   size_t off_keys, off_trow, off_tv, off_uniq, off_col, off_v, off_rowc, off_part, bytes;
 };
 
-BlkLayout blk_layout(int maxT, int maxI, int S, int BR) {
+BlkLayout blk_layout(int maxT, int maxI, int S, int BR, int BC) {
   BlkLayout L;
   L.Tmax = std::max(maxT, 1);
-  L.Tpad = 256;
+  L.Tpad = 64;
   while (L.Tpad < L.Tmax) L.Tpad <<= 1;
   L.maxI = std::max(maxI, 1);
   L.S = S;
   L.BR = BR;
+  L.BC = BC;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t r = o;
@@ -326,26 +327,28 @@ BlkLayout blk_layout(int maxT, int maxI, int S, int BR) {
     return r;
   };
   // sort keys, then the R staging buffer of the back substitution
-  L.off_keys = take(std::max((size_t)L.Tpad * 4, (size_t)kBC * kRld * 8));
+  L.off_keys = take(std::max((size_t)L.Tpad * 4, (size_t)BC * (BC + 1) * 8));
   L.off_trow = take((size_t)L.Tmax * 4);
   L.off_tv = take((size_t)L.Tmax * 8);
   L.off_uniq = take((size_t)L.maxI * 4);
-  L.off_col = take((size_t)(3 * kBC + 8) * 4);  // J, triple offsets (+1), diagonal rows, misc
+  L.off_col = take((size_t)(3 * BC + 8) * 4);  // J, triple offsets (+1), diagonal rows, misc
   L.off_v = take((size_t)2 * S * BR * 8);
-  L.off_rowc = take((size_t)2 * kBC * 8);
-  L.off_part = take((size_t)2 * BR * kBC * 8);
+  L.off_rowc = take((size_t)2 * BC * 8);
+  L.off_part = take((size_t)2 * BR * BC * 8);
   L.bytes = o;
   return L;
 }
 
 // (up to 16 slots: at least 3 blocks per CU; the steps are latency bound, so
 // blocks in flight matter more than registers)
-template <typename VT, int S, int BR>
-__global__ __launch_bounds__(kBC * BR, (S <= 16 ? 3 : 1)) void k_factor_ls_blk(
+template <typename VT, int S, int BR, int BC>
+__global__ __launch_bounds__(BC * BR, (S <= 16 ? 3 : 1)) void k_factor_ls_blk(
     const int32_t* __restrict__ trowptr, const int32_t* __restrict__ tcol,
     const double* __restrict__ tval, const double* __restrict__ e,
     const int32_t* __restrict__ tp2s, const int32_t* __restrict__ sellT_off, int64_t n,
     const FactorJob* __restrict__ jobs, int njobs, BlkLayout L, int* __restrict__ status) {
+  constexpr int kBC = BC;
+  constexpr int kRld = BC + 1;  // row stride of the R staging buffer
   extern __shared__ __align__(16) unsigned char lds[];
   int* keys = (int*)(lds + L.off_keys);
   double* R = (double*)(lds + L.off_keys);
@@ -561,24 +564,51 @@ __global__ __launch_bounds__(kBC * BR, (S <= 16 ? 3 : 1)) void k_factor_ls_blk(
   }
 }
 
-// Register slots per thread of the block kernel: rows per column / BR.
+// Register slots per thread of the register kernels: rows per column / BR.
 int blk_slots(int maxI, int BR) {
-  int S = 4;
+  int S = 2;
   while (S * BR < maxI) S <<= 1;
   return S;
 }
 
-// Row groups of the block kernel (8 or 16), or 0 when the per-wave kernel
-// handles the pattern: small column patterns keep the per-wave kernel, whose
-// lane groups match them.  The system's tuned choice wins when it is set.
-int blk_rows(morx_system sys) {
-  if (sys->max_J + 1 > kBC || sys->max_I > 32 * 8) return 0;
-  int BR = sys->tune_factor_rows;
-  if (BR < 0) BR = sys->max_J < 12 ? 0 : 16;
-  if (BR == 0) return 0;
-  if (BR == 16 && blk_slots(sys->max_I, 16) > 16) BR = 8;
-  const int S = blk_slots(sys->max_I, BR);
-  return blk_layout(sys->max_T, sys->max_I, S, BR).bytes <= (size_t)kLdsBudget ? BR : 0;
+// Shape of a register least-squares variant: factor_kernel 1 is one wave per
+// column (BC = 8 or 16 column lanes), 8 and 16 one block of 32 x BR threads.
+struct BlkShape {
+  int BC, BR, S;
+};
+
+bool blk_shape(morx_system sys, int variant, BlkShape* out) {
+  BlkShape b{};
+  if (variant == 1) {
+    if (sys->max_J + 1 > 16) return false;
+    b.BC = sys->max_J + 1 <= 8 ? 8 : 16;
+    b.BR = 64 / b.BC;
+    b.S = blk_slots(sys->max_I, b.BR);
+    if (b.S > (b.BC == 8 ? 16 : 32)) return false;
+  } else if (variant == 8 || variant == 16) {
+    if (sys->max_J + 1 > kBCmax) return false;
+    b.BC = kBCmax;
+    b.BR = variant;
+    b.S = std::max(4, blk_slots(sys->max_I, b.BR));
+    if (b.S > (variant == 16 ? 16 : 32)) return false;
+  } else {
+    return false;
+  }
+  if (blk_layout(sys->max_T, sys->max_I, b.S, b.BR, b.BC).bytes > (size_t)kLdsBudget) return false;
+  *out = b;
+  return true;
+}
+
+// The register variant that builds this system's factors, or 0 for the
+// per-wave LDS kernel.  The system's tuned choice wins when it is set;
+// otherwise small column patterns keep the per-wave kernel and larger ones
+// take the 32 x 16 block.
+int blk_variant(morx_system sys) {
+  int v = sys->tune_factor_rows;
+  if (v < 0) v = sys->max_J < 12 ? 0 : 16;
+  BlkShape b;
+  if (v == 16 && !blk_shape(sys, 16, &b)) v = 8;
+  return (v != 0 && blk_shape(sys, v, &b)) ? v : 0;
 }
 
 int ls_grid(morx_system sys) {
@@ -588,14 +618,11 @@ int ls_grid(morx_system sys) {
 
 }  // namespace
 
-bool factor_kernel_supported(morx_system sys, int rows) {
+bool factor_kernel_supported(morx_system sys, int variant) {
   if (!sys->ls_supported) return false;
-  if (rows == 0) return true;
-  if (rows != 8 && rows != 16) return false;
-  if (sys->max_J + 1 > kBC || sys->max_I > 32 * 8) return false;
-  const int S = blk_slots(sys->max_I, rows);
-  if (S > (rows == 16 ? 16 : 32)) return false;
-  return blk_layout(sys->max_T, sys->max_I, S, rows).bytes <= (size_t)kLdsBudget;
+  if (variant == 0) return true;
+  BlkShape b;
+  return blk_shape(sys, variant, &b);
 }
 
 morx_status ls_pattern_stats(morx_system sys, hipStream_t st) {
@@ -692,28 +719,46 @@ morx_status factor_build_many(morx_system sys, int32_t prec, const FactorJob* jo
   const int grid = ls_grid(sys);
   void* token = nullptr;
   trace_factor_begin(sys->ctx, st, &token);
-  const int BR = blk_rows(sys);
-  if (BR > 0) {
-    const int S = blk_slots(sys->max_I, BR);
-    const BlkLayout B = blk_layout(sys->max_T, sys->max_I, S, BR);
-    const int bgrid = (int)std::min<int64_t>(sys->n, (int64_t)std::max(sys->ctx->num_cu, 1) * 8);
-#define MORX_BLK_LAUNCH(VT, SV, BRV)                                                      \
-  k_factor_ls_blk<VT, SV, BRV><<<bgrid, kBC * BRV, B.bytes, st>>>(                         \
+  const int variant = blk_variant(sys);
+  BlkShape bs{};
+  if (variant > 0 && blk_shape(sys, variant, &bs)) {
+    const int S = bs.S, BR = bs.BR, BC = bs.BC;
+    const BlkLayout B = blk_layout(sys->max_T, sys->max_I, S, BR, BC);
+    // one-wave blocks: more of them to fill the CUs
+    const int per_cu = BC == kBCmax ? 8 : 32;
+    const int bgrid =
+        (int)std::min<int64_t>(sys->n, (int64_t)std::max(sys->ctx->num_cu, 1) * per_cu);
+#define MORX_BLK_LAUNCH(VT, SV, BRV, BCV)                                                 \
+  k_factor_ls_blk<VT, SV, BRV, BCV><<<bgrid, BCV * BRV, B.bytes, st>>>(                    \
       sys->trowptr, sys->tcol, sys->tval, sys->e, sys->tp2s, sys->sellT.off, sys->n,      \
       (FactorJob*)jb.p, njobs, B, (int*)sb.p)
 #define MORX_BLK_S(VT)                                                   \
-  if (BR == 8) {                                                         \
+  if (BC == 8) {                                                         \
     switch (S) {                                                         \
-      case 4: MORX_BLK_LAUNCH(VT, 4, 8); break;                          \
-      case 8: MORX_BLK_LAUNCH(VT, 8, 8); break;                          \
-      case 16: MORX_BLK_LAUNCH(VT, 16, 8); break;                        \
-      default: MORX_BLK_LAUNCH(VT, 32, 8); break;                        \
+      case 2: MORX_BLK_LAUNCH(VT, 2, 8, 8); break;                       \
+      case 4: MORX_BLK_LAUNCH(VT, 4, 8, 8); break;                       \
+      case 8: MORX_BLK_LAUNCH(VT, 8, 8, 8); break;                       \
+      default: MORX_BLK_LAUNCH(VT, 16, 8, 8); break;                     \
+    }                                                                    \
+  } else if (BC == 16) {                                                 \
+    switch (S) {                                                         \
+      case 2: case 4: MORX_BLK_LAUNCH(VT, 4, 4, 16); break;              \
+      case 8: MORX_BLK_LAUNCH(VT, 8, 4, 16); break;                      \
+      case 16: MORX_BLK_LAUNCH(VT, 16, 4, 16); break;                    \
+      default: MORX_BLK_LAUNCH(VT, 32, 4, 16); break;                    \
+    }                                                                    \
+  } else if (BR == 8) {                                                  \
+    switch (S) {                                                         \
+      case 4: MORX_BLK_LAUNCH(VT, 4, 8, 32); break;                      \
+      case 8: MORX_BLK_LAUNCH(VT, 8, 8, 32); break;                      \
+      case 16: MORX_BLK_LAUNCH(VT, 16, 8, 32); break;                    \
+      default: MORX_BLK_LAUNCH(VT, 32, 8, 32); break;                    \
     }                                                                    \
   } else {                                                               \
     switch (S) {                                                         \
-      case 4: MORX_BLK_LAUNCH(VT, 4, 16); break;                         \
-      case 8: MORX_BLK_LAUNCH(VT, 8, 16); break;                         \
-      default: MORX_BLK_LAUNCH(VT, 16, 16); break;                       \
+      case 4: MORX_BLK_LAUNCH(VT, 4, 16, 32); break;                     \
+      case 8: MORX_BLK_LAUNCH(VT, 8, 16, 32); break;                     \
+      default: MORX_BLK_LAUNCH(VT, 16, 16, 32); break;                   \
     }                                                                    \
   }
     if (prec == MORX_F64) { MORX_BLK_S(double) }

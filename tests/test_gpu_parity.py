@@ -119,8 +119,9 @@ def _oracle_factor(name, kind, args):
 
 
 # least-squares kernel variants: -1 the built-in choice, 0 one wave per
-# column, 8 / 16 one block per column with that many row groups
-@pytest.mark.parametrize("kernel", [-1, 0, 8, 16])
+# column (LDS), 1 one wave per column (registers), 8 / 16 one block per
+# column with that many row groups
+@pytest.mark.parametrize("kernel", [-1, 0, 1, 8, 16])
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
 def test_factor_columns_match_oracle(ctx, name, prec, kernel):
@@ -329,7 +330,7 @@ def test_autotune_then_solve(ctx, name):
     _say(f"autotune {name}")
     t = S.autotune(float(w.rounds[0][0]), ncols=len(w.rounds[0]), chain_len=len(w.rounds[0]),
                    prec="f32")
-    assert t["factor_kernel"] in (0, 8, 16)
+    assert t["factor_kernel"] in (0, 1, 8, 16)
     assert 1 <= t["cols_per_wave"] <= 8 and t["slices_per_wave"] >= 1
     assert t["factor_ms"] > 0 and t["iter_ms"] > 0
     assert S.get_tune()["cols_per_wave"] == t["cols_per_wave"]
