@@ -22,7 +22,11 @@ vector rounded to FP32, then every factor product formed in FP64 and its
 result rounded to FP32 before the next factor; the output is the last rounded
 vector.  The Krylov recurrences that consume it stay FP64.
 
-Pinned by: a hand-written expected schedule for three rounds, the chain
+Two comparators use other schedules: :func:`schedule_direct` (a fresh SPAI
+per shift, no reuse) and :func:`schedule_first` (Table 2's first approach,
+every update taken from the first shift).
+
+Pinned by: hand-written expected schedules (all three), the chain
 apply against the explicitly formed dense product on small matrices, and for
 the FP32 apply: exact agreement with the FP64 apply when every intermediate
 is an FP32 number, a rounding-error bound per pass, and FP32-representable
@@ -69,6 +73,41 @@ def _to_apply(v: np.ndarray, apply_prec: str) -> np.ndarray:
     if apply_prec != "f32":
         raise ValueError(apply_prec)
     return v.astype(np.float32).astype(np.float64)
+
+
+def schedule_direct(rounds: Sequence[Sequence[float]]):
+    """Comparator without reuse: a fresh SPAI at every shift of every round,
+    each preconditioner a single factor (the paper's plain SPAI columns in its
+    preconditioner-time tables).  Same ``(specs, chains)`` form as
+    :func:`schedule`."""
+    specs: List[FactorSpec] = []
+    chains: List[List[List[int]]] = []
+    for sig in rounds:
+        round_chains = []
+        for s in sig:
+            specs.append(("spai", float(s)))
+            round_chains.append([len(specs) - 1])
+        chains.append(round_chains)
+    return specs, chains
+
+
+def schedule_first(rounds: Sequence[Sequence[float]]):
+    """Table 2's first approach, round by round: ``P_1`` by SPAI at the round's
+    first shift, then ``P_i = Q_i P_1`` with ``Q_i`` from
+    ``min ||A_1 - A_i Q||_F`` (an update from the first shift to shift i), so
+    every chain is ``[P_1]`` or ``[P_1, Q_i]``."""
+    specs: List[FactorSpec] = []
+    chains: List[List[List[int]]] = []
+    for sig in rounds:
+        sig = [float(s) for s in sig]
+        specs.append(("spai", sig[0]))
+        p1 = len(specs) - 1
+        round_chains = [[p1]]
+        for i in range(1, len(sig)):
+            specs.append(("update", sig[0], sig[i]))
+            round_chains.append([p1, len(specs) - 1])
+        chains.append(round_chains)
+    return specs, chains
 
 
 def apply(factors, chain: Sequence[int], v: np.ndarray, apply_prec: str = "f64") -> np.ndarray:

@@ -32,20 +32,26 @@ def build_factors(A, e, specs, prec: str = "f64", columns=None):
     return factors
 
 
+SCHEDULES = {"reuse": chain.schedule, "direct": chain.schedule_direct,
+             "first": chain.schedule_first}
+
+
 def run(A, e, B, C, rounds, prec: str = "f64", tol: float = 1e-10, want_dual: bool = True,
         maxit=None, max_restarts: int = 3, project: bool = True, factors=None,
-        apply_prec: str = "f64"):
+        apply_prec: str = "f64", policy: str = "reuse"):
     """Return a dict with factor specs, factors, per-(round, shift, column)
     solutions and stats, and the reduced model of each round.
 
     ``prec`` is the storage precision of the factor values, ``apply_prec``
-    the precision of the preconditioner apply (:func:`oracle.chain.apply`)."""
+    the precision of the preconditioner apply (:func:`oracle.chain.apply`),
+    ``policy`` the factor schedule: "reuse" (Algorithm 4), "direct" (a SPAI
+    per shift) or "first" (Table 2's first approach)."""
     A = sp.csr_matrix(A)
     n = A.shape[0]
     e = np.asarray(e, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64).reshape(n, -1)
     C = np.asarray(C, dtype=np.float64).reshape(n, -1)
-    specs, chains = chain.schedule(rounds)
+    specs, chains = SCHEDULES[policy](rounds)
     if factors is None:
         factors = build_factors(A, e, specs, prec)
     E = sp.diags(e)

@@ -140,6 +140,36 @@ def test_schedule_follows_algorithm4():
             assert len(chains[z][i]) == (i + 1) + (z + 1) - 1
 
 
+def test_comparator_schedules():
+    rounds = [[1.0, 2.0, 3.0], [1.1, 2.1, 3.1]]
+    specs, chains = chain.schedule_direct(rounds)
+    assert specs == [("spai", 1.0), ("spai", 2.0), ("spai", 3.0),
+                     ("spai", 1.1), ("spai", 2.1), ("spai", 3.1)]
+    assert chains == [[[0], [1], [2]], [[3], [4], [5]]]
+    specs, chains = chain.schedule_first(rounds)
+    assert specs == [("spai", 1.0), ("update", 1.0, 2.0), ("update", 1.0, 3.0),
+                     ("spai", 1.1), ("update", 1.1, 2.1), ("update", 1.1, 3.1)]
+    assert chains == [[[0], [0, 1], [0, 2]], [[3], [3, 4], [3, 5]]]
+
+
+def test_first_approach_full_pattern_is_exact_inverse():
+    """Table 2, first approach: with a full pattern Q_i = A_i^{-1} A_1, so the
+    chain [P_1, Q_i] applies Q_i P_1 = A_i^{-1} exactly."""
+    n = 10
+    rng = np.random.default_rng(12)
+    Ad = rng.standard_normal((n, n)) - 6 * np.eye(n)
+    A = sp.csr_matrix(Ad)
+    e = rng.uniform(1, 2, n)
+    sig = [1.5, 4.0, 0.5]
+    specs, chains = chain.schedule_first([sig])
+    fs = job.build_factors(A, e, specs)
+    v = rng.standard_normal(n)
+    for i, s in enumerate(sig):
+        want = np.linalg.solve(s * np.diag(e) - Ad, v)
+        got = chain.apply(fs, chains[0][i], v)
+        assert np.allclose(got, want, rtol=1e-10, atol=1e-12)
+
+
 def test_chain_apply_matches_formed_product():
     n = 25
     fs = [_rand_sparse(n, 0.15, 20 + k) for k in range(4)]
@@ -235,9 +265,11 @@ def test_bicg_matches_dense_lu_on_laplace2d_n2025(apply_prec):
         assert np.linalg.norm(out["rounds"][0]["X"][:, i] - x) <= 1e-8 * np.linalg.norm(x)
 
 
-def test_bicg_nonsymmetric_three_rounds_vs_sparse_lu():
+@pytest.mark.parametrize("policy", ["reuse", "direct", "first"])
+def test_bicg_nonsymmetric_three_rounds_vs_sparse_lu(policy):
     w = make_workload(1, N=8, nshift=4, nrounds=3)
-    out = job.run(w.A, w.e, w.B, w.C, w.rounds, prec="f64", tol=1e-10, project=False)
+    out = job.run(w.A, w.e, w.B, w.C, w.rounds, prec="f64", tol=1e-10, project=False,
+                  policy=policy)
     for z, sig in enumerate(w.rounds):
         for i, s in enumerate(sig):
             st = out["rounds"][z]["stats"][i]
