@@ -53,14 +53,14 @@ def default_apply(prec: str) -> str:
 
 
 def run_job(S, w, Bd, Cd, batched: bool, apply: str, use_graph: bool = True, prec=None,
-            keep=None):
+            keep=None, policy: str = "reuse"):
     """One step: every round's shifted solves and projection.  ``keep`` (a
     list) receives the last round's (X, Y)."""
     stats_all = []
     for z, sig in enumerate(w.rounds):
         X, Y, st, stats = S.solve_shifts(sig, Bd, Cd, prec=prec or w.prec, tol=w.tol,
                                          batched=batched, next_round=z > 0, use_graph=use_graph,
-                                         apply=apply)
+                                         apply=apply, policy=policy)
         S.project(X, Y, Bd, Cd)
         stats_all.extend(stats)
     if keep is not None:
@@ -287,6 +287,9 @@ def main():
     ap.add_argument("--shapes", default=None,
                     help="pin the launch shapes instead of autotuning: "
                          "factor_kernel,cols_per_wave,slices_per_wave[,spmv_cols_per_wave]")
+    ap.add_argument("--compare-policies", action="store_true",
+                    help="also time the comparator schedules: a SPAI per shift, and "
+                         "Table 2's first approach")
     ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=16, help="serving: slots per system")
     ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 1.0],
@@ -416,6 +419,21 @@ def main():
 
     lad = ladder(S, w, Bd, Cd, nsolves) if index == 4 and args.prec is None else None
 
+    comparators = None
+    if args.compare_policies:
+        # the same batched job under the comparator factor schedules
+        comparators = {}
+        for pol in ("direct", "first"):
+            run_job(S, w, Bd, Cd, batched=True, apply=apply, policy=pol)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st_ = run_job(S, w, Bd, Cd, batched=True, apply=apply, policy=pol)
+            torch.cuda.synchronize()
+            dt_ = time.perf_counter() - t1
+            check(st_, w.tol)
+            comparators[pol] = {"value": round(nsolves / dt_, 3), "unit": "solves/s",
+                                "iters_per_step": sum(x.iters for x in st_)}
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, apply)
 
     out = {
@@ -446,6 +464,8 @@ def main():
     }
     if lad is not None:
         out["ladder"] = lad
+    if comparators is not None:
+        out["comparators"] = comparators
     print(json.dumps(out), flush=True)
     S.close()
     ctx.close()

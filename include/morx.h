@@ -67,8 +67,12 @@ typedef enum { MORX_F64 = 0, MORX_F32 = 1, MORX_BF16 = 2 } morx_prec;
 
 typedef enum {
   MORX_CHAIN_RESET = 0,      /* SPAI at sigmas[0], then horizontal updates (round 1)  */
-  MORX_CHAIN_NEXT_ROUND = 1  /* vertical update from the previous call's first shift
+  MORX_CHAIN_NEXT_ROUND = 1, /* vertical update from the previous call's first shift
                                 to sigmas[0], then horizontal updates (round z > 1)   */
+  /* comparators (no vertical chain is kept; a later NEXT_ROUND call resets):     */
+  MORX_CHAIN_DIRECT = 2,     /* a fresh SPAI at every shift, chains of one factor     */
+  MORX_CHAIN_FIRST = 3       /* Table 2's first approach: P_i = Q_i P_1, Q_i from
+                                min ||A_1 - A_i Q||_F (an update from sigmas[0])      */
 } morx_chain_policy;
 
 /* Solver options.  morx_opts_default() fills the defaults given here. */

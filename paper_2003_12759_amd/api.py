@@ -75,11 +75,14 @@ class System:
     def solve_shifts(self, sigmas: Sequence[float], B, C=None, prec: str = "f64", tol: float = 1e-10,
                      batched: bool = True, next_round: bool = False, use_graph: bool = True,
                      poll_iters: int = 8, maxit: int = 0, max_restarts: int = 3,
-                     raise_on_error: bool = True, apply: str = "f64"):
+                     raise_on_error: bool = True, apply: str = "f64", policy: str = "reuse"):
         """Returns (X, Y, status, stats); X, Y are column-major (n, m*nshift) tensors.
 
         ``prec`` is the storage precision of the factor values, ``apply`` the
-        precision of the preconditioner apply ("f64" or "f32")."""
+        precision of the preconditioner apply ("f64" or "f32"), ``policy`` the
+        factor schedule: "reuse" (Algorithm 4; ``next_round`` selects the
+        vertical update), "direct" (a SPAI per shift) or "first" (Table 2's
+        first approach)."""
         Bd = B if isinstance(B, torch.Tensor) else block_to_dev(B, self.device)
         Cd = None
         if C is not None:
@@ -91,7 +94,10 @@ class System:
         o = morx.morx_opts_default()
         o.tol = tol
         o.precond_prec = morx.PREC[prec]
-        o.chain = morx.MORX_CHAIN_NEXT_ROUND if next_round else morx.MORX_CHAIN_RESET
+        if policy == "reuse":
+            o.chain = morx.MORX_CHAIN_NEXT_ROUND if next_round else morx.MORX_CHAIN_RESET
+        else:
+            o.chain = {"direct": morx.MORX_CHAIN_DIRECT, "first": morx.MORX_CHAIN_FIRST}[policy]
         o.want_dual = 1 if Cd is not None else 0
         o.batched = 1 if batched else 0
         o.use_graph = 1 if use_graph else 0

@@ -1235,6 +1235,7 @@ void trace_collect_pending(TraceState* t) {
 struct BatchCol {
   double sigma;
   int L;
+  const std::vector<morx_factor>* chain;  // factors applied first to last (L of them)
   const double* b;
   const double* c;
   double* xout;
@@ -1243,16 +1244,20 @@ struct BatchCol {
   morx_col_stats* stats;
 };
 
-// Solve a set of columns whose chains are prefixes of one factor list G.
-static morx_status solve_batch(morx_system sys, std::vector<BatchCol>& cols,
-                               const std::vector<morx_factor>& G, int prec, const morx_opts& o,
-                               hipStream_t st) {
+// Solve a set of columns, each preconditioned by its own factor chain (in a
+// batched multi-shift solve the chains are prefixes of one factor list, so
+// the chain step shares every factor load among the columns of a wave).
+static morx_status solve_batch(morx_system sys, std::vector<BatchCol>& cols, int prec,
+                               const morx_opts& o, hipStream_t st) {
   const int aprec = o.apply_prec;
   const int nc = (int)cols.size();
   if (nc == 0) return MORX_OK;
   int maxL = 0;
-  for (auto& c : cols) maxL = std::max(maxL, c.L);
-  MORX_REQUIRE(maxL >= 1 && maxL <= (int)G.size(), MORX_E_INVALID, "bad chain length");
+  for (auto& c : cols) {
+    MORX_REQUIRE(c.chain && c.L >= 1 && c.L <= (int)c.chain->size(), MORX_E_INVALID,
+                 "bad chain length");
+    maxL = std::max(maxL, c.L);
+  }
   if (!sys->kb) sys->kb = new KrylovBatch();
   KrylovBatch& b = *sys->kb;
   if (b.cap < nc || b.lcap < maxL || b.prec != prec || b.aprec != aprec || b.ld != sys->n_pad) {
@@ -1282,8 +1287,8 @@ static morx_status solve_batch(morx_system sys, std::vector<BatchCol>& cols,
     b.hcols[c] = ci;
     for (int s = 0; s < b.lcap; ++s) {
       const bool in = s < cols[c].L;
-      b.hftab[(size_t)c * b.lcap + s] = in ? G[s]->vals.p : nullptr;
-      b.hftab[((size_t)b.cap + c) * b.lcap + s] = in ? G[s]->valsT.p : nullptr;
+      b.hftab[(size_t)c * b.lcap + s] = in ? (*cols[c].chain)[s]->vals.p : nullptr;
+      b.hftab[((size_t)b.cap + c) * b.lcap + s] = in ? (*cols[c].chain)[s]->valsT.p : nullptr;
     }
   }
   MORX_TRY(batch_upload(b, 0, nc, st));
@@ -1383,8 +1388,14 @@ static morx_status solve_shifts_impl(morx_system sys, int32_t nshift, const doub
   for (int j = 0; j < 2 * m; ++j)
     MORX_REQUIRE(std::isfinite(norms[j]), MORX_E_NONFINITE, "B or C holds NaN or Inf");
 
-  // factor list: vertical chain (+ this call's first factor), then horizontal
-  const bool reset = (o.chain == MORX_CHAIN_RESET) || sys->vertical.empty();
+  // Factor jobs and each shift's chain.  Algorithm 4 (RESET / NEXT_ROUND):
+  // the vertical chain (plus, for the next round, this call's first factor),
+  // then the horizontal updates.  Comparators: a SPAI per shift (DIRECT), or
+  // Table 2's first approach, P_i = Q_i P_1 with Q_i taken from sigmas[0]
+  // (FIRST); neither keeps a vertical chain.
+  const int policy = o.chain;
+  const bool reuse = policy == MORX_CHAIN_RESET || policy == MORX_CHAIN_NEXT_ROUND;
+  const bool reset = !reuse || policy == MORX_CHAIN_RESET || sys->vertical.empty();
   if (!reset)
     MORX_REQUIRE(sys->vertical_prec == prec, MORX_E_INVALID,
                  "MORX_CHAIN_NEXT_ROUND needs the precision of the previous round");
@@ -1398,12 +1409,13 @@ static morx_status solve_shifts_impl(morx_system sys, int32_t nshift, const doub
     MORX_TRY(factor_alloc(sys, prec, &f));
     fresh.push_back(f);
     FactorJob jb;
-    if (i == 0) {
-      jb.is_spai = reset ? 1 : 0;
-      jb.sigma_prev = reset ? 0.0 : sys->last_first_shift;
+    if (policy == MORX_CHAIN_DIRECT || i == 0) {
+      const bool spai = !reuse || reset;
+      jb.is_spai = spai ? 1 : 0;
+      jb.sigma_prev = spai ? 0.0 : sys->last_first_shift;
     } else {
       jb.is_spai = 0;
-      jb.sigma_prev = sigmas[i - 1];
+      jb.sigma_prev = policy == MORX_CHAIN_FIRST ? sigmas[0] : sigmas[i - 1];
     }
     jb.sigma_new = sigmas[i];
     jb.vals = f->vals.p;
@@ -1413,13 +1425,26 @@ static morx_status solve_shifts_impl(morx_system sys, int32_t nshift, const doub
     f->sigma_new = jb.sigma_new;
     jobs.push_back(jb);
   }
+  std::vector<std::vector<morx_factor>> chains(nshift);
+  for (int i = 0; i < nshift; ++i) {
+    if (policy == MORX_CHAIN_DIRECT) {
+      chains[i] = {fresh[i]};
+    } else if (policy == MORX_CHAIN_FIRST) {
+      chains[i] = {fresh[0]};
+      if (i > 0) chains[i].push_back(fresh[i]);
+    } else {
+      chains[i] = sys->vertical;
+      for (int k = 0; k <= i; ++k) chains[i].push_back(fresh[k]);
+    }
+  }
   auto trivial_col = [&](int j) { return norms[j] == 0.0 && (!want_dual || norms[m + j] == 0.0); };
-  auto make_col = [&](int i, int j, int L) -> BatchCol {
+  auto make_col = [&](int i, int j) -> BatchCol {
     BatchCol bc{};
     bc.sigma = sigmas[i];
     bc.xout = X + (int64_t)(i * m + j) * ldx;
     bc.yout = want_dual ? Y + (int64_t)(i * m + j) * ldy : nullptr;
-    bc.L = L;
+    bc.chain = &chains[i];
+    bc.L = (int)chains[i].size();
     bc.stats = stats ? &stats[i * m + j] : nullptr;
     const bool cz = !want_dual || norms[m + j] == 0.0;
     if (norms[j] != 0.0) {
@@ -1442,45 +1467,35 @@ static morx_status solve_shifts_impl(morx_system sys, int32_t nshift, const doub
   };
 
   if (o.batched) {
+    // every factor in one launch, every column pair in one batch
     MORX_TRY(factor_build_many(sys, prec, jobs.data(), nshift, st));
-    sys->vertical.push_back(fresh[0]);
-    for (int i = 1; i < nshift; ++i) horizontal.push_back(fresh[i]);
-    fresh.clear();
-    std::vector<morx_factor> G = sys->vertical;
-    const int Lv = (int)sys->vertical.size();
-    for (int i = 1; i < nshift; ++i) G.push_back(horizontal[i - 1]);
     std::vector<BatchCol> cols;
     for (int i = 0; i < nshift; ++i)
       for (int j = 0; j < m; ++j)
-        if (!trivial_col(j)) cols.push_back(make_col(i, j, Lv + i));
-    MORX_TRY(solve_batch(sys, cols, G, prec, o, st));
+        if (!trivial_col(j)) cols.push_back(make_col(i, j));
+    MORX_TRY(solve_batch(sys, cols, prec, o, st));
   } else {
     // one shift at a time, one column at a time (factor i built just before
     // the solves that first need it, as in Algorithm 4)
-    std::vector<morx_factor> G;
-    std::vector<morx_factor> mine = fresh;
-    fresh.clear();
     for (int i = 0; i < nshift; ++i) {
-      morx_status s = factor_build_many(sys, prec, &jobs[i], 1, st);
-      if (s != MORX_OK) {
-        for (int k = i; k < nshift; ++k) fresh.push_back(mine[k]);
-        return s;
-      }
-      if (i == 0) {
-        sys->vertical.push_back(mine[0]);
-        G = sys->vertical;
-      } else {
-        horizontal.push_back(mine[i]);
-        G.push_back(mine[i]);
-      }
+      MORX_TRY(factor_build_many(sys, prec, &jobs[i], 1, st));
       for (int j = 0; j < m; ++j) {
         if (trivial_col(j)) continue;
-        std::vector<BatchCol> one{make_col(i, j, (int)G.size())};
-        MORX_TRY(solve_batch(sys, one, G, prec, o, st));
+        std::vector<BatchCol> one{make_col(i, j)};
+        MORX_TRY(solve_batch(sys, one, prec, o, st));
       }
     }
   }
-  sys->vertical_prec = prec;
+  // the first factor joins the vertical chain (Algorithm 4); the rest are
+  // released when the call returns
+  size_t keep_from = 0;
+  if (reuse) {
+    sys->vertical.push_back(fresh[0]);
+    keep_from = 1;
+  }
+  for (size_t k = keep_from; k < fresh.size(); ++k) horizontal.push_back(fresh[k]);
+  fresh.clear();
+  sys->vertical_prec = reuse ? prec : -1;
   sys->last_first_shift = sigmas[0];
   morx_status worst = MORX_OK;
   for (int i = 0; i < nshift; ++i)
@@ -1523,6 +1538,8 @@ extern "C" morx_status morx_solve_shifts(morx_system sys, int32_t nshift, const 
                "morx_solve_shifts: bad precision");
   MORX_REQUIRE(o.apply_prec == MORX_F64 || o.apply_prec == MORX_F32, MORX_E_INVALID,
                "morx_solve_shifts: apply precision must be MORX_F64 or MORX_F32");
+  MORX_REQUIRE(o.chain >= MORX_CHAIN_RESET && o.chain <= MORX_CHAIN_FIRST, MORX_E_INVALID,
+               "morx_solve_shifts: unknown chain policy %d", o.chain);
   MORX_REQUIRE(o.tol >= 0.0 && o.max_restarts >= 0, MORX_E_INVALID,
                "morx_solve_shifts: bad tolerance or restart limit");
   for (int i = 0; i < nshift; ++i)

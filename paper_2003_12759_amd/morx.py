@@ -35,6 +35,8 @@ STATUS = {
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
 MORX_CHAIN_RESET = 0
 MORX_CHAIN_NEXT_ROUND = 1
+MORX_CHAIN_DIRECT = 2
+MORX_CHAIN_FIRST = 3
 
 
 class morx_opts(ctypes.Structure):

@@ -275,6 +275,37 @@ def test_solve_convdiff_three_rounds_vertical_reuse(ctx, prec, apply):
     S.close()
 
 
+@pytest.mark.parametrize("policy", ["direct", "first"])
+@pytest.mark.parametrize("batched", [True, False])
+def test_solve_comparator_policies(ctx, policy, batched):
+    """A SPAI per shift, and Table 2's first approach (P_i = Q_i P_1): the same
+    accuracy as the oracle run under the same schedule."""
+    from paper_2003_12759_amd import api
+
+    w = make_workload(1, N=12, nshift=5, nrounds=2)
+    S = api.System(ctx, w.A, w.e)
+    ref = ojob.run(w.A, w.e, w.B, w.C, w.rounds, prec="f32", tol=1e-10, project=False,
+                   policy=policy)
+    for z, sig in enumerate(w.rounds):
+        _say(f"solve convdiff n={w.n} round {z} policy={policy} batched={batched}")
+        X, Y, st, stats = S.solve_shifts(sig, w.B, w.C, prec="f32", policy=policy,
+                                         batched=batched)
+        Xg, Yg = X.cpu().numpy(), Y.cpu().numpy()
+        for i, s in enumerate(sig):
+            assert stats[i].status == 0
+            assert _true_relres(w.A, w.e, s, Xg[:, i], w.B[:, 0]) <= 1.01e-10
+            assert _true_relres(w.A, w.e, s, Yg[:, i], w.C[:, 0], trans=True) <= 1.01e-10
+            xr, yr = ref["rounds"][z]["X"][:, i], ref["rounds"][z]["Y"][:, i]
+            assert np.linalg.norm(Xg[:, i] - xr) <= 1e-8 * np.linalg.norm(xr)
+            assert np.linalg.norm(Yg[:, i] - yr) <= 1e-8 * np.linalg.norm(yr)
+            ro = ref["rounds"][z]["stats"][i]
+            assert abs(stats[i].iters - ro.iters) <= max(3, 0.1 * ro.iters), (stats[i].iters, ro.iters)
+    # a comparator keeps no vertical chain: the next reuse round starts afresh
+    _, _, st, stats = S.solve_shifts(w.rounds[0], w.B, w.C, prec="f32", next_round=True)
+    assert all(c.status == 0 for c in stats)
+    S.close()
+
+
 def test_batched_equals_plain_mimo(ctx):
     from paper_2003_12759_amd import api
 
