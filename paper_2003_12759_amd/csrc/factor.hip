@@ -308,7 +308,7 @@ constexpr int kBCmax = 32;  // column lanes: |J_k| + 1 <= 32
 
 struct BlkLayout {
   int Tpad, Tmax, maxI, S, BR, BC;
-  size_t off_keys, off_trow, off_tv, off_uniq, off_col, off_v, off_rowc, off_part, bytes;
+  size_t off_keys, off_trow, off_tv, off_uniq, off_R, off_col, off_v, off_rowc, off_part, bytes;
 };
 
 BlkLayout blk_layout(int maxT, int maxI, int S, int BR, int BC) {
@@ -326,11 +326,21 @@ BlkLayout blk_layout(int maxT, int maxI, int S, int BR, int BC) {
     o += (bytes + 15) / 16 * 16;
     return r;
   };
-  // sort keys, then the R staging buffer of the back substitution
-  L.off_keys = take(std::max((size_t)L.Tpad * 4, (size_t)BC * (BC + 1) * 8));
-  L.off_trow = take((size_t)L.Tmax * 4);
-  L.off_tv = take((size_t)L.Tmax * 8);
-  L.off_uniq = take((size_t)L.maxI * 4);
+  // Per column: the gather and sort arrays (keys, triples, values, rows I_k),
+  // then in the same space the dense -A(I_k, J_k), BC columns of S * BR rows,
+  // which every shift reads to build its matrix.
+  size_t gather = 0;
+  auto add = [&](size_t bytes) {
+    size_t r = gather;
+    gather += (bytes + 15) / 16 * 16;
+    return r;
+  };
+  L.off_keys = add((size_t)L.Tpad * 4);
+  L.off_trow = add((size_t)L.Tmax * 4);
+  L.off_tv = add((size_t)L.Tmax * 8);
+  L.off_uniq = add((size_t)L.maxI * 4);
+  take(std::max(gather, (size_t)BC * S * BR * 8));
+  L.off_R = take((size_t)BC * (BC + 1) * 8);  // R staging of the back substitution
   L.off_col = take((size_t)(3 * BC + 8) * 4);  // J, triple offsets (+1), diagonal rows, misc
   L.off_v = take((size_t)2 * S * BR * 8);
   L.off_rowc = take((size_t)2 * BC * 8);
@@ -351,7 +361,8 @@ __global__ __launch_bounds__(BC * BR, (S <= 16 ? 3 : 1)) void k_factor_ls_blk(
   constexpr int kRld = BC + 1;  // row stride of the R staging buffer
   extern __shared__ __align__(16) unsigned char lds[];
   int* keys = (int*)(lds + L.off_keys);
-  double* R = (double*)(lds + L.off_keys);
+  double* base = (double*)lds;  // -A(I_k, J_k) once the gather arrays are done
+  double* R = (double*)(lds + L.off_R);
   int* trow = (int*)(lds + L.off_trow);
   double* tv = (double*)(lds + L.off_tv);
   int* uniq = (int*)(lds + L.off_uniq);
@@ -446,6 +457,30 @@ __global__ __launch_bounds__(BC * BR, (S <= 16 ? 3 : 1)) void k_factor_ls_blk(
     if (tid == 0) misc[2] = find_row(uniq, nI, (int)k);
     __syncthreads();
     const int kloc = misc[2], ak = misc[3];
+    // dense -A(I_k, J_k): each thread merges its column's triples (rows
+    // ascending) into its rows, then stores them over the gather arrays
+    {
+      double B0[S];
+      int p = cc < m ? coloff[cc] : 0;
+      const int pe = cc < m ? coloff[cc + 1] : 0;
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2) {
+        const int r = s2 * kBR + g;
+        double x = 0.0;
+        while (p < pe && (trow[p] >> 5) < r) ++p;
+        if (p < pe && (trow[p] >> 5) == r) x = -tv[p];
+        B0[s2] = x;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2) base[cc * VS + s2 * kBR + g] = B0[s2];
+      __syncthreads();
+    }
+    // the shifted diagonal entry of this thread's column: column cc of
+    // A_new, or for an update's right-hand side A_prev(I_k, k) = column ak
+    const int acol = (cc == m) ? ak : min(cc, max(m - 1, 0));
+    const int dl = (cc <= m) ? coldiag[acol] : -1;
+    const double ej = (cc <= m) ? e[colJ[acol]] : 0.0;
 
     for (int jb = 0; jb < njobs; ++jb) {
       const FactorJob job = jobs[jb];
@@ -453,22 +488,12 @@ __global__ __launch_bounds__(BC * BR, (S <= 16 ? 3 : 1)) void k_factor_ls_blk(
       double M[S];
       const bool rhs = (cc == m);
       if (cc < m || (rhs && !job.is_spai)) {
-        // column cc of A_new, or for an update the right-hand side
-        // A_prev(I_k, k) = column ak with the previous shift
-        const int a = rhs ? ak : cc;
-        const double sh = rhs ? job.sigma_prev : job.sigma_new;
-        const int dl = coldiag[a];
-        const double dv = sh * e[colJ[a]];
-        int p = coloff[a];
-        const int pe = coloff[a + 1];
+        const double dv = (rhs ? job.sigma_prev : job.sigma_new) * ej;
 #pragma unroll
         for (int s2 = 0; s2 < S; ++s2) {
           const int r = s2 * kBR + g;
-          double x = 0.0;
-          while (p < pe && (trow[p] >> 5) < r) ++p;
-          if (p < pe && (trow[p] >> 5) == r) x = -tv[p];
-          if (r == dl) x += dv;
-          M[s2] = x;
+          const double x = base[acol * VS + r];
+          M[s2] = (r == dl) ? x + dv : x;
         }
       } else {
 #pragma unroll
@@ -544,9 +569,11 @@ __global__ __launch_bounds__(BC * BR, (S <= 16 ? 3 : 1)) void k_factor_ls_blk(
       __syncthreads();
       if (wave == 0) {
         double y = (lane < m) ? R[lane * kRld + m] : 0.0;
+        // reciprocals of R's diagonal up front, off the loop's critical path
+        const double rinv = (lane < m) ? 1.0 / R[lane * kRld + lane] : 0.0;
         double q = 0.0;
         for (int i = m - 1; i >= 0; --i) {
-          const double qi = __shfl(y, i, 64) / R[i * kRld + i];
+          const double qi = __shfl(y, i, 64) * __shfl(rinv, i, 64);
           if (lane == i) q = qi;
           if (lane < i) y = fma(-R[lane * kRld + i], qi, y);
         }
