@@ -208,11 +208,11 @@ morx_status morx_project(morx_system sys, int32_t r, const double* V, int64_t ld
  *                    column, the local matrix in registers (|J_k| < 32);
  *   cols_per_wave    chain step: most right-hand-side columns one wave
  *                    carries over its rows, sharing every factor load among
- *                    them (1..8);
+ *                    them (1..16);
  *   slices_per_wave  iteration kernels: 64-row slices per wave (1..64; raised
  *                    to the least value that keeps <= 1024 row blocks);
  *   spmv_cols_per_wave  shifted pair and true residual: the same as
- *                    cols_per_wave for the operator's loads (1..8; -1 follows
+ *                    cols_per_wave for the operator's loads (1..16; -1 follows
  *                    cols_per_wave).
  * morx_system_set_tune checks the values (MORX_E_INVALID) and they apply from
  * the next call on the system.  morx_autotune times the candidates on the

@@ -44,7 +44,8 @@ enum TraceClass : int { TR_CHAIN = 0, TR_SPMV = 1, TR_UPDATE = 2, TR_FACTOR = 3,
 
 namespace {
 
-constexpr int kMaxNC = 8;          // columns per wave
+constexpr int kMaxNC = 16;         // columns per wave (tuned)
+constexpr int kDefaultNC = 8;      // columns per wave without tuning
 constexpr int kMaxBlocks = 1024;   // row blocks per launch (partials per column)
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = 64 * kWavesPerBlock;
@@ -294,17 +295,20 @@ __device__ __forceinline__ const AT* chain_input(const IterArgs& a, int c, bool 
 // stay within the register budget.
 template <int NC>
 struct ChunkLen {
-  static constexpr int value = NC <= 4 ? 8 : 4;
+  static constexpr int value = NC <= 4 ? 8 : (NC <= 8 ? 4 : 2);
 };
 
-template <typename VT, typename AT, int NC>
-__global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s, int do_rho) {
+// RHO: the iteration's last chain launch, whose transposed half also forms
+// the partial sums of rho (a separate instantiation, so the other launches
+// do not hold those accumulators in registers)
+template <typename VT, typename AT, int NC, bool RHO>
+__global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s) {
   constexpr int kU = ChunkLen<NC>::value;
   const WaveCtx t = wave_ctx(a);
   const int c0 = blockIdx.y * NC;
   const bool bwd = blockIdx.z == 1;
   const int jf = bwd ? a.maxL - 1 - s : s;  // chain position applied by this half
-  const bool rho_half = bwd && do_rho;
+  const bool rho_half = RHO && bwd;
   unsigned valid = 0;
   const AT* src[NC];
   AT* dst[NC];
@@ -348,9 +352,9 @@ __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s, int do
     }
     shared = shared && fv[j] == fv0;
   }
-  double v[NC][3];
+  double v[RHO ? NC : 1][3];
 #pragma unroll
-  for (int j = 0; j < NC; ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
+  for (int j = 0; j < (RHO ? NC : 1); ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
   const int32_t* off = bwd ? a.offT : a.off;
   const int32_t* col = bwd ? a.colT : a.col;
   for (int64_t sl = t.s_begin; sl < t.s_end; ++sl) {
@@ -409,17 +413,20 @@ __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s, int do
         if (valid & (1u << j)) {
           const AT zs = (AT)acc[j];
           gst(dst[j] + i, zs);
-          if (rho_half) {
-            const double zi = (double)zs;
-            const double ri = gld(vptr(a, V_R, c0 + j) + i);
-            v[j][0] = fma(zi, ri, v[j][0]);
-            v[j][1] = fma(zi, zi, v[j][1]);
-            v[j][2] = fma(ri, ri, v[j][2]);
+          if constexpr (RHO) {
+            if (rho_half) {
+              const double zi = (double)zs;
+              const double ri = gld(vptr(a, V_R, c0 + j) + i);
+              v[j][0] = fma(zi, ri, v[j][0]);
+              v[j][1] = fma(zi, zi, v[j][1]);
+              v[j][2] = fma(ri, ri, v[j][2]);
+            }
           }
         }
     }
   }
-  if (rho_half) block_partials<NC, 3>(a, t, c0, valid, v, a.part_rho);
+  if constexpr (RHO)
+    if (rho_half) block_partials<NC, 3>(a, t, c0, valid, v, a.part_rho);
 }
 
 // convergence test on the residuals of the previous update (or of the start
@@ -1060,7 +1067,7 @@ static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   const int64_t per_blk_min = (a.nslices + kMaxBlocks - 1) / kMaxBlocks;
   a.spw = (int)std::max<int64_t>(1, (per_blk_min + kWavesPerBlock - 1) / kWavesPerBlock);
   if (sys->tune_spw > 0) a.spw = std::max(a.spw, (int)sys->tune_spw);
-  a.ncmax = sys->tune_nc > 0 ? (int)sys->tune_nc : kMaxNC;
+  a.ncmax = sys->tune_nc > 0 ? (int)sys->tune_nc : kDefaultNC;
   a.ncmax_spmv = sys->tune_nc_spmv > 0 ? (int)sys->tune_nc_spmv : a.ncmax;
   int64_t nb = (a.nslices + (int64_t)kWavesPerBlock * a.spw - 1) / ((int64_t)kWavesPerBlock * a.spw);
   nb = std::max<int64_t>(8, (nb + 7) / 8 * 8);
@@ -1089,10 +1096,13 @@ static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   return a;
 }
 
-// columns per wave: the batch split into equal chunks of at most ncmax
+// columns per wave: the batch split into equal chunks of at most ncmax,
+// rounded up to an instantiated tile width (1..8, 10, 12, 16; the extra
+// columns of a chunk are past the batch and masked)
 static int pick_nc(int nc, int ncmax) {
   const int chunks = (nc + ncmax - 1) / ncmax;
-  return (nc + chunks - 1) / chunks;
+  const int w = (nc + chunks - 1) / chunks;
+  return w <= 8 ? w : (w <= 10 ? 10 : (w <= 12 ? 12 : 16));
 }
 
 #define MORX_NC_DISPATCH(NCV, ...)                         \
@@ -1104,7 +1114,10 @@ static int pick_nc(int nc, int ncmax) {
     case 5: { constexpr int NC = 5; __VA_ARGS__; } break;  \
     case 6: { constexpr int NC = 6; __VA_ARGS__; } break;  \
     case 7: { constexpr int NC = 7; __VA_ARGS__; } break;  \
-    default: { constexpr int NC = 8; __VA_ARGS__; } break; \
+    case 8: { constexpr int NC = 8; __VA_ARGS__; } break;  \
+    case 10: { constexpr int NC = 10; __VA_ARGS__; } break; \
+    case 12: { constexpr int NC = 12; __VA_ARGS__; } break; \
+    default: { constexpr int NC = 16; __VA_ARGS__; } break; \
   }
 
 static dim3 grid_of(const IterArgs& a, int ncv, int halves) {
@@ -1123,8 +1136,8 @@ static void enqueue_chain(const IterArgs& a, hipStream_t st, TraceState* t) {
     e1 = trace_event(t);
     if (e0) hipEventRecord(e0, st);
   }
-  for (int s = 0; s < a.maxL; ++s)
-    k_chain_step<VT, AT, NC><<<g, kBlock, 0, st>>>(a, s, s == a.maxL - 1 ? 1 : 0);
+  for (int s = 0; s + 1 < a.maxL; ++s) k_chain_step<VT, AT, NC, false><<<g, kBlock, 0, st>>>(a, s);
+  k_chain_step<VT, AT, NC, true><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
   if (t && e0 && e1) {
     hipEventRecord(e1, st);
     t->pending.push_back({TR_CHAIN, e0, e1, a.maxL});
@@ -1719,7 +1732,7 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
   int best_nc = -1, best_spw = -1, best_ncs = -1;
   // chain tile and row block (the shifted pair follows the chain tile) ...
   std::vector<int> seen;
-  for (int ncmax : {8, 4, 2, 1}) {
+  for (int ncmax : {16, 8, 4, 2, 1}) {
     const int ncv = pick_nc(ncols, ncmax);
     if (std::find(seen.begin(), seen.end(), ncv) != seen.end()) continue;
     seen.push_back(ncv);
@@ -1743,7 +1756,7 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
   if (s == MORX_OK) {
     seen.clear();
     seen.push_back(pick_nc(ncols, best_nc));
-    for (int ncs : {8, 4, 2, 1}) {
+    for (int ncs : {16, 8, 4, 2, 1}) {
       const int ncv = pick_nc(ncols, ncs);
       if (std::find(seen.begin(), seen.end(), ncv) != seen.end()) continue;
       seen.push_back(ncv);

@@ -378,8 +378,8 @@ def test_tune_rejects_bad_values(ctx):
 
     w = make_workload(0, N=10, nshift=2)
     S = api.System(ctx, w.A, w.e)
-    for bad in ({"cols_per_wave": 9}, {"cols_per_wave": 0}, {"slices_per_wave": 65},
-                {"factor_kernel": 4}, {"spmv_cols_per_wave": 9}):
+    for bad in ({"cols_per_wave": 17}, {"cols_per_wave": 0}, {"slices_per_wave": 65},
+                {"factor_kernel": 4}, {"spmv_cols_per_wave": 17}):
         with pytest.raises(morx.MorxError):
             S.set_tune(**bad)
     S.close()
