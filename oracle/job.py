@@ -36,6 +36,42 @@ SCHEDULES = {"reuse": chain.schedule, "direct": chain.schedule_direct,
              "first": chain.schedule_first}
 
 
+def moments(A, e, B, C, sigmas, nmom: int, prec: str = "f64", tol: float = 1e-10,
+            policy: str = "reuse", maxit=None, max_restarts: int = 3):
+    """Moments ``X_j = (s E - A)^{-1} E X_{j-1}`` (``X_0`` solves with B) and the
+    transposed ones with C, j < nmom, at every shift of one round, with the
+    round's preconditioner chains (built once) and two-sided BiCG.  Returns
+    (X, Y, stats) with moment j of column c of shift i at column
+    ``(j * nshift + i) * m + c``."""
+    A = sp.csr_matrix(A)
+    n = A.shape[0]
+    e = np.asarray(e, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64).reshape(n, -1)
+    C = np.asarray(C, dtype=np.float64).reshape(n, -1)
+    m, ns = B.shape[1], len(sigmas)
+    specs, chains = SCHEDULES[policy]([list(sigmas)])
+    factors = build_factors(A, e, specs, prec)
+    E = sp.diags(e)
+    X = np.zeros((n, nmom * ns * m))
+    Y = np.zeros((n, nmom * ns * m))
+    stats = [None] * (nmom * ns * m)
+    for i, s in enumerate(sigmas):
+        As = (float(s) * E - A).tocsr()
+        AsT = As.T.tocsr()
+        ch = chains[0][i]
+        P = lambda v, ch=ch: chain.apply(factors, ch, v)
+        PT = lambda v, ch=ch: chain.apply_transpose(factors, ch, v)
+        for c in range(m):
+            b, cc = B[:, c], C[:, c]
+            for j in range(nmom):
+                res = bicg.solve(lambda v: As @ v, lambda v: AsT @ v, b, cc, P, PT, tol=tol,
+                                 maxit=maxit, max_restarts=max_restarts)
+                k = (j * ns + i) * m + c
+                X[:, k], Y[:, k], stats[k] = res.x, res.y, res
+                b, cc = e * res.x, e * res.y
+    return X, Y, stats
+
+
 def run(A, e, B, C, rounds, prec: str = "f64", tol: float = 1e-10, want_dual: bool = True,
         maxit=None, max_restarts: int = 3, project: bool = True, factors=None,
         apply_prec: str = "f64", policy: str = "reuse"):

@@ -370,6 +370,49 @@ def test_projection_hermite_interpolation():
     assert abs(projection.transfer(Ar2, Er2, Br2, Cr2, 7.0) - Hr).max() <= 1e-10 * abs(Hr).max()
 
 
+def test_transfer_derivatives_against_central_differences():
+    """H^(k) from the closed form against central differences of H^(k-1):
+    a wrong sign, factorial or power of (sE - A)^{-1} E fails."""
+    w = make_workload(0, N=8)
+    Ar, Er = w.A.toarray(), np.diag(w.e)
+    Br, Cr = w.B.reshape(-1, 1), w.C.reshape(-1, 1)
+    s, h = 3.0, 1e-4
+    for k in (1, 2, 3):
+        d = projection.transfer_derivative_k(Ar, Er, Br, Cr, s, k)
+        fd = (projection.transfer_derivative_k(Ar, Er, Br, Cr, s + h, k - 1)
+              - projection.transfer_derivative_k(Ar, Er, Br, Cr, s - h, k - 1)) / (2 * h)
+        assert abs(d - fd).max() <= 1e-6 * abs(d).max(), (k, d, fd)
+        full = projection.full_transfer_derivative_k(w.A, w.e, w.B, w.C, s, k)
+        assert abs(full - d).max() <= 1e-10 * abs(d).max()
+    assert np.allclose(projection.transfer_derivative_k(Ar, Er, Br, Cr, s, 1),
+                       projection.transfer_derivative(Ar, Er, Br, Cr, s), rtol=1e-12)
+
+
+def test_moments_match_derivatives_to_order_2J_minus_1():
+    """Two moments per shift on both sides: the reduced H and its first three
+    derivatives equal the full ones at every shift (oracle moments by BiCG);
+    away from the shifts the reduced model is only an approximation."""
+    w = make_workload(1, N=6, nshift=3)
+    sig = w.rounds[0]
+    X, Y, stats = job.moments(w.A, w.e, w.B, w.C, sig, 2)
+    assert all(st.status == "ok" for st in stats)
+    # the first moments satisfy their defining systems
+    E = sp.diags(w.e)
+    for i, s in enumerate(sig):
+        M = (s * E - w.A).tocsr()
+        rhs = w.e * X[:, i]
+        assert np.linalg.norm(M @ X[:, len(sig) + i] - rhs) <= 1e-9 * np.linalg.norm(rhs)
+    Ar, Er, Br, Cr = projection.reduce(w.A, w.e, w.B, w.C, X, Y)
+    for s in sig:
+        for k in range(4):
+            full = projection.full_transfer_derivative_k(w.A, w.e, w.B, w.C, s, k)
+            red = projection.transfer_derivative_k(Ar, Er, Br, Cr, s, k)
+            assert abs(red - full).max() <= 1e-7 * abs(full).max(), (s, k)
+    full4 = projection.full_transfer_derivative_k(w.A, w.e, w.B, w.C, 7.0, 4)
+    red4 = projection.transfer_derivative_k(Ar, Er, Br, Cr, 7.0, 4)
+    assert abs(red4 - full4).max() > 1e-8 * abs(full4).max()
+
+
 def test_two_way_transfer_identity_from_oracle_solves():
     w = make_workload(0, nshift=3)
     out = job.run(w.A, w.e, w.B, w.C, w.rounds, tol=1e-12, project=False)
