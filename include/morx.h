@@ -185,6 +185,25 @@ morx_status morx_solve_shifts(morx_system sys, int32_t nshift, const double* sig
                               const morx_opts* opts, morx_col_stats* stats, void* stream);
 
 /*
+ * Higher moments at the same shifts (the inner loop of AIRGA, Algorithm 1,
+ * in first-order form): moment 0 is morx_solve_shifts' solve, and moment
+ * j < nmom solves the same systems with E times moment j-1,
+ *   X_j(i) = (sigma_i E - A)^{-1} E X_{j-1}(i),
+ *   Y_j(i) = (sigma_i E - A)^{-T} E Y_{j-1}(i).
+ * The factors and chains (policy opts->chain) are built once and serve every
+ * moment; each moment is one batched solve (opts->batched).  X (dev) holds
+ * column c of shift i of moment j at column (j * nshift + i) * m + c, Y
+ * likewise; stats (host) has nmom * nshift * m entries in that order.  A
+ * two-sided projection on all moments matches the transfer function and its
+ * derivatives up to order 2 nmom - 1 at every shift.  Allocates two
+ * n x (nshift m) blocks for the right-hand sides when nmom > 1.
+ */
+morx_status morx_solve_moments(morx_system sys, int32_t nshift, const double* sigmas, int32_t m,
+                               const double* B, int64_t ldb, const double* C, int64_t ldc,
+                               int32_t nmom, double* X, int64_t ldx, double* Y, int64_t ldy,
+                               const morx_opts* opts, morx_col_stats* stats, void* stream);
+
+/*
  * Two-sided Petrov-Galerkin projection (Section II, reduced model after
  * Algorithm 2; descriptor form for E != I):
  *   Ar = W^T A V, Er = W^T E V (r x r), Br = W^T B (r x m), Cr = V^T C (r x q)

@@ -109,6 +109,30 @@ class System:
                                            raise_on_error=raise_on_error)
         return X, Y, st, stats
 
+    def solve_moments(self, sigmas: Sequence[float], B, C=None, nmom: int = 2, prec: str = "f64",
+                      tol: float = 1e-10, batched: bool = True, policy: str = "reuse",
+                      raise_on_error: bool = True):
+        """Moments 0..nmom-1 at every shift; returns (X, Y, status, stats) with
+        moment j of column c of shift i at column (j * nshift + i) * m + c."""
+        Bd = B if isinstance(B, torch.Tensor) else block_to_dev(B, self.device)
+        Cd = None
+        if C is not None:
+            Cd = C if isinstance(C, torch.Tensor) else block_to_dev(C, self.device)
+        m = Bd.shape[1]
+        ns = len(sigmas)
+        X = morx.colmajor(nmom * m * ns, self.n, device=self.device)
+        Y = morx.colmajor(nmom * m * ns, self.n, device=self.device) if Cd is not None else None
+        o = morx.morx_opts_default()
+        o.tol = tol
+        o.precond_prec = morx.PREC[prec]
+        o.want_dual = 1 if Cd is not None else 0
+        o.batched = 1 if batched else 0
+        o.chain = {"reuse": morx.MORX_CHAIN_RESET, "direct": morx.MORX_CHAIN_DIRECT,
+                   "first": morx.MORX_CHAIN_FIRST}[policy]
+        st, stats = morx.morx_solve_moments(self.handle, sigmas, Bd, Cd, nmom, X, Y, o,
+                                            raise_on_error=raise_on_error)
+        return X, Y, st, stats
+
     def autotune(self, sigma: float, ncols: int, chain_len: int = 1, prec: str = "f64") -> dict:
         """Time the launch-shape candidates on this system and keep the fastest."""
         return morx.morx_autotune(self.handle, sigma, ncols, chain_len, prec)

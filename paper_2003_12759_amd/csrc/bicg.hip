@@ -1384,11 +1384,63 @@ static morx_status rhs_norms(morx_system sys, const double* X, int64_t ld, int m
   return s;
 }
 
+namespace {
+
+// out[:, c] = e .* in[:, c] for ncol columns (the next moment's right-hand side)
+__global__ __launch_bounds__(256) void k_scale_cols(const double* __restrict__ e,
+                                                    const double* __restrict__ in, int64_t ldi,
+                                                    double* __restrict__ out, int64_t ldo,
+                                                    int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int64_t c = blockIdx.y;
+  out[c * ldo + i] = e[i] * in[c * ldi + i];
+}
+
+}  // namespace
+
+// One column pair of a solve: how it runs follows from its right-hand-side
+// norms (a zero primal side runs the transposed system as the shadow
+// recurrence; a missing or zero dual side uses b as the shadow right-hand side).
+static BatchCol pair_col(double sigma, const std::vector<morx_factor>* chain, const double* b,
+                         const double* c, double nb, double nc, bool want_dual, double* xout,
+                         double* yout, morx_col_stats* st) {
+  BatchCol bc{};
+  bc.sigma = sigma;
+  bc.xout = xout;
+  bc.yout = want_dual ? yout : nullptr;
+  bc.chain = chain;
+  bc.L = (int)chain->size();
+  bc.stats = st;
+  const bool cz = !want_dual || nc == 0.0;
+  if (nb != 0.0) {
+    bc.b = b;
+    bc.c = cz ? b : c;
+    bc.check_p = 1;
+    bc.check_d = cz ? 0 : 1;
+    bc.out_x = 1;
+    bc.out_y = cz ? 0 : 2;
+  } else {
+    bc.b = c;
+    bc.c = c;
+    bc.check_p = 0;
+    bc.check_d = 1;
+    bc.out_x = 0;
+    bc.out_y = 2;
+  }
+  return bc;
+}
+
+// Shifted solves of nmom moments: moment 0 solves (sigma_i E - A) x = b_c and
+// the transposed systems with c_c; moment j solves the same systems with
+// E times moment j-1 as right-hand sides.  The factors and chains (policy
+// o.chain) are built once and serve every moment.  X holds moment j of
+// column c of shift i at column (j * nshift + i) * m + c (Y, stats alike).
 static morx_status solve_shifts_impl(morx_system sys, int32_t nshift, const double* sigmas,
                                      int32_t m, const double* B, int64_t ldb, const double* C,
-                                     int64_t ldc, double* X, int64_t ldx, double* Y, int64_t ldy,
-                                     const morx_opts& o, morx_col_stats* stats, hipStream_t st,
-                                     std::vector<morx_factor>& horizontal,
+                                     int64_t ldc, int32_t nmom, double* X, int64_t ldx, double* Y,
+                                     int64_t ldy, const morx_opts& o, morx_col_stats* stats,
+                                     hipStream_t st, std::vector<morx_factor>& horizontal,
                                      std::vector<morx_factor>& fresh) {
   const bool want_dual = o.want_dual != 0;
   const int prec = o.precond_prec;
@@ -1450,55 +1502,96 @@ static morx_status solve_shifts_impl(morx_system sys, int32_t nshift, const doub
       for (int k = 0; k <= i; ++k) chains[i].push_back(fresh[k]);
     }
   }
-  auto trivial_col = [&](int j) { return norms[j] == 0.0 && (!want_dual || norms[m + j] == 0.0); };
-  auto make_col = [&](int i, int j) -> BatchCol {
-    BatchCol bc{};
-    bc.sigma = sigmas[i];
-    bc.xout = X + (int64_t)(i * m + j) * ldx;
-    bc.yout = want_dual ? Y + (int64_t)(i * m + j) * ldy : nullptr;
-    bc.chain = &chains[i];
-    bc.L = (int)chains[i].size();
-    bc.stats = stats ? &stats[i * m + j] : nullptr;
-    const bool cz = !want_dual || norms[m + j] == 0.0;
-    if (norms[j] != 0.0) {
-      bc.b = B + (int64_t)j * ldb;
-      bc.c = cz ? bc.b : C + (int64_t)j * ldc;  // shadow right-hand side b when c is absent
-      bc.check_p = 1;
-      bc.check_d = cz ? 0 : 1;
-      bc.out_x = 1;
-      bc.out_y = cz ? 0 : 2;
-    } else {
-      // only the transposed system is nontrivial: its recurrence is the shadow one
-      bc.b = C + (int64_t)j * ldc;
-      bc.c = bc.b;
-      bc.check_p = 0;
-      bc.check_d = 1;
-      bc.out_x = 0;
-      bc.out_y = 2;
-    }
-    return bc;
-  };
 
-  if (o.batched) {
-    // every factor in one launch, every column pair in one batch
-    MORX_TRY(factor_build_many(sys, prec, jobs.data(), nshift, st));
-    std::vector<BatchCol> cols;
-    for (int i = 0; i < nshift; ++i)
-      for (int j = 0; j < m; ++j)
-        if (!trivial_col(j)) cols.push_back(make_col(i, j));
-    MORX_TRY(solve_batch(sys, cols, prec, o, st));
-  } else {
-    // one shift at a time, one column at a time (factor i built just before
-    // the solves that first need it, as in Algorithm 4)
-    for (int i = 0; i < nshift; ++i) {
-      MORX_TRY(factor_build_many(sys, prec, &jobs[i], 1, st));
-      for (int j = 0; j < m; ++j) {
-        if (trivial_col(j)) continue;
-        std::vector<BatchCol> one{make_col(i, j)};
-        MORX_TRY(solve_batch(sys, one, prec, o, st));
+  // right-hand sides of moments j >= 1: E times the previous moment
+  const int64_t nm = (int64_t)nshift * m;
+  DevBuf rb, rc;
+  if (nmom > 1) {
+    MORX_TRY(dev_alloc(rb, (size_t)nm * sys->n_pad * sizeof(double)));
+    if (want_dual) {
+      const morx_status sa = dev_alloc(rc, (size_t)nm * sys->n_pad * sizeof(double));
+      if (sa != MORX_OK) {
+        dev_free(rb);
+        return sa;
       }
     }
   }
+  std::vector<double> nb(nm), nc(nm, 0.0);  // per (shift, column) of the current moment
+  for (int i = 0; i < nshift; ++i)
+    for (int c = 0; c < m; ++c) {
+      nb[i * m + c] = norms[c];
+      nc[i * m + c] = want_dual ? norms[m + c] : 0.0;
+    }
+  auto trivial = [&](int64_t k) { return nb[k] == 0.0 && (!want_dual || nc[k] == 0.0); };
+  morx_status s = MORX_OK;
+  for (int mom = 0; mom < nmom && s == MORX_OK; ++mom) {
+    double* Xm = X + (int64_t)mom * nm * ldx;
+    double* Ym = want_dual ? Y + (int64_t)mom * nm * ldy : nullptr;
+    morx_col_stats* Sm = stats ? stats + (int64_t)mom * nm : nullptr;
+    if (mom > 0) {
+      const dim3 g((unsigned)((sys->n + 255) / 256), (unsigned)nm);
+      k_scale_cols<<<g, 256, 0, st>>>(sys->e, X + (int64_t)(mom - 1) * nm * ldx, ldx,
+                                      (double*)rb.p, sys->n_pad, sys->n);
+      if (want_dual)
+        k_scale_cols<<<g, 256, 0, st>>>(sys->e, Y + (int64_t)(mom - 1) * nm * ldy, ldy,
+                                        (double*)rc.p, sys->n_pad, sys->n);
+      MORX_HIP(hipGetLastError());
+      s = rhs_norms(sys, (const double*)rb.p, sys->n_pad, (int)nm, nb.data(), st);
+      if (s == MORX_OK && want_dual)
+        s = rhs_norms(sys, (const double*)rc.p, sys->n_pad, (int)nm, nc.data(), st);
+      if (s != MORX_OK) break;
+    }
+    auto col = [&](int i, int c) -> BatchCol {
+      const int64_t k = (int64_t)i * m + c;
+      const double* b = mom == 0 ? B + (int64_t)c * ldb : (const double*)rb.p + k * sys->n_pad;
+      const double* cc = !want_dual ? nullptr
+                         : mom == 0 ? C + (int64_t)c * ldc
+                                    : (const double*)rc.p + k * sys->n_pad;
+      return pair_col(sigmas[i], &chains[i], b, cc, nb[k], nc[k], want_dual, Xm + k * ldx,
+                      Ym ? Ym + k * ldy : nullptr, Sm ? &Sm[k] : nullptr);
+    };
+    if (o.batched) {
+      // every factor in one launch, every column pair of a moment in one batch
+      if (mom == 0) s = factor_build_many(sys, prec, jobs.data(), nshift, st);
+      std::vector<BatchCol> cols;
+      for (int i = 0; i < nshift; ++i)
+        for (int c = 0; c < m; ++c)
+          if (!trivial((int64_t)i * m + c)) cols.push_back(col(i, c));
+      if (s == MORX_OK) s = solve_batch(sys, cols, prec, o, st);
+    } else {
+      // one shift at a time, one column at a time (factor i built just before
+      // the solves that first need it, as in Algorithm 4)
+      for (int i = 0; i < nshift && s == MORX_OK; ++i) {
+        if (mom == 0) s = factor_build_many(sys, prec, &jobs[i], 1, st);
+        for (int c = 0; c < m && s == MORX_OK; ++c) {
+          if (trivial((int64_t)i * m + c)) continue;
+          std::vector<BatchCol> one{col(i, c)};
+          s = solve_batch(sys, one, prec, o, st);
+        }
+      }
+    }
+    // trivial column pairs have the zero solution
+    for (int64_t k = 0; k < nm && s == MORX_OK; ++k) {
+      if (!trivial(k)) continue;
+      if (hipMemsetAsync(Xm + k * ldx, 0, sys->n * sizeof(double), st) != hipSuccess ||
+          (want_dual && hipMemsetAsync(Ym + k * ldy, 0, sys->n * sizeof(double), st) != hipSuccess)) {
+        morx_set_error("solve: clearing a zero column failed");
+        s = MORX_E_HIP;
+        break;
+      }
+      if (Sm) {
+        Sm[k].status = MORX_OK;
+        Sm[k].iters = 0;
+        Sm[k].restarts = 0;
+        Sm[k].relres_primal = 0.0;
+        Sm[k].relres_dual = 0.0;
+      }
+    }
+  }
+  hipStreamSynchronize(st);
+  dev_free(rb);
+  dev_free(rc);
+  MORX_TRY(s);
   // the first factor joins the vertical chain (Algorithm 4); the rest are
   // released when the call returns
   size_t keep_from = 0;
@@ -1511,53 +1604,39 @@ static morx_status solve_shifts_impl(morx_system sys, int32_t nshift, const doub
   sys->vertical_prec = reuse ? prec : -1;
   sys->last_first_shift = sigmas[0];
   morx_status worst = MORX_OK;
-  for (int i = 0; i < nshift; ++i)
-    for (int j = 0; j < m; ++j) {
-      if (trivial_col(j)) {
-        MORX_HIP(hipMemsetAsync(X + (int64_t)(i * m + j) * ldx, 0, sys->n * sizeof(double), st));
-        if (want_dual)
-          MORX_HIP(hipMemsetAsync(Y + (int64_t)(i * m + j) * ldy, 0, sys->n * sizeof(double), st));
-        if (stats) {
-          stats[i * m + j].status = MORX_OK;
-          stats[i * m + j].iters = 0;
-          stats[i * m + j].restarts = 0;
-          stats[i * m + j].relres_primal = 0.0;
-          stats[i * m + j].relres_dual = 0.0;
-        }
-      }
-      if (stats) worst = (morx_status)worse(worst, stats[i * m + j].status);
-    }
+  if (stats)
+    for (int64_t k = 0; k < (int64_t)nmom * nm; ++k) worst = (morx_status)worse(worst, stats[k].status);
   MORX_HIP(hipStreamSynchronize(st));
   return worst;
 }
 
-extern "C" morx_status morx_solve_shifts(morx_system sys, int32_t nshift, const double* sigmas,
-                                         int32_t m, const double* B, int64_t ldb, const double* C,
-                                         int64_t ldc, double* X, int64_t ldx, double* Y,
-                                         int64_t ldy, const morx_opts* opts,
-                                         morx_col_stats* stats, void* stream) {
-  MORX_REQUIRE(sys, MORX_E_INVALID, "morx_solve_shifts: null system");
+static morx_status solve_entry(const char* who, morx_system sys, int32_t nshift,
+                               const double* sigmas, int32_t m, const double* B, int64_t ldb,
+                               const double* C, int64_t ldc, int32_t nmom, double* X, int64_t ldx,
+                               double* Y, int64_t ldy, const morx_opts* opts,
+                               morx_col_stats* stats, void* stream) {
+  MORX_REQUIRE(sys, MORX_E_INVALID, "%s: null system", who);
   morx_opts o;
   if (opts) o = *opts;
   else morx_opts_default(&o);
   const bool want_dual = o.want_dual != 0;
   MORX_REQUIRE(nshift >= 1 && sigmas && m >= 1, MORX_E_INVALID,
-               "morx_solve_shifts: need at least one shift and one column");
-  MORX_REQUIRE(B && X && ldb >= sys->n && ldx >= sys->n, MORX_E_INVALID,
-               "morx_solve_shifts: bad B or X");
+               "%s: need at least one shift and one column", who);
+  MORX_REQUIRE(nmom >= 1 && (int64_t)nmom * nshift * m <= (1 << 20), MORX_E_INVALID,
+               "%s: bad number of moments", who);
+  MORX_REQUIRE(B && X && ldb >= sys->n && ldx >= sys->n, MORX_E_INVALID, "%s: bad B or X", who);
   MORX_REQUIRE(!want_dual || (C && Y && ldc >= sys->n && ldy >= sys->n), MORX_E_INVALID,
-               "morx_solve_shifts: want_dual needs C and Y");
+               "%s: want_dual needs C and Y", who);
   MORX_REQUIRE(o.precond_prec >= MORX_F64 && o.precond_prec <= MORX_BF16, MORX_E_INVALID,
-               "morx_solve_shifts: bad precision");
+               "%s: bad precision", who);
   MORX_REQUIRE(o.apply_prec == MORX_F64 || o.apply_prec == MORX_F32, MORX_E_INVALID,
-               "morx_solve_shifts: apply precision must be MORX_F64 or MORX_F32");
+               "%s: apply precision must be MORX_F64 or MORX_F32", who);
   MORX_REQUIRE(o.chain >= MORX_CHAIN_RESET && o.chain <= MORX_CHAIN_FIRST, MORX_E_INVALID,
-               "morx_solve_shifts: unknown chain policy %d", o.chain);
+               "%s: unknown chain policy %d", who, o.chain);
   MORX_REQUIRE(o.tol >= 0.0 && o.max_restarts >= 0, MORX_E_INVALID,
-               "morx_solve_shifts: bad tolerance or restart limit");
+               "%s: bad tolerance or restart limit", who);
   for (int i = 0; i < nshift; ++i)
-    MORX_REQUIRE(std::isfinite(sigmas[i]), MORX_E_NONFINITE,
-                 "morx_solve_shifts: shift %d not finite", i);
+    MORX_REQUIRE(std::isfinite(sigmas[i]), MORX_E_NONFINITE, "%s: shift %d not finite", who, i);
   morx_ctx ctx = sys->ctx;
   std::lock_guard<std::mutex> lk(ctx->mu);
   MORX_HIP(hipSetDevice(ctx->device));
@@ -1565,13 +1644,32 @@ extern "C" morx_status morx_solve_shifts(morx_system sys, int32_t nshift, const 
   MORX_TRY(stream_enter(ctx, caller));
   std::vector<morx_factor> horizontal, fresh;
   morx_status s = solve_shifts_impl(sys, nshift, sigmas, m, B, ldb, want_dual ? C : nullptr, ldc,
-                                    X, ldx, want_dual ? Y : nullptr, ldy, o, stats, ctx->stream,
-                                    horizontal, fresh);
+                                    nmom, X, ldx, want_dual ? Y : nullptr, ldy, o, stats,
+                                    ctx->stream, horizontal, fresh);
   hipStreamSynchronize(ctx->stream);
   for (morx_factor f : horizontal) factor_release(f);
   for (morx_factor f : fresh) factor_release(f);
   morx_status s2 = stream_leave(ctx, caller);
   return s != MORX_OK ? s : s2;
+}
+
+extern "C" morx_status morx_solve_shifts(morx_system sys, int32_t nshift, const double* sigmas,
+                                         int32_t m, const double* B, int64_t ldb, const double* C,
+                                         int64_t ldc, double* X, int64_t ldx, double* Y,
+                                         int64_t ldy, const morx_opts* opts,
+                                         morx_col_stats* stats, void* stream) {
+  return solve_entry("morx_solve_shifts", sys, nshift, sigmas, m, B, ldb, C, ldc, 1, X, ldx, Y,
+                     ldy, opts, stats, stream);
+}
+
+extern "C" morx_status morx_solve_moments(morx_system sys, int32_t nshift, const double* sigmas,
+                                          int32_t m, const double* B, int64_t ldb,
+                                          const double* C, int64_t ldc, int32_t nmom, double* X,
+                                          int64_t ldx, double* Y, int64_t ldy,
+                                          const morx_opts* opts, morx_col_stats* stats,
+                                          void* stream) {
+  return solve_entry("morx_solve_moments", sys, nshift, sigmas, m, B, ldb, C, ldc, nmom, X, ldx,
+                     Y, ldy, opts, stats, stream);
 }
 
 // ---------------------------------------------------------------------------

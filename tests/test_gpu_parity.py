@@ -476,3 +476,55 @@ def test_projection_hermite_interpolation_from_gpu_solves(ctx):
     eo = np.sort(sla.eigvals(Aro, Ero).real)
     assert np.allclose(eg, eo, rtol=1e-6)
     S.close()
+
+
+@pytest.mark.parametrize("batched", [True, False])
+def test_moments_match_oracle_and_derivatives(ctx, batched):
+    """Three moments per shift: each satisfies its defining system to 1e-10,
+    agrees with the oracle's moments, and the GPU projection on all of them
+    matches H and its derivatives up to order 5 at every shift."""
+    from paper_2003_12759_amd import api
+
+    # two well-separated shifts: moments at clustered shifts are numerically
+    # dependent (condition 1e13 for three shifts in [0.1, 0.8]), which the
+    # Cholesky-QR orthonormalisation rejects; here the basis has condition 1e6
+    w = make_workload(1, N=10, nshift=3)
+    sig, nmom = [0.5, 20.0], 3
+    S = api.System(ctx, w.A, w.e)
+    _say(f"moments n={w.n} nmom={nmom} batched={batched}")
+    X, Y, st, stats = S.solve_moments(sig, w.B, w.C, nmom=nmom, prec="f32", batched=batched)
+    assert st == 0 and all(c.status == 0 for c in stats) and len(stats) == nmom * len(sig)
+    Xo, Yo, _ = ojob.moments(w.A, w.e, w.B, w.C, sig, nmom, prec="f32")
+    Xg, Yg = X.cpu().numpy(), Y.cpu().numpy()
+    E = sp.diags(w.e)
+    ns = len(sig)
+    for j in range(nmom):
+        for i, s in enumerate(sig):
+            k = j * ns + i
+            M = (s * E - w.A).tocsr()
+            b = w.B[:, 0] if j == 0 else w.e * Xg[:, k - ns]
+            c = w.C[:, 0] if j == 0 else w.e * Yg[:, k - ns]
+            assert np.linalg.norm(b - M @ Xg[:, k]) <= 1.01e-10 * np.linalg.norm(b)
+            assert np.linalg.norm(c - M.T @ Yg[:, k]) <= 1.01e-10 * np.linalg.norm(c)
+            assert np.linalg.norm(Xg[:, k] - Xo[:, k]) <= 1e-7 * np.linalg.norm(Xo[:, k])
+            assert np.linalg.norm(Yg[:, k] - Yo[:, k]) <= 1e-7 * np.linalg.norm(Yo[:, k])
+    Ar, Er, Br, Cr = S.project(X, Y, api.block_to_dev(w.B), api.block_to_dev(w.C))
+    for s in sig:
+        for kd in range(2 * nmom):
+            full = oproj.full_transfer_derivative_k(w.A, w.e, w.B, w.C, s, kd)
+            red = oproj.transfer_derivative_k(Ar, Er, Br, Cr, s, kd)
+            assert abs(red - full).max() <= 1e-6 * abs(full).max(), (s, kd)
+    S.close()
+
+
+def test_one_moment_equals_solve_shifts(ctx):
+    from paper_2003_12759_amd import api
+
+    w = make_workload(2, N=8, nshift=3)
+    S = api.System(ctx, w.A, w.e)
+    _say("one moment vs solve_shifts (MIMO)")
+    X1, Y1, _, s1 = S.solve_moments(w.rounds[0], w.B, w.C, nmom=1)
+    X2, Y2, _, s2 = S.solve_shifts(w.rounds[0], w.B, w.C)
+    assert torch.equal(X1, X2) and torch.equal(Y1, Y2)
+    assert [c.iters for c in s1] == [c.iters for c in s2]
+    S.close()
