@@ -290,6 +290,9 @@ def main():
     ap.add_argument("--compare-policies", action="store_true",
                     help="also time the comparator schedules: a SPAI per shift, and "
                          "Table 2's first approach")
+    ap.add_argument("--moments", type=int, default=0,
+                    help="also time morx_solve_moments with this many moments per shift "
+                         "(every round of the job; each moment pair counts as a solve)")
     ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=16, help="serving: slots per system")
     ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 1.0],
@@ -434,6 +437,27 @@ def main():
             comparators[pol] = {"value": round(nsolves / dt_, 3), "unit": "solves/s",
                                 "iters_per_step": sum(x.iters for x in st_)}
 
+    moments = None
+    if args.moments > 0:
+        def moment_job():
+            sts = []
+            for z, sig in enumerate(w.rounds):
+                _, _, _, st_ = S.solve_moments(list(sig), Bd, Cd, nmom=args.moments,
+                                               prec=w.prec, tol=w.tol, next_round=z > 0)
+                sts.extend(st_)
+            return sts
+        moment_job()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st_ = moment_job()
+        torch.cuda.synchronize()
+        dt_ = time.perf_counter() - t1
+        check(st_, w.tol)
+        moments = {"moments_per_shift": args.moments, "solves_per_step": len(st_),
+                   "value": round(len(st_) / dt_, 3), "unit": "solves/s",
+                   "ms_per_step": round(1e3 * dt_, 3),
+                   "iters_per_step": sum(x.iters for x in st_)}
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, apply)
 
     out = {
@@ -466,6 +490,8 @@ def main():
         out["ladder"] = lad
     if comparators is not None:
         out["comparators"] = comparators
+    if moments is not None:
+        out["moments"] = moments
     print(json.dumps(out), flush=True)
     S.close()
     ctx.close()

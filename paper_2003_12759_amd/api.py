@@ -111,7 +111,7 @@ class System:
 
     def solve_moments(self, sigmas: Sequence[float], B, C=None, nmom: int = 2, prec: str = "f64",
                       tol: float = 1e-10, batched: bool = True, policy: str = "reuse",
-                      raise_on_error: bool = True):
+                      next_round: bool = False, raise_on_error: bool = True):
         """Moments 0..nmom-1 at every shift; returns (X, Y, status, stats) with
         moment j of column c of shift i at column (j * nshift + i) * m + c."""
         Bd = B if isinstance(B, torch.Tensor) else block_to_dev(B, self.device)
@@ -127,8 +127,10 @@ class System:
         o.precond_prec = morx.PREC[prec]
         o.want_dual = 1 if Cd is not None else 0
         o.batched = 1 if batched else 0
-        o.chain = {"reuse": morx.MORX_CHAIN_RESET, "direct": morx.MORX_CHAIN_DIRECT,
-                   "first": morx.MORX_CHAIN_FIRST}[policy]
+        if policy == "reuse":
+            o.chain = morx.MORX_CHAIN_NEXT_ROUND if next_round else morx.MORX_CHAIN_RESET
+        else:
+            o.chain = {"direct": morx.MORX_CHAIN_DIRECT, "first": morx.MORX_CHAIN_FIRST}[policy]
         st, stats = morx.morx_solve_moments(self.handle, sigmas, Bd, Cd, nmom, X, Y, o,
                                             raise_on_error=raise_on_error)
         return X, Y, st, stats
