@@ -11,7 +11,7 @@ import pytest
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from oracle import bicg, chain, job, pattern, projection, spai
+from oracle import bicg, chain, gmres, job, pattern, projection, spai
 from oracle.precision import round_storage
 from paper_2003_12759_amd.workloads import laplacian_5pt, make_workload
 
@@ -411,6 +411,61 @@ def test_moments_match_derivatives_to_order_2J_minus_1():
     full4 = projection.full_transfer_derivative_k(w.A, w.e, w.B, w.C, 7.0, 4)
     red4 = projection.transfer_derivative_k(Ar, Er, Br, Cr, 7.0, 4)
     assert abs(red4 - full4).max() > 1e-8 * abs(full4).max()
+
+
+def test_gmres_matches_dense_lu_with_spai_chain():
+    """GMRES(30) with the Algorithm-4 chain on the 45x45 workload (primal and
+    transposed systems): true residuals <= 1e-10 and the LU error bound."""
+    w = make_workload(0, N=30, nshift=3)
+    specs, chains = chain.schedule(w.rounds)
+    fs = job.build_factors(w.A, w.e, specs)
+    Ad = w.A.toarray()
+    for i, s in enumerate(w.rounds[0]):
+        M = s * np.diag(w.e) - Ad
+        ch = chains[0][i]
+        rp, rd = gmres.solve_pair(lambda v: M @ v, lambda v: M.T @ v, w.B[:, 0], w.C[:, 0],
+                                  lambda v: chain.apply(fs, ch, v),
+                                  lambda v: chain.apply_transpose(fs, ch, v), tol=1e-10, m=30)
+        assert rp.status == "ok" and rd.status == "ok"
+        smin = np.linalg.eigvalsh(M)[0]
+        for res, rhs, Mm in ((rp, w.B[:, 0], M), (rd, w.C[:, 0], M.T)):
+            exact = np.linalg.solve(Mm, rhs)
+            rel = np.linalg.norm(rhs - Mm @ res.x) / np.linalg.norm(rhs)
+            assert rel <= 1e-10
+            assert np.linalg.norm(res.x - exact) <= (rel + 1e-13) * np.linalg.norm(rhs) / smin
+
+
+def test_gmres_iterate_minimises_the_residual():
+    """After k steps the GMRES iterate has the least residual over
+    P K_k(A P, b): brute-force least squares over an explicit Krylov basis."""
+    n = 40
+    A = _rand_sparse(n, 0.1, 31).toarray()
+    rng = np.random.default_rng(32)
+    Pm = np.eye(n) + 0.05 * rng.standard_normal((n, n))
+    b = rng.standard_normal(n)
+    AP = A @ Pm
+    for k in range(1, 7):
+        x, steps, _ = gmres.cycle(lambda v: A @ v, lambda v: Pm @ v, np.zeros(n), b, 30, 0.0,
+                                  steps=k)
+        assert steps == k
+        K = np.zeros((n, k))
+        K[:, 0] = b
+        for j in range(1, k):
+            K[:, j] = AP @ K[:, j - 1]
+        Q, _ = np.linalg.qr(K)
+        y, *_ = np.linalg.lstsq(AP @ Q, b, rcond=None)
+        best = np.linalg.norm(b - AP @ Q @ y)
+        got = np.linalg.norm(b - A @ x)
+        assert abs(got - best) <= 1e-10 * np.linalg.norm(b), (k, got, best)
+
+
+def test_gmres_converges_within_n_steps():
+    n = 12
+    A = _rand_sparse(n, 0.3, 33).toarray()
+    b = np.random.default_rng(34).standard_normal(n)
+    res = gmres.solve(lambda v: A @ v, b, tol=1e-10, m=n, max_restarts=0)
+    assert res.status == "ok" and res.iters <= n and res.cycles == 1
+    assert np.linalg.norm(res.x - np.linalg.solve(A, b)) <= 1e-9 * np.linalg.norm(res.x)
 
 
 def test_two_way_transfer_identity_from_oracle_solves():
