@@ -293,6 +293,9 @@ def main():
     ap.add_argument("--moments", type=int, default=0,
                     help="also time morx_solve_moments with this many moments per shift "
                          "(every round of the job; each moment pair counts as a solve)")
+    ap.add_argument("--gmres", type=int, default=0,
+                    help="also time the job with GMRES(this restart length) instead of BiCG "
+                         "(one system at a time, the paper's solver)")
     ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=16, help="serving: slots per system")
     ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 1.0],
@@ -458,6 +461,26 @@ def main():
                    "ms_per_step": round(1e3 * dt_, 3),
                    "iters_per_step": sum(x.iters for x in st_)}
 
+    gm = None
+    if args.gmres > 0:
+        def gmres_job():
+            sts = []
+            for z, sig in enumerate(w.rounds):
+                _, _, _, st_ = S.gmres_shifts(list(sig), Bd, Cd, restart=args.gmres, prec=w.prec,
+                                              tol=w.tol, next_round=z > 0)
+                sts.extend(st_)
+            return sts
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st_ = gmres_job()
+        torch.cuda.synchronize()
+        dt_ = time.perf_counter() - t1
+        check(st_, w.tol)
+        gm = {"restart": args.gmres, "value": round(nsolves / dt_, 3), "unit": "solves/s",
+              "ms_per_step": round(1e3 * dt_, 3),
+              "iters_per_step": sum(x.iters for x in st_),
+              "mode": "GMRES, one system at a time, same chains"}
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, apply)
 
     out = {
@@ -492,6 +515,8 @@ def main():
         out["comparators"] = comparators
     if moments is not None:
         out["moments"] = moments
+    if gm is not None:
+        out["gmres"] = gm
     print(json.dumps(out), flush=True)
     S.close()
     ctx.close()

@@ -204,6 +204,26 @@ morx_status morx_solve_moments(morx_system sys, int32_t nshift, const double* si
                                const morx_opts* opts, morx_col_stats* stats, void* stream);
 
 /*
+ * Restarted GMRES(m), right-preconditioned (the solver of the paper's
+ * experiments, Section IV; a comparator of morx_solve_shifts' BiCG on the
+ * same factor chains, policy opts->chain).  Every system, the primal one with
+ * P and the transposed one with P^T, is solved by its own GMRES, one system
+ * at a time: Arnoldi on A_s P with classical Gram-Schmidt applied twice (on
+ * the device), the (m+1) x m Hessenberg matrix, Givens rotations and the
+ * triangular solve on the host (one synchronisation per Arnoldi step).  A
+ * cycle ends when the residual estimate passes opts->tol or after `restart`
+ * steps (1..64); the true residual is then recomputed, and the system
+ * restarts (a refinement restart, when the estimate had passed, counts
+ * against opts->max_restarts).  Layout of X, Y, stats as in
+ * morx_solve_shifts; stats.iters and stats.restarts add up both systems.
+ * opts->batched, use_graph, poll_iters and apply_prec are ignored.
+ */
+morx_status morx_gmres_shifts(morx_system sys, int32_t nshift, const double* sigmas, int32_t m,
+                              const double* B, int64_t ldb, const double* C, int64_t ldc,
+                              int32_t restart, double* X, int64_t ldx, double* Y, int64_t ldy,
+                              const morx_opts* opts, morx_col_stats* stats, void* stream);
+
+/*
  * Two-sided Petrov-Galerkin projection (Section II, reduced model after
  * Algorithm 2; descriptor form for E != I):
  *   Ar = W^T A V, Er = W^T E V (r x r), Br = W^T B (r x m), Cr = V^T C (r x q)

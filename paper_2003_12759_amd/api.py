@@ -135,6 +135,33 @@ class System:
                                             raise_on_error=raise_on_error)
         return X, Y, st, stats
 
+    def gmres_shifts(self, sigmas: Sequence[float], B, C=None, restart: int = 30,
+                     prec: str = "f64", tol: float = 1e-10, policy: str = "reuse",
+                     next_round: bool = False, max_restarts: int = 3, maxit: int = 0,
+                     raise_on_error: bool = True):
+        """GMRES(restart) on the same chains; returns (X, Y, status, stats)."""
+        Bd = B if isinstance(B, torch.Tensor) else block_to_dev(B, self.device)
+        Cd = None
+        if C is not None:
+            Cd = C if isinstance(C, torch.Tensor) else block_to_dev(C, self.device)
+        m = Bd.shape[1]
+        ns = len(sigmas)
+        X = morx.colmajor(m * ns, self.n, device=self.device)
+        Y = morx.colmajor(m * ns, self.n, device=self.device) if Cd is not None else None
+        o = morx.morx_opts_default()
+        o.tol = tol
+        o.precond_prec = morx.PREC[prec]
+        o.want_dual = 1 if Cd is not None else 0
+        o.max_restarts = max_restarts
+        o.maxit = maxit
+        if policy == "reuse":
+            o.chain = morx.MORX_CHAIN_NEXT_ROUND if next_round else morx.MORX_CHAIN_RESET
+        else:
+            o.chain = {"direct": morx.MORX_CHAIN_DIRECT, "first": morx.MORX_CHAIN_FIRST}[policy]
+        st, stats = morx.morx_gmres_shifts(self.handle, sigmas, Bd, Cd, restart, X, Y, o,
+                                           raise_on_error=raise_on_error)
+        return X, Y, st, stats
+
     def autotune(self, sigma: float, ncols: int, chain_len: int = 1, prec: str = "f64") -> dict:
         """Time the launch-shape candidates on this system and keep the fastest."""
         return morx.morx_autotune(self.handle, sigma, ncols, chain_len, prec)

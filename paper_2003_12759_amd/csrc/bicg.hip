@@ -1431,6 +1431,78 @@ static BatchCol pair_col(double sigma, const std::vector<morx_factor>* chain, co
   return bc;
 }
 
+// Factor jobs and each shift's chain.  Algorithm 4 (RESET / NEXT_ROUND): the
+// vertical chain (plus, for the next round, this call's first factor), then
+// the horizontal updates.  Comparators: a SPAI per shift (DIRECT), or Table
+// 2's first approach, P_i = Q_i P_1 with Q_i taken from sigmas[0] (FIRST);
+// neither keeps a vertical chain.  Factors are allocated into `fresh`, not
+// built.
+morx_status plan_chains(morx_system sys, int nshift, const double* sigmas, const morx_opts& o,
+                        std::vector<morx_factor>& fresh, ChainPlan& plan) {
+  const int prec = o.precond_prec;
+  const int policy = o.chain;
+  const bool reuse = policy == MORX_CHAIN_RESET || policy == MORX_CHAIN_NEXT_ROUND;
+  const bool reset = !reuse || policy == MORX_CHAIN_RESET || sys->vertical.empty();
+  plan.reuse = reuse;
+  if (!reset)
+    MORX_REQUIRE(sys->vertical_prec == prec, MORX_E_INVALID,
+                 "MORX_CHAIN_NEXT_ROUND needs the precision of the previous round");
+  if (reset) {
+    for (morx_factor f : sys->vertical) factor_release(f);
+    sys->vertical.clear();
+  }
+  plan.jobs.clear();
+  for (int i = 0; i < nshift; ++i) {
+    morx_factor f = nullptr;
+    MORX_TRY(factor_alloc(sys, prec, &f));
+    fresh.push_back(f);
+    FactorJob jb;
+    if (policy == MORX_CHAIN_DIRECT || i == 0) {
+      const bool spai = !reuse || reset;
+      jb.is_spai = spai ? 1 : 0;
+      jb.sigma_prev = spai ? 0.0 : sys->last_first_shift;
+    } else {
+      jb.is_spai = 0;
+      jb.sigma_prev = policy == MORX_CHAIN_FIRST ? sigmas[0] : sigmas[i - 1];
+    }
+    jb.sigma_new = sigmas[i];
+    jb.vals = f->vals.p;
+    jb.valsT = f->valsT.p;
+    f->is_spai = jb.is_spai != 0;
+    f->sigma_prev = jb.sigma_prev;
+    f->sigma_new = jb.sigma_new;
+    plan.jobs.push_back(jb);
+  }
+  plan.chains.assign(nshift, {});
+  for (int i = 0; i < nshift; ++i) {
+    if (policy == MORX_CHAIN_DIRECT) {
+      plan.chains[i] = {fresh[i]};
+    } else if (policy == MORX_CHAIN_FIRST) {
+      plan.chains[i] = {fresh[0]};
+      if (i > 0) plan.chains[i].push_back(fresh[i]);
+    } else {
+      plan.chains[i] = sys->vertical;
+      for (int k = 0; k <= i; ++k) plan.chains[i].push_back(fresh[k]);
+    }
+  }
+  return MORX_OK;
+}
+
+// After a successful call: the first factor joins the vertical chain
+// (Algorithm 4); the rest are released when the call returns.
+void commit_chains(morx_system sys, const ChainPlan& plan, const double* sigmas, int prec,
+                   std::vector<morx_factor>& fresh, std::vector<morx_factor>& horizontal) {
+  size_t keep_from = 0;
+  if (plan.reuse && !fresh.empty()) {
+    sys->vertical.push_back(fresh[0]);
+    keep_from = 1;
+  }
+  for (size_t k = keep_from; k < fresh.size(); ++k) horizontal.push_back(fresh[k]);
+  fresh.clear();
+  sys->vertical_prec = plan.reuse ? prec : -1;
+  sys->last_first_shift = sigmas[0];
+}
+
 // Shifted solves of nmom moments: moment 0 solves (sigma_i E - A) x = b_c and
 // the transposed systems with c_c; moment j solves the same systems with
 // E times moment j-1 as right-hand sides.  The factors and chains (policy
@@ -1453,55 +1525,10 @@ static morx_status solve_shifts_impl(morx_system sys, int32_t nshift, const doub
   for (int j = 0; j < 2 * m; ++j)
     MORX_REQUIRE(std::isfinite(norms[j]), MORX_E_NONFINITE, "B or C holds NaN or Inf");
 
-  // Factor jobs and each shift's chain.  Algorithm 4 (RESET / NEXT_ROUND):
-  // the vertical chain (plus, for the next round, this call's first factor),
-  // then the horizontal updates.  Comparators: a SPAI per shift (DIRECT), or
-  // Table 2's first approach, P_i = Q_i P_1 with Q_i taken from sigmas[0]
-  // (FIRST); neither keeps a vertical chain.
-  const int policy = o.chain;
-  const bool reuse = policy == MORX_CHAIN_RESET || policy == MORX_CHAIN_NEXT_ROUND;
-  const bool reset = !reuse || policy == MORX_CHAIN_RESET || sys->vertical.empty();
-  if (!reset)
-    MORX_REQUIRE(sys->vertical_prec == prec, MORX_E_INVALID,
-                 "MORX_CHAIN_NEXT_ROUND needs the precision of the previous round");
-  if (reset) {
-    for (morx_factor f : sys->vertical) factor_release(f);
-    sys->vertical.clear();
-  }
-  std::vector<FactorJob> jobs;
-  for (int i = 0; i < nshift; ++i) {
-    morx_factor f = nullptr;
-    MORX_TRY(factor_alloc(sys, prec, &f));
-    fresh.push_back(f);
-    FactorJob jb;
-    if (policy == MORX_CHAIN_DIRECT || i == 0) {
-      const bool spai = !reuse || reset;
-      jb.is_spai = spai ? 1 : 0;
-      jb.sigma_prev = spai ? 0.0 : sys->last_first_shift;
-    } else {
-      jb.is_spai = 0;
-      jb.sigma_prev = policy == MORX_CHAIN_FIRST ? sigmas[0] : sigmas[i - 1];
-    }
-    jb.sigma_new = sigmas[i];
-    jb.vals = f->vals.p;
-    jb.valsT = f->valsT.p;
-    f->is_spai = jb.is_spai != 0;
-    f->sigma_prev = jb.sigma_prev;
-    f->sigma_new = jb.sigma_new;
-    jobs.push_back(jb);
-  }
-  std::vector<std::vector<morx_factor>> chains(nshift);
-  for (int i = 0; i < nshift; ++i) {
-    if (policy == MORX_CHAIN_DIRECT) {
-      chains[i] = {fresh[i]};
-    } else if (policy == MORX_CHAIN_FIRST) {
-      chains[i] = {fresh[0]};
-      if (i > 0) chains[i].push_back(fresh[i]);
-    } else {
-      chains[i] = sys->vertical;
-      for (int k = 0; k <= i; ++k) chains[i].push_back(fresh[k]);
-    }
-  }
+  ChainPlan plan;
+  MORX_TRY(plan_chains(sys, nshift, sigmas, o, fresh, plan));
+  const std::vector<FactorJob>& jobs = plan.jobs;
+  const std::vector<std::vector<morx_factor>>& chains = plan.chains;
 
   // right-hand sides of moments j >= 1: E times the previous moment
   const int64_t nm = (int64_t)nshift * m;
@@ -1592,17 +1619,7 @@ static morx_status solve_shifts_impl(morx_system sys, int32_t nshift, const doub
   dev_free(rb);
   dev_free(rc);
   MORX_TRY(s);
-  // the first factor joins the vertical chain (Algorithm 4); the rest are
-  // released when the call returns
-  size_t keep_from = 0;
-  if (reuse) {
-    sys->vertical.push_back(fresh[0]);
-    keep_from = 1;
-  }
-  for (size_t k = keep_from; k < fresh.size(); ++k) horizontal.push_back(fresh[k]);
-  fresh.clear();
-  sys->vertical_prec = reuse ? prec : -1;
-  sys->last_first_shift = sigmas[0];
+  commit_chains(sys, plan, sigmas, prec, fresh, horizontal);
   morx_status worst = MORX_OK;
   if (stats)
     for (int64_t k = 0; k < (int64_t)nmom * nm; ++k) worst = (morx_status)worse(worst, stats[k].status);

@@ -67,5 +67,15 @@ morx_status batch_launch_segment(KrylovBatch& b, int nc, int maxL, int iters, bo
 morx_status batch_launch_true(KrylovBatch& b, int nc, hipStream_t st);
 // write iterates of the listed slots to their output pointers
 morx_status batch_launch_copy_out(KrylovBatch& b, const int* slots, int count, hipStream_t st);
+// factor jobs and chains of one call (policy opts.chain); see bicg.hip
+struct ChainPlan {
+  std::vector<FactorJob> jobs;
+  std::vector<std::vector<morx_factor>> chains;  // per shift, applied first to last
+  bool reuse = true;                             // Algorithm 4 (keeps a vertical chain)
+};
+morx_status plan_chains(morx_system sys, int nshift, const double* sigmas, const morx_opts& o,
+                        std::vector<morx_factor>& fresh, ChainPlan& plan);
+void commit_chains(morx_system sys, const ChainPlan& plan, const double* sigmas, int prec,
+                   std::vector<morx_factor>& fresh, std::vector<morx_factor>& horizontal);
 TraceState* trace_state_if_on(morx_ctx ctx);
 void trace_collect_pending(TraceState* t);

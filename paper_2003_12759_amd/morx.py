@@ -102,6 +102,9 @@ _SIG = {
     "morx_solve_moments": (_i32, [_p, _i32, ctypes.POINTER(_d), _i32, _p, _i64, _p, _i64, _i32,
                                   _p, _i64, _p, _i64, ctypes.POINTER(morx_opts),
                                   ctypes.POINTER(morx_col_stats), _p]),
+    "morx_gmres_shifts": (_i32, [_p, _i32, ctypes.POINTER(_d), _i32, _p, _i64, _p, _i64, _i32,
+                                 _p, _i64, _p, _i64, ctypes.POINTER(morx_opts),
+                                 ctypes.POINTER(morx_col_stats), _p]),
     "morx_project": (_i32, [_p, _i32, _p, _i64, _p, _i64, _i32, _p, _i64, _i32, _p, _i64,
                             ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
                             ctypes.POINTER(_d), _i32, _p]),
@@ -343,6 +346,30 @@ def morx_solve_moments(sys: int, sigmas: Sequence[float], B: torch.Tensor,
                                  ctypes.byref(opts), stats, _stream(stream))
     if raise_on_error and st != MORX_OK:
         raise MorxError(st, "morx_solve_moments")
+    return st, list(stats)
+
+
+def morx_gmres_shifts(sys: int, sigmas: Sequence[float], B: torch.Tensor,
+                      C: Optional[torch.Tensor], restart: int, X: torch.Tensor,
+                      Y: Optional[torch.Tensor], opts: Optional[morx_opts] = None, stream=None,
+                      raise_on_error: bool = True):
+    """Returns (status, list of morx_col_stats)."""
+    if opts is None:
+        opts = morx_opts_default()
+    pb, ldb, m = _block(B, "B")
+    px, ldx, _ = _block(X, "X")
+    if C is not None:
+        pc, ldc, _ = _block(C, "C")
+        py, ldy, _ = _block(Y, "Y")
+    else:
+        pc, ldc, py, ldy = None, B.shape[0], None, B.shape[0]
+    ns = len(sigmas)
+    sig = (_d * ns)(*[float(s) for s in sigmas])
+    stats = (morx_col_stats * (ns * m))()
+    st = _lib.morx_gmres_shifts(sys, ns, sig, m, pb, ldb, pc, ldc, int(restart), px, ldx, py, ldy,
+                                ctypes.byref(opts), stats, _stream(stream))
+    if raise_on_error and st != MORX_OK:
+        raise MorxError(st, "morx_gmres_shifts")
     return st, list(stats)
 
 

@@ -528,3 +528,37 @@ def test_one_moment_equals_solve_shifts(ctx):
     assert torch.equal(X1, X2) and torch.equal(Y1, Y2)
     assert [c.iters for c in s1] == [c.iters for c in s2]
     S.close()
+
+
+@pytest.mark.parametrize("policy", ["reuse", "direct"])
+def test_gmres_matches_oracle(ctx, policy):
+    """GMRES(20) on the same chains: true residuals <= 1e-10 on both sides,
+    solutions against the oracle's GMRES, iteration counts close to it."""
+    from oracle import gmres as ogmres
+    from paper_2003_12759_amd import api
+
+    w = make_workload(1, N=10, nshift=4, nrounds=2)
+    S = api.System(ctx, w.A, w.e)
+    sched = {"reuse": ochain.schedule, "direct": ochain.schedule_direct}[policy]
+    specs, chains = sched(w.rounds)
+    fs = ojob.build_factors(w.A, w.e, specs, "f32")
+    E = sp.diags(w.e)
+    for z, sig in enumerate(w.rounds):
+        _say(f"gmres convdiff n={w.n} round {z} policy={policy}")
+        X, Y, st, stats = S.gmres_shifts(sig, w.B, w.C, restart=20, prec="f32", policy=policy,
+                                         next_round=z > 0)
+        Xg, Yg = X.cpu().numpy(), Y.cpu().numpy()
+        for i, s in enumerate(sig):
+            assert stats[i].status == 0
+            M = (s * E - w.A).tocsr()
+            ch = chains[z][i]
+            rp, rd = ogmres.solve_pair(lambda v: M @ v, lambda v: M.T @ v, w.B[:, 0], w.C[:, 0],
+                                       lambda v: ochain.apply(fs, ch, v),
+                                       lambda v: ochain.apply_transpose(fs, ch, v), tol=1e-10,
+                                       m=20)
+            assert _true_relres(w.A, w.e, s, Xg[:, i], w.B[:, 0]) <= 1.01e-10
+            assert _true_relres(w.A, w.e, s, Yg[:, i], w.C[:, 0], trans=True) <= 1.01e-10
+            assert np.linalg.norm(Xg[:, i] - rp.x) <= 1e-8 * np.linalg.norm(rp.x)
+            assert np.linalg.norm(Yg[:, i] - rd.x) <= 1e-8 * np.linalg.norm(rd.x)
+            assert abs(stats[i].iters - (rp.iters + rd.iters)) <= max(3, 0.05 * (rp.iters + rd.iters))
+    S.close()
