@@ -255,8 +255,10 @@ morx_status morx_project(morx_system sys, int32_t r, const double* V, int64_t ld
  *                    cols_per_wave).
  * morx_system_set_tune checks the values (MORX_E_INVALID) and they apply from
  * the next call on the system.  morx_autotune times the candidates on the
- * system itself: one SPAI factor build at `sigma` (storage prec) per factor
- * kernel, then a few BiCG iterations of ncols column pairs per iteration
+ * system itself: per factor kernel one launch of min(chain_len, 16) SPAI
+ * problems at `sigma` (storage prec; fewer on large systems, about 8M column
+ * problems per candidate), then a few BiCG iterations of ncols column pairs
+ * per iteration
  * shape (HIP events), column c preconditioned by 1 + c * chain_len / ncols
  * distinct factors of one list, as the chains of one round are
  * (chain_len 1..64: the longest chain of the solves to come); chain tile and

@@ -1748,21 +1748,25 @@ static morx_status time_events(hipEvent_t a, hipEvent_t b, hipStream_t st, doubl
 static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int chain_len,
                                  int prec, morx_tune* out, hipStream_t st, hipEvent_t e0,
                                  hipEvent_t e1, std::vector<morx_factor>& keep) {
-  // 1. least-squares kernel: one SPAI build per candidate
+  // 1. least-squares kernel: per candidate one build of as many shifts as a
+  // round has (each shift is a job of the same launch, as in a solve; the
+  // jobs here are identical SPAI problems writing the same storage)
   double best_f = 1e300;
   int best_rows = -1;
-  FactorJob job{sigma, 0.0, 1, nullptr, nullptr};
   morx_factor f = nullptr;
   MORX_TRY(factor_alloc(sys, prec, &f));
   keep.push_back(f);
-  job.vals = f->vals.p;
-  job.valsT = f->valsT.p;
+  // (capped near 8M column problems per candidate, so tuning a large system
+  // stays short)
+  const int64_t cap_jobs = std::max<int64_t>(2, ((int64_t)8 << 20) / std::max<int64_t>(sys->n, 1));
+  const int njobs = (int)std::max<int64_t>(1, std::min<int64_t>({chain_len, 16, cap_jobs}));
+  std::vector<FactorJob> fjobs(njobs, FactorJob{sigma, 0.0, 1, f->vals.p, f->valsT.p});
   const int saved_rows = sys->tune_factor_rows;
   for (int rows : {0, 1, 8, 16}) {
     if (!factor_kernel_supported(sys, rows)) continue;
     sys->tune_factor_rows = rows;
     MORX_HIP(hipEventRecord(e0, st));
-    morx_status s = factor_build_many(sys, prec, &job, 1, st);
+    morx_status s = factor_build_many(sys, prec, fjobs.data(), njobs, st);
     MORX_HIP(hipEventRecord(e1, st));
     double ms = 0.0;
     MORX_TRY(time_events(e0, e1, st, &ms));
