@@ -44,6 +44,27 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
+def chain_kernel_name(A, vt: str, at: str, ncol: int, ncmax: int) -> str:
+    """Instance of the chain step the library launches for this batch: the
+    narrow variant when every row of S = pattern(A) + diagonal and of S^T
+    has at most 8 entries, at the tile width of the library's column split
+    (equal chunks of at most ncmax columns, rounded up to an instantiated
+    width)."""
+    import numpy as np
+    import scipy.sparse as sp
+
+    P = sp.csr_matrix(A, copy=True)
+    P.data[:] = 1.0
+    P = (P + sp.identity(P.shape[0], format="csr")).tocsr()
+    width = max(int(np.diff(P.indptr).max()), int(np.diff(P.tocsc().indptr).max()))
+    ncmax = ncmax if ncmax > 0 else 8
+    chunks = -(-ncol // ncmax)
+    nc = -(-ncol // chunks)
+    nc = nc if nc <= 8 else (10 if nc <= 10 else (12 if nc <= 12 else 16))
+    kind = "k_chain_narrow" if width <= 8 else "k_chain_step"
+    return f"{kind}<{vt}, {at}, {nc}>"
+
+
 def default_apply(prec: str) -> str:
     """Apply precision used unless --apply says otherwise: FP64 vectors for
     every storage precision (FP32 and BF16 factor values are widened as they
@@ -396,8 +417,7 @@ def main():
         ncol = len(w.rounds[0]) * w.B.shape[1]
         ctype = {"f64": "double", "f32": "float", "bf16": "unsigned short"}
         ncmax = S.get_tune()["cols_per_wave"]
-        chunks = -(-ncol // (ncmax if ncmax > 0 else 8))
-        roof_kernel = f"k_chain_step<{ctype[w.prec]}, {ctype[apply]}, {-(-ncol // chunks)}>"
+        roof_kernel = chain_kernel_name(w.A, ctype[w.prec], ctype[apply], ncol, ncmax)
         traffic = None
         if os.path.exists(TRAFFIC_FILE):
             with open(TRAFFIC_FILE) as f:

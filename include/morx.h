@@ -338,7 +338,8 @@ morx_status morx_serve_stop(morx_server srv);
  * vector it reads or writes once) are added up on the device.  Enabling
  * resets the totals.  Classes: "chain_step" (one factor of every
  * preconditioner chain, forward and transposed), "spmv_pair" (shifted
- * operator and its transpose), "update" (iterate and residual update),
+ * operator and its transpose), "form_p" (search directions p = z + beta p
+ * of both recurrences), "update" (iterate and residual update),
  * "factor_ls" (least-squares factor construction; no byte count).
  */
 typedef struct {

@@ -13,7 +13,8 @@
 //   L_max chain launches (forward and transposed halves side by side; the
 //   last one also forms the partial sums of rho = z~^T r),
 //   fin_rho   (one block: convergence test on the previous update, rho, beta),
-//   spmv_pair (p, p~ formed on the fly, q = A_s p, q~ = A_s^T p~, delta sums),
+//   form_p    (p = z + beta p, p~ = z~ + beta p~),
+//   spmv_pair (q = A_s p, q~ = A_s^T p~, delta sums),
 //   fin_delta (one block: alpha),
 //   update    (x, x~, r, r~ and the partial sums of their norms).
 // Scalars stay on the device; every reduction is block partials summed in a
@@ -25,6 +26,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include <hip/hip_ext.h>
@@ -40,7 +42,9 @@ enum ApplyVec : int { A_Z, A_ZT, A_T0, A_T1, A_TT0, A_TT1, A_R, A_RT };
 static int apply_vecs(int aprec) { return aprec == MORX_F64 ? 6 : 8; }
 
 // trace counters (algorithmic bytes per kernel class)
-enum TraceClass : int { TR_CHAIN = 0, TR_SPMV = 1, TR_UPDATE = 2, TR_FACTOR = 3, kTraceClasses = 8 };
+enum TraceClass : int {
+  TR_CHAIN = 0, TR_SPMV = 1, TR_UPDATE = 2, TR_FACTOR = 3, TR_FORMP = 4, kTraceClasses = 8
+};
 
 namespace {
 
@@ -58,11 +62,29 @@ constexpr double kBreakdown = 1e-14;
 // matrix or factor are shared by all NC columns.  Block indices are remapped
 // so that consecutive row ranges run on one XCD (workgroups are dealt to the
 // 8 XCDs round robin), keeping a range's stencil neighbours in that XCD's L2.
+// one (half, column) pair of a chain step: the factor it applies and the
+// vectors it reads and writes
+struct ChainItem {
+  const void* fv;   // factor values, forward or transposed order
+  const void* src;  // input (apply precision)
+  void* dst;        // output (apply precision)
+  int32_t c;        // column slot; -1: padding or past the list
+  // bit 0: transposed chain on the rows of S^T; on the first pair of a chunk
+  // also bit 1: every pair of the chunk applies the same factor, and bits
+  // 8 and up: pairs in the chunk
+  int32_t flags;
+};
+
 struct IterArgs {
   int64_t n, ld, nnzS, nslices;
+  int64_t nsell, nsellT;  // entries of the sliced-ELL arrays of S and S^T
   int cap, nc, nblk, spw, vbytes, maxL, lcap;
   int ncmax;       // most columns per wave, chain step
   int ncmax_spmv;  // most columns per wave, shifted pair and true residual
+  int ncv;         // chain tile width of this launch sequence
+  int ymax;        // chain launches: chunks of ncv (half, column) pairs in the grid
+  int plan_ld;     // work-list entries per step
+  int narrow;      // every slice of S and S^T at most kNarrow slots wide
   const int32_t *off, *col, *offT, *colT;
   const double *valA, *valAT, *e;
   double* vec;
@@ -74,6 +96,8 @@ struct IterArgs {
   double* part_delta;  // [3][cap][nblk]
   double* part_norm;   // [2][cap][nblk]
   double* trace;       // [kTraceClasses] or null
+  ChainItem* plan;     // [lcap][plan_ld] work lists of the chain steps
+  int32_t* plan_cnt;   // [lcap] chunks per step
 };
 
 __device__ __forceinline__ double* vptr(const IterArgs& a, int slot, int c) {
@@ -115,8 +139,8 @@ __device__ __forceinline__ WaveCtx wave_ctx(const IterArgs& a) {
 // Sum NQ per-lane values of each of the NC columns over the block and store
 // one partial per (quantity, column, block).  Every thread calls it.
 template <int NC, int NQ>
-__device__ void block_partials(const IterArgs& a, const WaveCtx& t, int c0, unsigned valid,
-                               double (&v)[NC][NQ], double* part) {
+__device__ void block_partials_cols(const IterArgs& a, const WaveCtx& t, const int (&cols)[NC],
+                                    unsigned valid, double (&v)[NC][NQ], double* part) {
   __shared__ double sh[kWavesPerBlock][NC][NQ];
 #pragma unroll
   for (int j = 0; j < NC; ++j)
@@ -132,9 +156,19 @@ __device__ void block_partials(const IterArgs& a, const WaveCtx& t, int c0, unsi
       double tot = 0.0;
 #pragma unroll
       for (int w = 0; w < kWavesPerBlock; ++w) tot += sh[w][j][q];
-      part[((int64_t)q * a.cap + c0 + j) * a.nblk + t.blk] = tot;
+      part[((int64_t)q * a.cap + cols[j]) * a.nblk + t.blk] = tot;
     }
   }
+}
+
+// the same for the columns c0 ... c0 + NC - 1
+template <int NC, int NQ>
+__device__ void block_partials(const IterArgs& a, const WaveCtx& t, int c0, unsigned valid,
+                               double (&v)[NC][NQ], double* part) {
+  int cols[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) cols[j] = c0 + j;
+  block_partials_cols<NC, NQ>(a, t, cols, valid, v, part);
 }
 
 // One wave sums the nblk partials of NQ quantities of column c, every load of
@@ -275,20 +309,21 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_init(IterArgs a) {
   }
 }
 
-// one chain step: the forward half (blockIdx.z == 0) applies factor s of
-// each column's chain on the rows of S, the transposed half applies factor
-// maxL-1-s transposed on the rows of S^T; the last step also forms the
-// partial sums of rho = z~^T r, ||z~||^2, ||r||^2.  Columns whose chains
-// share a factor share its value loads.
+// One chain step s applies, for every column whose chain is long enough,
+// factor s of the forward chain on the rows of S and factor maxL-1-s of the
+// transposed chain on the rows of S^T; the last step also forms the partial
+// sums of rho = z~^T r, ||z~||^2, ||r||^2.  The (half, column) pairs that
+// have work at a step come from the step's work list, built on the device by
+// the one-block kernels before the iteration (build_plan): blockIdx.y picks a
+// chunk of NC pairs of one half, so no block is launched for a column whose
+// chain is shorter than the step, and columns of a chunk that apply the same
+// factor share its value loads.
 // AT is the apply precision: each pass sums in FP64 and stores its result
 // rounded to AT; with AT = float the first pass reads the FP32 copy of r.
-template <typename AT>
-__device__ __forceinline__ const AT* chain_input(const IterArgs& a, int c, bool bwd) {
-  if constexpr (sizeof(AT) == 8)
-    return (const AT*)vptr(a, bwd ? V_RT : V_R, c);
-  else
-    return aptr<AT>(a, bwd ? A_RT : A_R, c);
-}
+
+// Offsets of slots past a slice's width point past every array, so their
+// loads return 0 without a memory access and add 0 to the row sums.
+constexpr uint32_t kOutside = 0xfffffff0u;
 
 // Slots per chunk of the product loops: every index, value and gather load of
 // a chunk is issued before its first use; wide tiles take shorter chunks to
@@ -304,130 +339,387 @@ struct ChunkLen {
 template <typename VT, typename AT, int NC, bool RHO>
 __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s) {
   constexpr int kU = ChunkLen<NC>::value;
+  constexpr uint32_t kVB = sizeof(VT), kAB = sizeof(AT);
   const WaveCtx t = wave_ctx(a);
-  const int c0 = blockIdx.y * NC;
-  const bool bwd = blockIdx.z == 1;
-  const int jf = bwd ? a.maxL - 1 - s : s;  // chain position applied by this half
-  const bool rho_half = RHO && bwd;
-  unsigned valid = 0;
-  const AT* src[NC];
-  AT* dst[NC];
-  const VT* fv[NC];
+  const ChainItem* plan = a.plan + (int64_t)s * a.plan_ld;
+  const int nchunks = gld(a.plan_cnt + s);
+  const int nsl = (int)max<int64_t>(t.s_end - t.s_begin, 0);
+  // slice starts of the wave's slices, lane l holding slice s_begin + wb + l
+  // for both orders (a window of 64, refilled as the wave moves past it)
+  const int wl = min(t.lane, nsl);
+  const int32_t owF = nsl > 0 ? gld(a.off + t.s_begin + wl) : 0;
+  const int32_t owB = nsl > 0 ? gld(a.offT + t.s_begin + wl) : 0;
+  for (int y = blockIdx.y;; y += gridDim.y) {
+    ChainItem it[NC];
 #pragma unroll
-  for (int j = 0; j < NC; ++j) {
-    const int c = min(c0 + j, a.nc - 1);
-    const ColInfo& ci = a.cols[c];
-    const int L = ci.L;
-    const bool on = c0 + j < a.nc && ci.state == COL_ACTIVE && L > jf;
-    if (on) valid |= 1u << j;
-    fv[j] = on ? (const VT*)a.ftab[((int64_t)(bwd ? a.cap : 0) + c) * a.lcap + jf] : nullptr;
-    if (!bwd) {
-      src[j] = (jf == 0) ? chain_input<AT>(a, c, false) : aptr<AT>(a, A_T0 + ((jf - 1) & 1), c);
-      dst[j] = (jf == L - 1) ? aptr<AT>(a, A_Z, c) : aptr<AT>(a, A_T0 + (jf & 1), c);
-    } else {
-      const int k = max(L - 1 - jf, 0);  // transposed factors this column applied before
-      src[j] = (k == 0) ? chain_input<AT>(a, c, true) : aptr<AT>(a, A_TT0 + ((k - 1) & 1), c);
-      dst[j] = (jf == 0) ? aptr<AT>(a, A_ZT, c) : aptr<AT>(a, A_TT0 + (k & 1), c);
+    for (int j = 0; j < NC; ++j) it[j] = plan[y * NC + j];
+    if (it[0].c < 0) break;  // past the last chunk (uniform over the block)
+    const bool bwd = (it[0].flags & 1) != 0;
+    const bool rho_half = RHO && bwd;
+    const int64_t nsell = bwd ? a.nsellT : a.nsell;
+    unsigned valid = 0;
+    BufRes rsrc[NC], rfv[NC];
+    AT* dst[NC];
+    bool shared = true;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const bool on = it[j].c >= 0;  // padding at the end of a half's list
+      if (on) valid |= 1u << j;
+      // padding runs along with the chunk's first pair (cache hits, results
+      // dropped), so the slot loop has no per-column branch
+      rsrc[j] = buf_res(on ? it[j].src : it[0].src, a.ld * (int64_t)kAB);
+      rfv[j] = buf_res(on ? it[j].fv : it[0].fv, nsell * (int64_t)kVB);
+      dst[j] = (AT*)it[j].dst;
+      shared = shared && (!on || it[j].fv == it[0].fv);
     }
-  }
-  // valid is the same for the whole block (one column chunk per block)
-  if (!valid) return;
-  // Inactive columns of the chunk run along with the first active one's
-  // source and factor (cache hits, results dropped), so the chunk loop has no
-  // per-column branch and every load of a chunk is in flight at once.
-  const AT* src0 = nullptr;
-  const VT* fv0 = nullptr;
+    const BufRes rcol = buf_res(bwd ? a.colT : a.col, nsell * 4);
+    const int32_t* off = bwd ? a.offT : a.off;
+    int32_t ow = bwd ? owB : owF;
+    int wb = 0;
+    double v[RHO ? NC : 1][3];
 #pragma unroll
-  for (int j = NC - 1; j >= 0; --j)
-    if (valid & (1u << j)) {
-      src0 = src[j];
-      fv0 = fv[j];
-    }
-  bool shared = true;  // every column applies the same factor (batched solves)
+    for (int j = 0; j < (RHO ? NC : 1); ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
+    if (nsl > 0) {
+      // first entry and width of relative slice k (wave-uniform); refills the
+      // window so that k and k+1 are in it
+      auto bounds = [&](int k, int32_t& base, int32_t& w) {
+        if (k + 1 - wb > 63) {
+          wb = k;
+          ow = gld(off + t.s_begin + wb + min(t.lane, nsl - wb));
+        }
+        base = __builtin_amdgcn_readfirstlane(__shfl(ow, k - wb, 64));
+        w = (__builtin_amdgcn_readfirstlane(__shfl(ow, k + 1 - wb, 64)) - base) >> 6;
+      };
+      // (slice, chunk) cursor over the wave's slices; the column indices of
+      // the next chunk, possibly in the next slice, are loaded while the
+      // current chunk's values and gathers are in flight.
+      int k = 0, m0 = 0;
+      int32_t base, w;
+      bounds(0, base, w);
+      int32_t nix[kU];
+      {
+        const uint32_t o = (uint32_t)(base + t.lane) * 4u;
 #pragma unroll
-  for (int j = 0; j < NC; ++j) {
-    if (!(valid & (1u << j))) {
-      src[j] = src0;
-      fv[j] = fv0;
-    }
-    shared = shared && fv[j] == fv0;
-  }
-  double v[RHO ? NC : 1][3];
-#pragma unroll
-  for (int j = 0; j < (RHO ? NC : 1); ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
-  const int32_t* off = bwd ? a.offT : a.off;
-  const int32_t* col = bwd ? a.colT : a.col;
-  for (int64_t sl = t.s_begin; sl < t.s_end; ++sl) {
-    const int32_t base = gld(off + sl);
-    const int32_t w = (gld(off + sl + 1) - base) >> 6;
-    const int32_t p0 = base + t.lane;
-    const int64_t i = sl * kSlice + t.lane;
-    double acc[NC];
-#pragma unroll
-    for (int j = 0; j < NC; ++j) acc[j] = 0.0;
-    // column indices of the next chunk are loaded while the current chunk's
-    // values and gathers are in flight
-    int32_t nix[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) nix[u] = gld(col + p0 + (u < w ? u * kSlice : 0));
-    for (int32_t m0 = 0; m0 < w; m0 += kU) {
-      int32_t pp[kU], cix[kU];
-      bool ok[kU];
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        ok[u] = m0 + u < w;
-        pp[u] = p0 + (ok[u] ? (m0 + u) * kSlice : 0);  // past the row: slot 0, value dropped
-        cix[u] = nix[u];
+        for (int u = 0; u < kU; ++u) nix[u] = buf_i32(rcol, u < w ? o + u * kSlice * 4 : kOutside);
       }
-      if (m0 + kU < w) {
+      double acc[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) acc[j] = 0.0;
+      while (true) {
+        const uint32_t pv = (uint32_t)(base + t.lane + m0 * kSlice) * kVB;
+        uint32_t fo[kU], go[kU];  // value and gather offsets of the chunk's slots
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-          const int32_t mn = m0 + kU + u;
-          nix[u] = gld(col + p0 + (mn < w ? mn * kSlice : 0));
+          const bool ok = m0 + u < w;
+          fo[u] = ok ? pv + u * kSlice * kVB : kOutside;
+          go[u] = ok ? (uint32_t)nix[u] * kAB : kOutside;
         }
-      }
-      if (shared) {
-        double vv[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const double raw = gload_val<VT>(fv0 + pp[u]);
-          vv[u] = ok[u] ? raw : 0.0;
+        int k2 = k, m2 = m0 + kU;
+        int32_t base2 = base, w2 = w;
+        if (m2 >= w) {
+          k2 = k + 1;
+          m2 = 0;
+          if (k2 < nsl) bounds(k2, base2, w2);
         }
+        if (k2 < nsl) {
+          const uint32_t o = (uint32_t)(base2 + t.lane + m2 * kSlice) * 4u;
 #pragma unroll
-        for (int j = 0; j < NC; ++j)
+          for (int u = 0; u < kU; ++u)
+            nix[u] = buf_i32(rcol, m2 + u < w2 ? o + u * kSlice * 4 : kOutside);
+        }
+        if (shared) {
+          double vv[kU];
 #pragma unroll
-          for (int u = 0; u < kU; ++u) acc[j] = fma(vv[u], (double)gld(src[j] + cix[u]), acc[j]);
-      } else {
+          for (int u = 0; u < kU; ++u) vv[u] = buf_val<VT>(rfv[0], fo[u]);
 #pragma unroll
-        for (int j = 0; j < NC; ++j)
+          for (int j = 0; j < NC; ++j)
 #pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            const double raw = gload_val<VT>(fv[j] + pp[u]);
-            acc[j] = fma(ok[u] ? raw : 0.0, (double)gld(src[j] + cix[u]), acc[j]);
+            for (int u = 0; u < kU; ++u) acc[j] = fma(vv[u], buf_val<AT>(rsrc[j], go[u]), acc[j]);
+        } else {
+          // pairs visited last to first: no load here is the same as the
+          // first load of the shared branch, which the compiler would hoist
+          // above the branch and wait for there
+#pragma unroll
+          for (int j = NC - 1; j >= 0; --j)
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+              acc[j] = fma(buf_val<VT>(rfv[j], fo[u]), buf_val<AT>(rsrc[j], go[u]), acc[j]);
+        }
+        if (m2 == 0) {  // slice k done
+          const int64_t i = (t.s_begin + k) * kSlice + t.lane;
+          if (i < a.n) {
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+              if (valid & (1u << j)) {
+                const AT zs = (AT)acc[j];
+                gst(dst[j] + i, zs);
+                if constexpr (RHO) {
+                  if (rho_half) {
+                    const double zi = (double)zs;
+                    const double ri = gld(vptr(a, V_R, it[j].c) + i);
+                    v[j][0] = fma(zi, ri, v[j][0]);
+                    v[j][1] = fma(zi, zi, v[j][1]);
+                    v[j][2] = fma(ri, ri, v[j][2]);
+                  }
+                }
+              }
           }
+#pragma unroll
+          for (int j = 0; j < NC; ++j) acc[j] = 0.0;
+          if (k2 >= nsl) break;
+        }
+        k = k2;
+        m0 = m2;
+        base = base2;
+        w = w2;
       }
     }
-    if (i < a.n) {
+    if constexpr (RHO)
+      if (rho_half) {
+        int cols[NC];
 #pragma unroll
-      for (int j = 0; j < NC; ++j)
-        if (valid & (1u << j)) {
-          const AT zs = (AT)acc[j];
-          gst(dst[j] + i, zs);
-          if constexpr (RHO) {
-            if (rho_half) {
-              const double zi = (double)zs;
-              const double ri = gld(vptr(a, V_R, c0 + j) + i);
-              v[j][0] = fma(zi, ri, v[j][0]);
-              v[j][1] = fma(zi, zi, v[j][1]);
-              v[j][2] = fma(ri, ri, v[j][2]);
-            }
-          }
-        }
-    }
+        for (int j = 0; j < NC; ++j) cols[j] = it[j].c;
+        block_partials_cols<NC, 3>(a, t, cols, valid, v, a.part_rho);
+        __syncthreads();  // the shared partials are reused by the next chunk
+      }
+    if (y + (int)gridDim.y >= nchunks) break;
   }
-  if constexpr (RHO)
-    if (rho_half) block_partials<NC, 3>(a, t, c0, valid, v, a.part_rho);
 }
+
+// The chain step for patterns whose slices are at most kNarrow slots wide
+// (stencils with up to eight entries per row).  Per slice the column indices
+// (and a chunk's shared factor values) stay in registers while the chunk's
+// pairs run one after the other, two gather buffers alternating so that
+// pair j+1's gathers are in flight during pair j's sums.  Registers do not
+// grow with the tile width, and a wide tile reads the slice's indices and
+// values once for all its pairs.  Slots past a slice's width are not loaded;
+// each row sums its slots in order from zero, as the general kernel does.
+// The rho partials (last step) are summed per slice over the wave and
+// collected per pair in LDS.
+constexpr int kNarrow = 8;
+
+template <typename VT>
+using NarrowVal = typename std::conditional<sizeof(VT) == 8, double, float>::type;
+
+template <typename VT>
+__device__ __forceinline__ NarrowVal<VT> buf_raw(BufRes r, uint32_t off);
+template <>
+__device__ __forceinline__ double buf_raw<double>(BufRes r, uint32_t off) {
+  return buf_val<double>(r, off);
+}
+template <>
+__device__ __forceinline__ float buf_raw<float>(BufRes r, uint32_t off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float buf_raw<uint16_t>(BufRes r, uint32_t off) {
+  return __uint_as_float(((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0)) << 16);
+}
+
+template <typename VT, typename AT, int NC, bool RHO, bool SHARED>
+__device__ __forceinline__ void narrow_slice(const IterArgs& a, const WaveCtx& t,
+                                             const ChainItem* ck, int ncol, BufRes rcol,
+                                             int32_t base, int w, int64_t i, int64_t fbytes,
+                                             int64_t vbytes, bool rho_half,
+                                             double (*rho_row)[3]) {
+  using FT = NarrowVal<VT>;
+  constexpr uint32_t kVB = sizeof(VT), kAB = sizeof(AT);
+  const uint32_t oi = (uint32_t)(base + t.lane) * 4u;
+  const uint32_t ov = (uint32_t)(base + t.lane) * kVB;
+  uint32_t go[kNarrow], fo[kNarrow];  // byte offsets of the gathers and of the values
+#pragma unroll
+  for (int u = 0; u < kNarrow; ++u) {
+    const bool in = u < w;
+    go[u] = (uint32_t)buf_i32(rcol, in ? oi + u * kSlice * 4 : kOutside);
+    fo[u] = in ? ov + u * kSlice * kVB : kOutside;
+  }
+#pragma unroll
+  for (int u = 0; u < kNarrow; ++u) go[u] = u < w ? go[u] * kAB : kOutside;
+  FT fb[SHARED ? 1 : 2][kNarrow];
+  AT gb[2][kNarrow];
+  auto issue = [&](int j, int q) {
+    const ChainItem* e = ck + j;
+    if (!SHARED || j == 0) {
+      const BufRes rf = buf_res(e->fv, fbytes);
+#pragma unroll
+      for (int u = 0; u < kNarrow; ++u) fb[SHARED ? 0 : q][u] = buf_raw<VT>(rf, fo[u]);
+    }
+    const BufRes rs = buf_res(e->src, vbytes);
+#pragma unroll
+    for (int u = 0; u < kNarrow; ++u) gb[q][u] = (AT)buf_val<AT>(rs, go[u]);
+  };
+  auto finish = [&](int j, int q) {
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < kNarrow; ++u)
+      acc = fma((double)fb[SHARED ? 0 : q][u], (double)gb[q][u], acc);
+    const ChainItem* e = ck + j;
+    const AT zs = (AT)acc;
+    if (i < a.n) gst((AT*)e->dst + i, zs);
+    if constexpr (RHO) {
+      if (rho_half) {
+        const double zi = i < a.n ? (double)zs : 0.0;
+        const double ri = i < a.n ? gld(vptr(a, V_R, e->c) + i) : 0.0;
+        const double s0 = wave_sum(zi * ri), s1 = wave_sum(zi * zi), s2 = wave_sum(ri * ri);
+        if (t.lane == 0) {
+          rho_row[j][0] += s0;
+          rho_row[j][1] += s1;
+          rho_row[j][2] += s2;
+        }
+      }
+    }
+  };
+  // pair j+1's loads are issued before pair j's sums (two buffers alternate)
+  issue(0, 0);
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    if (j >= ncol) break;
+    if (j + 1 < ncol) issue(j + 1, (j + 1) & 1);
+    finish(j, j & 1);
+  }
+}
+
+template <typename VT, typename AT, int NC, bool RHO>
+__global__ __launch_bounds__(kBlock) void k_chain_narrow(IterArgs a, int s) {
+  __shared__ double rho_sh[RHO ? kWavesPerBlock : 1][RHO ? NC : 1][3];
+  const WaveCtx t = wave_ctx(a);
+  const ChainItem* plan = a.plan + (int64_t)s * a.plan_ld;
+  const int nchunks = gld(a.plan_cnt + s);
+  const int nsl = (int)max<int64_t>(t.s_end - t.s_begin, 0);
+  const int wl = min(t.lane, nsl);
+  const int32_t owF = nsl > 0 ? gld(a.off + t.s_begin + wl) : 0;
+  const int32_t owB = nsl > 0 ? gld(a.offT + t.s_begin + wl) : 0;
+  for (int y = blockIdx.y;; y += gridDim.y) {
+    const ChainItem* ck = plan + (int64_t)y * NC;
+    const int c0 = ck->c;
+    if (c0 < 0) break;  // past the last chunk (uniform over the block)
+    const int flags = ck->flags;
+    const bool bwd = (flags & 1) != 0;
+    const bool shared = (flags & 2) != 0;  // every pair of the chunk applies one factor
+    const int ncol = flags >> 8;           // pairs of the chunk
+    const bool rho_half = RHO && bwd;
+    double(*rho_row)[3] = RHO ? rho_sh[t.wave] : nullptr;
+    if (rho_half)
+      for (int q = t.lane; q < ncol * 3; q += 64) rho_row[q / 3][q % 3] = 0.0;
+    const int64_t nsell = bwd ? a.nsellT : a.nsell;
+    const int64_t fbytes = nsell * (int64_t)sizeof(VT), vbytes = a.ld * (int64_t)sizeof(AT);
+    const BufRes rcol = buf_res(bwd ? a.colT : a.col, nsell * 4);
+    const int32_t* off = bwd ? a.offT : a.off;
+    int32_t ow = bwd ? owB : owF;
+    int wb = 0;
+    for (int k = 0; k < nsl; ++k) {
+      if (k + 1 - wb > 63) {  // keep slices k and k+1 in the window
+        wb = k;
+        ow = gld(off + t.s_begin + wb + min(t.lane, nsl - wb));
+      }
+      const int32_t base = __builtin_amdgcn_readfirstlane(__shfl(ow, k - wb, 64));
+      const int w = (__builtin_amdgcn_readfirstlane(__shfl(ow, k + 1 - wb, 64)) - base) >> 6;
+      const int64_t i = (t.s_begin + k) * kSlice + t.lane;
+      if (shared)
+        narrow_slice<VT, AT, NC, RHO, true>(a, t, ck, ncol, rcol, base, w, i, fbytes, vbytes,
+                                            rho_half, rho_row);
+      else
+        narrow_slice<VT, AT, NC, RHO, false>(a, t, ck, ncol, rcol, base, w, i, fbytes, vbytes,
+                                             rho_half, rho_row);
+    }
+    if constexpr (RHO)
+      if (rho_half) {
+        __syncthreads();
+        if (threadIdx.x < ncol * 3) {
+          const int j = threadIdx.x / 3, q = threadIdx.x % 3;
+          double tot = 0.0;
+#pragma unroll
+          for (int wv = 0; wv < kWavesPerBlock; ++wv) tot += rho_sh[wv][j][q];
+          a.part_rho[((int64_t)q * a.cap + ck[j].c) * a.nblk + t.blk] = tot;
+        }
+        __syncthreads();  // rho_sh is cleared again by the next chunk
+      }
+    if (y + (int)gridDim.y >= nchunks) break;
+  }
+}
+
+// vector `slot` of column c in the apply precision
+__device__ __forceinline__ void* apply_ptr(const IterArgs& a, int slot, int c) {
+  return (char*)a.avec + ((int64_t)slot * a.cap + c) * a.ld * a.abytes;
+}
+
+// what the first factor pass of a chain reads: r (r~), or its FP32 copy
+__device__ __forceinline__ const void* chain_in(const IterArgs& a, int c, bool bwd) {
+  if (a.abytes == 8) return vptr(a, bwd ? V_RT : V_R, c);
+  return apply_ptr(a, bwd ? A_RT : A_R, c);
+}
+
+// Work lists of the next iteration's chain steps.  Step s lists the forward
+// pairs (active columns with L > s: factor s of the chain) and then the
+// transposed pairs (L > maxL-1-s: factor maxL-1-s transposed), each half
+// padded with c = -1 to a multiple of the tile width ncv, then c = -1 up to
+// the grid's ymax chunks; plan_cnt[s] is the number of chunks.  One wave per
+// step, columns 64 at a time in slot order.  Called by every thread of a
+// one-block kernel after that kernel's last change of a column state.
+__device__ void build_plan(const IterArgs& a) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const int fill = min(a.plan_ld, a.ymax * a.ncv);
+  for (int s = threadIdx.x >> 6; s < a.maxL; s += kFinThreads / 64) {
+    ChainItem* out = a.plan + (int64_t)s * a.plan_ld;
+    int pos = 0;
+    for (int h = 0; h < 2; ++h) {
+      const int jf = h ? a.maxL - 1 - s : s;
+      for (int c0 = 0; c0 < a.nc; c0 += 64) {
+        const int c = c0 + lane;
+        int L = 0;
+        bool on = false;
+        if (c < a.nc) {
+          const ColInfo& ci = a.cols[c];
+          L = ci.L;
+          on = ci.state == COL_ACTIVE && L > jf;
+        }
+        const unsigned long long m = __ballot(on);
+        if (on) {
+          ChainItem e;
+          e.c = c;
+          e.flags = h;
+          e.fv = a.ftab[((int64_t)(h ? a.cap : 0) + c) * a.lcap + jf];
+          if (!h) {
+            e.src = jf == 0 ? chain_in(a, c, false) : apply_ptr(a, A_T0 + ((jf - 1) & 1), c);
+            e.dst = jf == L - 1 ? apply_ptr(a, A_Z, c) : apply_ptr(a, A_T0 + (jf & 1), c);
+          } else {
+            const int k = L - 1 - jf;  // transposed factors this column applied before
+            e.src = k == 0 ? chain_in(a, c, true) : apply_ptr(a, A_TT0 + ((k - 1) & 1), c);
+            e.dst = jf == 0 ? apply_ptr(a, A_ZT, c) : apply_ptr(a, A_TT0 + (k & 1), c);
+          }
+          out[pos + __popcll(m & below)] = e;
+        }
+        pos += __popcll(m);
+      }
+      const int pad = (a.ncv - pos % a.ncv) % a.ncv;
+      if (lane < pad) out[pos + lane] = ChainItem{nullptr, nullptr, nullptr, -1, h};
+      pos += pad;
+    }
+    for (int q = pos + lane; q < fill; q += 64) out[q] = ChainItem{nullptr, nullptr, nullptr, -1, 0};
+    if (lane == 0) a.plan_cnt[s] = pos / a.ncv;
+  }
+  __syncthreads();
+  // chunk summaries on each chunk's first pair (the same wave per step)
+  for (int s = threadIdx.x >> 6; s < a.maxL; s += kFinThreads / 64) {
+    ChainItem* out = a.plan + (int64_t)s * a.plan_ld;
+    const int nch = a.plan_cnt[s];
+    for (int q = lane; q < nch; q += 64) {
+      ChainItem* ck = out + (int64_t)q * a.ncv;
+      const void* f0 = ck[0].fv;
+      int ncol = 0;
+      bool same = true;
+      for (int j = 0; j < a.ncv; ++j)
+        if (ck[j].c >= 0) {
+          ++ncol;
+          same = same && ck[j].fv == f0;
+        }
+      ck[0].flags = (ck[0].flags & 1) | (same ? 2 : 0) | (ncol << 8);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_plan(IterArgs a) { build_plan(a); }
 
 // convergence test on the residuals of the previous update (or of the start
 // of the cycle), the iteration limit, then rho and beta
@@ -482,36 +774,57 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(IterArgs a) {
       // per column: z, z~ read; p, p~ read (not on a cycle's first step) and
       // written; q, q~ written
       const double amat = 2.0 * (12.0 * nnz + 4.0 * (n + 1.0)) + 8.0 * n;
-      a.trace[TR_SPMV] += amat + (2.0 * ab + 48.0) * n * vec_cols - 16.0 * n * first_cols;
+      a.trace[TR_SPMV] += amat + 32.0 * n * vec_cols;
+      // form_p: z, z~ read; p, p~ of the last step read (not on a cycle's
+      // first step); p, p~ written
+      a.trace[TR_FORMP] += (2.0 * ab + 32.0) * n * vec_cols - 16.0 * n * first_cols;
     }
   }
 }
 
-// p = z + beta p, p~ = z~ + beta p~ (formed on the fly at every gathered
-// index), q = (sigma E - A) p, q~ = (sigma E - A)^T p~, partial sums of
+// p = z + beta p_old, p~ = z~ + beta p~_old (p = z on a cycle's first
+// step), formed once per row so that the shifted products gather p itself
+template <typename AT>
+__global__ __launch_bounds__(kBlock) void k_form_p(IterArgs a, int par) {
+  const WaveCtx t = wave_ctx(a);
+  const int c = blockIdx.y;
+  const ColInfo& ci = a.cols[c];
+  if (ci.state != COL_ACTIVE) return;
+  const double beta = ci.beta;
+  const bool first = ci.first != 0;
+  const AT* z = aptr<AT>(a, A_Z, c);
+  const AT* zt = aptr<AT>(a, A_ZT, c);
+  const double* po = vptr(a, V_P0 + (par ^ 1), c);
+  const double* pto = vptr(a, V_PT0 + (par ^ 1), c);
+  double* pn = vptr(a, V_P0 + par, c);
+  double* ptn = vptr(a, V_PT0 + par, c);
+  for (int64_t sl = t.s_begin; sl < t.s_end; ++sl) {
+    const int64_t i = sl * kSlice + t.lane;
+    if (i >= a.n) continue;
+    const double zi = (double)z[i], zti = (double)zt[i];
+    pn[i] = first ? zi : fma(beta, po[i], zi);
+    ptn[i] = first ? zti : fma(beta, pto[i], zti);
+  }
+}
+
+// q = (sigma E - A) p, q~ = (sigma E - A)^T p~, partial sums of
 // delta = p~^T q, ||p~||^2, ||q||^2
-template <typename AT, int NC>
+template <int NC>
 __global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
   constexpr int kU = ChunkLen<NC>::value;
   const WaveCtx t = wave_ctx(a);
   const int c0 = blockIdx.y * NC;
   unsigned valid = 0;
-  double beta[NC], sig[NC];
-  bool first[NC];
-  const AT *z[NC], *zt[NC];
-  const double *po[NC], *pto[NC];
+  double sig[NC];
+  const double *p[NC], *pt[NC];
 #pragma unroll
   for (int j = 0; j < NC; ++j) {
     const int c = min(c0 + j, a.nc - 1);
     const ColInfo& ci = a.cols[c];
     if (c0 + j < a.nc && ci.state == COL_ACTIVE) valid |= 1u << j;
-    beta[j] = ci.beta;
     sig[j] = ci.sigma;
-    first[j] = ci.first != 0;
-    z[j] = aptr<AT>(a, A_Z, c);
-    zt[j] = aptr<AT>(a, A_ZT, c);
-    po[j] = vptr(a, V_P0 + (par ^ 1), c);
-    pto[j] = vptr(a, V_PT0 + (par ^ 1), c);
+    p[j] = vptr(a, V_P0 + par, c);
+    pt[j] = vptr(a, V_PT0 + par, c);
   }
   // valid is the same for the whole block; columns past the batch read the
   // last column's vectors and their results are dropped
@@ -524,8 +837,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
     double acc[NC], acct[NC];
 #pragma unroll
     for (int j = 0; j < NC; ++j) acc[j] = acct[j] = 0.0;
-    // p = z + beta p_old is formed at every gathered index (first step of a
-    // cycle: p = z)
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int32_t* off = h ? a.offT : a.off;
@@ -557,15 +868,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
         }
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
-          const AT* zz = h ? zt[j] : z[j];
-          const double* pp_old = h ? pto[j] : po[j];
+          const double* pv = h ? pt[j] : p[j];
           double sacc = h ? acct[j] : acc[j];
 #pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            const double zv = (double)gld(zz + cix[u]);
-            const double pv = fma(beta[j], gld(pp_old + cix[u]), zv);
-            sacc = fma(vv[u], first[j] ? zv : pv, sacc);
-          }
+          for (int u = 0; u < kU; ++u) sacc = fma(vv[u], gld(pv + cix[u]), sacc);
           if (h) acct[j] = sacc;
           else acc[j] = sacc;
         }
@@ -577,15 +883,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
       for (int j = 0; j < NC; ++j)
         if (valid & (1u << j)) {
           const int c = c0 + j;
-          const double zi = (double)gld(z[j] + i);
-          const double zti = (double)gld(zt[j] + i);
-          const double pi = first[j] ? zi : fma(beta[j], gld(po[j] + i), zi);
-          const double pti = first[j] ? zti : fma(beta[j], gld(pto[j] + i), zti);
+          const double pi = gld(p[j] + i);
+          const double pti = gld(pt[j] + i);
           const double se = sig[j] * ei;
           const double qi = fma(se, pi, -acc[j]);
           const double qti = fma(se, pti, -acct[j]);
-          gst(vptr(a, V_P0 + par, c) + i, pi);
-          gst(vptr(a, V_PT0 + par, c) + i, pti);
           gst(vptr(a, V_Q, c) + i, qi);
           gst(vptr(a, V_QT, c) + i, qti);
           v[j][0] = fma(pti, qi, v[j][0]);
@@ -622,8 +924,9 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_delta(IterArgs a) {
       }
     }
   }
-  if (!a.trace) return;
   __syncthreads();
+  build_plan(a);  // chain steps of the next iteration
+  if (!a.trace) return;
   // x, x~, r, r~ read and written, p, p~, q, q~ read (+ the FP32 copies of r, r~)
   const double rcopy = a.abytes == 4 ? 8.0 : 0.0;
   if (threadIdx.x == 0) a.trace[TR_UPDATE] += (96.0 + rcopy) * (double)a.n * upd_cols;
@@ -881,7 +1184,7 @@ static void trace_collect(TraceState* t) {
 }
 
 static const char* kTraceNames[kTraceClasses] = {"chain_step", "spmv_pair", "update", "factor_ls",
-                                                 "", "", "", ""};
+                                                 "form_p", "", "", ""};
 
 TraceState* trace_state_if_on(morx_ctx ctx) {
   TraceState* t = trace_of(ctx);
@@ -973,6 +1276,7 @@ void batch_free(KrylovBatch& b) {
   dev_free(b.cols);
   dev_free(b.part);
   dev_free(b.ftab);
+  dev_free(b.plan);
   if (b.hcols) hipHostFree(b.hcols);
   if (b.hftab) hipHostFree(b.hftab);
   b.hcols = nullptr;
@@ -986,11 +1290,17 @@ void krylov_batch_delete(KrylovBatch* kb) {
   delete kb;
 }
 
+// work-list entries per chain step: both halves, each padded to the tile width
+static int plan_ld(int cap) { return 2 * cap + 2 * kMaxNC; }
+static size_t plan_bytes(int cap, int lcap) {
+  return (size_t)lcap * plan_ld(cap) * sizeof(ChainItem) + (size_t)lcap * sizeof(int32_t);
+}
+
 size_t batch_bytes(morx_system sys, int cap, int aprec) {
   const size_t ld = (size_t)sys->n_pad;
   return (size_t)kNumVec * cap * ld * sizeof(double) +
          (size_t)apply_vecs(aprec) * cap * ld * prec_bytes(aprec) +
-         (size_t)8 * cap * kMaxBlocks * sizeof(double);
+         (size_t)8 * cap * kMaxBlocks * sizeof(double) + plan_bytes(cap, 64);
 }
 
 morx_status batch_alloc(KrylovBatch& b, morx_system sys, int cap, int lcap, int prec, int aprec,
@@ -1008,6 +1318,7 @@ morx_status batch_alloc(KrylovBatch& b, morx_system sys, int cap, int lcap, int 
   if (s == MORX_OK) s = dev_alloc(b.cols, (size_t)cap * sizeof(ColInfo));
   if (s == MORX_OK) s = dev_alloc(b.part, (size_t)8 * cap * kMaxBlocks * sizeof(double));
   if (s == MORX_OK) s = dev_alloc(b.ftab, (size_t)2 * cap * lcap * sizeof(void*));
+  if (s == MORX_OK) s = dev_alloc(b.plan, plan_bytes(cap, lcap));
   if (s == MORX_OK && hipHostMalloc((void**)&b.hcols, (size_t)cap * sizeof(ColInfo)) != hipSuccess)
     s = MORX_E_NOMEM;
   if (s == MORX_OK &&
@@ -1053,6 +1364,15 @@ morx_status batch_download(KrylovBatch& b, hipStream_t st) {
   return MORX_OK;
 }
 
+// columns per wave: the batch split into equal chunks of at most ncmax,
+// rounded up to an instantiated tile width (1..8, 10, 12, 16; the extra
+// columns of a chunk are past the batch and masked)
+static int pick_nc(int nc, int ncmax) {
+  const int chunks = (nc + ncmax - 1) / ncmax;
+  const int w = (nc + chunks - 1) / chunks;
+  return w <= 8 ? w : (w <= 10 ? 10 : (w <= 12 ? 12 : 16));
+}
+
 static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   morx_system sys = b.sys;
   IterArgs a;
@@ -1069,6 +1389,27 @@ static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   if (sys->tune_spw > 0) a.spw = std::max(a.spw, (int)sys->tune_spw);
   a.ncmax = sys->tune_nc > 0 ? (int)sys->tune_nc : kDefaultNC;
   a.ncmax_spmv = sys->tune_nc_spmv > 0 ? (int)sys->tune_nc_spmv : a.ncmax;
+  a.ncv = pick_nc(nc, a.ncmax);
+  // chain grid: the most chunks of (half, column) pairs any step has, from
+  // the chain lengths of the occupied slots; a batch whose slots change
+  // between segments (serving) takes the bound for nc columns instead, so
+  // its graphs do not depend on the mix
+  int ymax = 2 * ((nc + a.ncv - 1) / a.ncv);
+  if (b.profile_grid) {
+    ymax = 1;
+    for (int s = 0; s < maxL; ++s) {
+      int f = 0, r = 0;
+      for (int c = 0; c < nc; ++c) {
+        const ColInfo& ci = b.hcols[c];
+        if (ci.state == COL_IDLE) continue;
+        f += ci.L > s;
+        r += ci.L > maxL - 1 - s;
+      }
+      ymax = std::max(ymax, (f + a.ncv - 1) / a.ncv + (r + a.ncv - 1) / a.ncv);
+    }
+  }
+  a.ymax = ymax;
+  a.plan_ld = plan_ld(b.cap);
   int64_t nb = (a.nslices + (int64_t)kWavesPerBlock * a.spw - 1) / ((int64_t)kWavesPerBlock * a.spw);
   nb = std::max<int64_t>(8, (nb + 7) / 8 * 8);
   a.nblk = (int)nb;
@@ -1077,6 +1418,9 @@ static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   a.lcap = b.lcap;
   a.off = sys->sell.off;
   a.col = sys->sell.col;
+  a.nsell = sys->sell.nnz_sell;
+  a.nsellT = sys->sellT.nnz_sell;
+  a.narrow = std::max(sys->sell.max_width, sys->sellT.max_width) <= kNarrow;
   a.offT = sys->sellT.off;
   a.colT = sys->sellT.col;
   a.valA = sys->sell_val;
@@ -1093,16 +1437,9 @@ static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   a.part_delta = part + 3 * slab;
   a.part_norm = part + 6 * slab;
   a.trace = trace_counters(sys->ctx);
+  a.plan = (ChainItem*)b.plan.p;
+  a.plan_cnt = (int32_t*)((ChainItem*)b.plan.p + (size_t)b.lcap * a.plan_ld);
   return a;
-}
-
-// columns per wave: the batch split into equal chunks of at most ncmax,
-// rounded up to an instantiated tile width (1..8, 10, 12, 16; the extra
-// columns of a chunk are past the batch and masked)
-static int pick_nc(int nc, int ncmax) {
-  const int chunks = (nc + ncmax - 1) / ncmax;
-  const int w = (nc + chunks - 1) / chunks;
-  return w <= 8 ? w : (w <= 10 ? 10 : (w <= 12 ? 12 : 16));
 }
 
 #define MORX_NC_DISPATCH(NCV, ...)                         \
@@ -1129,15 +1466,20 @@ static dim3 grid_of(const IterArgs& a, int ncv, int halves) {
 // overhead is spread over the run instead of added to every launch.
 template <typename VT, typename AT, int NC>
 static void enqueue_chain(const IterArgs& a, hipStream_t st, TraceState* t) {
-  const dim3 g = grid_of(a, NC, 2);
+  const dim3 g((unsigned)a.nblk, (unsigned)a.ymax, 1);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (t) {
     e0 = trace_event(t);
     e1 = trace_event(t);
     if (e0) hipEventRecord(e0, st);
   }
-  for (int s = 0; s + 1 < a.maxL; ++s) k_chain_step<VT, AT, NC, false><<<g, kBlock, 0, st>>>(a, s);
-  k_chain_step<VT, AT, NC, true><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
+  if (a.narrow) {
+    for (int s = 0; s + 1 < a.maxL; ++s) k_chain_narrow<VT, AT, NC, false><<<g, kBlock, 0, st>>>(a, s);
+    k_chain_narrow<VT, AT, NC, true><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
+  } else {
+    for (int s = 0; s + 1 < a.maxL; ++s) k_chain_step<VT, AT, NC, false><<<g, kBlock, 0, st>>>(a, s);
+    k_chain_step<VT, AT, NC, true><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
+  }
   if (t && e0 && e1) {
     hipEventRecord(e1, st);
     t->pending.push_back({TR_CHAIN, e0, e1, a.maxL});
@@ -1153,9 +1495,11 @@ static void enqueue_chain_prec(const IterArgs& a, int prec, hipStream_t st, Trac
 
 static morx_status enqueue_iterations(const IterArgs& a, int prec, int iters, hipStream_t st,
                                       TraceState* t) {
-  const int ncv = pick_nc(a.nc, a.ncmax);
+  const int ncv = a.ncv;
   const int ncs = pick_nc(a.nc, a.ncmax_spmv);
   const bool f32 = a.abytes == 4;
+  // the first iteration's work lists (fin_delta writes the later ones)
+  k_plan<<<1, kFinThreads, 0, st>>>(a);
   for (int it = 0; it < iters; ++it) {
     const int par = it & 1;
     MORX_NC_DISPATCH(ncv, {
@@ -1163,10 +1507,10 @@ static morx_status enqueue_iterations(const IterArgs& a, int prec, int iters, hi
       else enqueue_chain_prec<double, NC>(a, prec, st, t);
     });
     k_fin_rho<<<1, kFinThreads, 0, st>>>(a);
+    if (f32) launch(t, TR_FORMP, k_form_p<float>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
+    else launch(t, TR_FORMP, k_form_p<double>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
     MORX_NC_DISPATCH(ncs, {
-      const dim3 g1 = grid_of(a, NC, 1);
-      if (f32) launch(t, TR_SPMV, k_spmv_pair<float, NC>, g1, dim3(kBlock), st, a, par);
-      else launch(t, TR_SPMV, k_spmv_pair<double, NC>, g1, dim3(kBlock), st, a, par);
+      launch(t, TR_SPMV, k_spmv_pair<NC>, grid_of(a, NC, 1), dim3(kBlock), st, a, par);
     });
     k_fin_delta<<<1, kFinThreads, 0, st>>>(a);
     // elementwise: one column per wave, nothing to share between columns
@@ -1212,7 +1556,8 @@ morx_status batch_launch_segment(KrylovBatch& b, int nc, int maxL, int iters, bo
   const IterArgs a = make_args(b, nc, maxL);
   if (!use_graph || t) return enqueue_iterations(a, b.prec, iters, st, t);
   const int64_t key =
-      ((((int64_t)iters * 1024 + nc) * 128 + a.spw) * 16 + a.ncmax) * 16 + a.ncmax_spmv;
+      (((((int64_t)iters * 1024 + nc) * 128 + a.spw) * 16 + a.ncmax) * 16 + a.ncmax_spmv) * 4096 +
+      a.ymax;
   for (auto& g : b.graphs)
     if (g.maxL == maxL && g.key == key) {
       MORX_HIP(hipGraphLaunch(g.x, st));
@@ -1273,6 +1618,7 @@ static morx_status solve_batch(morx_system sys, std::vector<BatchCol>& cols, int
   }
   if (!sys->kb) sys->kb = new KrylovBatch();
   KrylovBatch& b = *sys->kb;
+  b.profile_grid = true;
   if (b.cap < nc || b.lcap < maxL || b.prec != prec || b.aprec != aprec || b.ld != sys->n_pad) {
     MORX_HIP(hipStreamSynchronize(st));
     MORX_TRY(batch_alloc(b, sys, std::max(nc, b.cap), std::max(maxL, b.lcap), prec, aprec, st));
@@ -1797,6 +2143,7 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
     chain.push_back(g);
   }
   KrylovBatch kb;
+  kb.profile_grid = true;
   MORX_TRY(batch_alloc(kb, sys, ncols, chain_len, prec, MORX_F64, st));
   DevBuf rhs;
   morx_status s = dev_alloc(rhs, (size_t)ncols * sys->n_pad * sizeof(double));

@@ -236,6 +236,36 @@ __device__ __forceinline__ double gload_val<uint16_t>(const uint16_t* p) {
   return (double)__uint_as_float(((uint32_t)gld(p)) << 16);
 }
 
+// Buffer loads: a wave-uniform base and byte size in a resource descriptor
+// and a 32-bit per-lane byte offset (plus a wave-uniform one), so a load
+// needs one address register instead of two; the hardware checks the offset
+// against the size and reads past it return 0.  Every array read this way is
+// below 4 GiB (checked when a system is created).
+using BufRes = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ BufRes buf_res(const void* p, int64_t bytes) {
+  const uint32_t n = bytes >= 0xffffffffLL ? 0xffffffffu : (uint32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)n, 0x00020000);
+}
+__device__ __forceinline__ int32_t buf_i32(BufRes r, uint32_t off, uint32_t soff = 0) {
+  return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, 0);
+}
+template <typename T>
+__device__ __forceinline__ double buf_val(BufRes r, uint32_t off, uint32_t soff = 0);
+template <>
+__device__ __forceinline__ double buf_val<double>(BufRes r, uint32_t off, uint32_t soff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, (int)soff, 0);
+  return __hiloint2double((int)v[1], (int)v[0]);
+}
+template <>
+__device__ __forceinline__ double buf_val<float>(BufRes r, uint32_t off, uint32_t soff) {
+  return (double)__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ double buf_val<uint16_t>(BufRes r, uint32_t off, uint32_t soff) {
+  const uint32_t h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, 0);
+  return (double)__uint_as_float(h << 16);
+}
+
 inline size_t prec_bytes(int32_t prec) { return prec == MORX_F64 ? 8 : (prec == MORX_F32 ? 4 : 2); }
 
 // One row of a sliced-ELL product for up to NC columns: acc[j] += sum_m v_m * x_j[col_m].

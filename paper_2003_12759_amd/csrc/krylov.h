@@ -37,6 +37,10 @@ struct KrylovBatch {
   int aprec = MORX_F64;  // preconditioner apply (MORX_F64 or MORX_F32)
   int64_t ld = 0;
   DevBuf vec, avec, cols, part, ftab;
+  DevBuf plan;  // work lists of the chain steps (device-built each iteration)
+  // chain grid sized from the slots' chain lengths (a batch whose columns are
+  // fixed for its lifetime); otherwise from the slot count
+  bool profile_grid = false;
   ColInfo* hcols = nullptr;     // pinned host mirror of the slots
   const void** hftab = nullptr;  // pinned host mirror: [2][cap][lcap]
   // graphs of one iteration segment, cached per (chain length, segment

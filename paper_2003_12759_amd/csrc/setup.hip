@@ -279,12 +279,19 @@ morx_status build_sell(morx_system sys, const int32_t* rowptr, const int32_t* co
   MORX_HIP(hipMemsetAsync(w64.p, 0, (ns + 1) * sizeof(int64_t), st));
   k_slice_width<<<nblk(ns), kBlock, 0, st>>>(rowptr, n, ns, (int64_t*)w64.p);
   MORX_HIP(hipGetLastError());
+  std::vector<int64_t> hw((size_t)ns);
+  MORX_HIP(hipMemcpyAsync(hw.data(), w64.p, (size_t)ns * sizeof(int64_t), hipMemcpyDeviceToHost, st));
   MORX_TRY(scan_exclusive((int64_t*)w64.p, (int64_t*)off64.p, ns + 1, st, tmp));
   int64_t total = 0;
   MORX_HIP(hipMemcpyAsync(&total, (int64_t*)off64.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   MORX_HIP(hipStreamSynchronize(st));
-  MORX_REQUIRE(total < (int64_t)INT32_MAX, MORX_E_UNSUPPORTED,
-               "sliced-ELL size %lld exceeds 2^31", (long long)total);
+  int64_t wmax = 0;
+  for (int64_t w : hw) wmax = std::max(wmax, w / kSlice);
+  out.max_width = (int32_t)wmax;
+  // the iteration kernels address these arrays (and n-vectors, n <= total)
+  // with 32-bit byte offsets of 8-byte elements
+  MORX_REQUIRE(total < ((int64_t)1 << 29) - 4096, MORX_E_UNSUPPORTED,
+               "sliced-ELL size %lld exceeds 2^29 entries", (long long)total);
   out.nnz_sell = total;
   MORX_TRY(owned_alloc(sys, &out.off, ns + 1));
   MORX_TRY(owned_alloc(sys, &out.col, total));
