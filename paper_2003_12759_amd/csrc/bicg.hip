@@ -339,7 +339,6 @@ struct ChunkLen {
 template <typename VT, typename AT, int NC, bool RHO>
 __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s) {
   constexpr int kU = ChunkLen<NC>::value;
-  constexpr uint32_t kVB = sizeof(VT), kAB = sizeof(AT);
   const WaveCtx t = wave_ctx(a);
   const ChainItem* plan = a.plan + (int64_t)s * a.plan_ld;
   const int nchunks = gld(a.plan_cnt + s);
@@ -347,8 +346,8 @@ __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s) {
   // slice starts of the wave's slices, lane l holding slice s_begin + wb + l
   // for both orders (a window of 64, refilled as the wave moves past it)
   const int wl = min(t.lane, nsl);
-  const int32_t owF = nsl > 0 ? gld(a.off + t.s_begin + wl) : 0;
-  const int32_t owB = nsl > 0 ? gld(a.offT + t.s_begin + wl) : 0;
+  int32_t owF = nsl > 0 ? gld(a.off + t.s_begin + wl) : 0;
+  int32_t owB = nsl > 0 ? gld(a.offT + t.s_begin + wl) : 0;
   for (int y = blockIdx.y;; y += gridDim.y) {
     ChainItem it[NC];
 #pragma unroll
@@ -356,10 +355,10 @@ __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s) {
     if (it[0].c < 0) break;  // past the last chunk (uniform over the block)
     const bool bwd = (it[0].flags & 1) != 0;
     const bool rho_half = RHO && bwd;
-    const int64_t nsell = bwd ? a.nsellT : a.nsell;
     unsigned valid = 0;
-    BufRes rsrc[NC], rfv[NC];
+    const AT* src[NC];
     AT* dst[NC];
+    const VT* fv[NC];
     bool shared = true;
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
@@ -367,52 +366,50 @@ __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s) {
       if (on) valid |= 1u << j;
       // padding runs along with the chunk's first pair (cache hits, results
       // dropped), so the slot loop has no per-column branch
-      rsrc[j] = buf_res(on ? it[j].src : it[0].src, a.ld * (int64_t)kAB);
-      rfv[j] = buf_res(on ? it[j].fv : it[0].fv, nsell * (int64_t)kVB);
+      src[j] = (const AT*)(on ? it[j].src : it[0].src);
       dst[j] = (AT*)it[j].dst;
-      shared = shared && (!on || it[j].fv == it[0].fv);
+      fv[j] = (const VT*)(on ? it[j].fv : it[0].fv);
+      shared = shared && fv[j] == (const VT*)it[0].fv;
     }
-    const BufRes rcol = buf_res(bwd ? a.colT : a.col, nsell * 4);
+    const VT* fv0 = (const VT*)it[0].fv;
     const int32_t* off = bwd ? a.offT : a.off;
+    const int32_t* col = bwd ? a.colT : a.col;
     int32_t ow = bwd ? owB : owF;
     int wb = 0;
     double v[RHO ? NC : 1][3];
 #pragma unroll
     for (int j = 0; j < (RHO ? NC : 1); ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
     if (nsl > 0) {
-      // first entry and width of relative slice k (wave-uniform); refills the
-      // window so that k and k+1 are in it
+      // bounds of relative slice k; refills the window so that k and k+1 are in it
       auto bounds = [&](int k, int32_t& base, int32_t& w) {
         if (k + 1 - wb > 63) {
           wb = k;
           ow = gld(off + t.s_begin + wb + min(t.lane, nsl - wb));
         }
-        base = __builtin_amdgcn_readfirstlane(__shfl(ow, k - wb, 64));
-        w = (__builtin_amdgcn_readfirstlane(__shfl(ow, k + 1 - wb, 64)) - base) >> 6;
+        base = __shfl(ow, k - wb, 64);
+        w = (__shfl(ow, k + 1 - wb, 64) - base) >> 6;
       };
       // (slice, chunk) cursor over the wave's slices; the column indices of
       // the next chunk, possibly in the next slice, are loaded while the
-      // current chunk's values and gathers are in flight.
+      // current chunk's values and gathers are in flight
       int k = 0, m0 = 0;
       int32_t base, w;
       bounds(0, base, w);
       int32_t nix[kU];
-      {
-        const uint32_t o = (uint32_t)(base + t.lane) * 4u;
 #pragma unroll
-        for (int u = 0; u < kU; ++u) nix[u] = buf_i32(rcol, u < w ? o + u * kSlice * 4 : kOutside);
-      }
+      for (int u = 0; u < kU; ++u) nix[u] = gld(col + base + t.lane + (u < w ? u * kSlice : 0));
       double acc[NC];
 #pragma unroll
       for (int j = 0; j < NC; ++j) acc[j] = 0.0;
       while (true) {
-        const uint32_t pv = (uint32_t)(base + t.lane + m0 * kSlice) * kVB;
-        uint32_t fo[kU], go[kU];  // value and gather offsets of the chunk's slots
+        const int32_t p0 = base + t.lane;
+        int32_t pp[kU], cix[kU];
+        bool ok[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-          const bool ok = m0 + u < w;
-          fo[u] = ok ? pv + u * kSlice * kVB : kOutside;
-          go[u] = ok ? (uint32_t)nix[u] * kAB : kOutside;
+          ok[u] = m0 + u < w;
+          pp[u] = p0 + (ok[u] ? (m0 + u) * kSlice : 0);  // past the row: slot 0, value dropped
+          cix[u] = nix[u];
         }
         int k2 = k, m2 = m0 + kU;
         int32_t base2 = base, w2 = w;
@@ -422,28 +419,31 @@ __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s) {
           if (k2 < nsl) bounds(k2, base2, w2);
         }
         if (k2 < nsl) {
-          const uint32_t o = (uint32_t)(base2 + t.lane + m2 * kSlice) * 4u;
 #pragma unroll
-          for (int u = 0; u < kU; ++u)
-            nix[u] = buf_i32(rcol, m2 + u < w2 ? o + u * kSlice * 4 : kOutside);
+          for (int u = 0; u < kU; ++u) {
+            const int32_t mn = m2 + u;
+            nix[u] = gld(col + base2 + t.lane + (mn < w2 ? mn * kSlice : 0));
+          }
         }
         if (shared) {
           double vv[kU];
 #pragma unroll
-          for (int u = 0; u < kU; ++u) vv[u] = buf_val<VT>(rfv[0], fo[u]);
+          for (int u = 0; u < kU; ++u) {
+            const double raw = gload_val<VT>(fv0 + pp[u]);
+            vv[u] = ok[u] ? raw : 0.0;
+          }
 #pragma unroll
           for (int j = 0; j < NC; ++j)
 #pragma unroll
-            for (int u = 0; u < kU; ++u) acc[j] = fma(vv[u], buf_val<AT>(rsrc[j], go[u]), acc[j]);
+            for (int u = 0; u < kU; ++u) acc[j] = fma(vv[u], (double)gld(src[j] + cix[u]), acc[j]);
         } else {
-          // pairs visited last to first: no load here is the same as the
-          // first load of the shared branch, which the compiler would hoist
-          // above the branch and wait for there
 #pragma unroll
-          for (int j = NC - 1; j >= 0; --j)
+          for (int j = 0; j < NC; ++j)
 #pragma unroll
-            for (int u = 0; u < kU; ++u)
-              acc[j] = fma(buf_val<VT>(rfv[j], fo[u]), buf_val<AT>(rsrc[j], go[u]), acc[j]);
+            for (int u = 0; u < kU; ++u) {
+              const double raw = gload_val<VT>(fv[j] + pp[u]);
+              acc[j] = fma(ok[u] ? raw : 0.0, (double)gld(src[j] + cix[u]), acc[j]);
+            }
         }
         if (m2 == 0) {  // slice k done
           const int64_t i = (t.s_begin + k) * kSlice + t.lane;
@@ -480,7 +480,6 @@ __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s) {
 #pragma unroll
         for (int j = 0; j < NC; ++j) cols[j] = it[j].c;
         block_partials_cols<NC, 3>(a, t, cols, valid, v, a.part_rho);
-        __syncthreads();  // the shared partials are reused by the next chunk
       }
     if (y + (int)gridDim.y >= nchunks) break;
   }
