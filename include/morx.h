@@ -243,6 +243,11 @@ morx_status morx_project(morx_system sys, int32_t r, const double* V, int64_t ld
  *   factor_kernel    0: one wave per column, the local matrix in LDS;
  *                    1: one wave per column, the local matrix in registers
  *                    (8 or 16 column lanes; patterns with |J_k| < 16);
+ *                    2: normal equations (|J_k| <= 32): per column the
+ *                    m x m matrices (A^T A)(J_k, J_k) and A(J_k, J_k), then
+ *                    per shift a Cholesky solve in registers; columns whose
+ *                    pivots show poor conditioning are redone by kernel 0
+ *                    (the built-in choice when the pattern allows it);
  *                    8 or 16: one block of 32 x 8 or 32 x 16 threads per
  *                    column, the local matrix in registers (|J_k| < 32);
  *   cols_per_wave    chain step: most right-hand-side columns one wave

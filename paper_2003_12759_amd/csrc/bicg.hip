@@ -2107,7 +2107,7 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
   const int njobs = (int)std::max<int64_t>(1, std::min<int64_t>({chain_len, 16, cap_jobs}));
   std::vector<FactorJob> fjobs(njobs, FactorJob{sigma, 0.0, 1, f->vals.p, f->valsT.p});
   const int saved_rows = sys->tune_factor_rows;
-  for (int rows : {0, 1, 8, 16}) {
+  for (int rows : {2, 0, 1, 8, 16}) {
     if (!factor_kernel_supported(sys, rows)) continue;
     sys->tune_factor_rows = rows;
     MORX_HIP(hipEventRecord(e0, st));

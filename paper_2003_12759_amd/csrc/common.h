@@ -123,7 +123,8 @@ struct morx_system_s {
   int32_t max_J = 0, max_T = 0, max_I = 0;
   bool ls_supported = true;
   // launch shapes (morx_tune): -1 means the built-in heuristic
-  int32_t tune_factor_rows = -1;  // least-squares kernel: 0 per wave, 8 or 16 row groups
+  int32_t tune_factor_rows = -1;  // least-squares kernel (morx_tune.factor_kernel)
+  int32_t* ls_fallback = nullptr;  // columns the normal equations leave to Householder QR
   int32_t tune_nc = -1;           // chain step: most columns per wave (1..8)
   int32_t tune_nc_spmv = -1;      // shifted pair, true residual: the same (-1: tune_nc)
   int32_t tune_spw = -1;          // iteration kernels: 64-row slices per wave

@@ -168,7 +168,8 @@ __global__ __launch_bounds__(64) void k_factor_ls(
     const int32_t* __restrict__ trowptr, const int32_t* __restrict__ tcol,
     const double* __restrict__ tval, const double* __restrict__ e,
     const int32_t* __restrict__ tp2s, const int32_t* __restrict__ sellT_off, int64_t n,
-    const FactorJob* __restrict__ jobs, int njobs, LsLayout L, int* __restrict__ status) {
+    const FactorJob* __restrict__ jobs, int njobs, LsLayout L, int* __restrict__ status,
+    const int32_t* __restrict__ list, const int* __restrict__ list_count) {
   extern __shared__ __align__(16) unsigned char lds[];
   int* keys = (int*)(lds + L.off_keys);
   int* tri = (int*)(lds + L.off_tri);
@@ -179,8 +180,11 @@ __global__ __launch_bounds__(64) void k_factor_ls(
   double* M = (double*)(lds + L.off_M);
   const int lane = threadIdx.x;
   const int ldm = L.ldm;
+  // every column, or the columns listed (those the normal equations gave up)
+  const int64_t count = list ? (int64_t)*list_count : n;
 
-  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+  for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
+    const int64_t k = list ? (int64_t)list[it] : it;
     int m, T, nI;
     gather_sort_unique(trowptr, tcol, tval, k, lane, L.Tpad, keys, tri, tv, uniq, J, &m, &T, &nI);
     // local row of every gathered nonzero (keys[] is sorted now, so walk the
@@ -292,6 +296,220 @@ __global__ void k_factor_to_csr(const VT* __restrict__ vals, const int32_t* __re
                                 int64_t nnz, double* __restrict__ out) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p < nnz) out[p] = load_val<VT>(vals + csr2sell[p]);
+}
+
+// ---- normal-equations kernel (factor_kernel 2) -----------------------------
+//
+// With M(s) = s E(I_k, J_k) - A(I_k, J_k), m = |J_k| and a the position of k
+// in J_k, every product the normal equations of a column need comes from two
+// m x m matrices:
+//   G0  = A(I_k, J_k)^T A(I_k, J_k) = (A^T A)(J_k, J_k)  (I_k holds every row of
+//         those columns of A),
+//   Ajj = A(J_k, J_k),
+// since E(I_k, J_k) has one entry E_j per column, in row J_j:
+//   M(s1)^T M(s2) = G0 - s2 Ajj^T E_J - s1 E_J Ajj + s1 s2 E_J^2.
+// A SPAI column solves G(s) q = M(s)^T e_k with M(s)^T e_k = s E_k e_a -
+// Ajj(a, :)^T; an update column solves G(sn) q = M(sn)^T M(sp) e_a (its
+// right-hand side is column k of sp E - A).  Neither I_k nor the dense
+// |I_k| x m matrix is formed: one wave gathers the m columns of A, forms G0
+// (sorted merges of column pairs) and Ajj, and then groups of CG lanes, lane i
+// holding row i, each take one shift: Cholesky
+// factorisation and the two triangular solves in registers, the columns of
+// L exchanged through LDS.  The normal equations square the condition
+// number, so a column with a pivot below kNeTol times the diagonal entry it
+// started from is listed for the Householder kernel, which rebuilds every
+// shift of that column (and reports a rank-deficient problem as the other
+// kernels do).
+constexpr double kNeTol = 1e-6;
+
+struct NeLayout {
+  int T;
+  size_t off_J, off_off, off_E, off_H, off_G0, off_crow, off_cval, off_L, bytes;
+};
+
+NeLayout ne_layout(int maxT, int CG) {
+  NeLayout L;
+  L.T = std::max(maxT, 1);
+  const int G = 64 / CG;
+  const size_t mat = (size_t)CG * (CG + 1) * 8;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o += (bytes + 15) / 16 * 16;
+    return r;
+  };
+  L.off_J = take((size_t)CG * 4);
+  L.off_off = take((size_t)(CG + 1) * 4);
+  L.off_E = take((size_t)CG * 8);
+  L.off_H = take(mat);
+  L.off_G0 = take(mat);
+  // the gathered columns, later in the same space the L factors of the G
+  // shifts in flight
+  const size_t base = o;
+  L.off_crow = base;
+  L.off_cval = base + ((size_t)L.T * 4 + 15) / 16 * 16;
+  L.off_L = base;
+  const size_t gather = L.off_cval - base + (size_t)L.T * 8;
+  o += std::max(gather, (size_t)G * mat);
+  L.bytes = o;
+  return L;
+}
+
+template <typename VT, int CG>
+__global__ __launch_bounds__(64) void k_factor_ne(
+    const int32_t* __restrict__ trowptr, const int32_t* __restrict__ tcol,
+    const double* __restrict__ tval, const double* __restrict__ e,
+    const int32_t* __restrict__ tp2s, const int32_t* __restrict__ sellT_off, int64_t n,
+    const FactorJob* __restrict__ jobs, int njobs, NeLayout L, int* __restrict__ fb_count,
+    int32_t* __restrict__ fb_list) {
+  constexpr int G = 64 / CG;
+  constexpr int LD = CG + 1;  // stride of the m x m matrices in LDS
+  extern __shared__ __align__(16) unsigned char lds[];
+  int* J = (int*)(lds + L.off_J);
+  int* coff = (int*)(lds + L.off_off);
+  double* EJ = (double*)(lds + L.off_E);
+  double* Ajj = (double*)(lds + L.off_H);
+  double* G0 = (double*)(lds + L.off_G0);
+  int* crow = (int*)(lds + L.off_crow);
+  double* cval = (double*)(lds + L.off_cval);
+  const int lane = threadIdx.x;
+  const int g = lane / CG, i = lane % CG, gbase = g * CG;
+  double* Lc = (double*)(lds + L.off_L) + (size_t)g * CG * LD;  // L(r, c) at Lc[c * LD + r]
+
+  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+    const int lo = trowptr[k];
+    const int m = trowptr[k + 1] - lo;  // <= CG (checked on the host)
+    // gather the columns J_k of A in order (rows sorted within a column)
+    int len = 0, jc = -1, cb = 0;
+    if (lane < m) {
+      jc = tcol[lo + lane];
+      cb = trowptr[jc];
+      len = trowptr[jc + 1] - cb;
+      J[lane] = jc;
+      EJ[lane] = e[jc];
+    }
+    int T;
+    const int off = wave_excl_scan(len, lane, &T);
+    if (lane < m) coff[lane] = off;
+    if (lane == 0) coff[m] = T;
+    for (int u = 0; u < len; ++u) {
+      crow[off + u] = tcol[cb + u];
+      cval[off + u] = tval[cb + u];
+    }
+    const unsigned long long am = __ballot(jc == (int)k);
+    const int a = am ? (int)__ffsll((long long)am) - 1 : 0;  // the diagonal is always in S
+    for (int t = lane; t < m * LD; t += 64) Ajj[t] = 0.0;
+    __syncthreads();
+    // Ajj(r, l) = A(J_r, J_l): the rows of column l that lie in J_k
+    if (lane < m) {
+      for (int u = 0; u < len; ++u) {
+        const int row = crow[off + u];
+        int lo2 = 0, hi2 = m - 1;
+        while (lo2 < hi2) {
+          const int mid = (lo2 + hi2) >> 1;
+          if (J[mid] < row) lo2 = mid + 1;
+          else hi2 = mid;
+        }
+        if (J[lo2] == row) Ajj[lo2 * LD + lane] = cval[off + u];
+      }
+    }
+    // G0(r, l), r <= l: merge of the sorted rows of columns r and l
+    const int npair = m * (m + 1) / 2;
+    for (int p = lane; p < npair; p += 64) {
+      int r = 0, rem = p;
+      while (rem >= m - r) {
+        rem -= m - r;
+        ++r;
+      }
+      const int l = r + rem;
+      int x = coff[r], y = coff[l];
+      const int xe = coff[r + 1], ye = coff[l + 1];
+      double s = 0.0;
+      while (x < xe && y < ye) {
+        const int rx = crow[x], ry = crow[y];
+        if (rx == ry) s = fma(cval[x], cval[y], s);
+        x += rx <= ry;
+        y += ry <= rx;
+      }
+      G0[r * LD + l] = s;
+      G0[l * LD + r] = s;
+    }
+    __syncthreads();
+    // per lane: Ajj(a, i), Ajj(i, a), Ajj(i, i), G0(i, a), G0(i, i)
+    const bool row = i < m;
+    const double ei = row ? EJ[i] : 0.0, ek = EJ[a];
+    const double aai = row ? Ajj[a * LD + i] : 0.0;
+    const double aia = row ? Ajj[i * LD + a] : 0.0;
+    const double aii = row ? Ajj[i * LD + i] : 0.0;
+    const double g0a = row ? G0[i * LD + a] : 0.0;
+    const double g0i = row ? G0[i * LD + i] : 0.0;
+    __syncthreads();  // the gathered columns are dead: their space holds L now
+    bool bad = false;
+    for (int r0 = 0; r0 < njobs; r0 += G) {
+      const bool live = r0 + g < njobs;
+      const FactorJob job = jobs[live ? r0 + g : njobs - 1];
+      const double sn = job.sigma_new, sp = job.sigma_prev;
+      // row i of G(sn) = G0 - sn (E_J Ajj + Ajj^T E_J) + sn^2 E_J^2 (identity
+      // rows past m) and the right-hand side
+      double gr[CG];
+#pragma unroll
+      for (int l = 0; l < CG; ++l) {
+        double v = 0.0;
+        if (row && l < m) v = fma(-sn, fma(ei, Ajj[i * LD + l], EJ[l] * Ajj[l * LD + i]), G0[i * LD + l]);
+        gr[l] = v + (l == i ? (row ? sn * sn * ei * ei : 1.0) : 0.0);
+      }
+      const double gd = fma(sn * sn, ei * ei, fma(-2.0 * sn * ei, aii, g0i));  // G(sn)(i, i)
+      double y = 0.0;
+      if (row) {
+        if (job.is_spai)
+          y = (i == a ? sn * ek : 0.0) - aai;
+        else
+          y = g0a - sp * ek * aai - sn * ei * aia + (i == a ? sn * sp * ek * ek : 0.0);
+      }
+      // Cholesky G = L L^T: after step c lane r >= c holds L(r, c) in gr[c]
+      // (the loops run over all CG positions with uniform guards, so that
+      // they unroll completely and gr stays in registers)
+#pragma unroll
+      for (int c = 0; c < CG; ++c) {
+        if (c < m) {
+          const double piv = __shfl(gr[c], gbase + c, 64);
+          const double d = piv > 0.0 ? sqrt(piv) : 1.0;
+          if (i == c && live) bad = bad || !(piv > kNeTol * gd);
+          const double lic = i > c ? gr[c] / d : (i == c ? d : 0.0);
+          gr[c] = lic;
+          Lc[c * LD + i] = lic;
+          __syncthreads();
+#pragma unroll
+          for (int l = c + 1; l < CG; ++l)
+            if (l < m) gr[l] = fma(-lic, Lc[c * LD + l], gr[l]);
+        }
+      }
+      // L z = y, then L^T q = z
+#pragma unroll
+      for (int c = 0; c < CG; ++c) {
+        if (c < m) {
+          const double zc = __shfl(y / gr[c], gbase + c, 64);
+          if (i == c) y = zc;
+          else if (i > c) y = fma(-gr[c], zc, y);
+        }
+      }
+#pragma unroll
+      for (int c = CG - 1; c >= 0; --c) {
+        if (c < m) {
+          const double qc = __shfl(y / gr[c], gbase + c, 64);
+          if (i == c) y = qc;
+          else if (i < c) y = fma(-Lc[i * LD + c], qc, y);
+        }
+      }
+      if (row && live) {
+        const int64_t posT = (int64_t)sellT_off[k / kSlice] + (int64_t)i * kSlice + (k % kSlice);
+        store_val<VT>((VT*)job.valsT + posT, y);
+        store_val<VT>((VT*)job.vals + tp2s[lo + i], y);
+      }
+      __syncthreads();  // L of this round is read up to here
+    }
+    if (__ballot(bad) != 0ull && lane == 0) fb_list[atomicAdd(fb_count, 1)] = (int32_t)k;
+  }
 }
 
 // ---- block kernel for larger local problems ------------------------------------
@@ -632,6 +850,7 @@ bool blk_shape(morx_system sys, int variant, BlkShape* out) {
 // take the 32 x 16 block.
 int blk_variant(morx_system sys) {
   int v = sys->tune_factor_rows;
+  if (v == 2) return 0;
   if (v < 0) v = sys->max_J < 12 ? 0 : 16;
   BlkShape b;
   if (v == 16 && !blk_shape(sys, 16, &b)) v = 8;
@@ -645,9 +864,17 @@ int ls_grid(morx_system sys) {
 
 }  // namespace
 
+// column lanes of the normal-equations kernel, or 0 when it does not apply
+static int ne_lanes(morx_system sys) {
+  if (!sys->ls_supported || sys->max_J > 32) return 0;
+  const int cg = sys->max_J <= 8 ? 8 : (sys->max_J <= 16 ? 16 : 32);
+  return ne_layout(sys->max_T, cg).bytes <= (size_t)kLdsBudget ? cg : 0;
+}
+
 bool factor_kernel_supported(morx_system sys, int variant) {
   if (!sys->ls_supported) return false;
   if (variant == 0) return true;
+  if (variant == 2) return ne_lanes(sys) > 0;
   BlkShape b;
   return blk_shape(sys, variant, &b);
 }
@@ -740,15 +967,50 @@ morx_status factor_build_many(morx_system sys, int32_t prec, const FactorJob* jo
   LsLayout L = ls_layout(sys->max_J, sys->max_T, sys->max_I);
   DevBuf jb, sb;
   MORX_TRY(dev_alloc(jb, njobs * sizeof(FactorJob)));
-  MORX_TRY(dev_alloc(sb, sizeof(int)));
+  MORX_TRY(dev_alloc(sb, 2 * sizeof(int)));  // rank-deficient flag, normal-equations fallbacks
   MORX_HIP(hipMemcpyAsync(jb.p, jobs, njobs * sizeof(FactorJob), hipMemcpyHostToDevice, st));
-  MORX_HIP(hipMemsetAsync(sb.p, 0, sizeof(int), st));
+  MORX_HIP(hipMemsetAsync(sb.p, 0, 2 * sizeof(int), st));
   const int grid = ls_grid(sys);
   void* token = nullptr;
   trace_factor_begin(sys->ctx, st, &token);
   const int variant = blk_variant(sys);
+  const int cg = (sys->tune_factor_rows == 2 || sys->tune_factor_rows < 0) ? ne_lanes(sys) : 0;
+  int32_t* fb_list = nullptr;
+  if (cg > 0) {
+    if (!sys->ls_fallback) {
+      DevBuf fb;
+      MORX_TRY(dev_alloc(fb, (size_t)sys->n * sizeof(int32_t)));
+      sys->owned.push_back(fb);
+      sys->resident_bytes += (int64_t)fb.bytes;
+      sys->ls_fallback = (int32_t*)fb.p;
+    }
+    fb_list = sys->ls_fallback;
+  }
   BlkShape bs{};
-  if (variant > 0 && blk_shape(sys, variant, &bs)) {
+  if (cg > 0) {
+    const NeLayout N = ne_layout(sys->max_T, cg);
+    const int ngrid = (int)std::min<int64_t>(sys->n, (int64_t)std::max(sys->ctx->num_cu, 1) * 32);
+    int* fb_count = (int*)sb.p + 1;
+#define MORX_NE_LAUNCH(VT, CGV)                                                                 \
+  k_factor_ne<VT, CGV><<<ngrid, 64, N.bytes, st>>>(sys->trowptr, sys->tcol, sys->tval, sys->e, \
+                                                   sys->tp2s, sys->sellT.off, sys->n,         \
+                                                   (FactorJob*)jb.p, njobs, N, fb_count, fb_list)
+#define MORX_NE_CG(VT)                 \
+  if (cg == 8) MORX_NE_LAUNCH(VT, 8);   \
+  else if (cg == 16) MORX_NE_LAUNCH(VT, 16); \
+  else MORX_NE_LAUNCH(VT, 32);
+    // then the Householder kernel on the columns the normal equations listed
+#define MORX_NE_FALLBACK(VT)                                                                    \
+  k_factor_ls<VT><<<grid, 64, L.bytes, st>>>(sys->trowptr, sys->tcol, sys->tval, sys->e,         \
+                                            sys->tp2s, sys->sellT.off, sys->n, (FactorJob*)jb.p, \
+                                            njobs, L, (int*)sb.p, fb_list, fb_count)
+    if (prec == MORX_F64) { MORX_NE_CG(double) MORX_NE_FALLBACK(double); }
+    else if (prec == MORX_F32) { MORX_NE_CG(float) MORX_NE_FALLBACK(float); }
+    else { MORX_NE_CG(uint16_t) MORX_NE_FALLBACK(uint16_t); }
+#undef MORX_NE_FALLBACK
+#undef MORX_NE_CG
+#undef MORX_NE_LAUNCH
+  } else if (variant > 0 && blk_shape(sys, variant, &bs)) {
     const int S = bs.S, BR = bs.BR, BC = bs.BC;
     const BlkLayout B = blk_layout(sys->max_T, sys->max_I, S, BR, BC);
     // one-wave blocks: more of them to fill the CUs
@@ -797,17 +1059,20 @@ morx_status factor_build_many(morx_system sys, int32_t prec, const FactorJob* jo
     case MORX_F64:
       k_factor_ls<double><<<grid, 64, L.bytes, st>>>(sys->trowptr, sys->tcol, sys->tval, sys->e,
                                                      sys->tp2s, sys->sellT.off, sys->n,
-                                                     (FactorJob*)jb.p, njobs, L, (int*)sb.p);
+                                                     (FactorJob*)jb.p, njobs, L, (int*)sb.p,
+                                                     nullptr, nullptr);
       break;
     case MORX_F32:
       k_factor_ls<float><<<grid, 64, L.bytes, st>>>(sys->trowptr, sys->tcol, sys->tval, sys->e,
                                                     sys->tp2s, sys->sellT.off, sys->n,
-                                                    (FactorJob*)jb.p, njobs, L, (int*)sb.p);
+                                                    (FactorJob*)jb.p, njobs, L, (int*)sb.p,
+                                                    nullptr, nullptr);
       break;
     default:
       k_factor_ls<uint16_t><<<grid, 64, L.bytes, st>>>(sys->trowptr, sys->tcol, sys->tval,
                                                        sys->e, sys->tp2s, sys->sellT.off, sys->n,
-                                                       (FactorJob*)jb.p, njobs, L, (int*)sb.p);
+                                                       (FactorJob*)jb.p, njobs, L, (int*)sb.p,
+                                                       nullptr, nullptr);
   }
   trace_factor_end(sys->ctx, st, token);
   MORX_HIP(hipGetLastError());
