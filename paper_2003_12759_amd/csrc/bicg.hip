@@ -493,9 +493,20 @@ __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s) {
 // grow with the tile width, and a wide tile reads the slice's indices and
 // values once for all its pairs.  Slots past a slice's width are not loaded;
 // each row sums its slots in order from zero, as the general kernel does.
-// The rho partials (last step) are summed per slice over the wave and
-// collected per pair in LDS.
+// The rho partials (last step) are summed per lane over the wave's slices
+// and then over the block, as in the general kernel.
 constexpr int kNarrow = 8;
+
+// A pointer every lane holds the same value of, kept in scalar registers
+// (a buffer descriptor built from a vector register would need a loop over
+// its distinct values)
+template <typename T>
+__device__ __forceinline__ T* uniform(T* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (T*)(((uint64_t)hi << 32) | lo);
+}
 
 template <typename VT>
 using NarrowVal = typename std::conditional<sizeof(VT) == 8, double, float>::type;
@@ -520,7 +531,7 @@ __device__ __forceinline__ void narrow_slice(const IterArgs& a, const WaveCtx& t
                                              const ChainItem* ck, int ncol, BufRes rcol,
                                              int32_t base, int w, int64_t i, int64_t fbytes,
                                              int64_t vbytes, bool rho_half,
-                                             double (*rho_row)[3]) {
+                                             double (&v)[RHO ? NC : 1][3]) {
   using FT = NarrowVal<VT>;
   constexpr uint32_t kVB = sizeof(VT), kAB = sizeof(AT);
   const uint32_t oi = (uint32_t)(base + t.lane) * 4u;
@@ -536,34 +547,37 @@ __device__ __forceinline__ void narrow_slice(const IterArgs& a, const WaveCtx& t
   for (int u = 0; u < kNarrow; ++u) go[u] = u < w ? go[u] * kAB : kOutside;
   FT fb[SHARED ? 1 : 2][kNarrow];
   AT gb[2][kNarrow];
+  double rb[2] = {0.0, 0.0};  // r_i of the pair (rho partials, last step only)
   auto issue = [&](int j, int q) {
     const ChainItem* e = ck + j;
     if (!SHARED || j == 0) {
-      const BufRes rf = buf_res(e->fv, fbytes);
+      const BufRes rf = buf_res(uniform(e->fv), fbytes);
 #pragma unroll
       for (int u = 0; u < kNarrow; ++u) fb[SHARED ? 0 : q][u] = buf_raw<VT>(rf, fo[u]);
     }
-    const BufRes rs = buf_res(e->src, vbytes);
+    const BufRes rs = buf_res(uniform(e->src), vbytes);
 #pragma unroll
     for (int u = 0; u < kNarrow; ++u) gb[q][u] = (AT)buf_val<AT>(rs, go[u]);
+    if constexpr (RHO) {
+      const double* rp = vptr(a, V_R, __builtin_amdgcn_readfirstlane(e->c));
+      if (rho_half && i < a.n) rb[q] = gld(rp + i);
+    }
   };
   auto finish = [&](int j, int q) {
     double acc = 0.0;
 #pragma unroll
     for (int u = 0; u < kNarrow; ++u)
       acc = fma((double)fb[SHARED ? 0 : q][u], (double)gb[q][u], acc);
-    const ChainItem* e = ck + j;
+    AT* dst = (AT*)uniform(ck[j].dst);
     const AT zs = (AT)acc;
-    if (i < a.n) gst((AT*)e->dst + i, zs);
+    if (i < a.n) gst(dst + i, zs);
     if constexpr (RHO) {
       if (rho_half) {
-        const double zi = i < a.n ? (double)zs : 0.0;
-        const double ri = i < a.n ? gld(vptr(a, V_R, e->c) + i) : 0.0;
-        const double s0 = wave_sum(zi * ri), s1 = wave_sum(zi * zi), s2 = wave_sum(ri * ri);
-        if (t.lane == 0) {
-          rho_row[j][0] += s0;
-          rho_row[j][1] += s1;
-          rho_row[j][2] += s2;
+        if (i < a.n) {
+          const double zi = (double)zs, ri = rb[q];
+          v[j][0] = fma(zi, ri, v[j][0]);
+          v[j][1] = fma(zi, zi, v[j][1]);
+          v[j][2] = fma(ri, ri, v[j][2]);
         }
       }
     }
@@ -580,7 +594,6 @@ __device__ __forceinline__ void narrow_slice(const IterArgs& a, const WaveCtx& t
 
 template <typename VT, typename AT, int NC, bool RHO>
 __global__ __launch_bounds__(kBlock) void k_chain_narrow(IterArgs a, int s) {
-  __shared__ double rho_sh[RHO ? kWavesPerBlock : 1][RHO ? NC : 1][3];
   const WaveCtx t = wave_ctx(a);
   const ChainItem* plan = a.plan + (int64_t)s * a.plan_ld;
   const int nchunks = gld(a.plan_cnt + s);
@@ -597,9 +610,9 @@ __global__ __launch_bounds__(kBlock) void k_chain_narrow(IterArgs a, int s) {
     const bool shared = (flags & 2) != 0;  // every pair of the chunk applies one factor
     const int ncol = flags >> 8;           // pairs of the chunk
     const bool rho_half = RHO && bwd;
-    double(*rho_row)[3] = RHO ? rho_sh[t.wave] : nullptr;
-    if (rho_half)
-      for (int q = t.lane; q < ncol * 3; q += 64) rho_row[q / 3][q % 3] = 0.0;
+    double v[RHO ? NC : 1][3];  // per-lane rho partials of the chunk's pairs
+#pragma unroll
+    for (int j = 0; j < (RHO ? NC : 1); ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
     const int64_t nsell = bwd ? a.nsellT : a.nsell;
     const int64_t fbytes = nsell * (int64_t)sizeof(VT), vbytes = a.ld * (int64_t)sizeof(AT);
     const BufRes rcol = buf_res(bwd ? a.colT : a.col, nsell * 4);
@@ -616,22 +629,22 @@ __global__ __launch_bounds__(kBlock) void k_chain_narrow(IterArgs a, int s) {
       const int64_t i = (t.s_begin + k) * kSlice + t.lane;
       if (shared)
         narrow_slice<VT, AT, NC, RHO, true>(a, t, ck, ncol, rcol, base, w, i, fbytes, vbytes,
-                                            rho_half, rho_row);
+                                            rho_half, v);
       else
         narrow_slice<VT, AT, NC, RHO, false>(a, t, ck, ncol, rcol, base, w, i, fbytes, vbytes,
-                                             rho_half, rho_row);
+                                             rho_half, v);
     }
     if constexpr (RHO)
       if (rho_half) {
-        __syncthreads();
-        if (threadIdx.x < ncol * 3) {
-          const int j = threadIdx.x / 3, q = threadIdx.x % 3;
-          double tot = 0.0;
+        int cols[NC];
+        unsigned valid = 0;
 #pragma unroll
-          for (int wv = 0; wv < kWavesPerBlock; ++wv) tot += rho_sh[wv][j][q];
-          a.part_rho[((int64_t)q * a.cap + ck[j].c) * a.nblk + t.blk] = tot;
+        for (int j = 0; j < NC; ++j) {
+          cols[j] = j < ncol ? ck[j].c : 0;
+          if (j < ncol) valid |= 1u << j;
         }
-        __syncthreads();  // rho_sh is cleared again by the next chunk
+        block_partials_cols<NC, 3>(a, t, cols, valid, v, a.part_rho);
+        __syncthreads();  // the shared partials are reused by the next chunk
       }
     if (y + (int)gridDim.y >= nchunks) break;
   }
