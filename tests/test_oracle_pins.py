@@ -11,7 +11,7 @@ import pytest
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from oracle import bicg, chain, gmres, job, pattern, projection, spai
+from oracle import bicg, chain, gmres, irka, job, pattern, projection, spai
 from oracle.precision import round_storage
 from paper_2003_12759_amd.workloads import laplacian_5pt, make_workload
 
@@ -528,3 +528,48 @@ def test_generator_stencil_nnz(idx, N, nnz):
     d = M.diagonal()
     off = np.asarray(abs(M).sum(axis=1)).ravel() - abs(d)
     assert np.all(d > 0) and np.all(d >= off * (1 - 1e-12))
+
+
+def test_irka_full_order_model_gives_the_mirror_poles_in_one_round():
+    """With r = n the projection keeps the whole model, so the first round's
+    mirror images are -eig(A, E) of the full pencil and the second round
+    finds them unchanged."""
+    import scipy.linalg as sla
+
+    rng = np.random.default_rng(21)
+    n = 5
+    A = sp.diags([np.full(n - 1, 1.0), -4.0 - rng.uniform(0, 1, n), np.full(n - 1, 1.0)],
+                 [-1, 0, 1]).tocsr()
+    e = rng.uniform(1, 2, n)
+    b = rng.standard_normal(n)
+    full = np.sort(-sla.eigvals(A.toarray(), np.diag(e)).real)
+    res = irka.run(A, e, b, b, [0.5, 1.0, 2.0, 3.0, 7.0], max_rounds=5, tol=1e-10)
+    assert res.status == "converged" and res.rounds == 2
+    assert np.allclose(res.sigmas, full, rtol=1e-10, atol=0)
+
+
+def test_irka_fixed_point_satisfies_the_h2_interpolation_conditions():
+    """At a converged shift set of a symmetric system with c = b the reduced
+    poles are real, their mirror images are the shifts, and H and H' are
+    interpolated there (the first-order H2-optimality conditions)."""
+    w = make_workload(2, N=6)  # variable-coefficient 7-point, symmetric, n = 216
+    b = w.B[:, 0]
+    res = irka.run(w.A, w.e, b, b, [1.0, 10.0, 100.0, 1000.0], max_rounds=200, tol=1e-11)
+    assert res.status == "converged", (res.status, res.rounds, res.change)
+    assert np.abs(res.poles.imag).max() == 0.0
+    assert np.allclose(np.sort(-res.poles.real), res.sigmas, rtol=1e-9, atol=0)
+    for s in res.sigmas:
+        H, dH = projection.full_transfer(w.A, w.e, b, b, s)
+        Hr = projection.transfer(res.Ar, res.Er, res.Br, res.Cr, s)
+        dHr = projection.transfer_derivative(res.Ar, res.Er, res.Br, res.Cr, s)
+        assert abs(Hr - H).max() <= 1e-8 * abs(H).max()
+        assert abs(dHr - dH).max() <= 1e-7 * abs(dH).max()
+
+
+def test_irka_reports_complex_reduced_poles():
+    """The nonsymmetric convection-diffusion operator gives a complex pole
+    pair in its first round: the loop stops there with status "complex"."""
+    w = make_workload(1, N=6)
+    res = irka.run(w.A, w.e, w.B[:, 0], w.C[:, 0], w.rounds[0][:6], max_rounds=5)
+    assert res.status == "complex" and res.rounds == 1
+    assert np.abs(res.poles.imag).max() > 0.0
