@@ -317,6 +317,10 @@ def main():
     ap.add_argument("--gmres", type=int, default=0,
                     help="also time the job with GMRES(this restart length) instead of BiCG "
                          "(one system at a time, the paper's solver)")
+    ap.add_argument("--irka", type=int, default=0,
+                    help="also run the IRKA-style shift loop for at most this many rounds")
+    ap.add_argument("--irka-tol", type=float, default=1e-4,
+                    help="relative change of the shifts that ends the IRKA loop")
     ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=16, help="serving: slots per system")
     ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 1.0],
@@ -501,6 +505,28 @@ def main():
               "iters_per_step": sum(x.iters for x in st_),
               "mode": "GMRES, one system at a time, same chains"}
 
+    ik = None
+    if args.irka > 0:
+        # IRKA-style loop from the workload's first-round shifts, SISO on B's
+        # first column with c = b (a symmetric operator then has real reduced
+        # poles; a complex pair ends the loop with MORX_E_UNSUPPORTED)
+        b0 = Bd[:, 0].contiguous()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st_, res = S.irka(list(w.rounds[0]), b0, b0, max_rounds=args.irka,
+                          shift_tol=args.irka_tol, prec=w.prec, tol=w.tol, raise_on_error=False)
+        torch.cuda.synchronize()
+        dt_ = time.perf_counter() - t1
+        rounds = res["rounds"]
+        r = len(w.rounds[0])
+        ik = {"status": morx.morx_status_str(st_), "rounds": rounds, "shift_tol": args.irka_tol,
+              "final_change": res["change"], "seconds": round(dt_, 3),
+              "pairs_per_s": round(rounds * r / dt_, 3) if rounds else None,
+              "shifts": [round(x, 6) for x in res["sigmas"]],
+              "iters_last_round": sum(x.iters for x in res["stats"]),
+              "mode": "IRKA (Algorithm 2 shift update), c = b, r = shifts per round"}
+        print(f"[irka] {ik['status']} rounds={rounds} {dt_:.2f} s", file=sys.stderr, flush=True)
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, apply)
 
     out = {
@@ -537,6 +563,8 @@ def main():
         out["moments"] = moments
     if gm is not None:
         out["gmres"] = gm
+    if ik is not None:
+        out["irka"] = ik
     print(json.dumps(out), flush=True)
     S.close()
     ctx.close()

@@ -237,6 +237,41 @@ morx_status morx_project(morx_system sys, int32_t r, const double* V, int64_t ld
                          double* Br, double* Cr, int32_t orthonormalize, void* stream);
 
 /*
+ * Eigenvalues of the pencil (Ar, Er) (host, column-major r x r, r <= 64):
+ * Er^{-1} Ar by LU with partial pivoting, Householder reduction to upper
+ * Hessenberg form and double-shift QR steps.  wr, wi (host, r entries)
+ * receive real and imaginary parts, ascending by real part.  MORX_E_INVALID
+ * if Er is singular, MORX_E_NOT_CONVERGED if the QR steps do not deflate.
+ */
+morx_status morx_pencil_eigvals(int32_t r, const double* Ar, const double* Er, double* wr,
+                                double* wi);
+
+/*
+ * IRKA-style outer loop with computed shifts (Algorithm 2 without its
+ * bilinear terms), SISO: b, c (dev) are n-vectors.  Round z solves the r
+ * shifted pairs at the current shifts (morx_solve_shifts with m = 1; round 1
+ * under opts->chain, RESET or NEXT_ROUND, later rounds under NEXT_ROUND, so
+ * Algorithm 4's vertical link carries the first shift's factor from round to
+ * round), projects with orthonormalised bases (morx_project) and takes the
+ * eigenvalues lambda_i of (Ar, Er); the next shifts are -lambda_i, ascending.
+ * The loop stops when the largest relative change of the shifts is <= tol
+ * (MORX_OK), after max_rounds rounds (MORX_E_NOT_CONVERGED), or when the
+ * reduced pencil has a complex pole pair (|Im| > 1e-10 max |lambda|) or
+ * repeated mirror images (MORX_E_UNSUPPORTED: the solver takes real,
+ * distinct shifts).  On return sigmas (host, r; initial shifts on entry,
+ * distinct, any order) holds the ascending shifts of the last model
+ * projected, Ar, Er (host, r x r column-major), Br, Cr (host, r) that model,
+ * poles_re/poles_im (host, r) its poles, *rounds the rounds run, *change the
+ * relative change of the poles' mirror images against sigmas, and stats (r
+ * entries, may be null) the last round's solves.
+ */
+morx_status morx_irka(morx_system sys, int32_t r, double* sigmas, const double* b,
+                      const double* c, int32_t max_rounds, double tol, const morx_opts* opts,
+                      double* Ar, double* Er, double* Br, double* Cr, double* poles_re,
+                      double* poles_im, int32_t* rounds, double* change, morx_col_stats* stats,
+                      void* stream);
+
+/*
  * Launch shapes of a system's kernels (the batching extension: the tile and
  * row-block shapes of the multi-column iteration kernels and of the
  * least-squares factor kernel); -1 selects the built-in choice.

@@ -162,6 +162,23 @@ class System:
                                            raise_on_error=raise_on_error)
         return X, Y, st, stats
 
+    def irka(self, sigmas: Sequence[float], b, c, max_rounds: int = 20, shift_tol: float = 1e-6,
+             prec: str = "f64", tol: float = 1e-10, next_round: bool = False,
+             raise_on_error: bool = True):
+        """IRKA-style loop from the initial shifts (SISO b, c); returns
+        (status, result dict) as morx.morx_irka."""
+        bd = b if isinstance(b, torch.Tensor) else torch.as_tensor(
+            np.ascontiguousarray(b, dtype=np.float64), device=self.device)
+        cd = c if isinstance(c, torch.Tensor) else torch.as_tensor(
+            np.ascontiguousarray(c, dtype=np.float64), device=self.device)
+        o = morx.morx_opts_default()
+        o.tol = tol
+        o.precond_prec = morx.PREC[prec]
+        o.chain = morx.MORX_CHAIN_NEXT_ROUND if next_round else morx.MORX_CHAIN_RESET
+        return morx.morx_irka(self.handle, sigmas, bd.reshape(-1).contiguous(),
+                              cd.reshape(-1).contiguous(), max_rounds, shift_tol, o,
+                              raise_on_error=raise_on_error)
+
     def autotune(self, sigma: float, ncols: int, chain_len: int = 1, prec: str = "f64") -> dict:
         """Time the launch-shape candidates on this system and keep the fastest."""
         return morx.morx_autotune(self.handle, sigma, ncols, chain_len, prec)

@@ -108,6 +108,13 @@ _SIG = {
     "morx_project": (_i32, [_p, _i32, _p, _i64, _p, _i64, _i32, _p, _i64, _i32, _p, _i64,
                             ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
                             ctypes.POINTER(_d), _i32, _p]),
+    "morx_pencil_eigvals": (_i32, [_i32, ctypes.POINTER(_d), ctypes.POINTER(_d),
+                                   ctypes.POINTER(_d), ctypes.POINTER(_d)]),
+    "morx_irka": (_i32, [_p, _i32, ctypes.POINTER(_d), _p, _p, _i32, _d, ctypes.POINTER(morx_opts),
+                         ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
+                         ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
+                         ctypes.POINTER(_i32), ctypes.POINTER(_d), ctypes.POINTER(morx_col_stats),
+                         _p]),
     "morx_system_get_tune": (_i32, [_p, ctypes.POINTER(morx_tune)]),
     "morx_system_set_tune": (_i32, [_p, ctypes.POINTER(morx_tune)]),
     "morx_autotune": (_i32, [_p, _d, _i32, _i32, _i32, ctypes.POINTER(morx_tune), _p]),
@@ -395,6 +402,59 @@ def morx_project(sys: int, V: torch.Tensor, W: torch.Tensor, B: Optional[torch.T
         return np.frombuffer(buf, dtype=np.float64, count=rows * cols).reshape(cols, rows).T.copy()
 
     return mat(Ar, r, r), mat(Er, r, r), mat(Br, r, m), mat(Cr, r, q)
+
+
+def morx_pencil_eigvals(Ar, Er):
+    """Eigenvalues of the pencil (Ar, Er) (numpy r x r arrays): (wr, wi),
+    ascending by real part."""
+    import numpy as np
+
+    Ar = np.asarray(Ar, dtype=np.float64)
+    Er = np.asarray(Er, dtype=np.float64)
+    r = Ar.shape[0]
+    a = (_d * (r * r))(*Ar.T.ravel().tolist())
+    e = (_d * (r * r))(*Er.T.ravel().tolist())
+    wr = (_d * r)()
+    wi = (_d * r)()
+    _check(_lib.morx_pencil_eigvals(r, a, e, wr, wi), "morx_pencil_eigvals")
+    return np.array(wr[:]), np.array(wi[:])
+
+
+def morx_irka(sys: int, sigmas: Sequence[float], b: torch.Tensor, c: torch.Tensor,
+              max_rounds: int = 20, tol: float = 1e-6, opts: Optional[morx_opts] = None,
+              stream=None, raise_on_error: bool = True):
+    """Returns (status, dict): sigmas, Ar, Er, Br, Cr, poles (complex), rounds,
+    change, stats (the last round's)."""
+    import numpy as np
+
+    if opts is None:
+        opts = morx_opts_default()
+    r = len(sigmas)
+    if b.dim() != 1 or c.dim() != 1 or not b.is_contiguous() or not c.is_contiguous():
+        raise ValueError("b and c must be contiguous device vectors")
+    sig = (_d * r)(*[float(x) for x in sigmas])
+    Ar = (_d * (r * r))()
+    Er = (_d * (r * r))()
+    Br = (_d * r)()
+    Cr = (_d * r)()
+    pr = (_d * r)()
+    pi = (_d * r)()
+    rounds = _i32(0)
+    change = _d(0.0)
+    stats = (morx_col_stats * r)()
+    st = _lib.morx_irka(sys, r, sig, b.data_ptr(), c.data_ptr(), int(max_rounds), float(tol),
+                        ctypes.byref(opts), Ar, Er, Br, Cr, pr, pi, ctypes.byref(rounds),
+                        ctypes.byref(change), stats, _stream(stream))
+    if raise_on_error and st != MORX_OK:
+        raise MorxError(st, "morx_irka")
+
+    def mat(buf, rows, cols):
+        return np.frombuffer(buf, dtype=np.float64, count=rows * cols).reshape(cols, rows).T.copy()
+
+    return st, {"sigmas": np.array(sig[:]), "Ar": mat(Ar, r, r), "Er": mat(Er, r, r),
+                "Br": np.array(Br[:]).reshape(r, 1), "Cr": np.array(Cr[:]).reshape(r, 1),
+                "poles": np.array(pr[:]) + 1j * np.array(pi[:]), "rounds": rounds.value,
+                "change": change.value, "stats": list(stats)}
 
 
 def morx_trace_enable(ctx: int, enable: bool) -> None:
