@@ -584,11 +584,23 @@ __device__ __forceinline__ void narrow_slice(const IterArgs& a, const WaveCtx& t
   };
   // pair j+1's loads are issued before pair j's sums (two buffers alternate)
   issue(0, 0);
+  if constexpr (NC <= 8) {
 #pragma unroll
-  for (int j = 0; j < NC; ++j) {
-    if (j >= ncol) break;
-    if (j + 1 < ncol) issue(j + 1, (j + 1) & 1);
-    finish(j, j & 1);
+    for (int j = 0; j < NC; ++j) {
+      if (j >= ncol) break;
+      if (j + 1 < ncol) issue(j + 1, (j + 1) & 1);
+      finish(j, j & 1);
+    }
+  } else {
+    // wide tiles: uniform guards rather than an early exit, so that the loop
+    // still unrolls completely and the buffers stay in registers
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      if (j < ncol) {
+        if (j + 1 < ncol) issue(j + 1, (j + 1) & 1);
+        finish(j, j & 1);
+      }
+    }
   }
 }
 

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_chol(const double* __restrict__ G, int 
   }
   __syncthreads();
   const double shift = shift_coef * tr;
-  if (threadIdx.x < r) a[threadIdx.x + threadIdx.x * r] += shift;
+  if ((int)threadIdx.x < r) a[threadIdx.x + threadIdx.x * r] += shift;
   __syncthreads();
   // column-major a; compute upper R in place (R[i][j] at a[i + j*r], i <= j)
   for (int k = 0; k < r; ++k) {
