@@ -34,22 +34,24 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_chain_step_convdiff3d_n26
 
 
 def kernel_source_hash() -> str:
-    """sha256 of the sources of the iteration kernels (bicg.hip, common.h)."""
+    """sha256 of the sources of the iteration kernels (bicg.hip, chain_kernels.h,
+    common.h)."""
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("bicg.hip", "common.h"):
+    for f in ("bicg.hip", "chain_kernels.h", "common.h"):
         with open(os.path.join(ROOT, "paper_2003_12759_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def chain_kernel_name(A, vt: str, at: str, ncol: int, ncmax: int) -> str:
+def chain_kernel_name(A, vt: str, at: str, ncol: int, ncmax: int, halo: bool) -> str:
     """Instance of the chain step the library launches for this batch: the
     narrow variant when every row of S = pattern(A) + diagonal and of S^T
-    has at most 8 entries, at the tile width of the library's column split
-    (equal chunks of at most ncmax columns, rounded up to an instantiated
-    width)."""
+    has at most 8 entries, else the halo variant when the system uses it
+    (`halo`, from the tune the library reports) or the general one, at the
+    tile width of the library's column split (equal chunks of at most ncmax
+    columns, rounded up to an instantiated width)."""
     import numpy as np
     import scipy.sparse as sp
 
@@ -61,7 +63,7 @@ def chain_kernel_name(A, vt: str, at: str, ncol: int, ncmax: int) -> str:
     chunks = -(-ncol // ncmax)
     nc = -(-ncol // chunks)
     nc = nc if nc <= 8 else (10 if nc <= 10 else (12 if nc <= 12 else 16))
-    kind = "k_chain_narrow" if width <= 8 else "k_chain_step"
+    kind = "k_chain_narrow" if width <= 8 else ("k_chain_halo" if halo else "k_chain_step")
     return f"{kind}<{vt}, {at}, {nc}>"
 
 
@@ -307,7 +309,8 @@ def main():
                     help="keep the built-in launch shapes instead of timing candidates first")
     ap.add_argument("--shapes", default=None,
                     help="pin the launch shapes instead of autotuning: "
-                         "factor_kernel,cols_per_wave,slices_per_wave[,spmv_cols_per_wave]")
+                         "factor_kernel,cols_per_wave,slices_per_wave"
+                         "[,spmv_cols_per_wave[,chain_kernel]]")
     ap.add_argument("--compare-policies", action="store_true",
                     help="also time the comparator schedules: a SPAI per shift, and "
                          "Table 2's first approach")
@@ -358,9 +361,9 @@ def main():
     # one-time cost per system, like building it)
     tuned = None
     if args.shapes:
-        sh = [int(x) for x in args.shapes.split(",")] + [-1]
+        sh = [int(x) for x in args.shapes.split(",")] + [-1, -1]
         S.set_tune(factor_kernel=sh[0], cols_per_wave=sh[1], slices_per_wave=sh[2],
-                   spmv_cols_per_wave=sh[3])
+                   spmv_cols_per_wave=sh[3], chain_kernel=sh[4])
         tuned = dict(S.get_tune(), pinned=True)
     elif not args.no_autotune:
         t_tune = time.perf_counter()
@@ -420,8 +423,9 @@ def main():
         achieved = byts / (ms * 1e-3) / 1e9
         ncol = len(w.rounds[0]) * w.B.shape[1]
         ctype = {"f64": "double", "f32": "float", "bf16": "unsigned short"}
-        ncmax = S.get_tune()["cols_per_wave"]
-        roof_kernel = chain_kernel_name(w.A, ctype[w.prec], ctype[apply], ncol, ncmax)
+        tune_now = S.get_tune()
+        roof_kernel = chain_kernel_name(w.A, ctype[w.prec], ctype[apply], ncol,
+                                        tune_now["cols_per_wave"], tune_now["chain_kernel"] == 1)
         traffic = None
         if os.path.exists(TRAFFIC_FILE):
             with open(TRAFFIC_FILE) as f:

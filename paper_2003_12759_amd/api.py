@@ -184,9 +184,10 @@ class System:
         return morx.morx_autotune(self.handle, sigma, ncols, chain_len, prec)
 
     def set_tune(self, factor_kernel: int = -1, cols_per_wave: int = -1,
-                 slices_per_wave: int = -1, spmv_cols_per_wave: int = -1) -> None:
+                 slices_per_wave: int = -1, spmv_cols_per_wave: int = -1,
+                 chain_kernel: int = -1) -> None:
         morx.morx_system_set_tune(self.handle, factor_kernel, cols_per_wave, slices_per_wave,
-                                  spmv_cols_per_wave)
+                                  spmv_cols_per_wave, chain_kernel)
 
     def get_tune(self) -> dict:
         return morx.morx_system_get_tune(self.handle)

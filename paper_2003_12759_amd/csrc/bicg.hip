@@ -31,14 +31,9 @@
 
 #include <hip/hip_ext.h>
 
+#include "chain_kernels.h"
 #include "krylov.h"
 
-// FP64 Krylov vectors of a slot
-enum Vec : int { V_X, V_XT, V_R, V_RT, V_P0, V_P1, V_PT0, V_PT1, V_Q, V_QT, kNumVec };
-// vectors of the preconditioner apply, in the apply precision: z, z~, the
-// ping-pong intermediates of both chains and (FP32 apply only) the rounded
-// copies of r, r~ that the first factor pass reads
-enum ApplyVec : int { A_Z, A_ZT, A_T0, A_T1, A_TT0, A_TT1, A_R, A_RT };
 static int apply_vecs(int aprec) { return aprec == MORX_F64 ? 6 : 8; }
 
 // trace counters (algorithmic bytes per kernel class)
@@ -47,216 +42,6 @@ enum TraceClass : int {
 };
 
 namespace {
-
-constexpr int kMaxNC = 16;         // columns per wave (tuned)
-constexpr int kDefaultNC = 8;      // columns per wave without tuning
-constexpr int kMaxBlocks = 1024;   // row blocks per launch (partials per column)
-constexpr int kWavesPerBlock = 4;
-constexpr int kBlock = 64 * kWavesPerBlock;
-constexpr int kFinThreads = 1024;  // finalize kernels: one wave per column
-constexpr double kBreakdown = 1e-14;
-
-// Launch geometry shared by every iteration kernel.  A block has four waves;
-// each wave owns spw consecutive 64-row slices and handles the NC columns
-// blockIdx.y * NC ... of the batch on them, so index and value loads of the
-// matrix or factor are shared by all NC columns.  Block indices are remapped
-// so that consecutive row ranges run on one XCD (workgroups are dealt to the
-// 8 XCDs round robin), keeping a range's stencil neighbours in that XCD's L2.
-// one (half, column) pair of a chain step: the factor it applies and the
-// vectors it reads and writes
-struct ChainItem {
-  const void* fv;   // factor values, forward or transposed order
-  const void* src;  // input (apply precision)
-  void* dst;        // output (apply precision)
-  int32_t c;        // column slot; -1: padding or past the list
-  // bit 0: transposed chain on the rows of S^T; on the first pair of a chunk
-  // also bit 1: every pair of the chunk applies the same factor, and bits
-  // 8 and up: pairs in the chunk
-  int32_t flags;
-};
-
-struct IterArgs {
-  int64_t n, ld, nnzS, nslices;
-  int64_t nsell, nsellT;  // entries of the sliced-ELL arrays of S and S^T
-  int cap, nc, nblk, spw, vbytes, maxL, lcap;
-  int ncmax;       // most columns per wave, chain step
-  int ncmax_spmv;  // most columns per wave, shifted pair and true residual
-  int ncv;         // chain tile width of this launch sequence
-  int ymax;        // chain launches: chunks of ncv (half, column) pairs in the grid
-  int plan_ld;     // work-list entries per step
-  int narrow;      // every slice of S and S^T at most kNarrow slots wide
-  const int32_t *off, *col, *offT, *colT;
-  const double *valA, *valAT, *e;
-  double* vec;
-  void* avec;    // apply vectors (element type double or float)
-  int abytes;    // 8 or 4
-  ColInfo* cols;
-  const void* const* ftab;  // [2][cap][lcap]: factor values, forward then transposed order
-  double* part_rho;    // [3][cap][nblk]
-  double* part_delta;  // [3][cap][nblk]
-  double* part_norm;   // [2][cap][nblk]
-  double* trace;       // [kTraceClasses] or null
-  ChainItem* plan;     // [lcap][plan_ld] work lists of the chain steps
-  int32_t* plan_cnt;   // [lcap] chunks per step
-};
-
-__device__ __forceinline__ double* vptr(const IterArgs& a, int slot, int c) {
-  return a.vec + ((int64_t)slot * a.cap + c) * a.ld;
-}
-
-template <typename AT>
-__device__ __forceinline__ AT* aptr(const IterArgs& a, int slot, int c) {
-  return (AT*)a.avec + ((int64_t)slot * a.cap + c) * a.ld;
-}
-
-// the FP32 copies of r and r~ (apply precision FP32 only)
-__device__ __forceinline__ void store_rcopy(const IterArgs& a, int c, int64_t i, double ri,
-                                            double rti) {
-  if (a.abytes == 4) {
-    aptr<float>(a, A_R, c)[i] = (float)ri;
-    aptr<float>(a, A_RT, c)[i] = (float)rti;
-  }
-}
-
-struct WaveCtx {
-  int lane, wave, blk;
-  int64_t s_begin, s_end;
-};
-
-__device__ __forceinline__ WaveCtx wave_ctx(const IterArgs& a) {
-  WaveCtx t;
-  t.wave = threadIdx.x >> 6;
-  t.lane = threadIdx.x & 63;
-  const int per_xcd = a.nblk >> 3;  // nblk is a multiple of 8
-  t.blk = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  t.s_begin = ((int64_t)t.blk * kWavesPerBlock + t.wave) * a.spw;
-  t.s_end = min(a.nslices, t.s_begin + a.spw);
-  return t;
-}
-
-// ---- reductions --------------------------------------------------------------
-
-// Sum NQ per-lane values of each of the NC columns over the block and store
-// one partial per (quantity, column, block).  Every thread calls it.
-template <int NC, int NQ>
-__device__ void block_partials_cols(const IterArgs& a, const WaveCtx& t, const int (&cols)[NC],
-                                    unsigned valid, double (&v)[NC][NQ], double* part) {
-  __shared__ double sh[kWavesPerBlock][NC][NQ];
-#pragma unroll
-  for (int j = 0; j < NC; ++j)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const double s = wave_sum(v[j][q]);
-      if (t.lane == 0) sh[t.wave][j][q] = s;
-    }
-  __syncthreads();
-  if (threadIdx.x < NC * NQ) {
-    const int j = threadIdx.x / NQ, q = threadIdx.x % NQ;
-    if (valid & (1u << j)) {
-      double tot = 0.0;
-#pragma unroll
-      for (int w = 0; w < kWavesPerBlock; ++w) tot += sh[w][j][q];
-      part[((int64_t)q * a.cap + cols[j]) * a.nblk + t.blk] = tot;
-    }
-  }
-}
-
-// the same for the columns c0 ... c0 + NC - 1
-template <int NC, int NQ>
-__device__ void block_partials(const IterArgs& a, const WaveCtx& t, int c0, unsigned valid,
-                               double (&v)[NC][NQ], double* part) {
-  int cols[NC];
-#pragma unroll
-  for (int j = 0; j < NC; ++j) cols[j] = c0 + j;
-  block_partials_cols<NC, NQ>(a, t, cols, valid, v, part);
-}
-
-// One wave sums the nblk partials of NQ quantities of column c, every load of
-// the column issued before the first add (nblk <= 1024: 16 per lane and
-// quantity), then a fixed-order reduction.
-template <int NQ>
-__device__ __forceinline__ void wave_totals(const IterArgs& a, const double* part, int c,
-                                            double (&out)[NQ]) {
-  const int lane = threadIdx.x & 63;
-  double v[NQ][kMaxBlocks / 64];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const double* p = part + ((int64_t)q * a.cap + c) * a.nblk;
-#pragma unroll
-    for (int k = 0; k < kMaxBlocks / 64; ++k) {
-      const int b = lane + 64 * k;
-      v[q][k] = b < a.nblk ? p[b] : 0.0;
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < kMaxBlocks / 64; ++k) s += v[q][k];
-    out[q] = wave_sum(s);
-  }
-}
-
-__device__ __forceinline__ bool passed(const ColInfo& ci, double rr, double rtrt) {
-  return (!ci.check_p || sqrt(rr) <= ci.tol * ci.nb) && (!ci.check_d || sqrt(rtrt) <= ci.tol * ci.nc);
-}
-
-__device__ __forceinline__ bool stopped(int st) {
-  return st == COL_CONVERGED || st == COL_BREAKDOWN || st == COL_MAXIT;
-}
-
-// Slots of a slice are processed kUnroll at a time: the index and value loads
-// of a chunk are issued together, then every column's gathers for the chunk.
-constexpr int kUnroll = 8;
-
-struct SliceChunk {
-  int32_t c[kUnroll];
-  int32_t w;  // slots of the slice
-};
-
-template <typename VT>
-__device__ __forceinline__ void load_chunk(const int32_t* __restrict__ col,
-                                           const VT* __restrict__ val, int32_t p0, int32_t w,
-                                           int32_t m0, SliceChunk& ch, double (&v)[kUnroll]) {
-#pragma unroll
-  for (int u = 0; u < kUnroll; ++u) {
-    const bool ok = m0 + u < w;
-    const int32_t p = p0 + (ok ? (m0 + u) * kSlice : 0);
-    ch.c[u] = col[p];
-    v[u] = ok ? load_val<VT>(val + p) : 0.0;
-  }
-}
-
-template <typename XT>
-__device__ __forceinline__ double chunk_dot(const SliceChunk& ch, const double (&v)[kUnroll],
-                                            int32_t m0, int32_t w, const XT* __restrict__ x,
-                                            double acc) {
-  double g[kUnroll];
-#pragma unroll
-  for (int u = 0; u < kUnroll; ++u) g[u] = (double)x[ch.c[u]];
-#pragma unroll
-  for (int u = 0; u < kUnroll; ++u) acc = (m0 + u < w) ? fma(v[u], g[u], acc) : acc;
-  return acc;
-}
-
-// the same with p = z + beta * p_old formed at every gathered index
-template <typename AT>
-__device__ __forceinline__ double chunk_dot_p(const SliceChunk& ch, const double (&v)[kUnroll],
-                                              int32_t m0, int32_t w, const AT* __restrict__ z,
-                                              const double* __restrict__ po, double beta,
-                                              bool first, double acc) {
-  double g[kUnroll];
-  if (first) {
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) g[u] = (double)z[ch.c[u]];
-  } else {
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) g[u] = fma(beta, po[ch.c[u]], (double)z[ch.c[u]]);
-  }
-#pragma unroll
-  for (int u = 0; u < kUnroll; ++u) acc = (m0 + u < w) ? fma(v[u], g[u], acc) : acc;
-  return acc;
-}
 
 // ---- kernels -------------------------------------------------------------------
 
@@ -306,359 +91,6 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_init(IterArgs a) {
       ci.it_cycle = 0;
       ci.state = COL_ACTIVE;
     }
-  }
-}
-
-// One chain step s applies, for every column whose chain is long enough,
-// factor s of the forward chain on the rows of S and factor maxL-1-s of the
-// transposed chain on the rows of S^T; the last step also forms the partial
-// sums of rho = z~^T r, ||z~||^2, ||r||^2.  The (half, column) pairs that
-// have work at a step come from the step's work list, built on the device by
-// the one-block kernels before the iteration (build_plan): blockIdx.y picks a
-// chunk of NC pairs of one half, so no block is launched for a column whose
-// chain is shorter than the step, and columns of a chunk that apply the same
-// factor share its value loads.
-// AT is the apply precision: each pass sums in FP64 and stores its result
-// rounded to AT; with AT = float the first pass reads the FP32 copy of r.
-
-// Offsets of slots past a slice's width point past every array, so their
-// loads return 0 without a memory access and add 0 to the row sums.
-constexpr uint32_t kOutside = 0xfffffff0u;
-
-// Slots per chunk of the product loops: every index, value and gather load of
-// a chunk is issued before its first use; wide tiles take shorter chunks to
-// stay within the register budget.
-template <int NC>
-struct ChunkLen {
-  static constexpr int value = NC <= 4 ? 8 : (NC <= 8 ? 4 : 2);
-};
-
-// RHO: the iteration's last chain launch, whose transposed half also forms
-// the partial sums of rho (a separate instantiation, so the other launches
-// do not hold those accumulators in registers)
-template <typename VT, typename AT, int NC, bool RHO>
-__global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s) {
-  constexpr int kU = ChunkLen<NC>::value;
-  const WaveCtx t = wave_ctx(a);
-  const ChainItem* plan = a.plan + (int64_t)s * a.plan_ld;
-  const int nchunks = gld(a.plan_cnt + s);
-  const int nsl = (int)max<int64_t>(t.s_end - t.s_begin, 0);
-  // slice starts of the wave's slices, lane l holding slice s_begin + wb + l
-  // for both orders (a window of 64, refilled as the wave moves past it)
-  const int wl = min(t.lane, nsl);
-  int32_t owF = nsl > 0 ? gld(a.off + t.s_begin + wl) : 0;
-  int32_t owB = nsl > 0 ? gld(a.offT + t.s_begin + wl) : 0;
-  for (int y = blockIdx.y;; y += gridDim.y) {
-    ChainItem it[NC];
-#pragma unroll
-    for (int j = 0; j < NC; ++j) it[j] = plan[y * NC + j];
-    if (it[0].c < 0) break;  // past the last chunk (uniform over the block)
-    const bool bwd = (it[0].flags & 1) != 0;
-    const bool rho_half = RHO && bwd;
-    unsigned valid = 0;
-    const AT* src[NC];
-    AT* dst[NC];
-    const VT* fv[NC];
-    bool shared = true;
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      const bool on = it[j].c >= 0;  // padding at the end of a half's list
-      if (on) valid |= 1u << j;
-      // padding runs along with the chunk's first pair (cache hits, results
-      // dropped), so the slot loop has no per-column branch
-      src[j] = (const AT*)(on ? it[j].src : it[0].src);
-      dst[j] = (AT*)it[j].dst;
-      fv[j] = (const VT*)(on ? it[j].fv : it[0].fv);
-      shared = shared && fv[j] == (const VT*)it[0].fv;
-    }
-    const VT* fv0 = (const VT*)it[0].fv;
-    const int32_t* off = bwd ? a.offT : a.off;
-    const int32_t* col = bwd ? a.colT : a.col;
-    int32_t ow = bwd ? owB : owF;
-    int wb = 0;
-    double v[RHO ? NC : 1][3];
-#pragma unroll
-    for (int j = 0; j < (RHO ? NC : 1); ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
-    if (nsl > 0) {
-      // bounds of relative slice k; refills the window so that k and k+1 are in it
-      auto bounds = [&](int k, int32_t& base, int32_t& w) {
-        if (k + 1 - wb > 63) {
-          wb = k;
-          ow = gld(off + t.s_begin + wb + min(t.lane, nsl - wb));
-        }
-        base = __shfl(ow, k - wb, 64);
-        w = (__shfl(ow, k + 1 - wb, 64) - base) >> 6;
-      };
-      // (slice, chunk) cursor over the wave's slices; the column indices of
-      // the next chunk, possibly in the next slice, are loaded while the
-      // current chunk's values and gathers are in flight
-      int k = 0, m0 = 0;
-      int32_t base, w;
-      bounds(0, base, w);
-      int32_t nix[kU];
-#pragma unroll
-      for (int u = 0; u < kU; ++u) nix[u] = gld(col + base + t.lane + (u < w ? u * kSlice : 0));
-      double acc[NC];
-#pragma unroll
-      for (int j = 0; j < NC; ++j) acc[j] = 0.0;
-      while (true) {
-        const int32_t p0 = base + t.lane;
-        int32_t pp[kU], cix[kU];
-        bool ok[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          ok[u] = m0 + u < w;
-          pp[u] = p0 + (ok[u] ? (m0 + u) * kSlice : 0);  // past the row: slot 0, value dropped
-          cix[u] = nix[u];
-        }
-        int k2 = k, m2 = m0 + kU;
-        int32_t base2 = base, w2 = w;
-        if (m2 >= w) {
-          k2 = k + 1;
-          m2 = 0;
-          if (k2 < nsl) bounds(k2, base2, w2);
-        }
-        if (k2 < nsl) {
-#pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            const int32_t mn = m2 + u;
-            nix[u] = gld(col + base2 + t.lane + (mn < w2 ? mn * kSlice : 0));
-          }
-        }
-        if (shared) {
-          double vv[kU];
-#pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            const double raw = gload_val<VT>(fv0 + pp[u]);
-            vv[u] = ok[u] ? raw : 0.0;
-          }
-#pragma unroll
-          for (int j = 0; j < NC; ++j)
-#pragma unroll
-            for (int u = 0; u < kU; ++u) acc[j] = fma(vv[u], (double)gld(src[j] + cix[u]), acc[j]);
-        } else {
-#pragma unroll
-          for (int j = 0; j < NC; ++j)
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-              const double raw = gload_val<VT>(fv[j] + pp[u]);
-              acc[j] = fma(ok[u] ? raw : 0.0, (double)gld(src[j] + cix[u]), acc[j]);
-            }
-        }
-        if (m2 == 0) {  // slice k done
-          const int64_t i = (t.s_begin + k) * kSlice + t.lane;
-          if (i < a.n) {
-#pragma unroll
-            for (int j = 0; j < NC; ++j)
-              if (valid & (1u << j)) {
-                const AT zs = (AT)acc[j];
-                gst(dst[j] + i, zs);
-                if constexpr (RHO) {
-                  if (rho_half) {
-                    const double zi = (double)zs;
-                    const double ri = gld(vptr(a, V_R, it[j].c) + i);
-                    v[j][0] = fma(zi, ri, v[j][0]);
-                    v[j][1] = fma(zi, zi, v[j][1]);
-                    v[j][2] = fma(ri, ri, v[j][2]);
-                  }
-                }
-              }
-          }
-#pragma unroll
-          for (int j = 0; j < NC; ++j) acc[j] = 0.0;
-          if (k2 >= nsl) break;
-        }
-        k = k2;
-        m0 = m2;
-        base = base2;
-        w = w2;
-      }
-    }
-    if constexpr (RHO)
-      if (rho_half) {
-        int cols[NC];
-#pragma unroll
-        for (int j = 0; j < NC; ++j) cols[j] = it[j].c;
-        block_partials_cols<NC, 3>(a, t, cols, valid, v, a.part_rho);
-      }
-    if (y + (int)gridDim.y >= nchunks) break;
-  }
-}
-
-// The chain step for patterns whose slices are at most kNarrow slots wide
-// (stencils with up to eight entries per row).  Per slice the column indices
-// (and a chunk's shared factor values) stay in registers while the chunk's
-// pairs run one after the other, two gather buffers alternating so that
-// pair j+1's gathers are in flight during pair j's sums.  Registers do not
-// grow with the tile width, and a wide tile reads the slice's indices and
-// values once for all its pairs.  Slots past a slice's width are not loaded;
-// each row sums its slots in order from zero, as the general kernel does.
-// The rho partials (last step) are summed per lane over the wave's slices
-// and then over the block, as in the general kernel.
-constexpr int kNarrow = 8;
-
-// A pointer every lane holds the same value of, kept in scalar registers
-// (a buffer descriptor built from a vector register would need a loop over
-// its distinct values)
-template <typename T>
-__device__ __forceinline__ T* uniform(T* p) {
-  const uint64_t v = (uint64_t)p;
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return (T*)(((uint64_t)hi << 32) | lo);
-}
-
-template <typename VT>
-using NarrowVal = typename std::conditional<sizeof(VT) == 8, double, float>::type;
-
-template <typename VT>
-__device__ __forceinline__ NarrowVal<VT> buf_raw(BufRes r, uint32_t off);
-template <>
-__device__ __forceinline__ double buf_raw<double>(BufRes r, uint32_t off) {
-  return buf_val<double>(r, off);
-}
-template <>
-__device__ __forceinline__ float buf_raw<float>(BufRes r, uint32_t off) {
-  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
-}
-template <>
-__device__ __forceinline__ float buf_raw<uint16_t>(BufRes r, uint32_t off) {
-  return __uint_as_float(((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0)) << 16);
-}
-
-template <typename VT, typename AT, int NC, bool RHO, bool SHARED>
-__device__ __forceinline__ void narrow_slice(const IterArgs& a, const WaveCtx& t,
-                                             const ChainItem* ck, int ncol, BufRes rcol,
-                                             int32_t base, int w, int64_t i, int64_t fbytes,
-                                             int64_t vbytes, bool rho_half,
-                                             double (&v)[RHO ? NC : 1][3]) {
-  using FT = NarrowVal<VT>;
-  constexpr uint32_t kVB = sizeof(VT), kAB = sizeof(AT);
-  const uint32_t oi = (uint32_t)(base + t.lane) * 4u;
-  const uint32_t ov = (uint32_t)(base + t.lane) * kVB;
-  uint32_t go[kNarrow], fo[kNarrow];  // byte offsets of the gathers and of the values
-#pragma unroll
-  for (int u = 0; u < kNarrow; ++u) {
-    const bool in = u < w;
-    go[u] = (uint32_t)buf_i32(rcol, in ? oi + u * kSlice * 4 : kOutside);
-    fo[u] = in ? ov + u * kSlice * kVB : kOutside;
-  }
-#pragma unroll
-  for (int u = 0; u < kNarrow; ++u) go[u] = u < w ? go[u] * kAB : kOutside;
-  FT fb[SHARED ? 1 : 2][kNarrow];
-  AT gb[2][kNarrow];
-  double rb[2] = {0.0, 0.0};  // r_i of the pair (rho partials, last step only)
-  auto issue = [&](int j, int q) {
-    const ChainItem* e = ck + j;
-    if (!SHARED || j == 0) {
-      const BufRes rf = buf_res(uniform(e->fv), fbytes);
-#pragma unroll
-      for (int u = 0; u < kNarrow; ++u) fb[SHARED ? 0 : q][u] = buf_raw<VT>(rf, fo[u]);
-    }
-    const BufRes rs = buf_res(uniform(e->src), vbytes);
-#pragma unroll
-    for (int u = 0; u < kNarrow; ++u) gb[q][u] = (AT)buf_val<AT>(rs, go[u]);
-    if constexpr (RHO) {
-      const double* rp = vptr(a, V_R, __builtin_amdgcn_readfirstlane(e->c));
-      if (rho_half && i < a.n) rb[q] = gld(rp + i);
-    }
-  };
-  auto finish = [&](int j, int q) {
-    double acc = 0.0;
-#pragma unroll
-    for (int u = 0; u < kNarrow; ++u)
-      acc = fma((double)fb[SHARED ? 0 : q][u], (double)gb[q][u], acc);
-    AT* dst = (AT*)uniform(ck[j].dst);
-    const AT zs = (AT)acc;
-    if (i < a.n) gst(dst + i, zs);
-    if constexpr (RHO) {
-      if (rho_half) {
-        if (i < a.n) {
-          const double zi = (double)zs, ri = rb[q];
-          v[j][0] = fma(zi, ri, v[j][0]);
-          v[j][1] = fma(zi, zi, v[j][1]);
-          v[j][2] = fma(ri, ri, v[j][2]);
-        }
-      }
-    }
-  };
-  // pair j+1's loads are issued before pair j's sums (two buffers alternate)
-  issue(0, 0);
-  if constexpr (NC <= 8) {
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      if (j >= ncol) break;
-      if (j + 1 < ncol) issue(j + 1, (j + 1) & 1);
-      finish(j, j & 1);
-    }
-  } else {
-    // wide tiles: uniform guards rather than an early exit, so that the loop
-    // still unrolls completely and the buffers stay in registers
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      if (j < ncol) {
-        if (j + 1 < ncol) issue(j + 1, (j + 1) & 1);
-        finish(j, j & 1);
-      }
-    }
-  }
-}
-
-template <typename VT, typename AT, int NC, bool RHO>
-__global__ __launch_bounds__(kBlock) void k_chain_narrow(IterArgs a, int s) {
-  const WaveCtx t = wave_ctx(a);
-  const ChainItem* plan = a.plan + (int64_t)s * a.plan_ld;
-  const int nchunks = gld(a.plan_cnt + s);
-  const int nsl = (int)max<int64_t>(t.s_end - t.s_begin, 0);
-  const int wl = min(t.lane, nsl);
-  const int32_t owF = nsl > 0 ? gld(a.off + t.s_begin + wl) : 0;
-  const int32_t owB = nsl > 0 ? gld(a.offT + t.s_begin + wl) : 0;
-  for (int y = blockIdx.y;; y += gridDim.y) {
-    const ChainItem* ck = plan + (int64_t)y * NC;
-    const int c0 = ck->c;
-    if (c0 < 0) break;  // past the last chunk (uniform over the block)
-    const int flags = ck->flags;
-    const bool bwd = (flags & 1) != 0;
-    const bool shared = (flags & 2) != 0;  // every pair of the chunk applies one factor
-    const int ncol = flags >> 8;           // pairs of the chunk
-    const bool rho_half = RHO && bwd;
-    double v[RHO ? NC : 1][3];  // per-lane rho partials of the chunk's pairs
-#pragma unroll
-    for (int j = 0; j < (RHO ? NC : 1); ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
-    const int64_t nsell = bwd ? a.nsellT : a.nsell;
-    const int64_t fbytes = nsell * (int64_t)sizeof(VT), vbytes = a.ld * (int64_t)sizeof(AT);
-    const BufRes rcol = buf_res(bwd ? a.colT : a.col, nsell * 4);
-    const int32_t* off = bwd ? a.offT : a.off;
-    int32_t ow = bwd ? owB : owF;
-    int wb = 0;
-    for (int k = 0; k < nsl; ++k) {
-      if (k + 1 - wb > 63) {  // keep slices k and k+1 in the window
-        wb = k;
-        ow = gld(off + t.s_begin + wb + min(t.lane, nsl - wb));
-      }
-      const int32_t base = __builtin_amdgcn_readfirstlane(__shfl(ow, k - wb, 64));
-      const int w = (__builtin_amdgcn_readfirstlane(__shfl(ow, k + 1 - wb, 64)) - base) >> 6;
-      const int64_t i = (t.s_begin + k) * kSlice + t.lane;
-      if (shared)
-        narrow_slice<VT, AT, NC, RHO, true>(a, t, ck, ncol, rcol, base, w, i, fbytes, vbytes,
-                                            rho_half, v);
-      else
-        narrow_slice<VT, AT, NC, RHO, false>(a, t, ck, ncol, rcol, base, w, i, fbytes, vbytes,
-                                             rho_half, v);
-    }
-    if constexpr (RHO)
-      if (rho_half) {
-        int cols[NC];
-        unsigned valid = 0;
-#pragma unroll
-        for (int j = 0; j < NC; ++j) {
-          cols[j] = j < ncol ? ck[j].c : 0;
-          if (j < ncol) valid |= 1u << j;
-        }
-        block_partials_cols<NC, 3>(a, t, cols, valid, v, a.part_rho);
-        __syncthreads();  // the shared partials are reused by the next chunk
-      }
-    if (y + (int)gridDim.y >= nchunks) break;
   }
 }
 
@@ -1445,6 +877,15 @@ static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   a.nsell = sys->sell.nnz_sell;
   a.nsellT = sys->sellT.nnz_sell;
   a.narrow = std::max(sys->sell.max_width, sys->sellT.max_width) <= kNarrow;
+  a.hmax = (!a.narrow && sys->tune_chain != 0 && sys->sell.hmax > 0 && sys->sellT.hmax > 0)
+               ? std::max(sys->sell.hmax, sys->sellT.hmax)
+               : 0;
+  a.hoff = sys->sell.hoff;
+  a.hcol = sys->sell.hcol;
+  a.lidx = sys->sell.lidx;
+  a.hoffT = sys->sellT.hoff;
+  a.hcolT = sys->sellT.hcol;
+  a.lidxT = sys->sellT.lidx;
   a.offT = sys->sellT.off;
   a.colT = sys->sellT.col;
   a.valA = sys->sell_val;
@@ -1466,21 +907,6 @@ static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   return a;
 }
 
-#define MORX_NC_DISPATCH(NCV, ...)                         \
-  switch (NCV) {                                           \
-    case 1: { constexpr int NC = 1; __VA_ARGS__; } break;  \
-    case 2: { constexpr int NC = 2; __VA_ARGS__; } break;  \
-    case 3: { constexpr int NC = 3; __VA_ARGS__; } break;  \
-    case 4: { constexpr int NC = 4; __VA_ARGS__; } break;  \
-    case 5: { constexpr int NC = 5; __VA_ARGS__; } break;  \
-    case 6: { constexpr int NC = 6; __VA_ARGS__; } break;  \
-    case 7: { constexpr int NC = 7; __VA_ARGS__; } break;  \
-    case 8: { constexpr int NC = 8; __VA_ARGS__; } break;  \
-    case 10: { constexpr int NC = 10; __VA_ARGS__; } break; \
-    case 12: { constexpr int NC = 12; __VA_ARGS__; } break; \
-    default: { constexpr int NC = 16; __VA_ARGS__; } break; \
-  }
-
 static dim3 grid_of(const IterArgs& a, int ncv, int halves) {
   return dim3((unsigned)a.nblk, (unsigned)((a.nc + ncv - 1) / ncv), (unsigned)halves);
 }
@@ -1488,33 +914,20 @@ static dim3 grid_of(const IterArgs& a, int ncv, int halves) {
 // The maxL chain launches of an iteration run back to back; when tracing, one
 // event pair brackets the whole run and counts maxL launches, so the event
 // overhead is spread over the run instead of added to every launch.
-template <typename VT, typename AT, int NC>
-static void enqueue_chain(const IterArgs& a, hipStream_t st, TraceState* t) {
-  const dim3 g((unsigned)a.nblk, (unsigned)a.ymax, 1);
+static void enqueue_chain(const IterArgs& a, int prec, hipStream_t st, TraceState* t) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (t) {
     e0 = trace_event(t);
     e1 = trace_event(t);
     if (e0) hipEventRecord(e0, st);
   }
-  if (a.narrow) {
-    for (int s = 0; s + 1 < a.maxL; ++s) k_chain_narrow<VT, AT, NC, false><<<g, kBlock, 0, st>>>(a, s);
-    k_chain_narrow<VT, AT, NC, true><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
-  } else {
-    for (int s = 0; s + 1 < a.maxL; ++s) k_chain_step<VT, AT, NC, false><<<g, kBlock, 0, st>>>(a, s);
-    k_chain_step<VT, AT, NC, true><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
-  }
+  if (prec == MORX_F64) chain_launch_f64(a, st);
+  else if (prec == MORX_F32) chain_launch_f32(a, st);
+  else chain_launch_bf16(a, st);
   if (t && e0 && e1) {
     hipEventRecord(e1, st);
     t->pending.push_back({TR_CHAIN, e0, e1, a.maxL});
   }
-}
-
-template <typename AT, int NC>
-static void enqueue_chain_prec(const IterArgs& a, int prec, hipStream_t st, TraceState* t) {
-  if (prec == MORX_F64) enqueue_chain<double, AT, NC>(a, st, t);
-  else if (prec == MORX_F32) enqueue_chain<float, AT, NC>(a, st, t);
-  else enqueue_chain<uint16_t, AT, NC>(a, st, t);
 }
 
 static morx_status enqueue_iterations(const IterArgs& a, int prec, int iters, hipStream_t st,
@@ -1526,10 +939,7 @@ static morx_status enqueue_iterations(const IterArgs& a, int prec, int iters, hi
   k_plan<<<1, kFinThreads, 0, st>>>(a);
   for (int it = 0; it < iters; ++it) {
     const int par = it & 1;
-    MORX_NC_DISPATCH(ncv, {
-      if (f32) enqueue_chain_prec<float, NC>(a, prec, st, t);
-      else enqueue_chain_prec<double, NC>(a, prec, st, t);
-    });
+    enqueue_chain(a, prec, st, t);
     k_fin_rho<<<1, kFinThreads, 0, st>>>(a);
     if (f32) launch(t, TR_FORMP, k_form_p<float>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
     else launch(t, TR_FORMP, k_form_p<double>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
@@ -1580,8 +990,8 @@ morx_status batch_launch_segment(KrylovBatch& b, int nc, int maxL, int iters, bo
   const IterArgs a = make_args(b, nc, maxL);
   if (!use_graph || t) return enqueue_iterations(a, b.prec, iters, st, t);
   const int64_t key =
-      (((((int64_t)iters * 1024 + nc) * 128 + a.spw) * 16 + a.ncmax) * 16 + a.ncmax_spmv) * 4096 +
-      a.ymax;
+      ((((((int64_t)iters * 1024 + nc) * 128 + a.spw) * 16 + a.ncmax) * 16 + a.ncmax_spmv) * 4096 +
+       a.ymax) * 2 + (a.hmax > 0);
   for (auto& g : b.graphs)
     if (g.maxL == maxL && g.key == key) {
       MORX_HIP(hipGraphLaunch(g.x, st));
@@ -2062,6 +1472,12 @@ extern "C" morx_status morx_solve_moments(morx_system sys, int32_t nshift, const
 // ---------------------------------------------------------------------------
 // launch shapes: get, set, autotune
 
+// whether both orders of the pattern carry the halo layout (built only for
+// patterns wider than kNarrow slots)
+static bool halo_available(morx_system sys) {
+  return sys->sell.hmax > 0 && sys->sellT.hmax > 0;
+}
+
 extern "C" morx_status morx_system_get_tune(morx_system sys, morx_tune* out) {
   MORX_REQUIRE(sys && out, MORX_E_INVALID, "morx_system_get_tune: null argument");
   memset(out, 0, sizeof(*out));
@@ -2069,6 +1485,7 @@ extern "C" morx_status morx_system_get_tune(morx_system sys, morx_tune* out) {
   out->cols_per_wave = sys->tune_nc;
   out->slices_per_wave = sys->tune_spw;
   out->spmv_cols_per_wave = sys->tune_nc_spmv;
+  out->chain_kernel = (halo_available(sys) && sys->tune_chain != 0) ? 1 : 0;
   return MORX_OK;
 }
 
@@ -2085,8 +1502,15 @@ extern "C" morx_status morx_system_set_tune(morx_system sys, const morx_tune* t)
                    (t->spmv_cols_per_wave >= 1 && t->spmv_cols_per_wave <= kMaxNC),
                MORX_E_INVALID, "morx_system_set_tune: spmv_cols_per_wave must be -1 or 1..%d",
                kMaxNC);
+  MORX_REQUIRE(t->chain_kernel >= -1 && t->chain_kernel <= 1, MORX_E_INVALID,
+               "morx_system_set_tune: chain_kernel must be -1, 0 or 1");
+  MORX_REQUIRE(t->chain_kernel != 1 || halo_available(sys), MORX_E_UNSUPPORTED,
+               "morx_system_set_tune: the pattern has no halo layout (rows of 8 or fewer "
+               "entries, more than %d, or a block touching more than %d columns)",
+               kHaloMaxW, kHaloCap);
   std::lock_guard<std::mutex> lk(sys->ctx->mu);
   sys->tune_factor_rows = t->factor_kernel;
+  sys->tune_chain = t->chain_kernel;
   sys->tune_nc = t->cols_per_wave;
   sys->tune_spw = t->slices_per_wave;
   sys->tune_nc_spmv = t->spmv_cols_per_wave;
@@ -2178,9 +1602,11 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
   k_tune_rhs<<<(unsigned)((sys->n + 255) / 256), 256, 0, st>>>((double*)rhs.p, sys->n, sys->n_pad,
                                                                 ncols);
   const int saved_nc = sys->tune_nc, saved_spw = sys->tune_spw, saved_ncs = sys->tune_nc_spmv;
+  const int saved_chain = sys->tune_chain;
   sys->tune_nc = -1;
   sys->tune_spw = -1;
   sys->tune_nc_spmv = -1;
+  sys->tune_chain = -1;
   const IterArgs a0 = make_args(kb, ncols, chain_len);
   const int spw0 = a0.spw;
   constexpr int kWarm = 2, kTimed = 6;
@@ -2259,6 +1685,17 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
       }
     }
   }
+  // ... and, where the pattern has the halo layout, the gather kernel at that shape
+  int best_chain = -1;
+  if (s == MORX_OK && halo_available(sys)) {
+    sys->tune_chain = 0;
+    double ms = 0.0;
+    s = time_shape(best_nc, best_spw, best_ncs, &ms);
+    if (s == MORX_OK && ms < best_i) {
+      best_i = ms;
+      best_chain = 0;
+    }
+  }
   hipStreamSynchronize(st);
   dev_free(rhs);
   batch_free(kb);
@@ -2266,16 +1703,19 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
     sys->tune_nc = saved_nc;
     sys->tune_spw = saved_spw;
     sys->tune_nc_spmv = saved_ncs;
+    sys->tune_chain = saved_chain;
     return s;
   }
   sys->tune_nc = best_nc;
   sys->tune_spw = best_spw;
   sys->tune_nc_spmv = best_ncs;
+  sys->tune_chain = best_chain;
   memset(out, 0, sizeof(*out));
   out->factor_kernel = best_rows;
   out->cols_per_wave = best_nc;
   out->slices_per_wave = best_spw;
   out->spmv_cols_per_wave = best_ncs;
+  out->chain_kernel = (halo_available(sys) && best_chain != 0) ? 1 : 0;
   out->factor_ms = best_f;
   out->iter_ms = best_i;
   return MORX_OK;

@@ -1,0 +1,4 @@
+// Chain-step launches for factors stored in FP64 (kernels in chain_kernels.h).
+#include "chain_kernels.h"
+
+void chain_launch_f64(const IterArgs& a, hipStream_t st) { chain_launch_vt<double>(a, st); }

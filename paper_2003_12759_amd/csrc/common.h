@@ -42,6 +42,16 @@ void morx_set_error(const char* fmt, ...);
 // constants
 
 constexpr int kSlice = 64;         // sliced-ELL slice height = one wavefront
+// Halo layout of a wide pattern: rows are grouped in blocks of kHaloSlices
+// slices; each block lists the distinct columns its entries touch (at most
+// kHaloCap), and each entry stores its column's position in that list.
+constexpr int kHaloSlices = 4;
+constexpr int kHaloCap = 2048;
+constexpr int kHaloMaxW = 32;      // widest slice the halo layout takes
+// Entries past the end of a sliced-ELL value or local-index array: the halo
+// chain step reads all kHaloMaxW slots of a slice with one address and
+// discards those past its width, so the last slice may read this far beyond.
+constexpr int64_t kSellPad = (int64_t)kHaloMaxW * kSlice;
 constexpr int kMaxJ = 31;          // max entries of one column of S
 constexpr int kMaxI = 512;         // max rows of one local least-squares matrix
 constexpr int kMaxTriples = 2048;  // max nonzeros gathered for one column problem
@@ -76,6 +86,13 @@ struct Sell {
   int32_t* col = nullptr;  // [nnz_sell]
   int64_t nnz_sell = 0;
   int32_t max_width = 0;
+  // halo layout (patterns wider than eight slots): per block of kHaloSlices
+  // slices, its ascending distinct columns hcol[hoff[b] .. hoff[b+1]), and
+  // per entry the position of its column in its block's list
+  int32_t* hoff = nullptr;   // [ceil(nslice / kHaloSlices) + 1]
+  int32_t* hcol = nullptr;
+  uint16_t* lidx = nullptr;  // [nnz_sell]
+  int32_t hmax = 0;          // longest list; 0: no halo layout
 };
 
 struct morx_ctx_s {
@@ -128,6 +145,7 @@ struct morx_system_s {
   int32_t tune_nc = -1;           // chain step: most columns per wave (1..8)
   int32_t tune_nc_spmv = -1;      // shifted pair, true residual: the same (-1: tune_nc)
   int32_t tune_spw = -1;          // iteration kernels: 64-row slices per wave
+  int32_t tune_chain = -1;        // chain step: 0 row gathers, 1 halo in LDS (-1: built-in)
   std::vector<DevBuf> owned;
   // chain state between morx_solve_shifts calls (Algorithm 4)
   std::vector<morx_factor> vertical;  // P_1^(1), Q_1^(2), ..., Q_1^(z)

@@ -932,8 +932,8 @@ morx_status factor_alloc(morx_system sys, int32_t prec, morx_factor* out) {
   f->prec = prec;
   f->pooled = true;
   const size_t b = prec_bytes(prec);
-  morx_status s = dev_alloc(f->vals, (size_t)sys->sell.nnz_sell * b);
-  if (s == MORX_OK) s = dev_alloc(f->valsT, (size_t)sys->sellT.nnz_sell * b);
+  morx_status s = dev_alloc(f->vals, (size_t)(sys->sell.nnz_sell + kSellPad) * b);
+  if (s == MORX_OK) s = dev_alloc(f->valsT, (size_t)(sys->sellT.nnz_sell + kSellPad) * b);
   if (s != MORX_OK) {
     dev_free(f->vals);
     dev_free(f->valsT);

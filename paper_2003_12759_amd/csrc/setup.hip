@@ -257,6 +257,89 @@ __global__ void k_copy_pad(const double* __restrict__ in, double* __restrict__ o
 
 inline unsigned nblk(int64_t count) { return (unsigned)((count + kBlock - 1) / kBlock); }
 
+// ---- halo layout -------------------------------------------------------------------
+
+constexpr int kHaloEnt = kHaloSlices * kSlice * kHaloMaxW;  // entries of a block, at most
+constexpr int kHaloThreads = 256;
+
+// One workgroup per block of kHaloSlices slices: sort the block's column
+// indices (bitonic, in LDS), keep the distinct ones, and give every entry the
+// position of its column in that ascending list.  cnt[b] receives the list's
+// length; the list goes to tmp[b * kHaloCap ...] when it fits the cap.
+__global__ __launch_bounds__(kHaloThreads) void k_halo_block(const int32_t* __restrict__ off,
+                                                             const int32_t* __restrict__ col,
+                                                             int64_t nslice,
+                                                             int32_t* __restrict__ cnt,
+                                                             int32_t* __restrict__ tmp,
+                                                             uint16_t* __restrict__ lidx) {
+  __shared__ int32_t keys[kHaloEnt];
+  __shared__ int32_t uniq[kHaloCap];
+  __shared__ int32_t part[kHaloThreads + 1];
+  const int64_t b = blockIdx.x;
+  const int64_t s0 = b * kHaloSlices, s1 = min(nslice, s0 + kHaloSlices);
+  const int32_t e0 = off[s0];
+  const int E = off[s1] - e0;  // <= kHaloEnt: slices are at most kHaloMaxW wide
+  int P = 1;
+  while (P < E) P <<= 1;
+  for (int q = threadIdx.x; q < P; q += kHaloThreads) keys[q] = q < E ? col[e0 + q] : 0x7fffffff;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int q = threadIdx.x; q < P / 2; q += kHaloThreads) {
+        const int i = 2 * q - (q & (j - 1)), l = i + j;  // i has bit j clear
+        const bool up = (i & k) == 0;
+        const int32_t x = keys[i], y = keys[l];
+        if ((x > y) == up) {
+          keys[i] = y;
+          keys[l] = x;
+        }
+      }
+      __syncthreads();
+    }
+  // first occurrences, counted per thread over a contiguous range, then placed
+  const int per = (P + kHaloThreads - 1) / kHaloThreads;
+  const int q0 = min(P, (int)threadIdx.x * per), q1 = min(P, q0 + per);
+  auto first = [&](int q) { return keys[q] != 0x7fffffff && (q == 0 || keys[q] != keys[q - 1]); };
+  int c = 0;
+  for (int q = q0; q < q1; ++q) c += first(q);
+  part[threadIdx.x + 1] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[0] = 0;
+    for (int t = 1; t <= kHaloThreads; ++t) part[t] += part[t - 1];
+  }
+  __syncthreads();
+  const int H = part[kHaloThreads];
+  if (threadIdx.x == 0) cnt[b] = H;
+  if (H > kHaloCap) return;  // uniform: the layout is not built
+  int pos = part[threadIdx.x];
+  for (int q = q0; q < q1; ++q)
+    if (first(q)) {
+      uniq[pos] = keys[q];
+      tmp[b * kHaloCap + pos] = keys[q];
+      ++pos;
+    }
+  __syncthreads();
+  for (int q = threadIdx.x; q < E; q += kHaloThreads) {
+    const int32_t cq = col[e0 + q];
+    int lo = 0, hi = H - 1;  // cq is in uniq[0, H)
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (uniq[mid] < cq) lo = mid + 1;
+      else hi = mid;
+    }
+    lidx[e0 + q] = (uint16_t)lo;
+  }
+}
+
+__global__ __launch_bounds__(kHaloThreads) void k_halo_pack(const int32_t* __restrict__ hoff,
+                                                            const int32_t* __restrict__ tmp,
+                                                            int32_t* __restrict__ hcol) {
+  const int64_t b = blockIdx.x;
+  const int32_t h0 = hoff[b], H = hoff[b + 1] - h0;
+  for (int q = threadIdx.x; q < H; q += kHaloThreads) hcol[h0 + q] = tmp[b * kHaloCap + q];
+}
+
 template <typename T>
 morx_status owned_alloc(morx_system sys, T** p, int64_t count) {
   DevBuf b;
@@ -300,6 +383,52 @@ morx_status build_sell(morx_system sys, const int32_t* rowptr, const int32_t* co
   k_fill_sell<<<nblk(sys->n_pad), kBlock, 0, st>>>(rowptr, col, val, n, sys->n_pad, out.off,
                                                    out.col, *sval, csr2sell);
   MORX_HIP(hipGetLastError());
+  return MORX_OK;
+}
+
+// Halo layout of a pattern whose slices are 9 to kHaloMaxW slots wide; a
+// pattern with a block of more than kHaloCap distinct columns keeps none
+// (hmax = 0) and the chain step gathers from the vectors instead.
+morx_status build_halo(morx_system sys, Sell& sl, hipStream_t st, std::vector<DevBuf>& tmp) {
+  sl.hmax = 0;
+  if (sl.max_width <= 8 || sl.max_width > kHaloMaxW) return MORX_OK;
+  const int64_t nrb = (sys->nslice + kHaloSlices - 1) / kHaloSlices;
+  DevBuf cnt, lists, lidx;
+  MORX_TRY(dev_alloc(cnt, nrb * sizeof(int32_t)));
+  MORX_TRY(dev_alloc(lists, nrb * kHaloCap * sizeof(int32_t)));
+  tmp.push_back(cnt);
+  tmp.push_back(lists);
+  MORX_TRY(dev_alloc(lidx, (sl.nnz_sell + kSellPad) * sizeof(uint16_t)));
+  MORX_HIP(hipMemsetAsync(lidx.p, 0, (sl.nnz_sell + kSellPad) * sizeof(uint16_t), st));
+  k_halo_block<<<(unsigned)nrb, kHaloThreads, 0, st>>>(sl.off, sl.col, sys->nslice,
+                                                       (int32_t*)cnt.p, (int32_t*)lists.p,
+                                                       (uint16_t*)lidx.p);
+  MORX_HIP(hipGetLastError());
+  std::vector<int32_t> hc((size_t)nrb);
+  MORX_HIP(hipMemcpyAsync(hc.data(), cnt.p, nrb * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  MORX_HIP(hipStreamSynchronize(st));
+  int32_t hmax = 0;
+  std::vector<int32_t> hoff((size_t)nrb + 1, 0);
+  for (int64_t b = 0; b < nrb; ++b) {
+    hmax = std::max(hmax, hc[b]);
+    hoff[b + 1] = hoff[b] + hc[b];
+  }
+  if (hmax > kHaloCap) {
+    tmp.push_back(lidx);
+    return MORX_OK;
+  }
+  sys->owned.push_back(lidx);
+  sys->resident_bytes += (int64_t)lidx.bytes;
+  sl.lidx = (uint16_t*)lidx.p;
+  MORX_TRY(owned_alloc(sys, &sl.hoff, nrb + 1));
+  // list reads run up to kHaloCap entries past a block's start
+  MORX_TRY(owned_alloc(sys, &sl.hcol, hoff[nrb] + kHaloCap));
+  MORX_HIP(hipMemcpyAsync(sl.hoff, hoff.data(), (nrb + 1) * sizeof(int32_t),
+                          hipMemcpyHostToDevice, st));
+  k_halo_pack<<<(unsigned)nrb, kHaloThreads, 0, st>>>(sl.hoff, (int32_t*)lists.p, sl.hcol);
+  MORX_HIP(hipGetLastError());
+  MORX_HIP(hipStreamSynchronize(st));  // hoff's host copy goes out of scope
+  sl.hmax = hmax;
   return MORX_OK;
 }
 
@@ -390,6 +519,8 @@ static morx_status system_build(morx_system sys, const int32_t* rowptr, const in
                       sys->csr2sell, st, tmp));
   MORX_TRY(build_sell(sys, sys->trowptr, sys->tcol, sys->tval, sys->sellT, &sys->sellT_val,
                       nullptr, st, tmp));
+  MORX_TRY(build_halo(sys, sys->sell, st, tmp));
+  MORX_TRY(build_halo(sys, sys->sellT, st, tmp));
   MORX_TRY(owned_alloc(sys, &sys->tp2s, nnzS));
   k_compose<<<nblk(nnzS), kBlock, 0, st>>>(tsrcp, sys->csr2sell, nnzS, sys->tp2s);
   MORX_TRY(owned_alloc(sys, &sys->e, sys->n_pad));
