@@ -355,6 +355,149 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
   block_partials<NC, 3>(a, t, c0, valid, v, a.part_delta);
 }
 
+// The shifted pair on the halo layout (the chain step's layout, see
+// k_chain_halo): per block of four slices, A's product on the rows of S with
+// p staged in LDS, then A^T's on the rows of S^T with p~ staged, CB columns
+// per round.  Rows sum their slots in the gather kernel's order, so q and q~
+// are the same; the delta partial sums follow the forward half.
+constexpr int kSpmvHaloNC = 3;
+
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_spmv_halo(IterArgs a, int par) {
+  constexpr int CB = HaloGroup<NC>::value;
+  constexpr int kPT = kHaloCap / kBlock;
+  constexpr int kSG = 4;
+  constexpr int kGW = 8;
+  __shared__ double xs[kHaloCap * CB];  // [kHaloCap][CB], as in k_chain_halo
+  const WaveCtx t = wave_ctx(a);
+  const int c0 = blockIdx.y * NC;
+  unsigned valid = 0;
+  double sig[NC];
+  const double *p[NC], *pt[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const int c = min(c0 + j, a.nc - 1);
+    const ColInfo& ci = a.cols[c];
+    if (c0 + j < a.nc && ci.state == COL_ACTIVE) valid |= 1u << j;
+    sig[j] = ci.sigma;
+    p[j] = (const double*)uniform(vptr(a, V_P0 + par, c));
+    pt[j] = (const double*)uniform(vptr(a, V_PT0 + par, c));
+  }
+  // valid is the same for the whole block (before any barrier); columns past
+  // the batch read the last column's vectors and their results are dropped
+  if (!valid) return;
+  double v[NC][3];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
+  const int64_t nrb = (a.nslices + kHaloSlices - 1) / kHaloSlices;
+  const int64_t rb0 = (int64_t)t.blk * a.spw;
+  const int nrbk = (int)max<int64_t>(0, min<int64_t>(a.spw, nrb - rb0));
+  const uint32_t vbytes = (uint32_t)(a.ld * (int64_t)sizeof(double));
+  for (int k = 0; k < nrbk; ++k) {
+    const int64_t rb = rb0 + k;
+    const int64_t sl = rb * kHaloSlices + t.wave;
+    const int64_t slc = min<int64_t>(sl, a.nslices - 1);
+    const int64_t i = sl * kSlice + t.lane;
+    const double ei = i < a.n ? gld(a.e + i) : 0.0;
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      const int32_t* off = h ? a.offT : a.off;
+      const int32_t* hoff = h ? a.hoffT : a.hoff;
+      const int32_t* hcol = h ? a.hcolT : a.hcol;
+      const uint16_t* lidx = h ? a.lidxT : a.lidx;
+      const double* val = h ? a.valAT : a.valA;
+      const int32_t base = __builtin_amdgcn_readfirstlane(gld(off + slc));
+      const int w = sl < a.nslices
+                        ? (__builtin_amdgcn_readfirstlane(gld(off + slc + 1)) - base) >> 6
+                        : 0;
+      const int ngw = __builtin_amdgcn_readfirstlane((w + kGW - 1) / kGW);
+      const int32_t h0 = __builtin_amdgcn_readfirstlane(gld(hoff + rb));
+      const int H = __builtin_amdgcn_readfirstlane(gld(hoff + rb + 1)) - h0;
+      int32_t hv[kPT];
+      const int32_t* hp = hcol + h0 + threadIdx.x;
+#pragma unroll
+      for (int q = 0; q < kPT; ++q) {
+        const int32_t r = gld(hp + kBlock * q);
+        hv[q] = (int)threadIdx.x + kBlock * q < H ? r : 0;
+      }
+      const uint16_t* lp = lidx + base + t.lane;
+      const double* vp = val + base + t.lane;
+      uint32_t la[kHaloMaxW];
+      double fb[kHaloMaxW];
+#pragma unroll
+      for (int m = 0; m < kHaloMaxW; ++m) {
+        const uint32_t r = gld(lp + m * kSlice);
+        la[m] = m < w ? r * (uint32_t)(CB * sizeof(double)) : 0u;
+        const double x = gld(vp + m * kSlice);
+        fb[m] = m < w ? x : 0.0;
+      }
+#pragma unroll
+      for (int j0 = 0; j0 < NC; j0 += CB) {
+        BufRes rs[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          const int j = min(j0 + c, NC - 1);
+          rs[c] = buf_res(h ? pt[j] : p[j], vbytes);
+        }
+#pragma unroll
+        for (int q0 = 0; q0 < kPT; q0 += kSG) {
+          if (q0 * kBlock >= H) break;  // uniform
+          double sv[kSG][CB];
+#pragma unroll
+          for (int q = 0; q < kSG; ++q) {
+            const int e = (int)threadIdx.x + kBlock * (q0 + q);
+            const uint32_t o = e < H ? (uint32_t)hv[q0 + q] * 8u : kOutside;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) sv[q][c] = buf_val<double>(rs[c], o);
+          }
+#pragma unroll
+          for (int q = 0; q < kSG; ++q) {
+            const int e = (int)threadIdx.x + kBlock * (q0 + q);
+#pragma unroll
+            for (int c = 0; c < CB; ++c) xs[e * CB + c] = sv[q][c];
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          const int j = j0 + c;
+          if (j < NC && (valid & (1u << j))) {
+            const char* xc = (const char*)(xs + c);
+            double acc = 0.0;
+#pragma unroll
+            for (int g = 0; g < kHaloMaxW / kGW; ++g) {
+              if (g >= ngw) break;  // uniform
+              double xg[kGW];
+#pragma unroll
+              for (int u = 0; u < kGW; ++u) xg[u] = *(const double*)(xc + la[g * kGW + u]);
+#pragma unroll
+              for (int u = 0; u < kGW; ++u) acc = fma(fb[g * kGW + u], xg[u], acc);
+            }
+            if (i < a.n) {
+              const int cc = c0 + j;
+              const double se = sig[j] * ei;
+              if (h == 0) {
+                const double pi = gld(p[j] + i);
+                const double pti = gld(pt[j] + i);
+                const double qi = fma(se, pi, -acc);
+                gst(vptr(a, V_Q, cc) + i, qi);
+                v[j][0] = fma(pti, qi, v[j][0]);
+                v[j][1] = fma(pti, pti, v[j][1]);
+                v[j][2] = fma(qi, qi, v[j][2]);
+              } else {
+                const double pti = gld(pt[j] + i);
+                gst(vptr(a, V_QT, cc) + i, fma(se, pti, -acc));
+              }
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  block_partials<NC, 3>(a, t, c0, valid, v, a.part_delta);
+}
+
 __global__ __launch_bounds__(kFinThreads) void k_fin_delta(IterArgs a) {
   __shared__ double upd_cols;
   if (threadIdx.x == 0) upd_cols = 0.0;
@@ -943,9 +1086,19 @@ static morx_status enqueue_iterations(const IterArgs& a, int prec, int iters, hi
     k_fin_rho<<<1, kFinThreads, 0, st>>>(a);
     if (f32) launch(t, TR_FORMP, k_form_p<float>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
     else launch(t, TR_FORMP, k_form_p<double>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
-    MORX_NC_DISPATCH(ncs, {
-      launch(t, TR_SPMV, k_spmv_pair<NC>, grid_of(a, NC, 1), dim3(kBlock), st, a, par);
-    });
+    if (a.hmax > 0) {
+      // the halo product holds a row's FP64 values in registers: at most
+      // kSpmvHaloNC columns per block
+      switch (pick_nc(a.nc, std::min(ncs, kSpmvHaloNC))) {
+        case 1: launch(t, TR_SPMV, k_spmv_halo<1>, grid_of(a, 1, 1), dim3(kBlock), st, a, par); break;
+        case 2: launch(t, TR_SPMV, k_spmv_halo<2>, grid_of(a, 2, 1), dim3(kBlock), st, a, par); break;
+        default: launch(t, TR_SPMV, k_spmv_halo<3>, grid_of(a, 3, 1), dim3(kBlock), st, a, par); break;
+      }
+    } else {
+      MORX_NC_DISPATCH(ncs, {
+        launch(t, TR_SPMV, k_spmv_pair<NC>, grid_of(a, NC, 1), dim3(kBlock), st, a, par);
+      });
+    }
     k_fin_delta<<<1, kFinThreads, 0, st>>>(a);
     // elementwise: one column per wave, nothing to share between columns
     launch(t, TR_UPDATE, k_update<1>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);

@@ -378,7 +378,7 @@ morx_status build_sell(morx_system sys, const int32_t* rowptr, const int32_t* co
   out.nnz_sell = total;
   MORX_TRY(owned_alloc(sys, &out.off, ns + 1));
   MORX_TRY(owned_alloc(sys, &out.col, total));
-  MORX_TRY(owned_alloc(sys, sval, total));
+  MORX_TRY(owned_alloc(sys, sval, total + kSellPad));  // halo kernels read past the end
   k_narrow_off<<<nblk(ns + 1), kBlock, 0, st>>>((int64_t*)off64.p, out.off, ns + 1);
   k_fill_sell<<<nblk(sys->n_pad), kBlock, 0, st>>>(rowptr, col, val, n, sys->n_pad, out.off,
                                                    out.col, *sval, csr2sell);
