@@ -47,9 +47,9 @@ def kernel_source_hash() -> str:
 
 def chain_kernel_name(A, vt: str, at: str, ncol: int, ncmax: int, halo: bool) -> str:
     """Instance of the chain step the library launches for this batch: the
-    narrow variant when every row of S = pattern(A) + diagonal and of S^T
-    has at most 8 entries, else the halo variant when the system uses it
-    (`halo`, from the tune the library reports) or the general one, at the
+    halo variant when the system uses it (`halo`, from the tune the library
+    reports), else the narrow variant when every row of S = pattern(A) +
+    diagonal and of S^T has at most 8 entries, else the general one, at the
     tile width of the library's column split (equal chunks of at most ncmax
     columns, rounded up to an instantiated width)."""
     import numpy as np
@@ -63,7 +63,7 @@ def chain_kernel_name(A, vt: str, at: str, ncol: int, ncmax: int, halo: bool) ->
     chunks = -(-ncol // ncmax)
     nc = -(-ncol // chunks)
     nc = nc if nc <= 8 else (10 if nc <= 10 else (12 if nc <= 12 else 16))
-    kind = "k_chain_narrow" if width <= 8 else ("k_chain_halo" if halo else "k_chain_step")
+    kind = "k_chain_halo" if halo else ("k_chain_narrow" if width <= 8 else "k_chain_step")
     return f"{kind}<{vt}, {at}, {nc}>"
 
 

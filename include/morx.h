@@ -293,16 +293,17 @@ morx_status morx_irka(morx_system sys, int32_t r, double* sigmas, const double* 
  *   spmv_cols_per_wave  shifted pair and true residual: the same as
  *                    cols_per_wave for the operator's loads (1..16; -1 follows
  *                    cols_per_wave);
- *   chain_kernel     chain step on patterns with rows of more than 8 entries:
- *                    0 gathers the input vectors row by row; 1 copies, per
- *                    block of 256 rows, the input entries at the block's
- *                    distinct columns into LDS and sums from there (the halo
- *                    layout, built by morx_system_create for rows of 9..32
- *                    entries whose blocks touch at most 2048 columns;
- *                    MORX_E_UNSUPPORTED when the system has none); -1 takes 1
- *                    where the layout exists.  Both give the same results.
- *                    morx_system_get_tune reports the kernel the next solve
- *                    launches (0 or 1).
+ *   chain_kernel     chain step: 0 gathers the input vectors row by row; 1
+ *                    copies, per block of 256 rows, the input entries at the
+ *                    block's distinct columns into LDS and sums from there (the
+ *                    halo layout, built by morx_system_create for rows of at
+ *                    most 32 entries whose blocks touch at most 2048 columns,
+ *                    1024 for rows of at most 8; MORX_E_UNSUPPORTED when the
+ *                    system has none); -1 takes 1 for rows of more than 8
+ *                    entries where the layout exists, else 0.  On rows of more
+ *                    than 8 entries the shifted pair follows the same choice.
+ *                    Both give the same results.  morx_system_get_tune
+ *                    reports the kernel the next solve launches (0 or 1).
  * morx_system_set_tune checks the values (MORX_E_INVALID) and they apply from
  * the next call on the system.  morx_autotune times the candidates on the
  * system itself: per factor kernel one launch of min(chain_len, 16) SPAI
@@ -313,7 +314,7 @@ morx_status morx_irka(morx_system sys, int32_t r, double* sigmas, const double* 
  * distinct factors of one list, as the chains of one round are
  * (chain_len 1..64: the longest chain of the solves to come); chain tile and
  * row block first, then the shifted pair's tile, then (halo layout only)
- * the gather chain kernel at the chosen shape.  It keeps the
+ * the other chain kernel at the chosen shape.  It keeps the
  * fastest, fills *out (factor_ms and iter_ms: the chosen build and one
  * iteration) and returns MORX_OK.  Shapes change rounding order only.  It
  * allocates its own scratch on the device.

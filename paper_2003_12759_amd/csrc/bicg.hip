@@ -972,6 +972,23 @@ static int pick_nc(int nc, int ncmax) {
   return w <= 8 ? w : (w <= 10 ? 10 : (w <= 12 ? 12 : 16));
 }
 
+// whether both orders of the pattern carry a halo layout the chain step can
+// take: lists of at most kHaloCap entries, or kHaloCapNarrow for patterns of
+// at most kNarrow slots (their halo kernel keeps fewer slots and list entries)
+static bool pattern_narrow(morx_system sys) {
+  return std::max(sys->sell.max_width, sys->sellT.max_width) <= kNarrow;
+}
+static bool halo_available(morx_system sys) {
+  if (sys->sell.hmax <= 0 || sys->sellT.hmax <= 0) return false;
+  return !pattern_narrow(sys) || std::max(sys->sell.hmax, sys->sellT.hmax) <= kHaloCapNarrow;
+}
+// the chain step runs on the halo layout: by default for wide patterns, on
+// request (chain_kernel 1) for narrow ones
+static bool halo_in_use(morx_system sys) {
+  if (!halo_available(sys)) return false;
+  return sys->tune_chain == 1 || (sys->tune_chain == -1 && !pattern_narrow(sys));
+}
+
 static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   morx_system sys = b.sys;
   IterArgs a;
@@ -1020,9 +1037,7 @@ static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   a.nsell = sys->sell.nnz_sell;
   a.nsellT = sys->sellT.nnz_sell;
   a.narrow = std::max(sys->sell.max_width, sys->sellT.max_width) <= kNarrow;
-  a.hmax = (!a.narrow && sys->tune_chain != 0 && sys->sell.hmax > 0 && sys->sellT.hmax > 0)
-               ? std::max(sys->sell.hmax, sys->sellT.hmax)
-               : 0;
+  a.hmax = halo_in_use(sys) ? std::max(sys->sell.hmax, sys->sellT.hmax) : 0;
   a.hoff = sys->sell.hoff;
   a.hcol = sys->sell.hcol;
   a.lidx = sys->sell.lidx;
@@ -1086,7 +1101,7 @@ static morx_status enqueue_iterations(const IterArgs& a, int prec, int iters, hi
     k_fin_rho<<<1, kFinThreads, 0, st>>>(a);
     if (f32) launch(t, TR_FORMP, k_form_p<float>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
     else launch(t, TR_FORMP, k_form_p<double>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
-    if (a.hmax > 0) {
+    if (a.hmax > 0 && !a.narrow) {
       // the halo product holds a row's FP64 values in registers: at most
       // kSpmvHaloNC columns per block
       switch (pick_nc(a.nc, std::min(ncs, kSpmvHaloNC))) {
@@ -1625,12 +1640,6 @@ extern "C" morx_status morx_solve_moments(morx_system sys, int32_t nshift, const
 // ---------------------------------------------------------------------------
 // launch shapes: get, set, autotune
 
-// whether both orders of the pattern carry the halo layout (built only for
-// patterns wider than kNarrow slots)
-static bool halo_available(morx_system sys) {
-  return sys->sell.hmax > 0 && sys->sellT.hmax > 0;
-}
-
 extern "C" morx_status morx_system_get_tune(morx_system sys, morx_tune* out) {
   MORX_REQUIRE(sys && out, MORX_E_INVALID, "morx_system_get_tune: null argument");
   memset(out, 0, sizeof(*out));
@@ -1638,7 +1647,7 @@ extern "C" morx_status morx_system_get_tune(morx_system sys, morx_tune* out) {
   out->cols_per_wave = sys->tune_nc;
   out->slices_per_wave = sys->tune_spw;
   out->spmv_cols_per_wave = sys->tune_nc_spmv;
-  out->chain_kernel = (halo_available(sys) && sys->tune_chain != 0) ? 1 : 0;
+  out->chain_kernel = halo_in_use(sys) ? 1 : 0;
   return MORX_OK;
 }
 
@@ -1658,9 +1667,10 @@ extern "C" morx_status morx_system_set_tune(morx_system sys, const morx_tune* t)
   MORX_REQUIRE(t->chain_kernel >= -1 && t->chain_kernel <= 1, MORX_E_INVALID,
                "morx_system_set_tune: chain_kernel must be -1, 0 or 1");
   MORX_REQUIRE(t->chain_kernel != 1 || halo_available(sys), MORX_E_UNSUPPORTED,
-               "morx_system_set_tune: the pattern has no halo layout (rows of 8 or fewer "
-               "entries, more than %d, or a block touching more than %d columns)",
-               kHaloMaxW, kHaloCap);
+               "morx_system_set_tune: the pattern has no halo layout (rows of more than %d "
+               "entries, or a block of 256 rows touching more than %d columns, %d for rows "
+               "of at most %d entries)",
+               kHaloMaxW, kHaloCap, kHaloCapNarrow, kNarrow);
   std::lock_guard<std::mutex> lk(sys->ctx->mu);
   sys->tune_factor_rows = t->factor_kernel;
   sys->tune_chain = t->chain_kernel;
@@ -1838,15 +1848,17 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
       }
     }
   }
-  // ... and, where the pattern has the halo layout, the gather kernel at that shape
+  // ... and, where the pattern has a halo layout, the other chain kernel at
+  // that shape (gathers for wide patterns, the halo layout for narrow ones)
   int best_chain = -1;
   if (s == MORX_OK && halo_available(sys)) {
-    sys->tune_chain = 0;
+    const int alt = pattern_narrow(sys) ? 1 : 0;
+    sys->tune_chain = alt;
     double ms = 0.0;
     s = time_shape(best_nc, best_spw, best_ncs, &ms);
     if (s == MORX_OK && ms < best_i) {
       best_i = ms;
-      best_chain = 0;
+      best_chain = alt;
     }
   }
   hipStreamSynchronize(st);
@@ -1868,7 +1880,7 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
   out->cols_per_wave = best_nc;
   out->slices_per_wave = best_spw;
   out->spmv_cols_per_wave = best_ncs;
-  out->chain_kernel = (halo_available(sys) && best_chain != 0) ? 1 : 0;
+  out->chain_kernel = halo_in_use(sys) ? 1 : 0;
   out->factor_ms = best_f;
   out->iter_ms = best_i;
   return MORX_OK;

@@ -58,6 +58,7 @@ struct IterArgs {
   int plan_ld;     // work-list entries per step
   int narrow;      // every slice of S and S^T at most kNarrow slots wide
   int hmax;        // chain step on the halo layout: longest list of S and S^T; 0: gathers
+                   // (narrow patterns: the W = 8 kernel, lists of at most kHaloCapNarrow)
   const int32_t *hoff, *hcol, *hoffT, *hcolT;
   const uint16_t *lidx, *lidxT;
   const int32_t *off, *col, *offT, *colT;
@@ -609,17 +610,18 @@ __device__ __forceinline__ NarrowVal<VT> gload_narrow(const VT* p) {
   else return gld(p);
 }
 
-template <typename VT, typename AT, int NC, bool RHO>
+// W: slots a slice may have (8 or W); HC: list cap (LDS entries)
+template <typename VT, typename AT, int NC, bool RHO, int W, int HC>
 __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
   constexpr int CB = HaloGroup<NC>::value;
-  constexpr int kPT = kHaloCap / kBlock;  // list entries per thread
+  constexpr int kPT = HC / kBlock;  // list entries per thread
   constexpr int kSG = 4;                  // list entries per thread in flight while staging
   constexpr int kGW = 8;                  // slots per group of the row sums
   using FT = NarrowVal<VT>;
-  // [kHaloCap][CB]: the CB vectors' entries at one list position side by
+  // [HC][CB]: the CB vectors' entries at one list position side by
   // side; every position a staging round covers is written (past the list:
   // zeros), so the stores need no guard
-  __shared__ AT xs[kHaloCap * CB];
+  __shared__ AT xs[HC * CB];
   const WaveCtx t = wave_ctx(a);
   const int64_t nrb = (a.nslices + kHaloSlices - 1) / kHaloSlices;
   const int64_t rb0 = (int64_t)t.blk * a.spw;  // the block's row blocks: rb0 ... rb0 + spw - 1
@@ -656,7 +658,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
       const int64_t i = sl * kSlice + t.lane;
       const int32_t h0 = __builtin_amdgcn_readfirstlane(gld(hoff + rb));
       const int H = __builtin_amdgcn_readfirstlane(gld(hoff + rb + 1)) - h0;
-      // (the list array carries kHaloCap entries of padding)
+      // (the list array carries kHaloCap >= HC entries of padding)
       int32_t hv[kPT];
       const int32_t* hp = hcol + h0 + threadIdx.x;
 #pragma unroll
@@ -665,24 +667,24 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
         hv[q] = (int)threadIdx.x + kBlock * q < H ? r : 0;
       }
       // local indices, kept as LDS byte offsets, and (shared factor)
-      // values: all kHaloMaxW slots read from one address (slot m at a
+      // values: all W slots read from one address (slot m at a
       // constant offset; the arrays carry padding past the last slice), and
       // slots past the width replaced by list position 0 and value 0, which
       // add nothing
       const uint16_t* lp = lidx + base + t.lane;
-      uint32_t la[kHaloMaxW];
-      FT fb[kHaloMaxW];
+      uint32_t la[W];
+      FT fb[W];
 #pragma unroll
-      for (int m = 0; m < kHaloMaxW; ++m) {
+      for (int m = 0; m < W; ++m) {
         const uint32_t r = gld(lp + m * kSlice);
         la[m] = m < w ? r * (uint32_t)(CB * sizeof(AT)) : 0u;
       }
 #pragma unroll
-      for (int m = 0; m < kHaloMaxW; ++m) fb[m] = (FT)0;
+      for (int m = 0; m < W; ++m) fb[m] = (FT)0;
       if (shared) {
         const VT* fp = fv0 + base + t.lane;
 #pragma unroll
-        for (int m = 0; m < kHaloMaxW; ++m) {
+        for (int m = 0; m < W; ++m) {
           const FT r = gload_narrow<VT>(fp + m * kSlice);
           fb[m] = m < w ? r : (FT)0;
         }
@@ -723,7 +725,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
             if (!shared) {  // this pair's own factor values
               const VT* fp = (const VT*)uniform(ck[j].fv) + base + t.lane;
 #pragma unroll
-              for (int m = 0; m < kHaloMaxW; ++m) {
+              for (int m = 0; m < W; ++m) {
                 const FT r = gload_narrow<VT>(fp + m * kSlice);
                 fb[m] = m < w ? r : (FT)0;
               }
@@ -733,7 +735,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
             // block's first staged entry
             double acc = 0.0;
 #pragma unroll
-            for (int g = 0; g < kHaloMaxW / kGW; ++g) {
+            for (int g = 0; g < W / kGW; ++g) {
               if (g >= ngw) break;  // uniform
               AT xg[kGW];
 #pragma unroll
@@ -795,12 +797,17 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
 template <typename VT, typename AT, int NC>
 void chain_run(const IterArgs& a, hipStream_t st) {
   const dim3 g((unsigned)a.nblk, (unsigned)a.ymax, 1);
-  if (a.narrow) {
+  if (a.hmax > 0 && a.narrow) {
+    for (int s = 0; s + 1 < a.maxL; ++s)
+      k_chain_halo<VT, AT, NC, false, kNarrow, kHaloCapNarrow><<<g, kBlock, 0, st>>>(a, s);
+    k_chain_halo<VT, AT, NC, true, kNarrow, kHaloCapNarrow><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
+  } else if (a.hmax > 0) {
+    for (int s = 0; s + 1 < a.maxL; ++s)
+      k_chain_halo<VT, AT, NC, false, kHaloMaxW, kHaloCap><<<g, kBlock, 0, st>>>(a, s);
+    k_chain_halo<VT, AT, NC, true, kHaloMaxW, kHaloCap><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
+  } else if (a.narrow) {
     for (int s = 0; s + 1 < a.maxL; ++s) k_chain_narrow<VT, AT, NC, false><<<g, kBlock, 0, st>>>(a, s);
     k_chain_narrow<VT, AT, NC, true><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
-  } else if (a.hmax > 0) {
-    for (int s = 0; s + 1 < a.maxL; ++s) k_chain_halo<VT, AT, NC, false><<<g, kBlock, 0, st>>>(a, s);
-    k_chain_halo<VT, AT, NC, true><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
   } else {
     for (int s = 0; s + 1 < a.maxL; ++s) k_chain_step<VT, AT, NC, false><<<g, kBlock, 0, st>>>(a, s);
     k_chain_step<VT, AT, NC, true><<<g, kBlock, 0, st>>>(a, a.maxL - 1);

@@ -47,6 +47,7 @@ constexpr int kSlice = 64;         // sliced-ELL slice height = one wavefront
 // kHaloCap), and each entry stores its column's position in that list.
 constexpr int kHaloSlices = 4;
 constexpr int kHaloCap = 2048;
+constexpr int kHaloCapNarrow = 1024;  // list cap of the kernel for slices of <= 8 slots
 constexpr int kHaloMaxW = 32;      // widest slice the halo layout takes
 // Entries past the end of a sliced-ELL value or local-index array: the halo
 // chain step reads all kHaloMaxW slots of a slice with one address and

@@ -386,12 +386,12 @@ morx_status build_sell(morx_system sys, const int32_t* rowptr, const int32_t* co
   return MORX_OK;
 }
 
-// Halo layout of a pattern whose slices are 9 to kHaloMaxW slots wide; a
+// Halo layout of a pattern whose slices are at most kHaloMaxW slots wide; a
 // pattern with a block of more than kHaloCap distinct columns keeps none
 // (hmax = 0) and the chain step gathers from the vectors instead.
 morx_status build_halo(morx_system sys, Sell& sl, hipStream_t st, std::vector<DevBuf>& tmp) {
   sl.hmax = 0;
-  if (sl.max_width <= 8 || sl.max_width > kHaloMaxW) return MORX_OK;
+  if (sl.max_width > kHaloMaxW) return MORX_OK;
   const int64_t nrb = (sys->nslice + kHaloSlices - 1) / kHaloSlices;
   DevBuf cnt, lists, lidx;
   MORX_TRY(dev_alloc(cnt, nrb * sizeof(int32_t)));

@@ -1,12 +1,12 @@
 """The chain step on the halo layout against the gather kernel and exact
 solves, through the C ABI.
 
-Patterns with rows of 9..32 entries get, per block of 256 rows, the list of
-distinct columns the block touches (when it has at most 2048); the halo
-kernel copies the input vectors at those columns into LDS and sums each row
-from there.  Both kernels sum a row's slots in the same order, so the chain
-outputs agree; the BiCG runs differ only through the grouping of the rho
-partial sums.  Tolerances as in the other solve tests: true relative residual
+Patterns with rows of at most 32 entries get, per block of 256 rows, the list
+of distinct columns the block touches (when it has at most 2048, 1024 for
+rows of at most 8 entries); the halo kernel copies the input vectors at those
+columns into LDS and sums each row from there.  Both kernels sum a row's
+slots in the same order, so the chain outputs agree; the BiCG runs differ
+only through the grouping of the rho partial sums.  Tolerances as in the other solve tests: true relative residual
 <= 1e-10 (recomputed here in FP64), ||x - x_ref|| <= ||A_s^{-1}|| (||r|| +
 ||r_ref||) against a sparse direct solve with ||A_s^{-1}|| = 1 / sigma_min
 from a dense SVD, and iteration counts of the two kernels within
@@ -55,11 +55,18 @@ def _varcoef27(N):
     return w.A, w.e
 
 
+def _convdiff(N):
+    w = make_workload(1, N=N)
+    return w.A, w.e
+
+
 # 27-point on 11^3 = 1331 rows: 21 slices, so the last block of four slices
-# has one; the random pattern has no stencil structure and rows of ~11 entries
+# has one; the random pattern has no stencil structure and rows of ~11
+# entries; the 7-point operator takes the halo kernel for rows of at most 8
 CASES = {
     "varcoef27_n1331": lambda: _varcoef27(11),
     "random_wide_n1300": lambda: _wide_random(1300, 10, 7),
+    "convdiff_n1331": lambda: _convdiff(11),
 }
 
 
@@ -135,13 +142,12 @@ def test_halo_layout_absent_on_scattered_pattern(ctx):
 def test_chain_kernel_tune_values(ctx):
     from paper_2003_12759_amd import api, morx
 
-    # a 7-point pattern is narrow: no halo layout
+    # a 7-point pattern has a halo layout, used on request only
     w = make_workload(1, N=8, nshift=2)
     S = api.System(ctx, w.A, w.e)
     assert S.get_tune()["chain_kernel"] == 0
-    with pytest.raises(morx.MorxError) as ei:
-        S.set_tune(chain_kernel=1)
-    assert ei.value.status == MORX_E_UNSUPPORTED
+    S.set_tune(chain_kernel=1)
+    assert S.get_tune()["chain_kernel"] == 1
     S.close()
     # a 27-point pattern has one, used by default
     A, e = _varcoef27(6)
