@@ -300,9 +300,9 @@ morx_status morx_irka(morx_system sys, int32_t r, double* sigmas, const double* 
  *                    most 32 entries whose blocks touch at most 2048 columns,
  *                    1024 for rows of at most 8; MORX_E_UNSUPPORTED when the
  *                    system has none); -1 takes 1 for rows of more than 8
- *                    entries where the layout exists, else 0.  On rows of more
- *                    than 8 entries the shifted pair follows the same choice.
- *                    Both give the same results.  morx_system_get_tune
+ *                    entries where the layout exists, else 0.  The shifted
+ *                    pair follows the same choice.  Both give the same
+ *                    results.  morx_system_get_tune
  *                    reports the kernel the next solve launches (0 or 1).
  * morx_system_set_tune checks the values (MORX_E_INVALID) and they apply from
  * the next call on the system.  morx_autotune times the candidates on the
@@ -313,8 +313,8 @@ morx_status morx_irka(morx_system sys, int32_t r, double* sigmas, const double* 
  * shape (HIP events), column c preconditioned by 1 + c * chain_len / ncols
  * distinct factors of one list, as the chains of one round are
  * (chain_len 1..64: the longest chain of the solves to come); chain tile and
- * row block first, then the shifted pair's tile, then (halo layout only)
- * the other chain kernel at the chosen shape.  It keeps the
+ * row block first, then (halo layout only) the other chain kernel at the
+ * chosen shape, then the shifted pair's tile.  It keeps the
  * fastest, fills *out (factor_ms and iter_ms: the chosen build and one
  * iteration) and returns MORX_OK.  Shapes change rounding order only.  It
  * allocates its own scratch on the device.

@@ -360,15 +360,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
 // p staged in LDS, then A^T's on the rows of S^T with p~ staged, CB columns
 // per round.  Rows sum their slots in the gather kernel's order, so q and q~
 // are the same; the delta partial sums follow the forward half.
+// most columns per block of the halo product: a row's FP64 values stay in
+// registers (32 slots: three columns; 8 slots: eight)
 constexpr int kSpmvHaloNC = 3;
+constexpr int kSpmvHaloNCNarrow = 8;
 
-template <int NC>
+// W: slots a slice may have (8 or W); HC: list cap (LDS entries)
+template <int NC, int W, int HC>
 __global__ __launch_bounds__(kBlock) void k_spmv_halo(IterArgs a, int par) {
   constexpr int CB = HaloGroup<NC>::value;
-  constexpr int kPT = kHaloCap / kBlock;
+  constexpr int kPT = HC / kBlock;
   constexpr int kSG = 4;
   constexpr int kGW = 8;
-  __shared__ double xs[kHaloCap * CB];  // [kHaloCap][CB], as in k_chain_halo
+  __shared__ double xs[HC * CB];  // [HC][CB], as in k_chain_halo
   const WaveCtx t = wave_ctx(a);
   const int c0 = blockIdx.y * NC;
   unsigned valid = 0;
@@ -422,10 +426,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_halo(IterArgs a, int par) {
       }
       const uint16_t* lp = lidx + base + t.lane;
       const double* vp = val + base + t.lane;
-      uint32_t la[kHaloMaxW];
-      double fb[kHaloMaxW];
+      uint32_t la[W];
+      double fb[W];
 #pragma unroll
-      for (int m = 0; m < kHaloMaxW; ++m) {
+      for (int m = 0; m < W; ++m) {
         const uint32_t r = gld(lp + m * kSlice);
         la[m] = m < w ? r * (uint32_t)(CB * sizeof(double)) : 0u;
         const double x = gld(vp + m * kSlice);
@@ -465,7 +469,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_halo(IterArgs a, int par) {
             const char* xc = (const char*)(xs + c);
             double acc = 0.0;
 #pragma unroll
-            for (int g = 0; g < kHaloMaxW / kGW; ++g) {
+            for (int g = 0; g < W / kGW; ++g) {
               if (g >= ngw) break;  // uniform
               double xg[kGW];
 #pragma unroll
@@ -1102,13 +1106,18 @@ static morx_status enqueue_iterations(const IterArgs& a, int prec, int iters, hi
     if (f32) launch(t, TR_FORMP, k_form_p<float>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
     else launch(t, TR_FORMP, k_form_p<double>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
     if (a.hmax > 0 && !a.narrow) {
-      // the halo product holds a row's FP64 values in registers: at most
-      // kSpmvHaloNC columns per block
       switch (pick_nc(a.nc, std::min(ncs, kSpmvHaloNC))) {
-        case 1: launch(t, TR_SPMV, k_spmv_halo<1>, grid_of(a, 1, 1), dim3(kBlock), st, a, par); break;
-        case 2: launch(t, TR_SPMV, k_spmv_halo<2>, grid_of(a, 2, 1), dim3(kBlock), st, a, par); break;
-        default: launch(t, TR_SPMV, k_spmv_halo<3>, grid_of(a, 3, 1), dim3(kBlock), st, a, par); break;
+        case 1: launch(t, TR_SPMV, k_spmv_halo<1, kHaloMaxW, kHaloCap>, grid_of(a, 1, 1), dim3(kBlock), st, a, par); break;
+        case 2: launch(t, TR_SPMV, k_spmv_halo<2, kHaloMaxW, kHaloCap>, grid_of(a, 2, 1), dim3(kBlock), st, a, par); break;
+        default: launch(t, TR_SPMV, k_spmv_halo<3, kHaloMaxW, kHaloCap>, grid_of(a, 3, 1), dim3(kBlock), st, a, par); break;
       }
+    } else if (a.hmax > 0) {
+      const int nch = pick_nc(a.nc, std::min(ncs, kSpmvHaloNCNarrow));
+      MORX_NC_DISPATCH(nch, {
+        if constexpr (NC <= kSpmvHaloNCNarrow)
+          launch(t, TR_SPMV, k_spmv_halo<NC, kNarrow, kHaloCapNarrow>, grid_of(a, NC, 1),
+                 dim3(kBlock), st, a, par);
+      });
     } else {
       MORX_NC_DISPATCH(ncs, {
         launch(t, TR_SPMV, k_spmv_pair<NC>, grid_of(a, NC, 1), dim3(kBlock), st, a, par);
@@ -1831,7 +1840,22 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
     }
     if (s != MORX_OK) break;
   }
-  // ... then the shifted pair's own tile with the chain shape fixed
+  // ... then, where the pattern has a halo layout, the other chain kernel at
+  // that shape (gathers for wide patterns, the halo layout for narrow ones;
+  // the shifted pair follows the chain kernel) ...
+  int best_chain = -1;
+  if (s == MORX_OK && halo_available(sys)) {
+    const int alt = pattern_narrow(sys) ? 1 : 0;
+    sys->tune_chain = alt;
+    double ms = 0.0;
+    s = time_shape(best_nc, best_spw, -1, &ms);
+    if (s == MORX_OK && ms < best_i) {
+      best_i = ms;
+      best_chain = alt;
+    }
+    sys->tune_chain = best_chain;
+  }
+  // ... and the shifted pair's own tile with the chain shape and kernel fixed
   if (s == MORX_OK) {
     seen.clear();
     seen.push_back(pick_nc(ncols, best_nc));
@@ -1846,19 +1870,6 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
         best_i = ms;
         best_ncs = ncs;
       }
-    }
-  }
-  // ... and, where the pattern has a halo layout, the other chain kernel at
-  // that shape (gathers for wide patterns, the halo layout for narrow ones)
-  int best_chain = -1;
-  if (s == MORX_OK && halo_available(sys)) {
-    const int alt = pattern_narrow(sys) ? 1 : 0;
-    sys->tune_chain = alt;
-    double ms = 0.0;
-    s = time_shape(best_nc, best_spw, best_ncs, &ms);
-    if (s == MORX_OK && ms < best_i) {
-      best_i = ms;
-      best_chain = alt;
     }
   }
   hipStreamSynchronize(st);
