@@ -30,7 +30,9 @@ if ROOT not in sys.path:
 METRIC = "shifted solves/sec to rel-res 1e-10 (batched vs plain); HBM GB/s; p99 lat"
 HBM_PEAK_GBPS = 8000.0
 DOMINANT = "chain_step"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_chain_step_convdiff3d_n262144.json")
+def traffic_file(workload: str) -> str:
+    """Measured HBM traffic of the chain step on a workload (rocprofv3 counters)."""
+    return os.path.join(ROOT, "profiles", f"traffic_chain_step_{workload}.json")
 
 
 def kernel_source_hash() -> str:
@@ -427,8 +429,8 @@ def main():
         roof_kernel = chain_kernel_name(w.A, ctype[w.prec], ctype[apply], ncol,
                                         tune_now["cols_per_wave"], tune_now["chain_kernel"] == 1)
         traffic = None
-        if os.path.exists(TRAFFIC_FILE):
-            with open(TRAFFIC_FILE) as f:
+        if os.path.exists(traffic_file(w.name)):
+            with open(traffic_file(w.name)) as f:
                 tf = json.load(f)
             # counters describe the kernel source and instance they were taken on
             entry = tf.get("kernels", {}).get(roof_kernel)

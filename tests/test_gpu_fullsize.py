@@ -1,6 +1,8 @@
 """Full-size checks of the benchmark job (64^3 convection-diffusion, n = 262,144),
 in the launch configurations bench.py times (batched, FP32 factors, 3 rounds,
-preconditioner applied in FP64 and in FP32).
+preconditioner applied in FP64 and in FP32; launch shapes built in, and
+autotuned on the system as bench.py does, which takes the halo chain kernel
+where it is faster).
 
 At this size the oracle cannot solve every system, so the checks are:
 * sampled factor columns against the oracle's column least squares;
@@ -36,15 +38,22 @@ def setup():
     ctx.close()
 
 
+@pytest.mark.parametrize("launch", ["built-in", "autotuned"])
 @pytest.mark.parametrize("apply", ["f64", "f32"])
-def test_bench_job_fullsize_residuals_and_interpolation(setup, apply):
+def test_bench_job_fullsize_residuals_and_interpolation(setup, apply, launch):
     from paper_2003_12759_amd import api
 
     w, ctx, S = setup
+    if launch == "autotuned":
+        S.autotune(float(w.rounds[0][0]), ncols=len(w.rounds[0]) * w.B.shape[1],
+                   chain_len=len(w.rounds[0]) + len(w.rounds) - 1, prec=w.prec)
+    else:
+        S.set_tune()
     Bd, Cd = api.block_to_dev(w.B), api.block_to_dev(w.C)
     E = sp.diags(w.e)
     for z, sig in enumerate(w.rounds):
-        print(f"[case] full-size round {z} apply={apply}", flush=True)
+        print(f"[case] full-size round {z} apply={apply} launch={launch} tune={S.get_tune()}",
+              flush=True)
         X, Y, st, stats = S.solve_shifts(sig, Bd, Cd, prec="f32", next_round=z > 0, apply=apply)
         Ar, Er, Br, Cr = S.project(X, Y, Bd, Cd)
         Xg, Yg = X.cpu().numpy(), Y.cpu().numpy()
