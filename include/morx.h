@@ -312,9 +312,9 @@ morx_status morx_irka(morx_system sys, int32_t r, double* sigmas, const double* 
  * per iteration
  * shape (HIP events), column c preconditioned by 1 + c * chain_len / ncols
  * distinct factors of one list, as the chains of one round are
- * (chain_len 1..64: the longest chain of the solves to come); chain tile and
- * row block first, then (halo layout only) the other chain kernel at the
- * chosen shape, then the shifted pair's tile.  It keeps the
+ * (chain_len 1..64: the longest chain of the solves to come); chain kernel
+ * (both where the system has a halo layout), tile and row block first, then
+ * the shifted pair's tile.  It keeps the
  * fastest, fills *out (factor_ms and iter_ms: the chosen build and one
  * iteration) and returns MORX_OK.  Shapes change rounding order only.  It
  * allocates its own scratch on the device.

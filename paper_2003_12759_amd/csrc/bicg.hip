@@ -360,9 +360,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
 // p staged in LDS, then A^T's on the rows of S^T with p~ staged, CB columns
 // per round.  Rows sum their slots in the gather kernel's order, so q and q~
 // are the same; the delta partial sums follow the forward half.
-// most columns per block of the halo product: a row's FP64 values stay in
-// registers (32 slots: three columns; 8 slots: eight)
-constexpr int kSpmvHaloNC = 3;
+// most columns per block of the halo product (three per LDS round)
+constexpr int kSpmvHaloNC = 8;
 constexpr int kSpmvHaloNCNarrow = 8;
 
 // W: slots a slice may have (8 or W); HC: list cap (LDS entries)
@@ -426,14 +425,22 @@ __global__ __launch_bounds__(kBlock) void k_spmv_halo(IterArgs a, int par) {
       }
       const uint16_t* lp = lidx + base + t.lane;
       const double* vp = val + base + t.lane;
-      uint32_t la[W];
-      double fb[W];
+      constexpr uint32_t kStride = (uint32_t)(CB * sizeof(double));
+      // 8 slots: a row's local indices and values stay in registers for all
+      // rounds; 32 slots: they are read again per round, a group of kGW
+      // slots at a time with the next group's loads in flight (L2 hits after
+      // the first round), so that wider tiles fit the register budget
+      constexpr bool kHold = W <= kNarrow;
+      uint32_t la[kHold ? W : 1];
+      double fb[kHold ? W : 1];
+      if constexpr (kHold) {
 #pragma unroll
-      for (int m = 0; m < W; ++m) {
-        const uint32_t r = gld(lp + m * kSlice);
-        la[m] = m < w ? r * (uint32_t)(CB * sizeof(double)) : 0u;
-        const double x = gld(vp + m * kSlice);
-        fb[m] = m < w ? x : 0.0;
+        for (int m = 0; m < W; ++m) {
+          const uint32_t r = gld(lp + m * kSlice);
+          la[m] = m < w ? r * kStride : 0u;
+          const double x = gld(vp + m * kSlice);
+          fb[m] = m < w ? x : 0.0;
+        }
       }
 #pragma unroll
       for (int j0 = 0; j0 < NC; j0 += CB) {
@@ -461,37 +468,62 @@ __global__ __launch_bounds__(kBlock) void k_spmv_halo(IterArgs a, int par) {
             for (int c = 0; c < CB; ++c) xs[e * CB + c] = sv[q][c];
           }
         }
+        // (reload form) the round's first group, in flight across the barrier
+        uint32_t lb[2][kGW];
+        double vb[2][kGW];
+        auto load_group = [&](int g, int q) {
+#pragma unroll
+          for (int u = 0; u < kGW; ++u) {
+            const int m = g * kGW + u;
+            const uint32_t r = gld(lp + m * kSlice);
+            lb[q][u] = m < w ? r * kStride : 0u;
+            const double x = gld(vp + m * kSlice);
+            vb[q][u] = m < w ? x : 0.0;
+          }
+        };
+        if constexpr (!kHold) load_group(0, 0);
         __syncthreads();
+        double acc[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) acc[c] = 0.0;
+        const char* xc = (const char*)xs;
+#pragma unroll
+        for (int g = 0; g < W / kGW; ++g) {
+          if (g >= ngw) break;  // uniform
+          if constexpr (!kHold)
+            if (g + 1 < W / kGW && g + 1 < ngw) load_group(g + 1, (g + 1) & 1);
+#pragma unroll
+          for (int c = 0; c < CB; ++c) {
+            double xg[kGW];
+#pragma unroll
+            for (int u = 0; u < kGW; ++u) {
+              const uint32_t ad = kHold ? la[kHold ? g * kGW + u : 0] : lb[g & 1][u];
+              xg[u] = *(const double*)(xc + ad + c * sizeof(double));
+            }
+#pragma unroll
+            for (int u = 0; u < kGW; ++u) {
+              const double f = kHold ? fb[kHold ? g * kGW + u : 0] : vb[g & 1][u];
+              acc[c] = fma(f, xg[u], acc[c]);
+            }
+          }
+        }
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
           const int j = j0 + c;
-          if (j < NC && (valid & (1u << j))) {
-            const char* xc = (const char*)(xs + c);
-            double acc = 0.0;
-#pragma unroll
-            for (int g = 0; g < W / kGW; ++g) {
-              if (g >= ngw) break;  // uniform
-              double xg[kGW];
-#pragma unroll
-              for (int u = 0; u < kGW; ++u) xg[u] = *(const double*)(xc + la[g * kGW + u]);
-#pragma unroll
-              for (int u = 0; u < kGW; ++u) acc = fma(fb[g * kGW + u], xg[u], acc);
-            }
-            if (i < a.n) {
-              const int cc = c0 + j;
-              const double se = sig[j] * ei;
-              if (h == 0) {
-                const double pi = gld(p[j] + i);
-                const double pti = gld(pt[j] + i);
-                const double qi = fma(se, pi, -acc);
-                gst(vptr(a, V_Q, cc) + i, qi);
-                v[j][0] = fma(pti, qi, v[j][0]);
-                v[j][1] = fma(pti, pti, v[j][1]);
-                v[j][2] = fma(qi, qi, v[j][2]);
-              } else {
-                const double pti = gld(pt[j] + i);
-                gst(vptr(a, V_QT, cc) + i, fma(se, pti, -acc));
-              }
+          if (j < NC && (valid & (1u << j)) && i < a.n) {
+            const int cc = c0 + j;
+            const double se = sig[j] * ei;
+            if (h == 0) {
+              const double pi = gld(p[j] + i);
+              const double pti = gld(pt[j] + i);
+              const double qi = fma(se, pi, -acc[c]);
+              gst(vptr(a, V_Q, cc) + i, qi);
+              v[j][0] = fma(pti, qi, v[j][0]);
+              v[j][1] = fma(pti, pti, v[j][1]);
+              v[j][2] = fma(qi, qi, v[j][2]);
+            } else {
+              const double pti = gld(pt[j] + i);
+              gst(vptr(a, V_QT, cc) + i, fma(se, pti, -acc[c]));
             }
           }
         }
@@ -1106,11 +1138,12 @@ static morx_status enqueue_iterations(const IterArgs& a, int prec, int iters, hi
     if (f32) launch(t, TR_FORMP, k_form_p<float>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
     else launch(t, TR_FORMP, k_form_p<double>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
     if (a.hmax > 0 && !a.narrow) {
-      switch (pick_nc(a.nc, std::min(ncs, kSpmvHaloNC))) {
-        case 1: launch(t, TR_SPMV, k_spmv_halo<1, kHaloMaxW, kHaloCap>, grid_of(a, 1, 1), dim3(kBlock), st, a, par); break;
-        case 2: launch(t, TR_SPMV, k_spmv_halo<2, kHaloMaxW, kHaloCap>, grid_of(a, 2, 1), dim3(kBlock), st, a, par); break;
-        default: launch(t, TR_SPMV, k_spmv_halo<3, kHaloMaxW, kHaloCap>, grid_of(a, 3, 1), dim3(kBlock), st, a, par); break;
-      }
+      const int nch = pick_nc(a.nc, std::min(ncs, kSpmvHaloNC));
+      MORX_NC_DISPATCH(nch, {
+        if constexpr (NC <= kSpmvHaloNC)
+          launch(t, TR_SPMV, k_spmv_halo<NC, kHaloMaxW, kHaloCap>, grid_of(a, NC, 1),
+                 dim3(kBlock), st, a, par);
+      });
     } else if (a.hmax > 0) {
       const int nch = pick_nc(a.nc, std::min(ncs, kSpmvHaloNCNarrow));
       MORX_NC_DISPATCH(nch, {
@@ -1817,48 +1850,43 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
     return MORX_OK;
   };
   double best_i = 1e300;
-  int best_nc = -1, best_spw = -1, best_ncs = -1;
-  // chain tile and row block (the shifted pair follows the chain tile) ...
-  std::vector<int> seen;
-  for (int ncmax : {16, 8, 4, 2, 1}) {
-    const int ncv = pick_nc(ncols, ncmax);
-    if (std::find(seen.begin(), seen.end(), ncv) != seen.end()) continue;
-    seen.push_back(ncv);
-    for (int mult : {1, 2, 4}) {
-      const int spw = spw0 * mult;
-      if (mult > 1 && (sys->nslice + (int64_t)kWavesPerBlock * spw - 1) /
-                              ((int64_t)kWavesPerBlock * spw) < 256)
-        break;  // too few row blocks to fill the chip
-      double ms = 0.0;
-      s = time_shape(ncmax, spw, -1, &ms);
-      if (s != MORX_OK) break;
-      if (ms < best_i) {
-        best_i = ms;
-        best_nc = ncmax;
-        best_spw = spw;
+  int best_nc = -1, best_spw = -1, best_ncs = -1, best_chain = -1;
+  // chain kernel (the built-in one, and where the pattern has a halo layout
+  // the other: row gathers for wide patterns, the halo layout for narrow
+  // ones), chain tile and row block; the shifted pair follows the chain tile
+  // and kernel ...
+  std::vector<int> kernels{-1};
+  if (halo_available(sys)) kernels.push_back(pattern_narrow(sys) ? 1 : 0);
+  for (int kern : kernels) {
+    sys->tune_chain = kern;
+    std::vector<int> seen;
+    for (int ncmax : {16, 12, 8, 6, 4, 3, 2, 1}) {
+      const int ncv = pick_nc(ncols, ncmax);
+      if (std::find(seen.begin(), seen.end(), ncv) != seen.end()) continue;
+      seen.push_back(ncv);
+      for (int mult : {1, 2, 4}) {
+        const int spw = spw0 * mult;
+        if (mult > 1 && (sys->nslice + (int64_t)kWavesPerBlock * spw - 1) /
+                                ((int64_t)kWavesPerBlock * spw) < 256)
+          break;  // too few row blocks to fill the chip
+        double ms = 0.0;
+        s = time_shape(ncmax, spw, -1, &ms);
+        if (s != MORX_OK) break;
+        if (ms < best_i) {
+          best_i = ms;
+          best_nc = ncmax;
+          best_spw = spw;
+          best_chain = kern;
+        }
       }
+      if (s != MORX_OK) break;
     }
     if (s != MORX_OK) break;
   }
-  // ... then, where the pattern has a halo layout, the other chain kernel at
-  // that shape (gathers for wide patterns, the halo layout for narrow ones;
-  // the shifted pair follows the chain kernel) ...
-  int best_chain = -1;
-  if (s == MORX_OK && halo_available(sys)) {
-    const int alt = pattern_narrow(sys) ? 1 : 0;
-    sys->tune_chain = alt;
-    double ms = 0.0;
-    s = time_shape(best_nc, best_spw, -1, &ms);
-    if (s == MORX_OK && ms < best_i) {
-      best_i = ms;
-      best_chain = alt;
-    }
-    sys->tune_chain = best_chain;
-  }
+  sys->tune_chain = best_chain;
   // ... and the shifted pair's own tile with the chain shape and kernel fixed
   if (s == MORX_OK) {
-    seen.clear();
-    seen.push_back(pick_nc(ncols, best_nc));
+    std::vector<int> seen{pick_nc(ncols, best_nc)};
     for (int ncs : {16, 8, 4, 2, 1}) {
       const int ncv = pick_nc(ncols, ncs);
       if (std::find(seen.begin(), seen.end(), ncv) != seen.end()) continue;
