@@ -36,12 +36,12 @@ def traffic_file(workload: str) -> str:
 
 
 def kernel_source_hash() -> str:
-    """sha256 of the sources of the iteration kernels (bicg.hip, chain_kernels.h,
-    common.h)."""
+    """sha256 of the chain step's sources (the kernels, their launches and the
+    shared helpers)."""
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("bicg.hip", "chain_kernels.h", "common.h"):
+    for f in ("chain_kernels.h", "chain_f64.hip", "chain_f32.hip", "chain_bf16.hip", "common.h"):
         with open(os.path.join(ROOT, "paper_2003_12759_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

@@ -60,13 +60,30 @@ def _convdiff(N):
     return w.A, w.e
 
 
+def _dense(n, seed, per_row=None):
+    """Diagonally dominant; every entry stored (per_row None) or about
+    per_row random entries a row."""
+    rng = np.random.default_rng(seed)
+    M = rng.standard_normal((n, n)) * 0.2
+    if per_row is not None:
+        M *= rng.random((n, n)) < per_row / n
+    M -= np.diag(1.0 + np.abs(M).sum(axis=1))
+    return sp.csr_matrix(M), rng.uniform(1, 2, n)
+
+
 # 27-point on 11^3 = 1331 rows: 21 slices, so the last block of four slices
 # has one; the random pattern has no stencil structure and rows of ~11
-# entries; the 7-point operator takes the halo kernel for rows of at most 8
+# entries; the 7-point operator takes the halo kernel for rows of at most 8;
+# the small dense systems have one slice (three waves of the block without
+# rows), rows of 9 and of 31 entries, and a partial slice of 70 rows with
+# ~20 entries a row
 CASES = {
     "varcoef27_n1331": lambda: _varcoef27(11),
     "random_wide_n1300": lambda: _wide_random(1300, 10, 7),
     "convdiff_n1331": lambda: _convdiff(11),
+    "dense_n9": lambda: _dense(9, 1),
+    "dense_n31": lambda: _dense(31, 2),
+    "random_n70": lambda: _dense(70, 3, per_row=20),
 }
 
 
