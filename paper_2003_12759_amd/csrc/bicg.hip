@@ -482,6 +482,17 @@ __global__ __launch_bounds__(kBlock) void k_spmv_halo(IterArgs a, int par) {
           }
         };
         if constexpr (!kHold) load_group(0, 0);
+        // the row's p_i and p~_i of the round's columns, in flight during the sums
+        double pr[CB], ptr_[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          const int j = min(j0 + c, NC - 1);
+          pr[c] = ptr_[c] = 0.0;
+          if (i < a.n) {
+            if (h == 0) pr[c] = gld(p[j] + i);
+            ptr_[c] = gld(pt[j] + i);
+          }
+        }
         __syncthreads();
         double acc[CB];
 #pragma unroll
@@ -514,16 +525,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv_halo(IterArgs a, int par) {
             const int cc = c0 + j;
             const double se = sig[j] * ei;
             if (h == 0) {
-              const double pi = gld(p[j] + i);
-              const double pti = gld(pt[j] + i);
+              const double pi = pr[c];
+              const double pti = ptr_[c];
               const double qi = fma(se, pi, -acc[c]);
               gst(vptr(a, V_Q, cc) + i, qi);
               v[j][0] = fma(pti, qi, v[j][0]);
               v[j][1] = fma(pti, pti, v[j][1]);
               v[j][2] = fma(qi, qi, v[j][2]);
             } else {
-              const double pti = gld(pt[j] + i);
-              gst(vptr(a, V_QT, cc) + i, fma(se, pti, -acc[c]));
+              gst(vptr(a, V_QT, cc) + i, fma(se, ptr_[c], -acc[c]));
             }
           }
         }

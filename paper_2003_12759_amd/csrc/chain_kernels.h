@@ -716,6 +716,16 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
             for (int c = 0; c < CB; ++c) xs[e * CB + c] = (AT)sv[q][c];
           }
         }
+        // (last step) r_i of the round's pairs, in flight during the sums
+        double rr[RHO ? CB : 1];
+        if constexpr (RHO) {
+#pragma unroll
+          for (int c = 0; c < CB; ++c) {
+            rr[c] = 0.0;
+            if (rho_half && j0 + c < ncol && i < a.n)
+              rr[c] = gld(vptr(a, V_R, __builtin_amdgcn_readfirstlane(ck[j0 + c].c)) + i);
+          }
+        }
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
@@ -750,7 +760,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
               if constexpr (RHO) {
                 if (rho_half) {
                   const double zi = (double)zs;
-                  const double ri = gld(vptr(a, V_R, __builtin_amdgcn_readfirstlane(ck[j].c)) + i);
+                  const double ri = rr[c];
                   v[j][0] = fma(zi, ri, v[j][0]);
                   v[j][1] = fma(zi, zi, v[j][1]);
                   v[j][2] = fma(ri, ri, v[j][2]);
