@@ -1136,7 +1136,6 @@ static void enqueue_chain(const IterArgs& a, int prec, hipStream_t st, TraceStat
 
 static morx_status enqueue_iterations(const IterArgs& a, int prec, int iters, hipStream_t st,
                                       TraceState* t) {
-  const int ncv = a.ncv;
   const int ncs = pick_nc(a.nc, a.ncmax_spmv);
   const bool f32 = a.abytes == 4;
   // the first iteration's work lists (fin_delta writes the later ones)

@@ -640,7 +640,6 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
     double v[RHO ? NC : 1][3];
 #pragma unroll
     for (int j = 0; j < (RHO ? NC : 1); ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
-    const int64_t nsell = bwd ? a.nsellT : a.nsell;
     const int32_t* off = bwd ? a.offT : a.off;
     const int32_t* hoff = bwd ? a.hoffT : a.hoff;
     const int32_t* hcol = bwd ? a.hcolT : a.hcol;
