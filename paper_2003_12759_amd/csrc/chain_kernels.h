@@ -589,16 +589,18 @@ __global__ __launch_bounds__(kBlock) void k_chain_narrow(IterArgs a, int s) {
   }
 }
 
-// The chain step on the halo layout, for patterns wider than kNarrow slots
-// whose blocks of kHaloSlices slices touch at most kHaloCap distinct columns
-// (a 27-point stencil: 1,536 for 256 rows).  A block's four waves take one
-// such row block at a time: the entries of CB input vectors at the row
-// block's distinct columns are copied into LDS, then every row sums its
-// slots from LDS through the entries' 16-bit local indices.  The 27 x 256
-// gathers of a 27-point row block read 1,536 distinct entries, so vector
-// reads through the L1 path fall about 4.5-fold and the index stream
-// halves.  Each row sums its slots in order from zero, as the gather
-// kernels do, so the results are the same.
+// The chain step on the halo layout, for patterns whose blocks of
+// kHaloSlices slices touch at most kHaloCap distinct columns (a 27-point
+// stencil: 1,536 for 256 rows; a 7-point one: about 900).  A block's four
+// waves take one such row block at a time: the entries of CB input vectors
+// at the row block's distinct columns are copied into LDS, then every row
+// sums its slots from LDS through the entries' 16-bit local indices.  The
+// 27 x 256 gathers of a 27-point row block read 1,536 distinct entries, so
+// vector reads through the L1 path fall about 4.5-fold (7-point: about
+// 2-fold) and the index stream halves.  Each row sums its slots in order
+// from zero, as the gather kernels do, so the results are the same.  Two
+// forms: W = 32 slots with lists of at most kHaloCap, and W = kNarrow slots
+// with lists of at most kHaloCapNarrow (fewer registers, half the LDS).
 template <int NC>
 struct HaloGroup {
   static constexpr int value = NC < 3 ? NC : 3;  // input vectors per LDS round
