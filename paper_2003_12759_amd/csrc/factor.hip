@@ -350,7 +350,9 @@ NeLayout ne_layout(int maxT, int CG) {
   L.off_cval = base + ((size_t)L.T * 4 + 15) / 16 * 16;
   L.off_L = base;
   const size_t gather = L.off_cval - base + (size_t)L.T * 8;
-  o += std::max(gather, (size_t)G * mat);
+  // the Cholesky factors: lower triangles, packed by columns
+  const size_t tri = (size_t)CG * (CG + 1) / 2 * 8;
+  o += std::max(gather, (size_t)G * tri);
   L.bytes = o;
   return L;
 }
@@ -374,7 +376,10 @@ __global__ __launch_bounds__(64) void k_factor_ne(
   double* cval = (double*)(lds + L.off_cval);
   const int lane = threadIdx.x;
   const int g = lane / CG, i = lane % CG, gbase = g * CG;
-  double* Lc = (double*)(lds + L.off_L) + (size_t)g * CG * LD;  // L(r, c) at Lc[c * LD + r]
+  // L(r, c), r >= c, at Lc[lix(r, c)]: column c (rows c .. CG-1) starts at
+  // c CG - c (c - 1) / 2
+  double* Lc = (double*)(lds + L.off_L) + (size_t)g * (CG * (CG + 1) / 2);
+  auto lix = [](int r, int c) { return c * CG - (c * (c - 1)) / 2 + (r - c); };
 
   for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
     const int lo = trowptr[k];
@@ -477,11 +482,11 @@ __global__ __launch_bounds__(64) void k_factor_ne(
           if (i == c && live) bad = bad || !(piv > kNeTol * gd);
           const double lic = i > c ? gr[c] / d : (i == c ? d : 0.0);
           gr[c] = lic;
-          Lc[c * LD + i] = lic;
+          if (i >= c) Lc[lix(i, c)] = lic;
           __syncthreads();
 #pragma unroll
           for (int l = c + 1; l < CG; ++l)
-            if (l < m) gr[l] = fma(-lic, Lc[c * LD + l], gr[l]);
+            if (l < m) gr[l] = fma(-lic, Lc[lix(l, c)], gr[l]);
         }
       }
       // L z = y, then L^T q = z
@@ -498,7 +503,7 @@ __global__ __launch_bounds__(64) void k_factor_ne(
         if (c < m) {
           const double qc = __shfl(y / gr[c], gbase + c, 64);
           if (i == c) y = qc;
-          else if (i < c) y = fma(-Lc[i * LD + c], qc, y);
+          else if (i < c) y = fma(-Lc[lix(c, i)], qc, y);
         }
       }
       if (row && live) {
