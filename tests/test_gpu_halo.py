@@ -179,3 +179,48 @@ def test_chain_kernel_tune_values(ctx):
     S.set_tune(chain_kernel=-1)
     assert S.get_tune()["chain_kernel"] == 1
     S.close()
+
+
+@pytest.mark.parametrize("name", ["varcoef7_n1000_mimo", "varcoef27_n729_mimo"])
+def test_halo_kernels_widest_tiles(ctx, name):
+    """32 columns (8 shifts x 4 inputs) with the chain tile pinned at 16 and the
+    shifted pair's at 8: the widest instances of both halo kernels (8-slot
+    forms for the 7-point operator, 32-slot forms for the 27-point one)
+    against the gather kernels (both solutions within their residuals of the
+    exact one), and every pair's true residuals."""
+    from paper_2003_12759_amd import api
+
+    if name.startswith("varcoef7"):
+        w = make_workload(2, N=10, nshift=8)
+        A, e, B, C, sig = w.A, w.e, w.B, w.C, w.rounds[0]
+    else:
+        A, e = _varcoef27(9)
+        rng = np.random.default_rng(21)
+        B = rng.standard_normal((A.shape[0], 4))
+        C = rng.standard_normal((A.shape[0], 4))
+        sig = list(np.logspace(0, 3, 8))
+    m = B.shape[1]
+    S = api.System(ctx, A, e)
+    runs = {}
+    for k in (1, 0):
+        S.set_tune(cols_per_wave=16, spmv_cols_per_wave=8, chain_kernel=k)
+        _say(f"{name} tile 16/8 chain_kernel={k}")
+        X, Y, st, stats = S.solve_shifts(sig, B, C, prec="f64")
+        runs[k] = (X.cpu().numpy(), Y.cpu().numpy(), stats)
+    S.close()
+    for i, s in enumerate(sig):
+        M = (s * sp.diags(e) - A).tocsr()
+        smin = np.abs(np.linalg.eigvalsh(M.toarray())).min()  # both operators are symmetric
+        for j in range(m):
+            c = i * m + j
+            res = {}
+            for k in (1, 0):
+                Xg, Yg, stats = runs[k]
+                assert stats[c].status == 0
+                res[k] = _relres(M, Xg[:, c], B[:, j])
+                assert res[k] <= 1.01e-10
+                assert _relres(M.T, Yg[:, c], C[:, j]) <= 1.01e-10
+            # both within their residual of the exact solution
+            xh, xg = runs[1][0][:, c], runs[0][0][:, c]
+            bound = (res[1] + res[0]) * np.linalg.norm(B[:, j]) / smin * 1.01
+            assert np.linalg.norm(xh - xg) <= bound, (i, j)
