@@ -327,10 +327,16 @@ struct NeLayout {
   size_t off_J, off_off, off_E, off_H, off_G0, off_crow, off_cval, off_L, bytes;
 };
 
+// threads of a normal-equations block, whose lane groups solve as many shifts
+// of one column problem at a time: two waves for groups of 32 lanes (the LDS
+// copy of the column's matrices is then shared by four shifts), one wave for
+// narrower groups (their patterns already fit eight or four shifts per wave)
+constexpr int ne_threads(int CG) { return CG >= 32 ? 128 : 64; }
+
 NeLayout ne_layout(int maxT, int CG) {
   NeLayout L;
   L.T = std::max(maxT, 1);
-  const int G = 64 / CG;
+  const int G = ne_threads(CG) / CG;
   const size_t mat = (size_t)CG * (CG + 1) * 8;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -358,14 +364,16 @@ NeLayout ne_layout(int maxT, int CG) {
 }
 
 template <typename VT, int CG>
-__global__ __launch_bounds__(64) void k_factor_ne(
+__global__ __launch_bounds__(ne_threads(CG)) void k_factor_ne(
     const int32_t* __restrict__ trowptr, const int32_t* __restrict__ tcol,
     const double* __restrict__ tval, const double* __restrict__ e,
     const int32_t* __restrict__ tp2s, const int32_t* __restrict__ sellT_off, int64_t n,
     const FactorJob* __restrict__ jobs, int njobs, NeLayout L, int* __restrict__ fb_count,
     int32_t* __restrict__ fb_list) {
-  constexpr int G = 64 / CG;
+  constexpr int kNeThreads = ne_threads(CG);
+  constexpr int G = kNeThreads / CG;
   constexpr int LD = CG + 1;  // stride of the m x m matrices in LDS
+  __shared__ int a_sh, bad_sh;  // the diagonal's position in J; a shift's fallback
   extern __shared__ __align__(16) unsigned char lds[];
   int* J = (int*)(lds + L.off_J);
   int* coff = (int*)(lds + L.off_off);
@@ -374,8 +382,11 @@ __global__ __launch_bounds__(64) void k_factor_ne(
   double* G0 = (double*)(lds + L.off_G0);
   int* crow = (int*)(lds + L.off_crow);
   double* cval = (double*)(lds + L.off_cval);
+  // the column's set-up (gathers, scan, ballot) runs on the first wave; the
+  // lane groups of both waves then take one shift each
   const int lane = threadIdx.x;
-  const int g = lane / CG, i = lane % CG, gbase = g * CG;
+  const int g = lane / CG, i = lane % CG, gbase = (g * CG) & 63;  // group's first lane in its wave
+  if (lane == 0) bad_sh = 0;
   // L(r, c), r >= c, at Lc[lix(r, c)]: column c (rows c .. CG-1) starts at
   // c CG - c (c - 1) / 2
   double* Lc = (double*)(lds + L.off_L) + (size_t)g * (CG * (CG + 1) / 2);
@@ -393,18 +404,22 @@ __global__ __launch_bounds__(64) void k_factor_ne(
       J[lane] = jc;
       EJ[lane] = e[jc];
     }
-    int T;
-    const int off = wave_excl_scan(len, lane, &T);
-    if (lane < m) coff[lane] = off;
-    if (lane == 0) coff[m] = T;
-    for (int u = 0; u < len; ++u) {
-      crow[off + u] = tcol[cb + u];
-      cval[off + u] = tval[cb + u];
+    int off = 0;
+    if (lane < 64) {  // uniform over each wave
+      int T;
+      off = wave_excl_scan(len, lane, &T);
+      if (lane < m) coff[lane] = off;
+      if (lane == 0) coff[m] = T;
+      for (int u = 0; u < len; ++u) {
+        crow[off + u] = tcol[cb + u];
+        cval[off + u] = tval[cb + u];
+      }
+      const unsigned long long am = __ballot(jc == (int)k);
+      if (lane == 0) a_sh = am ? (int)__ffsll((long long)am) - 1 : 0;  // the diagonal is in S
     }
-    const unsigned long long am = __ballot(jc == (int)k);
-    const int a = am ? (int)__ffsll((long long)am) - 1 : 0;  // the diagonal is always in S
-    for (int t = lane; t < m * LD; t += 64) Ajj[t] = 0.0;
+    for (int t = lane; t < m * LD; t += kNeThreads) Ajj[t] = 0.0;
     __syncthreads();
+    const int a = a_sh;
     // Ajj(r, l) = A(J_r, J_l): the rows of column l that lie in J_k
     if (lane < m) {
       for (int u = 0; u < len; ++u) {
@@ -420,7 +435,7 @@ __global__ __launch_bounds__(64) void k_factor_ne(
     }
     // G0(r, l), r <= l: merge of the sorted rows of columns r and l
     const int npair = m * (m + 1) / 2;
-    for (int p = lane; p < npair; p += 64) {
+    for (int p = lane; p < npair; p += kNeThreads) {
       int r = 0, rem = p;
       while (rem >= m - r) {
         rem -= m - r;
@@ -513,7 +528,12 @@ __global__ __launch_bounds__(64) void k_factor_ne(
       }
       __syncthreads();  // L of this round is read up to here
     }
-    if (__ballot(bad) != 0ull && lane == 0) fb_list[atomicAdd(fb_count, 1)] = (int32_t)k;
+    if (__ballot(bad) != 0ull && (lane & 63) == 0) atomicOr(&bad_sh, 1);
+    __syncthreads();
+    if (lane == 0 && bad_sh) {
+      fb_list[atomicAdd(fb_count, 1)] = (int32_t)k;
+      bad_sh = 0;
+    }
   }
 }
 
@@ -997,7 +1017,7 @@ morx_status factor_build_many(morx_system sys, int32_t prec, const FactorJob* jo
     const int ngrid = (int)std::min<int64_t>(sys->n, (int64_t)std::max(sys->ctx->num_cu, 1) * 32);
     int* fb_count = (int*)sb.p + 1;
 #define MORX_NE_LAUNCH(VT, CGV)                                                                 \
-  k_factor_ne<VT, CGV><<<ngrid, 64, N.bytes, st>>>(sys->trowptr, sys->tcol, sys->tval, sys->e, \
+  k_factor_ne<VT, CGV><<<ngrid, ne_threads(CGV), N.bytes, st>>>(sys->trowptr, sys->tcol, sys->tval, sys->e, \
                                                    sys->tp2s, sys->sellT.off, sys->n,         \
                                                    (FactorJob*)jb.p, njobs, N, fb_count, fb_list)
 #define MORX_NE_CG(VT)                 \
