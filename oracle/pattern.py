@@ -3,7 +3,7 @@
 The SPAI column problem (Section III-A, eq. gen-precond-par) restricts column
 k of the approximate inverse to a prescribed support.  Here that support is
 the pattern of column k of ``A`` plus the diagonal entry (the paper's MSPAI
-grows patterns adaptively; this build fixes them to A's pattern).  Because
+grows patterns adaptively; here they are fixed to A's pattern).  Because
 ``E`` is diagonal, ``sigma E - A`` has exactly this pattern ``S`` for every
 shift, and the reuse factors ``Q_i`` are given the same support.
 
