@@ -30,6 +30,8 @@ if ROOT not in sys.path:
 METRIC = "shifted solves/sec to rel-res 1e-10 (batched vs plain); HBM GB/s; p99 lat"
 HBM_PEAK_GBPS = 8000.0
 DOMINANT = "chain_step"
+
+
 def traffic_file(workload: str) -> str:
     """Measured HBM traffic of the chain step on a workload (rocprofv3 counters)."""
     return os.path.join(ROOT, "profiles", f"traffic_chain_step_{workload}.json")
