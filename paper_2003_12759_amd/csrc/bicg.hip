@@ -1873,6 +1873,7 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
       const int ncv = pick_nc(ncols, ncmax);
       if (std::find(seen.begin(), seen.end(), ncv) != seen.end()) continue;
       seen.push_back(ncv);
+      double prev = 1e300;
       for (int mult : {1, 2, 4}) {
         const int spw = spw0 * mult;
         if (mult > 1 && (sys->nslice + (int64_t)kWavesPerBlock * spw - 1) /
@@ -1887,6 +1888,8 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
           best_spw = spw;
           best_chain = kern;
         }
+        if (ms > prev) break;  // a wider row block already lost at this tile
+        prev = ms;
       }
       if (s != MORX_OK) break;
     }
