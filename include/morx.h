@@ -135,6 +135,8 @@ morx_status morx_system_pattern(morx_system sys, int32_t* rowptr, int32_t* colin
  * Y = (sigma E - A) X, or (sigma E - A)^T X when trans != 0, for ncol
  * columns (X, Y (dev), column-major, ldx, ldy >= n).  The shifted matrix is
  * never formed: E's diagonal is applied inside the product (appendix B form).
+ * Runs the shifted-pair kernel of a solve (morx_shifted_apply_pair with one
+ * side); ncol 1..1024.
  */
 morx_status morx_shifted_apply(morx_system sys, double sigma, int32_t trans, int32_t ncol,
                                const double* X, int64_t ldx, double* Y, int64_t ldy,
@@ -159,14 +161,85 @@ morx_status morx_factor_values(morx_factor f, double* val, void* stream);
 morx_status morx_factor_destroy(morx_factor f);
 
 /*
+ * What a factor is: a SPAI of sigma_new E - A (is_spai = 1, sigma_prev
+ * unused and 0), or the update with min ||A_prev - A_new Q||_F between
+ * sigma_prev and sigma_new (is_spai = 0; Table 2, second approach).
+ */
+typedef struct {
+  int32_t is_spai;
+  int32_t reserved;
+  double sigma_prev;
+  double sigma_new;
+} morx_factor_spec;
+
+/*
+ * Build njobs factors (jobs, host) in one launch of the least-squares
+ * kernel, as a solve builds the factors of its shifts (Algorithm 4 builds
+ * each shift's factor from the shifts alone, so every factor of a call is
+ * independent).  out (host, njobs handles) receives the factors; on failure
+ * none is returned.  Limits as morx_factor_spai; njobs 1..4096.
+ */
+morx_status morx_factor_build(morx_system sys, int32_t njobs, const morx_factor_spec* jobs,
+                              int32_t prec, void* stream, morx_factor* out);
+
+/*
+ * A factor with given values: val (dev, nnz(S) entries in the CSR order of
+ * S that morx_system_pattern returns) is rounded to prec (FP64 -> FP32 by
+ * round-to-nearest-even, then -> BF16 by round-to-nearest-even on the FP32
+ * bits) and stored in both orders, as the least-squares kernels store their
+ * results.  The paper computes its preconditioners in a separate program
+ * and loads them into the solver (Section IV); this is that hand-over.  The
+ * factor's spec reads SPAI at sigma 0.
+ */
+morx_status morx_factor_import(morx_system sys, const double* val, int32_t prec, void* stream,
+                               morx_factor* out);
+
+/*
  * Apply the product F_{k-1} ... F_1 F_0 (chain[0] applied first) to ncol
  * columns, or its transpose F_0^T ... F_{k-1}^T when trans != 0, one sparse
- * product per factor (Section III-B: the product is never formed).
- * X and Y (dev) may not overlap.
+ * product per factor (Section III-B: the product is never formed), in FP64,
+ * by the chain kernels of a solve (morx_chain_apply_batch with one chain
+ * for every column and one side).  X and Y (dev) may not overlap; ncol
+ * 1..1024, nfactor 1..64.
  */
 morx_status morx_chain_apply(morx_system sys, int32_t nfactor, const morx_factor* chain,
                              int32_t trans, int32_t ncol, const double* X, int64_t ldx,
                              double* Y, int64_t ldy, void* stream);
+
+/*
+ * The chain apply of a solve, outside a solve: column c of X is multiplied
+ * by the chain chains[c * lcap + 0 .. lens[c] - 1] (factor 0 applied first),
+ * column c of Xt by its transpose (factor lens[c] - 1 transposed first), by
+ * the very kernels, work lists, tile widths and row blocks an iteration of
+ * morx_solve_shifts launches for ncol column pairs with these chains
+ * (Section III-B: one sparse product per factor, the product never formed).
+ * apply_prec MORX_F32 rounds the input and every pass result to FP32, as
+ * morx_opts.apply_prec does.  X/Y (dev, n x ncol, ldx/ldy >= n) and Xt/Yt
+ * (likewise) may each be NULL as a pair: that direction's input is then
+ * zero and its output dropped.  Every factor has one storage precision;
+ * chains (host) holds ncol * lcap handles, lens (host) ncol lengths in
+ * 1..lcap; ncol 1..1024, lcap 1..64.  Outputs do not overlap inputs.
+ * Allocates a workspace for ncol columns for the duration of the call.
+ */
+morx_status morx_chain_apply_batch(morx_system sys, int32_t ncol, int32_t lcap,
+                                   const morx_factor* chains, const int32_t* lens,
+                                   const double* X, int64_t ldx, double* Y, int64_t ldy,
+                                   const double* Xt, int64_t ldxt, double* Yt, int64_t ldyt,
+                                   int32_t apply_prec, void* stream);
+
+/*
+ * The shifted pair of a solve, outside a solve: Y[:, c] = (sigmas[c] E - A)
+ * X[:, c] and Yt[:, c] = (sigmas[c] E - A)^T Xt[:, c] by the kernel and
+ * launch shape an iteration of morx_solve_shifts runs for ncol column pairs
+ * (E's diagonal applied inside the product; appendix B form).  sigmas
+ * (host, ncol finite values); either side may be NULL as a pair (its input
+ * is then zero and its output dropped); ncol 1..1024.  Allocates a
+ * workspace for ncol columns for the duration of the call.
+ */
+morx_status morx_shifted_apply_pair(morx_system sys, int32_t ncol, const double* sigmas,
+                                    const double* X, int64_t ldx, double* Y, int64_t ldy,
+                                    const double* Xt, int64_t ldxt, double* Yt, int64_t ldyt,
+                                    void* stream);
 
 /*
  * The hot path.  For the nshift shifts sigmas[] (host, chain order) and the
@@ -183,6 +256,20 @@ morx_status morx_solve_shifts(morx_system sys, int32_t nshift, const double* sig
                               const double* B, int64_t ldb, const double* C, int64_t ldc,
                               double* X, int64_t ldx, double* Y, int64_t ldy,
                               const morx_opts* opts, morx_col_stats* stats, void* stream);
+
+/*
+ * The preconditioner chains of the last morx_solve_shifts,
+ * morx_solve_moments or morx_gmres_shifts call on sys, one per shift in
+ * the call's order (Algorithm 4 for MORX_CHAIN_RESET / NEXT_ROUND: the
+ * vertical chain P_1^(1), Q_1^(2), ..., Q_1^(z), then Q_2^(z) ... Q_i^(z);
+ * the comparator schedules otherwise), each factor described by its spec in
+ * application order.  *nshift receives the call's shift count; for shifts
+ * i < cap_shifts, lens[i] (host) receives the chain length and
+ * specs[i * ldspec + k] (host) factor k, for k < min(lens[i], ldspec).
+ * MORX_E_INVALID if no solve has run on the system.
+ */
+morx_status morx_last_chains(morx_system sys, int32_t cap_shifts, int32_t ldspec, int32_t* nshift,
+                             int32_t* lens, morx_factor_spec* specs);
 
 /*
  * Higher moments at the same shifts (the inner loop of AIRGA, Algorithm 1,
@@ -344,9 +431,15 @@ morx_status morx_autotune(morx_system sys, double sigma, int32_t ncols, int32_t 
  * keeps a chain of `anchors` factors (SPAI at the first anchor, column-wise
  * updates between consecutive anchors, log-spaced over [anchor_min,
  * anchor_max]); a request adds one update from its nearest anchor
- * (Section III-B, Table 2 second approach).  Systems must outlive the server;
- * b and x (dev, n entries) stay owned by the caller until the request is
- * finished.  submit, poll, wait and info are thread-safe.
+ * (Section III-B, Table 2 second approach; the nearest anchor in log(sigma),
+ * the first on ties).  A system is made resident (slot batch and anchors)
+ * on its first admitted request; when a request's system or factor does not
+ * fit the budget, idle resident systems (no request in a slot) are released,
+ * least recently used first, and a request that cannot fit even then, with
+ * nothing left running, finishes with MORX_E_ADMISSION.  Systems must
+ * outlive the server; b and x (dev, n entries) stay owned by the caller
+ * until the request is finished.  submit, poll, wait, info, counts and
+ * chain are thread-safe.
  */
 typedef struct morx_server_s* morx_server;
 
@@ -380,7 +473,36 @@ morx_status morx_serve_wait(morx_server srv, uint64_t ticket, morx_col_stats* st
                             double* latency_s);
 morx_status morx_serve_info(morx_server srv, uint64_t* submitted, uint64_t* completed,
                             int32_t* running, int32_t* queued, int64_t* bytes_in_use);
-/* Finishes every submitted request, then frees the server. */
+
+/* Scheduler counters since morx_serve_start. */
+typedef struct {
+  uint64_t admitted;        /* requests given a slot                                  */
+  uint64_t joined_running;  /* of those, admitted while another request of the same
+                               system was already iterating on the device (the
+                               continuous-batching case)                              */
+  uint64_t segments;        /* iteration segments launched (one per busy system and
+                               scheduler pass)                                        */
+  uint64_t systems_made;    /* systems made resident (slot batch and anchors built)   */
+  uint64_t systems_evicted; /* idle resident systems released, least recently used
+                               first, to admit a request that did not fit             */
+  int32_t resident;         /* systems resident now                                   */
+  int32_t max_running;      /* most requests running at once                          */
+} morx_serve_counts;
+morx_status morx_serve_counts_get(morx_server srv, morx_serve_counts* out);
+
+/*
+ * The preconditioner chain of an admitted request, in application order:
+ * the system's anchor factors up to its nearest anchor (SPAI at the first
+ * anchor, then the updates between consecutive anchors) and the request's
+ * own update from that anchor to its shift.  MORX_E_PENDING until the
+ * request is admitted; valid until the ticket is taken by poll or wait.
+ * *len receives the chain length and specs (host) its first min(len, cap)
+ * factors.
+ */
+morx_status morx_serve_chain(morx_server srv, uint64_t ticket, int32_t cap, int32_t* len,
+                             morx_factor_spec* specs);
+/* Finishes every submitted request, then frees the server (and the slot
+   batches and anchor factors it holds). */
 morx_status morx_serve_stop(morx_server srv);
 
 /*

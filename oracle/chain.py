@@ -24,9 +24,10 @@ vector.  The Krylov recurrences that consume it stay FP64.
 
 Two comparators use other schedules: :func:`schedule_direct` (a fresh SPAI
 per shift, no reuse) and :func:`schedule_first` (Table 2's first approach,
-every update taken from the first shift).
+every update taken from the first shift).  Serving uses
+:func:`schedule_anchored`: a resident anchor chain and one update per request.
 
-Pinned by: hand-written expected schedules (all three), the chain
+Pinned by: hand-written expected schedules (all four), the chain
 apply against the explicitly formed dense product on small matrices, and for
 the FP32 apply: exact agreement with the FP64 apply when every intermediate
 is an FP32 number, a rounding-error bound per pass, and FP32-representable
@@ -34,6 +35,7 @@ outputs (tests/test_oracle_pins.py).
 """
 from __future__ import annotations
 
+import math
 from typing import List, Sequence, Tuple
 
 import numpy as np
@@ -108,6 +110,29 @@ def schedule_first(rounds: Sequence[Sequence[float]]):
             round_chains.append([p1, len(specs) - 1])
         chains.append(round_chains)
     return specs, chains
+
+
+def anchor_shifts(count: int, lo: float, hi: float) -> List[float]:
+    """``count`` anchor shifts log-spaced over ``[lo, hi]``: ``lo (hi/lo)^(k/(count-1))``."""
+    if count == 1:
+        return [lo * (hi / lo) ** 0.0]
+    return [lo * (hi / lo) ** (k / (count - 1)) for k in range(count)]
+
+
+def schedule_anchored(anchors: Sequence[float], sigma: float) -> List[FactorSpec]:
+    """The serving reading of Table 2's second approach along the horizontal
+    direction of Section III-C: a resident chain of anchors (SPAI at the
+    first, an update between each pair of consecutive anchors) and, for a
+    request at ``sigma``, one more update from its nearest anchor (smallest
+    ``|log sigma - log a_k|``, the first on ties).  Returns the request's
+    chain as factor specs in application order."""
+    dist = [abs(math.log(sigma) - math.log(a)) for a in anchors]
+    k = min(range(len(anchors)), key=lambda j: (dist[j], j))
+    out: List[FactorSpec] = [("spai", float(anchors[0]))]
+    for j in range(1, k + 1):
+        out.append(("update", float(anchors[j - 1]), float(anchors[j])))
+    out.append(("update", float(anchors[k]), float(sigma)))
+    return out
 
 
 def apply(factors, chain: Sequence[int], v: np.ndarray, apply_prec: str = "f64") -> np.ndarray:

@@ -731,6 +731,46 @@ __global__ __launch_bounds__(256) void k_copy_out(IterArgs a, SlotList sl) {
   }
 }
 
+// Inputs of a product run outside a solve: column c of X into slot vector
+// vf (and its FP32 copy when the apply is FP32), of Xt into vb; missing
+// sides are zero
+__global__ __launch_bounds__(256) void k_probe_in(IterArgs a, int vf, int vb, const double* X,
+                                                  int64_t ldx, const double* Xt, int64_t ldxt,
+                                                  int rcopy) {
+  const int c = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n;
+       i += (int64_t)gridDim.x * 256) {
+    const double x = X ? X[(int64_t)c * ldx + i] : 0.0;
+    const double xt = Xt ? Xt[(int64_t)c * ldxt + i] : 0.0;
+    vptr(a, vf, c)[i] = x;
+    vptr(a, vb, c)[i] = xt;
+    if (rcopy) store_rcopy(a, c, i, x, xt);
+  }
+}
+
+// Outputs of such a product: the chain results z, z~ (apply precision,
+// widened) when `chain`, else the shifted pair's q, q~
+__global__ __launch_bounds__(256) void k_probe_out(IterArgs a, int chain, double* Y, int64_t ldy,
+                                                   double* Yt, int64_t ldyt) {
+  const int c = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n;
+       i += (int64_t)gridDim.x * 256) {
+    double y, yt;
+    if (!chain) {
+      y = vptr(a, V_Q, c)[i];
+      yt = vptr(a, V_QT, c)[i];
+    } else if (a.abytes == 4) {
+      y = (double)aptr<float>(a, A_Z, c)[i];
+      yt = (double)aptr<float>(a, A_ZT, c)[i];
+    } else {
+      y = aptr<double>(a, A_Z, c)[i];
+      yt = aptr<double>(a, A_ZT, c)[i];
+    }
+    if (Y) Y[(int64_t)c * ldy + i] = y;
+    if (Yt) Yt[(int64_t)c * ldyt + i] = yt;
+  }
+}
+
 __global__ void k_zero(double* p, int64_t count) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = 0.0;
@@ -1134,9 +1174,33 @@ static void enqueue_chain(const IterArgs& a, int prec, hipStream_t st, TraceStat
   }
 }
 
+// q = A_s p, q~ = A_s^T p~ of an iteration (p in the parity-`par` slots):
+// the halo kernel where the chain step uses the halo layout, else row gathers
+static void enqueue_spmv(const IterArgs& a, int par, hipStream_t st, TraceState* t) {
+  const int ncs = pick_nc(a.nc, a.ncmax_spmv);
+  if (a.hmax > 0 && !a.narrow) {
+    const int nch = pick_nc(a.nc, std::min(ncs, kSpmvHaloNC));
+    MORX_NC_DISPATCH(nch, {
+      if constexpr (NC <= kSpmvHaloNC)
+        launch(t, TR_SPMV, k_spmv_halo<NC, kHaloMaxW, kHaloCap>, grid_of(a, NC, 1),
+               dim3(kBlock), st, a, par);
+    });
+  } else if (a.hmax > 0) {
+    const int nch = pick_nc(a.nc, std::min(ncs, kSpmvHaloNCNarrow));
+    MORX_NC_DISPATCH(nch, {
+      if constexpr (NC <= kSpmvHaloNCNarrow)
+        launch(t, TR_SPMV, k_spmv_halo<NC, kNarrow, kHaloCapNarrow>, grid_of(a, NC, 1),
+               dim3(kBlock), st, a, par);
+    });
+  } else {
+    MORX_NC_DISPATCH(ncs, {
+      launch(t, TR_SPMV, k_spmv_pair<NC>, grid_of(a, NC, 1), dim3(kBlock), st, a, par);
+    });
+  }
+}
+
 static morx_status enqueue_iterations(const IterArgs& a, int prec, int iters, hipStream_t st,
                                       TraceState* t) {
-  const int ncs = pick_nc(a.nc, a.ncmax_spmv);
   const bool f32 = a.abytes == 4;
   // the first iteration's work lists (fin_delta writes the later ones)
   k_plan<<<1, kFinThreads, 0, st>>>(a);
@@ -1146,25 +1210,7 @@ static morx_status enqueue_iterations(const IterArgs& a, int prec, int iters, hi
     k_fin_rho<<<1, kFinThreads, 0, st>>>(a);
     if (f32) launch(t, TR_FORMP, k_form_p<float>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
     else launch(t, TR_FORMP, k_form_p<double>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
-    if (a.hmax > 0 && !a.narrow) {
-      const int nch = pick_nc(a.nc, std::min(ncs, kSpmvHaloNC));
-      MORX_NC_DISPATCH(nch, {
-        if constexpr (NC <= kSpmvHaloNC)
-          launch(t, TR_SPMV, k_spmv_halo<NC, kHaloMaxW, kHaloCap>, grid_of(a, NC, 1),
-                 dim3(kBlock), st, a, par);
-      });
-    } else if (a.hmax > 0) {
-      const int nch = pick_nc(a.nc, std::min(ncs, kSpmvHaloNCNarrow));
-      MORX_NC_DISPATCH(nch, {
-        if constexpr (NC <= kSpmvHaloNCNarrow)
-          launch(t, TR_SPMV, k_spmv_halo<NC, kNarrow, kHaloCapNarrow>, grid_of(a, NC, 1),
-                 dim3(kBlock), st, a, par);
-      });
-    } else {
-      MORX_NC_DISPATCH(ncs, {
-        launch(t, TR_SPMV, k_spmv_pair<NC>, grid_of(a, NC, 1), dim3(kBlock), st, a, par);
-      });
-    }
+    enqueue_spmv(a, par, st, t);
     k_fin_delta<<<1, kFinThreads, 0, st>>>(a);
     // elementwise: one column per wave, nothing to share between columns
     launch(t, TR_UPDATE, k_update<1>, grid_of(a, 1, 1), dim3(kBlock), st, a, par);
@@ -1484,6 +1530,17 @@ morx_status plan_chains(morx_system sys, int nshift, const double* sigmas, const
       for (int k = 0; k <= i; ++k) plan.chains[i].push_back(fresh[k]);
     }
   }
+  // what each shift's chain is, for morx_last_chains
+  sys->last_chains.assign(nshift, {});
+  for (int i = 0; i < nshift; ++i)
+    for (morx_factor f : plan.chains[i]) {
+      morx_factor_spec sp{};
+      sp.is_spai = f->is_spai ? 1 : 0;
+      sp.sigma_prev = f->is_spai ? 0.0 : f->sigma_prev;
+      sp.sigma_new = f->sigma_new;
+      sys->last_chains[i].push_back(sp);
+    }
+  sys->has_last_chains = true;
   return MORX_OK;
 }
 
@@ -1968,4 +2025,166 @@ extern "C" morx_status morx_autotune(morx_system sys, double sigma, int32_t ncol
   if (e1) hipEventDestroy(e1);
   morx_status s2 = stream_leave(ctx, caller);
   return s != MORX_OK ? s : s2;
+}
+
+// ---------------------------------------------------------------------------
+// the chain step and the shifted pair of a solve, on caller columns
+//
+// A temporary slot batch holds the columns as active BiCG slots: the inputs
+// go where an iteration's first chain pass (r, r~) or the shifted pair (p,
+// p~) reads them, the work lists come from the same device-side builder, and
+// the launches are the ones an iteration enqueues for that many columns,
+// with the system's launch shapes.
+
+static dim3 probe_grid(const morx_system sys, int ncol) {
+  return dim3((unsigned)std::min<int64_t>((sys->n + 255) / 256, 2048), (unsigned)ncol, 1);
+}
+
+morx_status hot_chain_apply(morx_system sys, int ncol, int lcap, const morx_factor* chains,
+                            const int32_t* lens, const double* X, int64_t ldx, double* Y,
+                            int64_t ldy, const double* Xt, int64_t ldxt, double* Yt, int64_t ldyt,
+                            int aprec, hipStream_t st) {
+  const int prec = chains[0]->prec;
+  int maxL = 0;
+  for (int c = 0; c < ncol; ++c) maxL = std::max(maxL, (int)lens[c]);
+  KrylovBatch b;
+  b.profile_grid = true;
+  MORX_TRY(batch_alloc(b, sys, ncol, maxL, prec, aprec, st));
+  for (int c = 0; c < ncol; ++c) {
+    ColInfo ci = {};
+    ci.state = COL_ACTIVE;
+    ci.L = lens[c];
+    b.hcols[c] = ci;
+    for (int s = 0; s < b.lcap; ++s) {
+      morx_factor f = s < lens[c] ? chains[(size_t)c * lcap + s] : nullptr;
+      b.hftab[(size_t)c * b.lcap + s] = f ? f->vals.p : nullptr;
+      b.hftab[((size_t)b.cap + c) * b.lcap + s] = f ? f->valsT.p : nullptr;
+    }
+  }
+  morx_status s = batch_upload(b, 0, ncol, st);
+  if (s == MORX_OK) {
+    const IterArgs a = make_args(b, ncol, maxL);
+    k_probe_in<<<probe_grid(sys, ncol), 256, 0, st>>>(a, V_R, V_RT, X, ldx, Xt, ldxt,
+                                                       aprec == MORX_F32);
+    k_plan<<<1, kFinThreads, 0, st>>>(a);
+    enqueue_chain(a, prec, st, nullptr);
+    k_probe_out<<<probe_grid(sys, ncol), 256, 0, st>>>(a, 1, Y, ldy, Yt, ldyt);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      morx_set_error("chain apply: %s", hipGetErrorString(e));
+      s = MORX_E_HIP;
+    }
+  }
+  hipStreamSynchronize(st);
+  batch_free(b);
+  return s;
+}
+
+morx_status hot_shifted_pair(morx_system sys, int ncol, const double* sigmas, const double* X,
+                             int64_t ldx, double* Y, int64_t ldy, const double* Xt, int64_t ldxt,
+                             double* Yt, int64_t ldyt, hipStream_t st) {
+  KrylovBatch b;
+  b.profile_grid = true;
+  MORX_TRY(batch_alloc(b, sys, ncol, 1, MORX_F64, MORX_F64, st));
+  for (int c = 0; c < ncol; ++c) {
+    ColInfo ci = {};
+    ci.state = COL_ACTIVE;
+    ci.sigma = sigmas[c];
+    ci.L = 1;
+    b.hcols[c] = ci;
+  }
+  morx_status s = batch_upload(b, 0, ncol, st);
+  if (s == MORX_OK) {
+    const IterArgs a = make_args(b, ncol, 1);
+    k_probe_in<<<probe_grid(sys, ncol), 256, 0, st>>>(a, V_P0, V_PT0, X, ldx, Xt, ldxt, 0);
+    enqueue_spmv(a, 0, st, nullptr);
+    k_probe_out<<<probe_grid(sys, ncol), 256, 0, st>>>(a, 0, Y, ldy, Yt, ldyt);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      morx_set_error("shifted pair: %s", hipGetErrorString(e));
+      s = MORX_E_HIP;
+    }
+  }
+  hipStreamSynchronize(st);
+  batch_free(b);
+  return s;
+}
+
+extern "C" morx_status morx_chain_apply_batch(morx_system sys, int32_t ncol, int32_t lcap,
+                                              const morx_factor* chains, const int32_t* lens,
+                                              const double* X, int64_t ldx, double* Y,
+                                              int64_t ldy, const double* Xt, int64_t ldxt,
+                                              double* Yt, int64_t ldyt, int32_t apply_prec,
+                                              void* stream) {
+  MORX_REQUIRE(sys && chains && lens, MORX_E_INVALID, "morx_chain_apply_batch: null argument");
+  MORX_REQUIRE(ncol >= 1 && ncol <= 1024 && lcap >= 1 && lcap <= 64, MORX_E_INVALID,
+               "morx_chain_apply_batch: ncol must be 1..1024 and lcap 1..64");
+  MORX_REQUIRE((X == nullptr) == (Y == nullptr) && (Xt == nullptr) == (Yt == nullptr),
+               MORX_E_INVALID, "morx_chain_apply_batch: an input without its output");
+  MORX_REQUIRE(!X || (ldx >= sys->n && ldy >= sys->n), MORX_E_INVALID,
+               "morx_chain_apply_batch: leading dimension below n");
+  MORX_REQUIRE(!Xt || (ldxt >= sys->n && ldyt >= sys->n), MORX_E_INVALID,
+               "morx_chain_apply_batch: leading dimension below n");
+  MORX_REQUIRE(apply_prec == MORX_F64 || apply_prec == MORX_F32, MORX_E_INVALID,
+               "morx_chain_apply_batch: apply precision must be MORX_F64 or MORX_F32");
+  int prec = -1;
+  for (int c = 0; c < ncol; ++c) {
+    MORX_REQUIRE(lens[c] >= 1 && lens[c] <= lcap, MORX_E_INVALID,
+                 "morx_chain_apply_batch: chain length %d of column %d outside 1..%d", lens[c], c,
+                 lcap);
+    for (int k = 0; k < lens[c]; ++k) {
+      const morx_factor f = chains[(size_t)c * lcap + k];
+      MORX_REQUIRE(f && f->sys == sys, MORX_E_INVALID,
+                   "morx_chain_apply_batch: factor %d of column %d does not belong to this system",
+                   k, c);
+      MORX_REQUIRE(prec < 0 || f->prec == prec, MORX_E_INVALID,
+                   "morx_chain_apply_batch: factors of different storage precisions");
+      prec = f->prec;
+    }
+  }
+  std::lock_guard<std::mutex> lk(sys->ctx->mu);
+  MORX_HIP(hipSetDevice(sys->ctx->device));
+  std::vector<morx_factor> tab(chains, chains + (size_t)ncol * lcap);
+  for (int c = 0; c < ncol; ++c)
+    for (int k = lens[c]; k < lcap; ++k) tab[(size_t)c * lcap + k] = nullptr;
+  return hot_chain_apply(sys, ncol, lcap, tab.data(), lens, X, ldx, Y, ldy, Xt, ldxt, Yt, ldyt,
+                         apply_prec, (hipStream_t)stream);
+}
+
+extern "C" morx_status morx_shifted_apply_pair(morx_system sys, int32_t ncol, const double* sigmas,
+                                               const double* X, int64_t ldx, double* Y,
+                                               int64_t ldy, const double* Xt, int64_t ldxt,
+                                               double* Yt, int64_t ldyt, void* stream) {
+  MORX_REQUIRE(sys && sigmas, MORX_E_INVALID, "morx_shifted_apply_pair: null argument");
+  MORX_REQUIRE(ncol >= 1 && ncol <= 1024, MORX_E_INVALID,
+               "morx_shifted_apply_pair: ncol must be 1..1024");
+  MORX_REQUIRE((X == nullptr) == (Y == nullptr) && (Xt == nullptr) == (Yt == nullptr),
+               MORX_E_INVALID, "morx_shifted_apply_pair: an input without its output");
+  MORX_REQUIRE(!X || (ldx >= sys->n && ldy >= sys->n), MORX_E_INVALID,
+               "morx_shifted_apply_pair: leading dimension below n");
+  MORX_REQUIRE(!Xt || (ldxt >= sys->n && ldyt >= sys->n), MORX_E_INVALID,
+               "morx_shifted_apply_pair: leading dimension below n");
+  for (int c = 0; c < ncol; ++c)
+    MORX_REQUIRE(std::isfinite(sigmas[c]), MORX_E_NONFINITE,
+                 "morx_shifted_apply_pair: shift %d not finite", c);
+  std::lock_guard<std::mutex> lk(sys->ctx->mu);
+  MORX_HIP(hipSetDevice(sys->ctx->device));
+  return hot_shifted_pair(sys, ncol, sigmas, X, ldx, Y, ldy, Xt, ldxt, Yt, ldyt,
+                          (hipStream_t)stream);
+}
+
+extern "C" morx_status morx_last_chains(morx_system sys, int32_t cap_shifts, int32_t ldspec,
+                                        int32_t* nshift, int32_t* lens, morx_factor_spec* specs) {
+  MORX_REQUIRE(sys && nshift, MORX_E_INVALID, "morx_last_chains: null argument");
+  MORX_REQUIRE(cap_shifts >= 0 && ldspec >= 0 && (cap_shifts == 0 || (lens && specs)),
+               MORX_E_INVALID, "morx_last_chains: bad output arrays");
+  std::lock_guard<std::mutex> lk(sys->ctx->mu);
+  MORX_REQUIRE(sys->has_last_chains, MORX_E_INVALID, "morx_last_chains: no solve has run");
+  *nshift = (int32_t)sys->last_chains.size();
+  for (int i = 0; i < cap_shifts && i < (int)sys->last_chains.size(); ++i) {
+    const auto& ch = sys->last_chains[i];
+    lens[i] = (int32_t)ch.size();
+    for (int k = 0; k < (int)ch.size() && k < ldspec; ++k) specs[(size_t)i * ldspec + k] = ch[k];
+  }
+  return MORX_OK;
 }

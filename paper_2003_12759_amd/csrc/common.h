@@ -152,6 +152,9 @@ struct morx_system_s {
   std::vector<morx_factor> vertical;  // P_1^(1), Q_1^(2), ..., Q_1^(z)
   double last_first_shift = 0.0;
   int32_t vertical_prec = -1;
+  // factor chains of the last solve call, per shift in application order
+  std::vector<std::vector<morx_factor_spec>> last_chains;
+  bool has_last_chains = false;
   // recycled factor storage and BiCG workspace
   std::vector<morx_factor> factor_pool;
   KrylovBatch* kb = nullptr;
@@ -172,11 +175,21 @@ struct FactorJob {
 morx_status factor_alloc(morx_system sys, int32_t prec, morx_factor* out);
 // whether the least-squares kernel variant (0, 8 or 16 row groups) handles the pattern
 bool factor_kernel_supported(morx_system sys, int rows);
-void factor_release(morx_factor f);
+void factor_release(morx_factor f);  // back to the system's pool
+void factor_discard(morx_factor f);  // device memory freed (no work may still use it)
 morx_status factor_build_many(morx_system sys, int32_t prec, const FactorJob* jobs, int njobs,
                               hipStream_t st);
 
-// spmm.hip
+// bicg.hip: the solve's chain and shifted-pair kernels on caller columns
+morx_status hot_chain_apply(morx_system sys, int ncol, int lcap, const morx_factor* chains,
+                            const int32_t* lens, const double* X, int64_t ldx, double* Y,
+                            int64_t ldy, const double* Xt, int64_t ldxt, double* Yt, int64_t ldyt,
+                            int aprec, hipStream_t st);
+morx_status hot_shifted_pair(morx_system sys, int ncol, const double* sigmas, const double* X,
+                             int64_t ldx, double* Y, int64_t ldy, const double* Xt, int64_t ldxt,
+                             double* Yt, int64_t ldyt, hipStream_t st);
+
+// spmm.hip (single-column helpers of the GMRES comparator and the projection)
 morx_status launch_shifted_apply(morx_system sys, double sigma, bool trans, int ncol,
                                  const double* X, int64_t ldx, double* Y, int64_t ldy,
                                  hipStream_t st);

@@ -291,6 +291,27 @@ __global__ void k_fill_zero_bytes(uint32_t* p, int64_t words) {
   if (i < words) p[i] = 0u;
 }
 
+// Imported values: CSR(S) order -> SELL(S) order, rounded to the storage type
+template <typename VT>
+__global__ void k_import_sell(const double* __restrict__ val, const int32_t* __restrict__ csr2sell,
+                              int64_t nnz, VT* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nnz) store_val<VT>(out + csr2sell[p], val[p]);
+}
+
+// ... and SELL(S) -> SELL(S^T): row k of S^T lists column k of S; its entry m
+// sits at SELL(S^T) position off[k / 64] + 64 m + k % 64
+template <typename VT>
+__global__ void k_import_sellT(const VT* __restrict__ sellv, const int32_t* __restrict__ trowptr,
+                               const int32_t* __restrict__ tp2s, const int32_t* __restrict__ offT,
+                               int64_t n, VT* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int32_t p0 = trowptr[k], p1 = trowptr[k + 1];
+  const int64_t base = offT[k >> 6] + (k & 63);
+  for (int32_t p = p0; p < p1; ++p) out[base + (int64_t)(p - p0) * 64] = sellv[tp2s[p]];
+}
+
 template <typename VT>
 __global__ void k_factor_to_csr(const VT* __restrict__ vals, const int32_t* __restrict__ csr2sell,
                                 int64_t nnz, double* __restrict__ out) {
@@ -982,6 +1003,13 @@ void factor_release(morx_factor f) {
   f->sys->factor_pool.push_back(f);
 }
 
+void factor_discard(morx_factor f) {
+  if (!f) return;
+  dev_free(f->vals);
+  dev_free(f->valsT);
+  delete f;
+}
+
 morx_status factor_build_many(morx_system sys, int32_t prec, const FactorJob* jobs, int njobs,
                               hipStream_t st) {
   MORX_REQUIRE(sys->ls_supported, MORX_E_UNSUPPORTED,
@@ -1177,5 +1205,87 @@ extern "C" morx_status morx_factor_destroy(morx_factor f) {
   hipSetDevice(f->sys->ctx->device);
   hipStreamSynchronize(f->sys->ctx->stream);
   factor_release(f);
+  return MORX_OK;
+}
+
+extern "C" morx_status morx_factor_build(morx_system sys, int32_t njobs,
+                                         const morx_factor_spec* jobs, int32_t prec, void* stream,
+                                         morx_factor* out) {
+  MORX_REQUIRE(sys && jobs && out, MORX_E_INVALID, "morx_factor_build: null argument");
+  MORX_REQUIRE(njobs >= 1 && njobs <= 4096, MORX_E_INVALID, "morx_factor_build: njobs must be 1..4096");
+  MORX_REQUIRE(prec >= MORX_F64 && prec <= MORX_BF16, MORX_E_INVALID, "morx_factor_build: bad precision");
+  for (int j = 0; j < njobs; ++j)
+    MORX_REQUIRE(std::isfinite(jobs[j].sigma_new) && (jobs[j].is_spai || std::isfinite(jobs[j].sigma_prev)),
+                 MORX_E_NONFINITE, "morx_factor_build: shift of job %d not finite", j);
+  for (int j = 0; j < njobs; ++j) out[j] = nullptr;
+  morx_ctx ctx = sys->ctx;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  MORX_HIP(hipSetDevice(ctx->device));
+  MORX_TRY(stream_enter(ctx, (hipStream_t)stream));
+  std::vector<morx_factor> fs;
+  std::vector<FactorJob> fj;
+  morx_status s = MORX_OK;
+  for (int j = 0; j < njobs && s == MORX_OK; ++j) {
+    morx_factor f = nullptr;
+    s = factor_alloc(sys, prec, &f);
+    if (s != MORX_OK) break;
+    f->is_spai = jobs[j].is_spai != 0;
+    f->sigma_prev = f->is_spai ? 0.0 : jobs[j].sigma_prev;
+    f->sigma_new = jobs[j].sigma_new;
+    fs.push_back(f);
+    fj.push_back(FactorJob{f->sigma_new, f->sigma_prev, f->is_spai ? 1 : 0, f->vals.p, f->valsT.p});
+  }
+  if (s == MORX_OK) s = factor_build_many(sys, prec, fj.data(), njobs, ctx->stream);
+  if (s != MORX_OK) {
+    hipStreamSynchronize(ctx->stream);
+    for (morx_factor f : fs) factor_release(f);
+    return s;
+  }
+  MORX_TRY(stream_leave(ctx, (hipStream_t)stream));
+  for (int j = 0; j < njobs; ++j) out[j] = fs[j];
+  return MORX_OK;
+}
+
+extern "C" morx_status morx_factor_import(morx_system sys, const double* val, int32_t prec,
+                                          void* stream, morx_factor* out) {
+  MORX_REQUIRE(sys && val && out, MORX_E_INVALID, "morx_factor_import: null argument");
+  MORX_REQUIRE(prec >= MORX_F64 && prec <= MORX_BF16, MORX_E_INVALID, "morx_factor_import: bad precision");
+  *out = nullptr;
+  morx_ctx ctx = sys->ctx;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  MORX_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  morx_factor f = nullptr;
+  MORX_TRY(factor_alloc(sys, prec, &f));
+  f->is_spai = true;
+  f->sigma_prev = 0.0;
+  f->sigma_new = 0.0;
+  const unsigned g1 = (unsigned)((sys->nnzS + 255) / 256), g2 = (unsigned)((sys->n + 255) / 256);
+  switch (prec) {
+    case MORX_F64:
+      k_import_sell<double><<<g1, 256, 0, st>>>(val, sys->csr2sell, sys->nnzS, (double*)f->vals.p);
+      k_import_sellT<double><<<g2, 256, 0, st>>>((const double*)f->vals.p, sys->trowptr, sys->tp2s,
+                                                 sys->sellT.off, sys->n, (double*)f->valsT.p);
+      break;
+    case MORX_F32:
+      k_import_sell<float><<<g1, 256, 0, st>>>(val, sys->csr2sell, sys->nnzS, (float*)f->vals.p);
+      k_import_sellT<float><<<g2, 256, 0, st>>>((const float*)f->vals.p, sys->trowptr, sys->tp2s,
+                                                sys->sellT.off, sys->n, (float*)f->valsT.p);
+      break;
+    default:
+      k_import_sell<uint16_t><<<g1, 256, 0, st>>>(val, sys->csr2sell, sys->nnzS,
+                                                  (uint16_t*)f->vals.p);
+      k_import_sellT<uint16_t><<<g2, 256, 0, st>>>((const uint16_t*)f->vals.p, sys->trowptr,
+                                                   sys->tp2s, sys->sellT.off, sys->n,
+                                                   (uint16_t*)f->valsT.p);
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    factor_release(f);
+    morx_set_error("morx_factor_import: %s", hipGetErrorString(e));
+    return MORX_E_HIP;
+  }
+  *out = f;
   return MORX_OK;
 }

@@ -48,6 +48,8 @@ struct Request {
   int anchor = 0;
   morx_factor q = nullptr;
   size_t q_bytes = 0;
+  bool started = false;  // its recurrence has been launched
+  std::vector<morx_factor_spec> chain;  // filled at admission (under the server lock)
 };
 
 struct SysServe {
@@ -58,7 +60,7 @@ struct SysServe {
   std::vector<double> anchor_sigma;
   std::vector<Request*> slot_req;
   size_t bytes = 0;
-  bool ready = false;
+  uint64_t last_use = 0;  // admission counter at the system's last admitted request
 };
 
 size_t factor_bytes(morx_system sys, int prec) {
@@ -85,6 +87,7 @@ struct morx_server_s {
   std::atomic<int> running{0};
   bool stop = false;
   morx_status fatal = MORX_OK;
+  morx_serve_counts counts{};  // under mu
 };
 
 namespace {
@@ -117,17 +120,62 @@ morx_status build_anchors(morx_server srv, SysServe* ss) {
     ss->anchors.push_back(f);
     ss->anchor_sigma.push_back(a);
     FactorJob jb{a, k == 0 ? 0.0 : ss->anchor_sigma[k - 1], k == 0 ? 1 : 0, f->vals.p, f->valsT.p};
+    f->is_spai = k == 0;
+    f->sigma_prev = jb.sigma_prev;
+    f->sigma_new = a;
     jobs.push_back(jb);
   }
   return factor_build_many(ss->sys, prec, jobs.data(), na, ss->stream);
 }
 
+size_t system_bytes(morx_server srv, morx_system sys) {
+  return batch_bytes(sys, srv->cfg.slots_per_system, srv->opts.apply_prec) +
+         (size_t)srv->cfg.anchors * factor_bytes(sys, srv->opts.precond_prec);
+}
+
+bool idle(const SysServe* ss) {
+  for (const Request* r : ss->slot_req)
+    if (r) return false;
+  return true;
+}
+
+// release a resident system: its slot batch, anchors and stream
+void evict(morx_server srv, SysServe* ss) {
+  hipStreamSynchronize(ss->stream);
+  for (morx_factor f : ss->anchors) factor_discard(f);
+  // finished requests' factors wait in the system's pool for its next
+  // requests: free them with the system
+  std::vector<morx_factor>& pool = ss->sys->factor_pool;
+  for (morx_factor f : pool) factor_discard(f);
+  pool.clear();
+  batch_free(ss->kb);
+  hipStreamDestroy(ss->stream);
+  srv->used -= ss->bytes;
+  srv->systems.erase(std::find(srv->systems.begin(), srv->systems.end(), ss));
+  delete ss;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->counts.systems_evicted += 1;
+  srv->counts.resident = (int32_t)srv->systems.size();
+}
+
+// make room for `need` more bytes by releasing idle systems other than
+// `keep`, least recently used first; whether the bytes fit afterwards
+bool make_room(morx_server srv, size_t need, const SysServe* keep) {
+  while (srv->used + need > srv->cfg.hbm_budget_bytes) {
+    SysServe* lru = nullptr;
+    for (SysServe* ss : srv->systems)
+      if (ss != keep && idle(ss) && (!lru || ss->last_use < lru->last_use)) lru = ss;
+    if (!lru) return false;
+    evict(srv, lru);
+  }
+  return true;
+}
+
 morx_status make_system(morx_server srv, morx_system sys, SysServe** out) {
   *out = nullptr;
   const int slots = srv->cfg.slots_per_system;
-  const size_t need = batch_bytes(sys, slots, srv->opts.apply_prec) +
-                      (size_t)srv->cfg.anchors * factor_bytes(sys, srv->opts.precond_prec);
-  if (srv->used + need > srv->cfg.hbm_budget_bytes) return MORX_E_ADMISSION;
+  const size_t need = system_bytes(srv, sys);
+  if (!make_room(srv, need, nullptr)) return MORX_E_ADMISSION;
   SysServe* ss = new SysServe();
   ss->sys = sys;
   if (hipStreamCreateWithFlags(&ss->stream, hipStreamNonBlocking) != hipSuccess) {
@@ -140,7 +188,7 @@ morx_status make_system(morx_server srv, morx_system sys, SysServe** out) {
   if (s == MORX_OK) s = build_anchors(srv, ss);
   if (s != MORX_OK) {
     hipStreamSynchronize(ss->stream);
-    for (morx_factor f : ss->anchors) factor_release(f);
+    for (morx_factor f : ss->anchors) factor_discard(f);
     batch_free(ss->kb);
     hipStreamDestroy(ss->stream);
     delete ss;
@@ -150,6 +198,11 @@ morx_status make_system(morx_server srv, morx_system sys, SysServe** out) {
   ss->bytes = need;
   srv->used += need;
   srv->systems.push_back(ss);
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->counts.systems_made += 1;
+    srv->counts.resident = (int32_t)srv->systems.size();
+  }
   *out = ss;
   return MORX_OK;
 }
@@ -194,7 +247,7 @@ morx_status admit(morx_server srv) {
         break;
       }
     const size_t qb = factor_bytes(r->sys, srv->opts.precond_prec);
-    if (slot < 0 || srv->used + qb > srv->cfg.hbm_budget_bytes) {
+    if (slot < 0 || !make_room(srv, qb, ss)) {
       if (slot >= 0 && srv->running == 0 && fresh.empty()) {
         it = srv->waiting.erase(it);
         finish(srv, r, MORX_E_ADMISSION);
@@ -203,11 +256,21 @@ morx_status admit(morx_server srv) {
       ++it;
       continue;
     }
+    // joins work already on the device when another slot of its system is
+    // iterating
+    bool joins = false;
+    for (const Request* o : ss->slot_req) joins = joins || (o && o->started);
     ss->slot_req[slot] = r;
     r->slot = slot;
     r->q_bytes = qb;
     srv->used += qb;
     srv->running += 1;
+    {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      ss->last_use = ++srv->counts.admitted;
+      if (joins) srv->counts.joined_running += 1;
+      srv->counts.max_running = std::max<int32_t>(srv->counts.max_running, srv->running);
+    }
     fresh.push_back({ss, r});
     it = srv->waiting.erase(it);
   }
@@ -220,8 +283,19 @@ morx_status admit(morx_server srv) {
         Request* r = p.second;
         MORX_TRY(factor_alloc(ss->sys, srv->opts.precond_prec, &r->q));
         r->anchor = nearest_anchor(ss, r->sigma);
+        r->q->is_spai = false;
+        r->q->sigma_prev = ss->anchor_sigma[r->anchor];
+        r->q->sigma_new = r->sigma;
         jobs.push_back({r->sigma, ss->anchor_sigma[r->anchor], 0, r->q->vals.p, r->q->valsT.p});
         reqs.push_back(r);
+        std::vector<morx_factor_spec> ch;
+        for (int k = 0; k <= r->anchor; ++k) {
+          const morx_factor f = ss->anchors[k];
+          ch.push_back({f->is_spai ? 1 : 0, 0, f->is_spai ? 0.0 : f->sigma_prev, f->sigma_new});
+        }
+        ch.push_back({0, 0, r->q->sigma_prev, r->q->sigma_new});
+        std::lock_guard<std::mutex> lk(srv->mu);
+        r->chain = std::move(ch);
       }
     if (jobs.empty()) continue;
     MORX_TRY(factor_build_many(ss->sys, srv->opts.precond_prec, jobs.data(), (int)jobs.size(),
@@ -256,6 +330,7 @@ morx_status admit(morx_server srv) {
       MORX_TRY(batch_upload(b, r->slot, 1, ss->stream));
     }
     MORX_TRY(batch_launch_init(b, b.cap, ss->stream));
+    for (Request* r : reqs) r->started = true;
   }
   return MORX_OK;
 }
@@ -271,6 +346,10 @@ morx_status step(morx_server srv) {
       if (r) maxL = std::max(maxL, r->anchor + 2);
     if (maxL == 0) continue;
     busy.push_back(ss);
+    {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      srv->counts.segments += 1;
+    }
     MORX_TRY(batch_launch_segment(ss->kb, ss->kb.cap, maxL, seg, srv->opts.use_graph != 0,
                                   ss->stream, nullptr));
   }
@@ -466,6 +545,28 @@ extern "C" morx_status morx_serve_info(morx_server srv, uint64_t* submitted, uin
   return MORX_OK;
 }
 
+extern "C" morx_status morx_serve_counts_get(morx_server srv, morx_serve_counts* out) {
+  MORX_REQUIRE(srv && out, MORX_E_INVALID, "morx_serve_counts_get: null argument");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  *out = srv->counts;
+  return MORX_OK;
+}
+
+extern "C" morx_status morx_serve_chain(morx_server srv, uint64_t ticket, int32_t cap, int32_t* len,
+                                        morx_factor_spec* specs) {
+  MORX_REQUIRE(srv && len && cap >= 0 && (cap == 0 || specs), MORX_E_INVALID,
+               "morx_serve_chain: bad argument");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->table.find(ticket);
+  MORX_REQUIRE(it != srv->table.end(), MORX_E_INVALID, "serve: unknown ticket %llu",
+               (unsigned long long)ticket);
+  const Request* r = it->second;
+  if (r->chain.empty()) return MORX_E_PENDING;
+  *len = (int32_t)r->chain.size();
+  for (int k = 0; k < cap && k < (int)r->chain.size(); ++k) specs[k] = r->chain[k];
+  return MORX_OK;
+}
+
 extern "C" morx_status morx_serve_stop(morx_server srv) {
   if (!srv) return MORX_OK;
   {
@@ -479,7 +580,7 @@ extern "C" morx_status morx_serve_stop(morx_server srv) {
     hipSetDevice(srv->ctx->device);
     for (SysServe* ss : srv->systems) {
       hipStreamSynchronize(ss->stream);
-      for (morx_factor f : ss->anchors) factor_release(f);
+      for (morx_factor f : ss->anchors) factor_discard(f);
       batch_free(ss->kb);
       hipStreamDestroy(ss->stream);
       delete ss;

@@ -6,8 +6,11 @@
 //
 // One thread per row, up to NC columns per thread; the shifted matrix and the
 // preconditioner product are never formed (Section III-B; appendix B form).
+// These simple kernels serve the GMRES comparator and the projection; the
+// public product entry points below run the solve's own kernels instead.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "common.h"
 
@@ -109,6 +112,10 @@ morx_status launch_factor_apply(morx_system sys, morx_factor f, bool trans, int 
   return MORX_OK;
 }
 
+// The public single products run the solve's kernels (bicg.hip), in chunks
+// of at most 1024 columns.
+constexpr int kProbeChunk = 1024;
+
 extern "C" morx_status morx_shifted_apply(morx_system sys, double sigma, int32_t trans,
                                           int32_t ncol, const double* X, int64_t ldx, double* Y,
                                           int64_t ldy, void* stream) {
@@ -118,49 +125,55 @@ extern "C" morx_status morx_shifted_apply(morx_system sys, double sigma, int32_t
   MORX_REQUIRE(ldx >= sys->n && ldy >= sys->n, MORX_E_INVALID,
                "morx_shifted_apply: leading dimension below n");
   MORX_REQUIRE(std::isfinite(sigma), MORX_E_NONFINITE, "morx_shifted_apply: shift not finite");
+  if (ncol == 0) return MORX_OK;
   std::lock_guard<std::mutex> lk(sys->ctx->mu);
   MORX_HIP(hipSetDevice(sys->ctx->device));
   hipStream_t st = (hipStream_t)stream;
-  MORX_TRY(launch_shifted_apply(sys, sigma, trans != 0, ncol, X, ldx, Y, ldy, st));
-  MORX_HIP(hipStreamSynchronize(st));
+  const std::vector<double> sig(std::min(ncol, kProbeChunk), sigma);
+  for (int c0 = 0; c0 < ncol; c0 += kProbeChunk) {
+    const int nc = std::min(kProbeChunk, ncol - c0);
+    const double* x = X + (int64_t)c0 * ldx;
+    double* y = Y + (int64_t)c0 * ldy;
+    if (trans) MORX_TRY(hot_shifted_pair(sys, nc, sig.data(), nullptr, 0, nullptr, 0, x, ldx, y, ldy, st));
+    else MORX_TRY(hot_shifted_pair(sys, nc, sig.data(), x, ldx, y, ldy, nullptr, 0, nullptr, 0, st));
+  }
   return MORX_OK;
 }
 
 extern "C" morx_status morx_chain_apply(morx_system sys, int32_t nfactor, const morx_factor* chain,
                                         int32_t trans, int32_t ncol, const double* X, int64_t ldx,
                                         double* Y, int64_t ldy, void* stream) {
-  MORX_REQUIRE(sys && nfactor >= 1 && chain, MORX_E_INVALID, "morx_chain_apply: bad chain");
+  MORX_REQUIRE(sys && nfactor >= 1 && nfactor <= 64 && chain, MORX_E_INVALID,
+               "morx_chain_apply: bad chain");
   MORX_REQUIRE(ncol >= 0 && (ncol == 0 || (X && Y)), MORX_E_INVALID,
                "morx_chain_apply: bad columns or null pointer");
   MORX_REQUIRE(ldx >= sys->n && ldy >= sys->n, MORX_E_INVALID,
                "morx_chain_apply: leading dimension below n");
-  for (int i = 0; i < nfactor; ++i)
+  for (int i = 0; i < nfactor; ++i) {
     MORX_REQUIRE(chain[i] && chain[i]->sys == sys, MORX_E_INVALID,
                  "morx_chain_apply: factor %d does not belong to this system", i);
+    MORX_REQUIRE(chain[i]->prec == chain[0]->prec, MORX_E_INVALID,
+                 "morx_chain_apply: factors of different storage precisions");
+  }
   if (ncol == 0) return MORX_OK;
   std::lock_guard<std::mutex> lk(sys->ctx->mu);
   MORX_HIP(hipSetDevice(sys->ctx->device));
   hipStream_t st = (hipStream_t)stream;
-  const int64_t ld = sys->n_pad;
-  DevBuf tmp;
-  if (nfactor > 1) MORX_TRY(dev_alloc(tmp, (size_t)2 * ld * ncol * sizeof(double)));
-  double* T[2] = {(double*)tmp.p, (double*)tmp.p + ld * ncol};
-  const double* src = X;
-  int64_t lds = ldx;
-  morx_status s = MORX_OK;
-  for (int t = 0; t < nfactor && s == MORX_OK; ++t) {
-    // forward: chain[0] first; transpose: chain[nfactor-1]^T first
-    morx_factor f = trans ? chain[nfactor - 1 - t] : chain[t];
-    bool last = (t == nfactor - 1);
-    double* dst = last ? Y : T[t & 1];
-    int64_t ldd = last ? ldy : ld;
-    s = launch_factor_apply(sys, f, trans != 0, ncol, src, lds, dst, ldd, st);
-    src = dst;
-    lds = ldd;
+  const int nmax = std::min(ncol, kProbeChunk);
+  std::vector<morx_factor> tab((size_t)nmax * nfactor);
+  for (int c = 0; c < nmax; ++c)
+    for (int k = 0; k < nfactor; ++k) tab[(size_t)c * nfactor + k] = chain[k];
+  const std::vector<int32_t> lens(nmax, nfactor);
+  for (int c0 = 0; c0 < ncol; c0 += kProbeChunk) {
+    const int nc = std::min(kProbeChunk, ncol - c0);
+    const double* x = X + (int64_t)c0 * ldx;
+    double* y = Y + (int64_t)c0 * ldy;
+    if (trans)
+      MORX_TRY(hot_chain_apply(sys, nc, nfactor, tab.data(), lens.data(), nullptr, 0, nullptr, 0,
+                               x, ldx, y, ldy, MORX_F64, st));
+    else
+      MORX_TRY(hot_chain_apply(sys, nc, nfactor, tab.data(), lens.data(), x, ldx, y, ldy, nullptr,
+                               0, nullptr, 0, MORX_F64, st));
   }
-  hipError_t e = hipStreamSynchronize(st);
-  dev_free(tmp);
-  if (s != MORX_OK) return s;
-  MORX_REQUIRE(e == hipSuccess, MORX_E_HIP, "morx_chain_apply: %s", hipGetErrorString(e));
   return MORX_OK;
 }

@@ -72,6 +72,18 @@ class morx_tune(ctypes.Structure):
                 ("factor_ms", ctypes.c_double), ("iter_ms", ctypes.c_double)]
 
 
+class morx_factor_spec(ctypes.Structure):
+    _fields_ = [("is_spai", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sigma_prev", ctypes.c_double), ("sigma_new", ctypes.c_double)]
+
+
+class morx_serve_counts(ctypes.Structure):
+    _fields_ = [("admitted", ctypes.c_uint64), ("joined_running", ctypes.c_uint64),
+                ("segments", ctypes.c_uint64), ("systems_made", ctypes.c_uint64),
+                ("systems_evicted", ctypes.c_uint64), ("resident", ctypes.c_int32),
+                ("max_running", ctypes.c_int32)]
+
+
 class MorxError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -97,6 +109,15 @@ _SIG = {
     "morx_factor_values": (_i32, [_p, _p, _p]),
     "morx_factor_destroy": (_i32, [_p]),
     "morx_chain_apply": (_i32, [_p, _i32, ctypes.POINTER(_p), _i32, _i32, _p, _i64, _p, _i64, _p]),
+    "morx_chain_apply_batch": (_i32, [_p, _i32, _i32, ctypes.POINTER(_p), ctypes.POINTER(_i32),
+                                      _p, _i64, _p, _i64, _p, _i64, _p, _i64, _i32, _p]),
+    "morx_shifted_apply_pair": (_i32, [_p, _i32, ctypes.POINTER(_d), _p, _i64, _p, _i64, _p, _i64,
+                                       _p, _i64, _p]),
+    "morx_factor_build": (_i32, [_p, _i32, ctypes.POINTER(morx_factor_spec), _i32, _p,
+                                 ctypes.POINTER(_p)]),
+    "morx_factor_import": (_i32, [_p, _p, _i32, _p, ctypes.POINTER(_p)]),
+    "morx_last_chains": (_i32, [_p, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                ctypes.POINTER(morx_factor_spec)]),
     "morx_solve_shifts": (_i32, [_p, _i32, ctypes.POINTER(_d), _i32, _p, _i64, _p, _i64, _p, _i64,
                                  _p, _i64, ctypes.POINTER(morx_opts),
                                  ctypes.POINTER(morx_col_stats), _p]),
@@ -130,6 +151,9 @@ _SIG = {
     "morx_serve_info": (_i32, [_p, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
                                ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i64)]),
     "morx_serve_stop": (_i32, [_p]),
+    "morx_serve_counts_get": (_i32, [_p, ctypes.POINTER(morx_serve_counts)]),
+    "morx_serve_chain": (_i32, [_p, ctypes.c_uint64, _i32, ctypes.POINTER(_i32),
+                                ctypes.POINTER(morx_factor_spec)]),
     "morx_trace_enable": (_i32, [_p, _i32]),
     "morx_trace_read": (_i32, [_p, ctypes.POINTER(morx_trace_entry), _i32, ctypes.POINTER(_i32)]),
 }
@@ -310,6 +334,95 @@ def morx_chain_apply(sys: int, chain: Sequence[int], trans: bool, X: torch.Tenso
         raise ValueError("X and Y column counts differ")
     _check(_lib.morx_chain_apply(sys, len(chain), arr, int(bool(trans)), nc, px, ldx, py, ldy,
                                  _stream(stream)), "morx_chain_apply")
+
+
+def _spec_tuple(sp: morx_factor_spec):
+    """("spai", sigma) or ("update", sigma_prev, sigma_new), the oracle's form."""
+    if sp.is_spai:
+        return ("spai", sp.sigma_new)
+    return ("update", sp.sigma_prev, sp.sigma_new)
+
+
+def _opt_block(t, name):
+    if t is None:
+        return None, 1, 0
+    return _block(t, name)
+
+
+def morx_chain_apply_batch(sys: int, chains: Sequence[Sequence[int]], X: Optional[torch.Tensor],
+                           Y: Optional[torch.Tensor], Xt: Optional[torch.Tensor] = None,
+                           Yt: Optional[torch.Tensor] = None, apply: str = "f64",
+                           stream=None) -> None:
+    """Column c of X times chain c (chains[c][0] applied first), column c of
+    Xt times its transpose, with the solve's chain kernels."""
+    ncol = len(chains)
+    lcap = max(len(ch) for ch in chains)
+    tab = (_p * (ncol * lcap))()
+    lens = (_i32 * ncol)()
+    for c, ch in enumerate(chains):
+        lens[c] = len(ch)
+        for k, f in enumerate(ch):
+            tab[c * lcap + k] = f
+    px, ldx, n1 = _opt_block(X, "X")
+    py, ldy, n2 = _opt_block(Y, "Y")
+    pxt, ldxt, n3 = _opt_block(Xt, "Xt")
+    pyt, ldyt, n4 = _opt_block(Yt, "Yt")
+    for nn in (n1, n2, n3, n4):
+        if nn not in (0, ncol):
+            raise ValueError("column counts differ from the number of chains")
+    _check(_lib.morx_chain_apply_batch(sys, ncol, lcap, tab, lens, px, ldx, py, ldy, pxt, ldxt,
+                                       pyt, ldyt, PREC[apply], _stream(stream)),
+           "morx_chain_apply_batch")
+
+
+def morx_shifted_apply_pair(sys: int, sigmas: Sequence[float], X: Optional[torch.Tensor],
+                            Y: Optional[torch.Tensor], Xt: Optional[torch.Tensor] = None,
+                            Yt: Optional[torch.Tensor] = None, stream=None) -> None:
+    ncol = len(sigmas)
+    sig = (_d * ncol)(*[float(x) for x in sigmas])
+    px, ldx, n1 = _opt_block(X, "X")
+    py, ldy, n2 = _opt_block(Y, "Y")
+    pxt, ldxt, n3 = _opt_block(Xt, "Xt")
+    pyt, ldyt, n4 = _opt_block(Yt, "Yt")
+    for nn in (n1, n2, n3, n4):
+        if nn not in (0, ncol):
+            raise ValueError("column counts differ from the number of shifts")
+    _check(_lib.morx_shifted_apply_pair(sys, ncol, sig, px, ldx, py, ldy, pxt, ldxt, pyt, ldyt,
+                                        _stream(stream)), "morx_shifted_apply_pair")
+
+
+def morx_factor_build(sys: int, specs, prec: str = "f64", stream=None):
+    """Factors of the given specs (("spai", s) or ("update", s_prev, s_new))
+    built in one launch; returns their handles."""
+    nj = len(specs)
+    arr = (morx_factor_spec * nj)()
+    for j, sp in enumerate(specs):
+        if sp[0] == "spai":
+            arr[j] = morx_factor_spec(1, 0, 0.0, float(sp[1]))
+        else:
+            arr[j] = morx_factor_spec(0, 0, float(sp[1]), float(sp[2]))
+    out = (_p * nj)()
+    _check(_lib.morx_factor_build(sys, nj, arr, PREC[prec], _stream(stream), out),
+           "morx_factor_build")
+    return [out[j] for j in range(nj)]
+
+
+def morx_factor_import(sys: int, val: torch.Tensor, prec: str = "f64", stream=None) -> int:
+    h = _p()
+    _check(_lib.morx_factor_import(sys, _dev(val, torch.float64, "val"), PREC[prec],
+                                   _stream(stream), ctypes.byref(h)), "morx_factor_import")
+    return h.value
+
+
+def morx_last_chains(sys: int, cap_shifts: int = 1024, ldspec: int = 64):
+    """Per shift of the last solve call, its chain as a list of spec tuples."""
+    ns = _i32()
+    lens = (_i32 * cap_shifts)()
+    specs = (morx_factor_spec * (cap_shifts * ldspec))()
+    _check(_lib.morx_last_chains(sys, cap_shifts, ldspec, ctypes.byref(ns), lens, specs),
+           "morx_last_chains")
+    return [[_spec_tuple(specs[i * ldspec + k]) for k in range(min(lens[i], ldspec))]
+            for i in range(min(ns.value, cap_shifts))]
 
 
 def morx_solve_shifts(sys: int, sigmas: Sequence[float], B: torch.Tensor, C: Optional[torch.Tensor],
@@ -525,6 +638,23 @@ def morx_serve_info(srv: int):
                                 ctypes.byref(d), ctypes.byref(e)), "morx_serve_info")
     return {"submitted": a.value, "completed": b.value, "running": c.value, "queued": d.value,
             "bytes_in_use": e.value}
+
+
+def morx_serve_counts_get(srv: int) -> dict:
+    c = morx_serve_counts()
+    _check(_lib.morx_serve_counts_get(srv, ctypes.byref(c)), "morx_serve_counts_get")
+    return {name: getattr(c, name) for name, _ in c._fields_}
+
+
+def morx_serve_chain(srv: int, ticket: int, cap: int = 64):
+    """The request's chain as spec tuples, or None while it waits for admission."""
+    n = _i32()
+    specs = (morx_factor_spec * cap)()
+    st = _lib.morx_serve_chain(srv, ticket, cap, ctypes.byref(n), specs)
+    if st == -10:
+        return None
+    _check(st, "morx_serve_chain")
+    return [_spec_tuple(specs[k]) for k in range(min(n.value, cap))]
 
 
 def morx_serve_stop(srv: int) -> None:

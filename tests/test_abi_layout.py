@@ -10,7 +10,8 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-STRUCTS = ["morx_opts", "morx_col_stats", "morx_trace_entry", "morx_serve_config", "morx_tune"]
+STRUCTS = ["morx_opts", "morx_col_stats", "morx_trace_entry", "morx_serve_config", "morx_tune",
+           "morx_factor_spec", "morx_serve_counts"]
 
 
 def test_struct_layouts_match_the_header(tmp_path):

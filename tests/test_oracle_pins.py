@@ -140,6 +140,23 @@ def test_schedule_follows_algorithm4():
             assert len(chains[z][i]) == (i + 1) + (z + 1) - 1
 
 
+def test_anchored_schedule_for_serving():
+    """Anchors 1, 10, 100 (log-spaced over [1, 100]); each request's chain is
+    the anchor prefix up to its nearest anchor in log(sigma) plus one update."""
+    a = chain.anchor_shifts(3, 1.0, 100.0)
+    assert a[0] == 1.0 and abs(a[1] - 10.0) < 1e-14 and abs(a[2] - 100.0) < 1e-12
+    a = [1.0, 10.0, 100.0]
+    assert chain.schedule_anchored(a, 2.0) == [("spai", 1.0), ("update", 1.0, 2.0)]
+    assert chain.schedule_anchored(a, 5.0) == [("spai", 1.0), ("update", 1.0, 10.0),
+                                               ("update", 10.0, 5.0)]
+    assert chain.schedule_anchored(a, 1e4) == [("spai", 1.0), ("update", 1.0, 10.0),
+                                               ("update", 10.0, 100.0), ("update", 100.0, 1e4)]
+    # log-distance tie between 1 and 10 (sigma = sqrt(10)): the first anchor
+    assert chain.schedule_anchored([1.0, 100.0], 10.0)[0:1] == [("spai", 1.0)]
+    assert len(chain.schedule_anchored([1.0, 100.0], 10.0)) == 2
+    assert chain.anchor_shifts(1, 3.0, 3.0) == [3.0]
+
+
 def test_comparator_schedules():
     rounds = [[1.0, 2.0, 3.0], [1.1, 2.1, 3.1]]
     specs, chains = chain.schedule_direct(rounds)
