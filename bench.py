@@ -1,19 +1,22 @@
 """Throughput of the shifted-solve hot path on one MI355X.
 
-One step = the whole job of the 64^3 convection-diffusion workload
-(n = 262,144, 7-point upwind stencil, E = diag U[1,2], SISO): three rounds of
-ten shifts (rounds 2 and 3 jittered, vertical reuse between rounds), SPAI at
-the first shift and the column-wise reuse update for every other one (FP32
-factor storage), two-sided BiCG to a true relative residual of 1e-10 for all
-30 primal + dual pairs, and the Petrov-Galerkin projection after each round.
-Inputs are resident on the device before the clock starts.
+One step = the whole job of a workload, with inputs resident on the device
+before the clock starts.  The default workload is the largest single-GPU
+one, the 128^3 27-point variable-coefficient operator (n = 2,097,152, nnz =
+55,742,968, E = diag U[1,2], SISO): 12 shifts log-spaced in [1, 1e4], SPAI at
+the first and the column-wise reuse update for every other one (one factor
+build of 12 jobs), factors stored in FP64 (the ladder adds FP32 and BF16),
+two-sided BiCG to a true relative residual of 1e-10 for all 12 primal + dual
+pairs, and the Petrov-Galerkin projection.
 
 Printed JSON (one line): value = shifted solves per second (a solve is one
 primal + dual pair meeting 1e-10 on both), batched multi-shift path;
 ``plain`` is the one-shift-one-column path on the same job; ``roofline`` is
 measured on the dominant kernel (the chain step) with HIP events around its
-launches in one extra traced step; ``cpu_baseline`` times the CPU oracle on a
-bounded sample (one factor build + one pair solve, the per-shift unit).
+launches in one extra traced step, and carries the HBM traffic measured by
+rocprofv3 counters on the same kernel source; ``ladder`` is the same job at
+each factor storage precision; ``cpu_baseline`` times the CPU oracle on a
+bounded sample on a process pool of the host's cores (the sample is stated).
 """
 from __future__ import annotations
 
@@ -29,6 +32,7 @@ if ROOT not in sys.path:
 
 METRIC = "shifted solves/sec to rel-res 1e-10 (batched vs plain); HBM GB/s; p99 lat"
 HBM_PEAK_GBPS = 8000.0
+LLC_BYTES = 256e6  # MI355X last-level (Infinity) cache
 DOMINANT = "chain_step"
 
 
@@ -47,28 +51,6 @@ def kernel_source_hash() -> str:
         with open(os.path.join(ROOT, "paper_2003_12759_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
-
-
-def chain_kernel_name(A, vt: str, at: str, ncol: int, ncmax: int, halo: bool) -> str:
-    """Instance of the chain step the library launches for this batch: the
-    halo variant when the system uses it (`halo`, from the tune the library
-    reports), else the narrow variant when every row of S = pattern(A) +
-    diagonal and of S^T has at most 8 entries, else the general one, at the
-    tile width of the library's column split (equal chunks of at most ncmax
-    columns, rounded up to an instantiated width)."""
-    import numpy as np
-    import scipy.sparse as sp
-
-    P = sp.csr_matrix(A, copy=True)
-    P.data[:] = 1.0
-    P = (P + sp.identity(P.shape[0], format="csr")).tocsr()
-    width = max(int(np.diff(P.indptr).max()), int(np.diff(P.tocsc().indptr).max()))
-    ncmax = ncmax if ncmax > 0 else 8
-    chunks = -(-ncol // ncmax)
-    nc = -(-ncol // chunks)
-    nc = nc if nc <= 8 else (10 if nc <= 10 else (12 if nc <= 12 else 16))
-    kind = "k_chain_halo" if halo else ("k_chain_narrow" if width <= 8 else "k_chain_step")
-    return f"{kind}<{vt}, {at}, {nc}>"
 
 
 def default_apply(prec: str) -> str:
@@ -106,6 +88,7 @@ def ladder(S, w, Bd, Cd, nsolves):
     import torch
 
     E = sp.diags(w.e)
+    emin = float(np.min(w.e))
     out, ref = {}, None
     for prec in ("f64", "f32", "bf16"):
         keep = []
@@ -118,13 +101,19 @@ def ladder(S, w, Bd, Cd, nsolves):
         check(st, w.tol)
         X, Y = keep[0].cpu().numpy(), keep[1].cpu().numpy()
         m = w.B.shape[1]
-        res = 0.0
+        res, ebound = 0.0, 0.0
         for i, sig in enumerate(w.rounds[-1]):
             M = (sig * E - w.A).tocsr()
             for j in range(m):
                 k = i * m + j
-                res = max(res, np.linalg.norm(w.B[:, j] - M @ X[:, k]) / np.linalg.norm(w.B[:, j]),
-                          np.linalg.norm(w.C[:, j] - M.T @ Y[:, k]) / np.linalg.norm(w.C[:, j]))
+                rp = np.linalg.norm(w.B[:, j] - M @ X[:, k])
+                rd = np.linalg.norm(w.C[:, j] - M.T @ Y[:, k])
+                res = max(res, rp / np.linalg.norm(w.B[:, j]), rd / np.linalg.norm(w.C[:, j]))
+                # -A has a positive semidefinite symmetric part, so the
+                # smallest singular value of s E - A is at least s min(e):
+                # ||x - x_exact|| <= ||r|| / (s min(e))
+                ebound = max(ebound, rp / (sig * emin * np.linalg.norm(X[:, k])),
+                             rd / (sig * emin * np.linalg.norm(Y[:, k])))
         if ref is None:
             ref = (X, Y)
         err = max(float(np.max(np.linalg.norm(X - ref[0], axis=0) / np.linalg.norm(ref[0], axis=0))),
@@ -133,6 +122,7 @@ def ladder(S, w, Bd, Cd, nsolves):
         out[prec] = {"value": round(nsolves / dt, 3), "unit": "solves/s",
                      "iters_per_shift": its, "iters_total": sum(its),
                      "max_true_relres": float(f"{res:.3e}"),
+                     "max_rel_error_bound_vs_exact": float(f"{ebound:.3e}"),
                      "max_rel_diff_vs_f64_storage": float(f"{err:.3e}")}
     return out
 
@@ -144,33 +134,133 @@ def check(stats, tol):
         raise SystemExit(f"accuracy check failed: {bad[:5]}")
 
 
-def cpu_baseline(w, apply):
-    """Oracle on one factor build + one pair solve (round 1, shift 1)."""
-    import numpy as np
-    import scipy.sparse as sp
+def _host_cpu():
+    """(model name, usable cores) of the host, from /proc/cpuinfo and the
+    process's affinity."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+# state the pool's workers inherit (fork), so the large matrices are not copied
+_POOL = {}
+
+
+def _pool_columns(cols):
+    """Oracle SPAI columns (single-threaded) for a list of column indices."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import spai as ospai
+
+    g = _POOL
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for k in cols:
+            ospai.spai_column(g["A"], g["e"], g["sigma"], int(k), As=g["As"])
+        return time.perf_counter() - t0
+
+
+def _pool_iterations(L):
+    """Seconds per oracle BiCG iteration (single-threaded) with a chain of L
+    factor passes per direction: the difference of runs with 3 and 1
+    iterations, halved."""
     from threadpoolctl import threadpool_limits
 
     from oracle import bicg as obicg
     from oracle import chain as ochain
-    from oracle import job as ojob
 
+    g = _POOL
+    F = [g["F"]]
+    chain = [0] * L
+    As, AsT = g["As_csr"], g["AsT"]
+    b, c = g["b"], g["c"]
     with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        specs, chains = ochain.schedule([w.rounds[0][:1]])
-        factors = ojob.build_factors(w.A, w.e, specs, w.prec)
-        s = float(w.rounds[0][0])
-        As = (s * sp.diags(w.e) - w.A).tocsr()
-        AsT = As.T.tocsr()
-        res = obicg.solve(lambda v: As @ v, lambda v: AsT @ v, w.B[:, 0], w.C[:, 0],
-                          lambda v: ochain.apply(factors, [0], v, apply),
-                          lambda v: ochain.apply_transpose(factors, [0], v, apply), tol=w.tol)
-        dt = time.perf_counter() - t0
-    assert res.status == "ok"
-    return {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"one SPAI factor build (n={w.n}, {w.prec.upper()} storage, "
-                      f"{apply.upper()} apply) + one primal+dual "
-                      f"BiCG pair solve to 1e-10 ({res.iters} iterations), {dt:.1f} s, "
-                      "single-threaded NumPy/SciPy"}
+        out = []
+        for it in (1, 3):
+            t0 = time.perf_counter()
+            obicg.solve(lambda v: As @ v, lambda v: AsT @ v, b, c,
+                        lambda v: ochain.apply(F, chain, v, "f64"),
+                        lambda v: ochain.apply_transpose(F, chain, v, "f64"), tol=0.0,
+                        maxit=it, max_restarts=0)
+            out.append(time.perf_counter() - t0)
+    return (out[1] - out[0]) / 2.0
+
+
+def cpu_sample(w):
+    """Time the CPU oracle on a bounded sample of the workload, on a process
+    pool of the host's cores (at most 16), each worker single-threaded:
+    (a) SPAI columns of the first shift, 1500 per worker, from the oracle's
+    column least squares; (b) oracle BiCG iterations on the full system with
+    chains of 1 and 3 factor passes (factor values random on the pattern S:
+    the cost does not depend on them), every worker at once.  Runs before
+    the GPU is touched (the pool forks)."""
+    import multiprocessing as mp
+
+    import numpy as np
+    import scipy.sparse as sp
+
+    from oracle import pattern as opattern
+
+    model, ncpu = _host_cpu()
+    P = max(1, min(16, ncpu))
+    sigma = float(w.rounds[0][0])
+    As = opattern.shifted_pattern_values(w.A, w.e, sigma)
+    rng = np.random.default_rng(5)
+    Scsr = As.tocsr()
+    fv = rng.standard_normal(Scsr.nnz)
+    fv[Scsr.indices == np.repeat(np.arange(w.n), np.diff(Scsr.indptr))] += 3.0
+    F = sp.csr_matrix((fv, Scsr.indices, Scsr.indptr), shape=Scsr.shape)
+    _POOL.update(A=w.A, e=w.e, sigma=sigma, As=As, As_csr=Scsr, AsT=Scsr.T.tocsr(), F=F,
+                 b=np.ascontiguousarray(w.B[:, 0]), c=np.ascontiguousarray(w.C[:, 0]))
+    per = 1500
+    cols = rng.choice(w.n, P * per, replace=False)
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(P) as pool:
+        pool.map(_pool_columns, [cols[k::P] for k in range(P)])
+        t_cols = time.perf_counter() - t0
+        it1 = pool.map(_pool_iterations, [1] * P)
+        it3 = pool.map(_pool_iterations, [3] * P)
+    wall = time.perf_counter() - t0
+    _POOL.clear()
+    t1, t3 = float(np.mean(it1)), float(np.mean(it3))
+    tf = max((t3 - t1) / 2.0, 0.0)  # one factor pass per direction
+    return {"model": model, "cores": P, "cols_per_s": P * per / t_cols,
+            "iter_s_base": max(t1 - tf, 0.0), "iter_s_per_factor": tf, "wall_s": wall}
+
+
+def cpu_baseline(w, sample, chain_lens, iters, nfactors):
+    """The oracle's job time on the pool, from the sample: every factor's n
+    column problems at the pool's column rate, then the shifts' BiCG solves
+    spread over the workers (longest first), shift i taking iters[i]
+    iterations at (base + L_i per-factor) seconds each; value = solves / time."""
+    P = sample["cores"]
+    t_factor = nfactors * w.n / sample["cols_per_s"]
+    load = [0.0] * P
+    for t in sorted((it * (sample["iter_s_base"] + L * sample["iter_s_per_factor"])
+                     for it, L in zip(iters, chain_lens)), reverse=True):
+        load[load.index(min(load))] += t
+    t_solve = max(load)
+    total = t_factor + t_solve
+    return {"value": round(len(iters) / total, 6), "unit": "solves/s", "cores": P,
+            "kind": "oracle", "cpu_model": sample["model"],
+            "sample": (f"oracle on a pool of {P} single-threaded processes "
+                       f"({sample['wall_s']:.1f} s): SPAI column least squares of the first "
+                       f"shift ({sample['cols_per_s']:.0f} columns/s over the pool) and BiCG "
+                       f"iterations on the full n={w.n} system with chains of 1 and 3 factors "
+                       f"({sample['iter_s_base']:.3f} s + {sample['iter_s_per_factor']:.3f} s per "
+                       f"factor per iteration, all workers at once); job time = {nfactors} factor "
+                       f"builds at that rate ({t_factor:.0f} s) + the {len(iters)} shifts' solves "
+                       f"at the GPU run's iteration counts spread over the workers "
+                       f"({t_solve:.0f} s)"),
+            "projected_job_s": round(total, 1)}
 
 
 def serving_bench(args):
@@ -260,9 +350,11 @@ def serving_bench(args):
         A, e = pool.systems[pool.req_system[t]]
         M = (pool.req_sigma[t] * sp.diags(e) - A).tocsr()
         b, x = bs[t].cpu().numpy(), xs[t].cpu().numpy()
-        rr = np.linalg.norm(b - M @ x) / np.linalg.norm(b)
-        if rr > 1.01e-10:
-            raise SystemExit(f"serving: request {t} true residual {rr}")
+        # the host recomputation's own rounding, (w + 2) u (|b| + |M||x|), w <= 8
+        rr = np.linalg.norm(b - M @ x)
+        slack = 10 * 2.0**-53 * np.linalg.norm(np.abs(b) + abs(M) @ np.abs(x))
+        if rr > 1e-10 * np.linalg.norm(b) + slack:
+            raise SystemExit(f"serving: request {t} true residual {rr / np.linalg.norm(b)}")
     loads = {}
     for rho in args.loads:
         times = np.cumsum(pool.gaps) / (rho * lam_max)
@@ -295,18 +387,21 @@ def serving_bench(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ladder", action="store_true",
+                    help="skip the precision ladder of the 27-point workload")
     ap.add_argument("--no-trace", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--workload", default="convdiff3d_n262144",
+    ap.add_argument("--workload", default="varcoef27_n2097152",
                     choices=["convdiff3d_n262144", "laplace2d_n2025", "varcoef3d_n1191016_mimo4",
                              "varcoef27_n2097152", "serving_pool16"])
     ap.add_argument("--prec", default=None, choices=[None, "f64", "f32", "bf16"],
-                    help="factor storage precision (default: the workload's)")
+                    help="factor storage precision (default: FP64 for the 27-point "
+                         "workload, whose ladder adds FP32 and BF16; the workload's otherwise)")
     ap.add_argument("--apply", default=None, choices=[None, "f64", "f32"],
                     help="preconditioner apply precision (default: FP64)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -348,9 +443,12 @@ def main():
         return
     index = {"laplace2d_n2025": 0, "convdiff3d_n262144": 1, "varcoef3d_n1191016_mimo4": 2,
              "varcoef27_n2097152": 4}[args.workload]
-    w = make_workload(index, prec=args.prec)
+    w = make_workload(index, prec=args.prec or ("f64" if index == 4 else None))
     apply = args.apply or default_apply(w.prec)
     nsolves = sum(len(r) for r in w.rounds) * w.B.shape[1]
+    # the CPU oracle's sample runs first: its process pool forks, which is
+    # done before anything touches the GPU
+    sample = None if args.no_cpu_baseline else cpu_sample(w)
     ctx = api.Context(0)
     torch.cuda.synchronize()
     t_setup = time.perf_counter()
@@ -426,10 +524,8 @@ def main():
         launches, ms, byts = tr[DOMINANT]
         achieved = byts / (ms * 1e-3) / 1e9
         ncol = len(w.rounds[0]) * w.B.shape[1]
-        ctype = {"f64": "double", "f32": "float", "bf16": "unsigned short"}
-        tune_now = S.get_tune()
-        roof_kernel = chain_kernel_name(w.A, ctype[w.prec], ctype[apply], ncol,
-                                        tune_now["cols_per_wave"], tune_now["chain_kernel"] == 1)
+        # the instance the library launches, as rocprofv3 names it
+        roof_kernel = morx.morx_chain_kernel_name(S.handle, ncol, w.prec, apply)
         traffic = None
         if os.path.exists(traffic_file(w.name)):
             with open(traffic_file(w.name)) as f:
@@ -445,6 +541,10 @@ def main():
                     "kernel": roof_kernel,
                     "avg_launch_us": round(1e3 * ms / launches, 2),
                     "alg_bytes_per_launch": byts / launches}
+        if byts / launches < LLC_BYTES:
+            # one launch's bytes fit the 256 MB last-level cache: the rate is
+            # not an HBM rate
+            roofline["cache_resident"] = True
 
     if args.calibrate_copy:
         # a plain copy of known size: 1 GiB read + 1 GiB written per launch
@@ -455,7 +555,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    lad = ladder(S, w, Bd, Cd, nsolves) if index == 4 and args.prec is None else None
+    lad = (ladder(S, w, Bd, Cd, nsolves)
+           if index == 4 and args.prec is None and not args.no_ladder else None)
 
     comparators = None
     if args.compare_policies:
@@ -535,7 +636,15 @@ def main():
               "mode": "IRKA (Algorithm 2 shift update), c = b, r = shifts per round"}
         print(f"[irka] {ik['status']} rounds={rounds} {dt_:.2f} s", file=sys.stderr, flush=True)
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(w, apply)
+    cpu = None
+    if sample is not None:
+        from oracle import chain as ochain
+
+        specs, chains = ochain.schedule(w.rounds)
+        m = w.B.shape[1]
+        lens = [len(chains[z][i]) for z in range(len(w.rounds))
+                for i in range(len(w.rounds[z])) for _ in range(m)]
+        cpu = cpu_baseline(w, sample, lens, [st.iters for st in last], len(specs))
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1,

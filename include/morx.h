@@ -417,6 +417,16 @@ typedef struct {
 } morx_tune;
 
 morx_status morx_system_get_tune(morx_system sys, morx_tune* out);
+/*
+ * The chain-step kernel instance a solve of ncol column pairs on sys
+ * launches now (for every chain step but the last of an iteration, whose
+ * instance also forms the rho partial sums), with factors stored at prec and
+ * applied at apply_prec, written as its demangled name, e.g.
+ * "k_chain_halo<double, double, 12, false, 32, 2048>" (host buf, cap bytes,
+ * NUL-terminated; MORX_E_INVALID if it does not fit).
+ */
+morx_status morx_chain_kernel_name(morx_system sys, int32_t ncol, int32_t prec,
+                                   int32_t apply_prec, char* buf, int32_t cap);
 morx_status morx_system_set_tune(morx_system sys, const morx_tune* tune);
 morx_status morx_autotune(morx_system sys, double sigma, int32_t ncols, int32_t chain_len,
                           int32_t prec, morx_tune* out, void* stream);
@@ -473,6 +483,15 @@ morx_status morx_serve_wait(morx_server srv, uint64_t ticket, morx_col_stats* st
                             double* latency_s);
 morx_status morx_serve_info(morx_server srv, uint64_t* submitted, uint64_t* completed,
                             int32_t* running, int32_t* queued, int64_t* bytes_in_use);
+
+/*
+ * Device bytes a server with this configuration and these options counts
+ * against its budget for sys: *system_bytes when the system is made
+ * resident (its slot batch and anchor factors), *request_bytes per admitted
+ * request (its update factor).  cfg and opts may be NULL for the defaults.
+ */
+morx_status morx_serve_footprint(const morx_serve_config* cfg, const morx_opts* opts,
+                                 morx_system sys, size_t* system_bytes, size_t* request_bytes);
 
 /* Scheduler counters since morx_serve_start. */
 typedef struct {

@@ -145,6 +145,35 @@ def apply(factors, chain: Sequence[int], v: np.ndarray, apply_prec: str = "f64")
     return out
 
 
+def apply_rows(factors, chain: Sequence[int], v: np.ndarray, rows: Sequence[int],
+               transpose: bool = False, factors_t=None) -> np.ndarray:
+    """Selected entries of :func:`apply` (or :func:`apply_transpose` when
+    ``transpose``), FP64, for systems too large to apply whole: row ``i`` of
+    the chain's product is formed as the sparse row vector
+    ``e_i^T F_chain[-1] ... F_chain[0]`` (``e_i^T F_chain[0]^T ... F_chain[-1]^T``)
+    one factor at a time, then multiplied with ``v``.  The product is the
+    same linear map; only the summation order differs.  ``factors_t`` may
+    hold the transposes in CSR form (formed here otherwise)."""
+    import scipy.sparse as sp
+
+    n = factors[chain[0]].shape[0]
+    if transpose:
+        if factors_t is None:
+            factors_t = {f: factors[f].T.tocsr() for f in set(chain)}
+        mats = factors_t
+        order = list(chain)
+    else:
+        mats = factors
+        order = list(reversed(chain))
+    out = np.empty(len(rows))
+    for k, i in enumerate(rows):
+        r = sp.csr_matrix(([1.0], ([0], [int(i)])), shape=(1, n))
+        for f in order:
+            r = r @ mats[f]
+        out[k] = (r @ np.asarray(v, dtype=np.float64))[0]
+    return out
+
+
 def apply_transpose(factors, chain: Sequence[int], v: np.ndarray,
                     apply_prec: str = "f64") -> np.ndarray:
     """Transpose of :func:`apply`: ``F_chain[0]^T ( ... (F_chain[-1]^T v))``."""

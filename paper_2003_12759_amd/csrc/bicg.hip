@@ -22,6 +22,7 @@
 // fences inside a kernel).  The host polls the column states every few
 // iterations.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -1759,6 +1760,30 @@ extern "C" morx_status morx_system_get_tune(morx_system sys, morx_tune* out) {
   return MORX_OK;
 }
 
+extern "C" morx_status morx_chain_kernel_name(morx_system sys, int32_t ncol, int32_t prec,
+                                              int32_t apply_prec, char* buf, int32_t cap) {
+  MORX_REQUIRE(sys && buf && cap > 0 && ncol >= 1, MORX_E_INVALID,
+               "morx_chain_kernel_name: bad argument");
+  MORX_REQUIRE(prec >= MORX_F64 && prec <= MORX_BF16 &&
+                   (apply_prec == MORX_F64 || apply_prec == MORX_F32),
+               MORX_E_INVALID, "morx_chain_kernel_name: bad precision");
+  std::lock_guard<std::mutex> lk(sys->ctx->mu);
+  const char* vt = prec == MORX_F64 ? "double" : (prec == MORX_F32 ? "float" : "unsigned short");
+  const char* at = apply_prec == MORX_F64 ? "double" : "float";
+  const int nc = pick_nc(ncol, sys->tune_nc > 0 ? (int)sys->tune_nc : kDefaultNC);
+  const bool narrow = pattern_narrow(sys);
+  char tmp[128];
+  if (halo_in_use(sys))
+    snprintf(tmp, sizeof(tmp), "k_chain_halo<%s, %s, %d, false, %d, %d>", vt, at, nc,
+             narrow ? kNarrow : kHaloMaxW, narrow ? kHaloCapNarrow : kHaloCap);
+  else
+    snprintf(tmp, sizeof(tmp), "%s<%s, %s, %d, false>", narrow ? "k_chain_narrow" : "k_chain_step",
+             vt, at, nc);
+  MORX_REQUIRE((int)strlen(tmp) < cap, MORX_E_INVALID, "morx_chain_kernel_name: buffer too small");
+  memcpy(buf, tmp, strlen(tmp) + 1);
+  return MORX_OK;
+}
+
 extern "C" morx_status morx_system_set_tune(morx_system sys, const morx_tune* t) {
   MORX_REQUIRE(sys && t, MORX_E_INVALID, "morx_system_set_tune: null argument");
   MORX_REQUIRE(t->factor_kernel == -1 || factor_kernel_supported(sys, t->factor_kernel),
@@ -1802,6 +1827,13 @@ __global__ void k_tune_rhs(double* p, int64_t n, int64_t ld, int ncol) {
 
 }  // namespace
 
+// systems above this size skip the Householder least-squares candidates when
+// the normal equations apply
+constexpr int64_t kTuneHouseholderMaxN = (int64_t)1 << 17;
+// relative slowdown that ends a tile's row-block search (single timings of
+// 6 iterations vary by about 1 % between launches)
+constexpr double kTuneMargin = 0.03;
+
 static morx_status time_events(hipEvent_t a, hipEvent_t b, hipStream_t st, double* ms) {
   MORX_HIP(hipStreamSynchronize(st));
   float f = 0.f;
@@ -1827,8 +1859,15 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
   const int njobs = (int)std::max<int64_t>(1, std::min<int64_t>({chain_len, 16, cap_jobs}));
   std::vector<FactorJob> fjobs(njobs, FactorJob{sigma, 0.0, 1, f->vals.p, f->valsT.p});
   const int saved_rows = sys->tune_factor_rows;
+  // Where the normal equations apply, a column costs them two m x m
+  // matrices and an m x m Cholesky per shift against a Householder QR of the
+  // |I_k| x m local matrix (|I_k| about 4m for stencils): measured 5-9x
+  // faster.  On large systems the Householder candidates, each a full build,
+  // are therefore not timed.
+  const bool ne_ok = factor_kernel_supported(sys, 2);
   for (int rows : {2, 0, 1, 8, 16}) {
     if (!factor_kernel_supported(sys, rows)) continue;
+    if (rows != 2 && ne_ok && sys->n > kTuneHouseholderMaxN) continue;
     sys->tune_factor_rows = rows;
     MORX_HIP(hipEventRecord(e0, st));
     morx_status s = factor_build_many(sys, prec, fjobs.data(), njobs, st);
@@ -1945,8 +1984,9 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
           best_spw = spw;
           best_chain = kern;
         }
-        if (ms > prev) break;  // a wider row block already lost at this tile
-        prev = ms;
+        // a wider row block lost at this tile (beyond launch-to-launch jitter)
+        if (ms > prev * (1.0 + kTuneMargin)) break;
+        prev = std::min(prev, ms);
       }
       if (s != MORX_OK) break;
     }

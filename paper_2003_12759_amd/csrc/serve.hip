@@ -545,6 +545,26 @@ extern "C" morx_status morx_serve_info(morx_server srv, uint64_t* submitted, uin
   return MORX_OK;
 }
 
+extern "C" morx_status morx_serve_footprint(const morx_serve_config* cfg, const morx_opts* opts,
+                                            morx_system sys, size_t* system_bytes,
+                                            size_t* request_bytes) {
+  MORX_REQUIRE(sys && system_bytes && request_bytes, MORX_E_INVALID,
+               "morx_serve_footprint: null argument");
+  morx_serve_config c;
+  morx_opts o;
+  if (cfg) c = *cfg;
+  else morx_serve_config_default(&c);
+  if (opts) o = *opts;
+  else morx_opts_default(&o);
+  MORX_REQUIRE(c.slots_per_system >= 1 && c.anchors >= 1 && o.precond_prec >= MORX_F64 &&
+                   o.precond_prec <= MORX_BF16 && (o.apply_prec == MORX_F64 || o.apply_prec == MORX_F32),
+               MORX_E_INVALID, "morx_serve_footprint: bad configuration");
+  *system_bytes = batch_bytes(sys, c.slots_per_system, o.apply_prec) +
+                  (size_t)c.anchors * factor_bytes(sys, o.precond_prec);
+  *request_bytes = factor_bytes(sys, o.precond_prec);
+  return MORX_OK;
+}
+
 extern "C" morx_status morx_serve_counts_get(morx_server srv, morx_serve_counts* out) {
   MORX_REQUIRE(srv && out, MORX_E_INVALID, "morx_serve_counts_get: null argument");
   std::lock_guard<std::mutex> lk(srv->mu);

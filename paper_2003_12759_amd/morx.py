@@ -138,6 +138,7 @@ _SIG = {
                          ctypes.POINTER(_i32), ctypes.POINTER(_d), ctypes.POINTER(morx_col_stats),
                          _p]),
     "morx_system_get_tune": (_i32, [_p, ctypes.POINTER(morx_tune)]),
+    "morx_chain_kernel_name": (_i32, [_p, _i32, _i32, _i32, ctypes.c_char_p, _i32]),
     "morx_system_set_tune": (_i32, [_p, ctypes.POINTER(morx_tune)]),
     "morx_autotune": (_i32, [_p, _d, _i32, _i32, _i32, ctypes.POINTER(morx_tune), _p]),
     "morx_serve_config_default": (None, [ctypes.POINTER(morx_serve_config)]),
@@ -152,6 +153,9 @@ _SIG = {
                                ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i64)]),
     "morx_serve_stop": (_i32, [_p]),
     "morx_serve_counts_get": (_i32, [_p, ctypes.POINTER(morx_serve_counts)]),
+    "morx_serve_footprint": (_i32, [ctypes.POINTER(morx_serve_config), ctypes.POINTER(morx_opts),
+                                    _p, ctypes.POINTER(ctypes.c_size_t),
+                                    ctypes.POINTER(ctypes.c_size_t)]),
     "morx_serve_chain": (_i32, [_p, ctypes.c_uint64, _i32, ctypes.POINTER(_i32),
                                 ctypes.POINTER(morx_factor_spec)]),
     "morx_trace_enable": (_i32, [_p, _i32]),
@@ -267,6 +271,13 @@ def morx_system_get_tune(sys: int) -> dict:
     t = morx_tune()
     _check(_lib.morx_system_get_tune(sys, ctypes.byref(t)), "morx_system_get_tune")
     return _tune_dict(t)
+
+
+def morx_chain_kernel_name(sys: int, ncol: int, prec: str = "f64", apply: str = "f64") -> str:
+    buf = ctypes.create_string_buffer(128)
+    _check(_lib.morx_chain_kernel_name(sys, int(ncol), PREC[prec], PREC[apply], buf, 128),
+           "morx_chain_kernel_name")
+    return buf.value.decode()
 
 
 def morx_system_set_tune(sys: int, factor_kernel: int = -1, cols_per_wave: int = -1,
@@ -638,6 +649,16 @@ def morx_serve_info(srv: int):
                                 ctypes.byref(d), ctypes.byref(e)), "morx_serve_info")
     return {"submitted": a.value, "completed": b.value, "running": c.value, "queued": d.value,
             "bytes_in_use": e.value}
+
+
+def morx_serve_footprint(sys: int, cfg: Optional[morx_serve_config] = None,
+                         opts: Optional[morx_opts] = None):
+    """(system_bytes, request_bytes) a server counts for sys."""
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(_lib.morx_serve_footprint(ctypes.byref(cfg) if cfg is not None else None,
+                                     ctypes.byref(opts) if opts is not None else None, sys,
+                                     ctypes.byref(a), ctypes.byref(b)), "morx_serve_footprint")
+    return a.value, b.value
 
 
 def morx_serve_counts_get(srv: int) -> dict:

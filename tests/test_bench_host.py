@@ -1,32 +1,42 @@
-"""Host-side helpers of bench.py (no GPU): the name of the chain-step
-instance the library launches, which keys the measured HBM traffic, and the
-structure of the committed traffic files."""
+"""Host-side parts of bench.py (no GPU): the CPU baseline's job-time model
+and the structure of the committed traffic files."""
 import json
-import os
 
 import bench
-from paper_2003_12759_amd.workloads import make_workload
 
 
-def test_chain_kernel_labels():
-    w1 = make_workload(1, N=8)  # 7-point: every row of S and S^T has at most 8 entries
-    name = bench.chain_kernel_name
-    assert name(w1.A, "float", "double", 10, 2, True) == "k_chain_halo<float, double, 2>"
-    assert name(w1.A, "float", "double", 10, 2, False) == "k_chain_narrow<float, double, 2>"
-    # 10 columns balanced into chunks of at most 8 (two of 5) or 16 (one of 10)
-    assert name(w1.A, "float", "double", 10, 8, True) == "k_chain_halo<float, double, 5>"
-    assert name(w1.A, "float", "double", 10, 16, True) == "k_chain_halo<float, double, 10>"
-    w4 = make_workload(4, N=6)  # 27-point
-    assert (name(w4.A, "unsigned short", "double", 12, 16, False)
-            == "k_chain_step<unsigned short, double, 12>")
-    assert (name(w4.A, "unsigned short", "double", 12, 16, True)
-            == "k_chain_halo<unsigned short, double, 12>")
+class _W:
+    n = 1000
+
+
+def test_cpu_baseline_job_model():
+    """Factor builds at the pool's column rate, then the shifts' solves spread
+    over the workers longest first (the makespan), value = solves / time."""
+    sample = {"model": "x", "cores": 2, "cols_per_s": 1000.0, "iter_s_base": 0.01,
+              "iter_s_per_factor": 0.002, "wall_s": 1.0}
+    # 3 factors of 1000 columns: 3 s; solves of 100 iterations with chains of
+    # 1, 2, 3: 1.2, 1.4, 1.6 s; on 2 workers: {1.6}, {1.4, 1.2} -> 2.6 s
+    out = bench.cpu_baseline(_W(), sample, [1, 2, 3], [100, 100, 100], 3)
+    assert abs(out["projected_job_s"] - 5.6) < 1e-9
+    assert abs(out["value"] - round(3 / 5.6, 6)) < 1e-12
+    assert out["cores"] == 2 and out["kind"] == "oracle" and out["unit"] == "solves/s"
+
+
+def test_host_cpu_description():
+    model, cores = bench._host_cpu()
+    assert isinstance(model, str) and cores >= 1
 
 
 def test_traffic_files_describe_their_workload():
-    for workload in ("convdiff3d_n262144", "varcoef27_n2097152"):
-        with open(bench.traffic_file(workload)) as f:
+    import glob
+    import os
+
+    files = glob.glob(os.path.join(bench.ROOT, "profiles", "traffic_chain_step_*.json"))
+    assert files
+    for path in files:
+        with open(path) as f:
             d = json.load(f)
+        workload = os.path.basename(path)[len("traffic_chain_step_"):-len(".json")]
         assert workload in d["workload"] and len(d["source_sha256"]) == 64
         assert d["kernels"]
         for label, e in d["kernels"].items():

@@ -21,6 +21,8 @@ torch = pytest.importorskip("torch")
 
 from paper_2003_12759_amd.workloads import make_workload
 
+from host_residual import residual_ok  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 
 MORX_E_INVALID = -1
@@ -124,7 +126,7 @@ def test_halo_kernel_against_gather_kernel_and_direct_solves(ctx, name, prec, ap
             assert stats[i].status == 0
             rp = _relres(M, Xg[:, i], B[:, 0])
             rd = _relres(M.T, Yg[:, i], C[:, 0])
-            assert rp <= 1.01e-10 and rd <= 1.01e-10, (k, i, rp, rd)
+            assert residual_ok(M, Xg[:, i], B[:, 0]) and residual_ok(M.T, Yg[:, i], C[:, 0]), (k, i)
             rpr = _relres(M, xr, B[:, 0])
             rdr = _relres(M.T, yr, C[:, 0])
             assert np.linalg.norm(Xg[:, i] - xr) <= (rp + rpr) * np.linalg.norm(B) / smin * 1.01
@@ -152,7 +154,7 @@ def test_halo_layout_absent_on_scattered_pattern(ctx):
     Xg = X.cpu().numpy()
     for i, s in enumerate([1.0, 10.0]):
         assert stats[i].status == 0
-        assert _relres(s * sp.diags(e) - A, Xg[:, i], B[:, 0]) <= 1.01e-10
+        assert residual_ok(s * sp.diags(e) - A, Xg[:, i], B[:, 0])
     S.close()
 
 
@@ -218,8 +220,8 @@ def test_halo_kernels_widest_tiles(ctx, name):
                 Xg, Yg, stats = runs[k]
                 assert stats[c].status == 0
                 res[k] = _relres(M, Xg[:, c], B[:, j])
-                assert res[k] <= 1.01e-10
-                assert _relres(M.T, Yg[:, c], C[:, j]) <= 1.01e-10
+                assert residual_ok(M, Xg[:, c], B[:, j])
+                assert residual_ok(M.T, Yg[:, c], C[:, j])
             # both within their residual of the exact solution
             xh, xg = runs[1][0][:, c], runs[0][0][:, c]
             bound = (res[1] + res[0]) * np.linalg.norm(B[:, j]) / smin * 1.01

@@ -197,6 +197,33 @@ def test_chain_apply_matches_formed_product():
     assert np.allclose(chain.apply_transpose(fs, ch, v), dense.T @ v, rtol=1e-13, atol=1e-13)
 
 
+def test_chain_apply_rows_match_the_whole_apply():
+    """Sampled rows of a chain product (row vectors pushed through the
+    factors) against the whole apply, both directions, on a chain with a
+    repeated factor."""
+    rng = np.random.default_rng(17)
+    n = 60
+    mats = []
+    for _ in range(3):
+        M = sp.random(n, n, density=0.08, random_state=rng, format="csr")
+        M.data = rng.standard_normal(M.nnz)
+        mats.append((M + sp.identity(n)).tocsr())
+    ch = [0, 1, 2, 1, 0]
+    v = rng.standard_normal(n)
+    rows = [0, 7, 31, 59]
+    whole = chain.apply(mats, ch, v)
+    whole_t = chain.apply_transpose(mats, ch, v)
+    dense = np.eye(n)
+    for f in ch:
+        dense = mats[f].toarray() @ dense
+    scale = np.abs(dense) @ np.abs(v)
+    scale_t = np.abs(dense.T) @ np.abs(v)
+    got = chain.apply_rows(mats, ch, v, rows)
+    got_t = chain.apply_rows(mats, ch, v, rows, transpose=True)
+    assert np.all(np.abs(got - whole[rows]) <= 1e-13 * scale[rows])
+    assert np.all(np.abs(got_t - whole_t[rows]) <= 1e-13 * scale_t[rows])
+
+
 def test_chain_apply_f32_exact_when_every_pass_is_representable():
     """Small-integer factors and input: every pass result is an FP32 number,
     so the FP32 apply equals the FP64 apply bit for bit (both directions)."""
