@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 #include <hip/hip_ext.h>
@@ -116,9 +117,13 @@ __device__ __forceinline__ const void* chain_in(const IterArgs& a, int c, bool b
 __device__ void build_plan(const IterArgs& a) {
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (1ull << lane) - 1ull;
-  const int fill = min(a.plan_ld, a.ymax * a.ncv);
-  for (int s = threadIdx.x >> 6; s < a.maxL; s += kFinThreads / 64) {
-    ChainItem* out = a.plan + (int64_t)s * a.plan_ld;
+  // step maxL: the shifted pair's list (every active column, both halves),
+  // kept after the chain steps' lists, at index lcap
+  for (int s = threadIdx.x >> 6; s <= a.maxL; s += kFinThreads / 64) {
+    const bool spmv = s == a.maxL;
+    const int list = spmv ? a.lcap : s;
+    const int fill = spmv ? a.plan_ld : min(a.plan_ld, a.ymax * a.ncv);
+    ChainItem* out = a.plan + (int64_t)list * a.plan_ld;
     int pos = 0;
     for (int h = 0; h < 2; ++h) {
       const int jf = h ? a.maxL - 1 - s : s;
@@ -129,10 +134,12 @@ __device__ void build_plan(const IterArgs& a) {
         if (c < a.nc) {
           const ColInfo& ci = a.cols[c];
           L = ci.L;
-          on = ci.state == COL_ACTIVE && L > jf;
+          on = ci.state == COL_ACTIVE && (spmv || L > jf);
         }
         const unsigned long long m = __ballot(on);
-        if (on) {
+        if (on && spmv) {
+          out[pos + __popcll(m & below)] = ChainItem{nullptr, nullptr, nullptr, c, h};
+        } else if (on) {
           ChainItem e;
           e.c = c;
           e.flags = h;
@@ -154,13 +161,14 @@ __device__ void build_plan(const IterArgs& a) {
       pos += pad;
     }
     for (int q = pos + lane; q < fill; q += 64) out[q] = ChainItem{nullptr, nullptr, nullptr, -1, 0};
-    if (lane == 0) a.plan_cnt[s] = pos / a.ncv;
+    if (lane == 0) a.plan_cnt[list] = pos / a.ncv;
   }
   __syncthreads();
   // chunk summaries on each chunk's first pair (the same wave per step)
-  for (int s = threadIdx.x >> 6; s < a.maxL; s += kFinThreads / 64) {
-    ChainItem* out = a.plan + (int64_t)s * a.plan_ld;
-    const int nch = a.plan_cnt[s];
+  for (int s = threadIdx.x >> 6; s <= a.maxL; s += kFinThreads / 64) {
+    const int list = s == a.maxL ? a.lcap : s;
+    ChainItem* out = a.plan + (int64_t)list * a.plan_ld;
+    const int nch = a.plan_cnt[list];
     for (int q = lane; q < nch; q += 64) {
       ChainItem* ck = out + (int64_t)q * a.ncv;
       const void* f0 = ck[0].fv;
@@ -241,6 +249,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(IterArgs a) {
 
 // p = z + beta p_old, p~ = z~ + beta p~_old (p = z on a cycle's first
 // step), formed once per row so that the shifted products gather p itself
+// (and the partial sums of ||p~||^2, slot 1 of the delta partials)
 template <typename AT>
 __global__ __launch_bounds__(kBlock) void k_form_p(IterArgs a, int par) {
   const WaveCtx t = wave_ctx(a);
@@ -255,17 +264,21 @@ __global__ __launch_bounds__(kBlock) void k_form_p(IterArgs a, int par) {
   const double* pto = vptr(a, V_PT0 + (par ^ 1), c);
   double* pn = vptr(a, V_P0 + par, c);
   double* ptn = vptr(a, V_PT0 + par, c);
+  double v[1][1] = {{0.0}};
   for (int64_t sl = t.s_begin; sl < t.s_end; ++sl) {
     const int64_t i = sl * kSlice + t.lane;
     if (i >= a.n) continue;
     const double zi = (double)z[i], zti = (double)zt[i];
     pn[i] = first ? zi : fma(beta, po[i], zi);
-    ptn[i] = first ? zti : fma(beta, pto[i], zti);
+    const double pti = first ? zti : fma(beta, pto[i], zti);
+    ptn[i] = pti;
+    v[0][0] = fma(pti, pti, v[0][0]);
   }
+  block_partials<1, 1>(a, t, c, 1u, v, a.part_delta + (int64_t)a.cap * a.nblk);
 }
 
 // q = (sigma E - A) p, q~ = (sigma E - A)^T p~, partial sums of
-// delta = p~^T q, ||p~||^2, ||q||^2
+// delta = p~^T q and ||q||^2
 template <int NC>
 __global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
   constexpr int kU = ChunkLen<NC>::value;
@@ -286,9 +299,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
   // valid is the same for the whole block; columns past the batch read the
   // last column's vectors and their results are dropped
   if (!valid) return;
-  double v[NC][3];
+  double v[NC][2];
 #pragma unroll
-  for (int j = 0; j < NC; ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
+  for (int j = 0; j < NC; ++j) v[j][0] = v[j][1] = 0.0;
   for (int64_t sl = t.s_begin; sl < t.s_end; ++sl) {
     const int64_t i = sl * kSlice + t.lane;
     double acc[NC], acct[NC];
@@ -348,201 +361,12 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pair(IterArgs a, int par) {
           gst(vptr(a, V_Q, c) + i, qi);
           gst(vptr(a, V_QT, c) + i, qti);
           v[j][0] = fma(pti, qi, v[j][0]);
-          v[j][1] = fma(pti, pti, v[j][1]);
-          v[j][2] = fma(qi, qi, v[j][2]);
+          v[j][1] = fma(qi, qi, v[j][1]);
         }
     }
   }
-  block_partials<NC, 3>(a, t, c0, valid, v, a.part_delta);
-}
-
-// The shifted pair on the halo layout (the chain step's layout, see
-// k_chain_halo): per block of four slices, A's product on the rows of S with
-// p staged in LDS, then A^T's on the rows of S^T with p~ staged, CB columns
-// per round.  Rows sum their slots in the gather kernel's order, so q and q~
-// are the same; the delta partial sums follow the forward half.
-// most columns per block of the halo product (three per LDS round)
-constexpr int kSpmvHaloNC = 8;
-constexpr int kSpmvHaloNCNarrow = 8;
-
-// W: slots a slice may have (8 or W); HC: list cap (LDS entries)
-template <int NC, int W, int HC>
-__global__ __launch_bounds__(kBlock) void k_spmv_halo(IterArgs a, int par) {
-  constexpr int CB = HaloGroup<NC>::value;
-  constexpr int kPT = HC / kBlock;
-  constexpr int kSG = 4;
-  constexpr int kGW = 8;
-  __shared__ double xs[HC * CB];  // [HC][CB], as in k_chain_halo
-  const WaveCtx t = wave_ctx(a);
-  const int c0 = blockIdx.y * NC;
-  unsigned valid = 0;
-  double sig[NC];
-  const double *p[NC], *pt[NC];
-#pragma unroll
-  for (int j = 0; j < NC; ++j) {
-    const int c = min(c0 + j, a.nc - 1);
-    const ColInfo& ci = a.cols[c];
-    if (c0 + j < a.nc && ci.state == COL_ACTIVE) valid |= 1u << j;
-    sig[j] = ci.sigma;
-    p[j] = (const double*)uniform(vptr(a, V_P0 + par, c));
-    pt[j] = (const double*)uniform(vptr(a, V_PT0 + par, c));
-  }
-  // valid is the same for the whole block (before any barrier); columns past
-  // the batch read the last column's vectors and their results are dropped
-  if (!valid) return;
-  double v[NC][3];
-#pragma unroll
-  for (int j = 0; j < NC; ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
-  const int64_t nrb = (a.nslices + kHaloSlices - 1) / kHaloSlices;
-  const int64_t rb0 = (int64_t)t.blk * a.spw;
-  const int nrbk = (int)max<int64_t>(0, min<int64_t>(a.spw, nrb - rb0));
-  const uint32_t vbytes = (uint32_t)(a.ld * (int64_t)sizeof(double));
-  for (int k = 0; k < nrbk; ++k) {
-    const int64_t rb = rb0 + k;
-    const int64_t sl = rb * kHaloSlices + t.wave;
-    const int64_t slc = min<int64_t>(sl, a.nslices - 1);
-    const int64_t i = sl * kSlice + t.lane;
-    const double ei = i < a.n ? gld(a.e + i) : 0.0;
-#pragma unroll 1
-    for (int h = 0; h < 2; ++h) {
-      const int32_t* off = h ? a.offT : a.off;
-      const int32_t* hoff = h ? a.hoffT : a.hoff;
-      const int32_t* hcol = h ? a.hcolT : a.hcol;
-      const uint16_t* lidx = h ? a.lidxT : a.lidx;
-      const double* val = h ? a.valAT : a.valA;
-      const int32_t base = __builtin_amdgcn_readfirstlane(gld(off + slc));
-      const int w = sl < a.nslices
-                        ? (__builtin_amdgcn_readfirstlane(gld(off + slc + 1)) - base) >> 6
-                        : 0;
-      const int ngw = __builtin_amdgcn_readfirstlane((w + kGW - 1) / kGW);
-      const int32_t h0 = __builtin_amdgcn_readfirstlane(gld(hoff + rb));
-      const int H = __builtin_amdgcn_readfirstlane(gld(hoff + rb + 1)) - h0;
-      int32_t hv[kPT];
-      const int32_t* hp = hcol + h0 + threadIdx.x;
-#pragma unroll
-      for (int q = 0; q < kPT; ++q) {
-        const int32_t r = gld(hp + kBlock * q);
-        hv[q] = (int)threadIdx.x + kBlock * q < H ? r : 0;
-      }
-      const uint16_t* lp = lidx + base + t.lane;
-      const double* vp = val + base + t.lane;
-      constexpr uint32_t kStride = (uint32_t)(CB * sizeof(double));
-      // 8 slots: a row's local indices and values stay in registers for all
-      // rounds; 32 slots: they are read again per round, a group of kGW
-      // slots at a time with the next group's loads in flight (L2 hits after
-      // the first round), so that wider tiles fit the register budget
-      constexpr bool kHold = W <= kNarrow;
-      uint32_t la[kHold ? W : 1];
-      double fb[kHold ? W : 1];
-      if constexpr (kHold) {
-#pragma unroll
-        for (int m = 0; m < W; ++m) {
-          const uint32_t r = gld(lp + m * kSlice);
-          la[m] = m < w ? r * kStride : 0u;
-          const double x = gld(vp + m * kSlice);
-          fb[m] = m < w ? x : 0.0;
-        }
-      }
-#pragma unroll
-      for (int j0 = 0; j0 < NC; j0 += CB) {
-        BufRes rs[CB];
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-          const int j = min(j0 + c, NC - 1);
-          rs[c] = buf_res(h ? pt[j] : p[j], vbytes);
-        }
-#pragma unroll
-        for (int q0 = 0; q0 < kPT; q0 += kSG) {
-          if (q0 * kBlock >= H) break;  // uniform
-          double sv[kSG][CB];
-#pragma unroll
-          for (int q = 0; q < kSG; ++q) {
-            const int e = (int)threadIdx.x + kBlock * (q0 + q);
-            const uint32_t o = e < H ? (uint32_t)hv[q0 + q] * 8u : kOutside;
-#pragma unroll
-            for (int c = 0; c < CB; ++c) sv[q][c] = buf_val<double>(rs[c], o);
-          }
-#pragma unroll
-          for (int q = 0; q < kSG; ++q) {
-            const int e = (int)threadIdx.x + kBlock * (q0 + q);
-#pragma unroll
-            for (int c = 0; c < CB; ++c) xs[e * CB + c] = sv[q][c];
-          }
-        }
-        // (reload form) the round's first group, in flight across the barrier
-        uint32_t lb[2][kGW];
-        double vb[2][kGW];
-        auto load_group = [&](int g, int q) {
-#pragma unroll
-          for (int u = 0; u < kGW; ++u) {
-            const int m = g * kGW + u;
-            const uint32_t r = gld(lp + m * kSlice);
-            lb[q][u] = m < w ? r * kStride : 0u;
-            const double x = gld(vp + m * kSlice);
-            vb[q][u] = m < w ? x : 0.0;
-          }
-        };
-        if constexpr (!kHold) load_group(0, 0);
-        // the row's p_i and p~_i of the round's columns, in flight during the sums
-        double pr[CB], ptr_[CB];
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-          const int j = min(j0 + c, NC - 1);
-          pr[c] = ptr_[c] = 0.0;
-          if (i < a.n) {
-            if (h == 0) pr[c] = gld(p[j] + i);
-            ptr_[c] = gld(pt[j] + i);
-          }
-        }
-        __syncthreads();
-        double acc[CB];
-#pragma unroll
-        for (int c = 0; c < CB; ++c) acc[c] = 0.0;
-        const char* xc = (const char*)xs;
-#pragma unroll
-        for (int g = 0; g < W / kGW; ++g) {
-          if (g >= ngw) break;  // uniform
-          if constexpr (!kHold)
-            if (g + 1 < W / kGW && g + 1 < ngw) load_group(g + 1, (g + 1) & 1);
-#pragma unroll
-          for (int c = 0; c < CB; ++c) {
-            double xg[kGW];
-#pragma unroll
-            for (int u = 0; u < kGW; ++u) {
-              const uint32_t ad = kHold ? la[kHold ? g * kGW + u : 0] : lb[g & 1][u];
-              xg[u] = *(const double*)(xc + ad + c * sizeof(double));
-            }
-#pragma unroll
-            for (int u = 0; u < kGW; ++u) {
-              const double f = kHold ? fb[kHold ? g * kGW + u : 0] : vb[g & 1][u];
-              acc[c] = fma(f, xg[u], acc[c]);
-            }
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-          const int j = j0 + c;
-          if (j < NC && (valid & (1u << j)) && i < a.n) {
-            const int cc = c0 + j;
-            const double se = sig[j] * ei;
-            if (h == 0) {
-              const double pi = pr[c];
-              const double pti = ptr_[c];
-              const double qi = fma(se, pi, -acc[c]);
-              gst(vptr(a, V_Q, cc) + i, qi);
-              v[j][0] = fma(pti, qi, v[j][0]);
-              v[j][1] = fma(pti, pti, v[j][1]);
-              v[j][2] = fma(qi, qi, v[j][2]);
-            } else {
-              gst(vptr(a, V_QT, cc) + i, fma(se, ptr_[c], -acc[c]));
-            }
-          }
-        }
-        __syncthreads();
-      }
-    }
-  }
-  block_partials<NC, 3>(a, t, c0, valid, v, a.part_delta);
+  // delta and ||q||^2 in slots 0 and 2 (form_p fills slot 1 with ||p~||^2)
+  block_partials<NC, 2, 2>(a, t, c0, valid, v, a.part_delta);
 }
 
 __global__ __launch_bounds__(kFinThreads) void k_fin_delta(IterArgs a) {
@@ -978,8 +802,9 @@ void krylov_batch_delete(KrylovBatch* kb) {
 
 // work-list entries per chain step: both halves, each padded to the tile width
 static int plan_ld(int cap) { return 2 * cap + 2 * kMaxNC; }
+// lcap chain-step lists and the shifted pair's, then their chunk counts
 static size_t plan_bytes(int cap, int lcap) {
-  return (size_t)lcap * plan_ld(cap) * sizeof(ChainItem) + (size_t)lcap * sizeof(int32_t);
+  return (size_t)(lcap + 1) * plan_ld(cap) * sizeof(ChainItem) + (size_t)(lcap + 1) * sizeof(int32_t);
 }
 
 size_t batch_bytes(morx_system sys, int cap, int aprec) {
@@ -1125,6 +950,13 @@ static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   a.nsellT = sys->sellT.nnz_sell;
   a.narrow = std::max(sys->sell.max_width, sys->sellT.max_width) <= kNarrow;
   a.hmax = halo_in_use(sys) ? std::max(sys->sell.hmax, sys->sellT.hmax) : 0;
+  // strided row blocks when the groups of hstride * spw row blocks tile the
+  // pattern exactly (the grid's blocks then cover every row block once)
+  {
+    const int64_t nrb = (a.nslices + kHaloSlices - 1) / kHaloSlices;
+    const int64_t S = sys->sell.hstride;
+    a.hstride = (S > 1 && nrb % (S * a.spw) == 0 && nrb / a.spw == a.nblk) ? (int)S : 1;
+  }
   a.hoff = sys->sell.hoff;
   a.hcol = sys->sell.hcol;
   a.lidx = sys->sell.lidx;
@@ -1148,7 +980,7 @@ static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   a.part_norm = part + 6 * slab;
   a.trace = trace_counters(sys->ctx);
   a.plan = (ChainItem*)b.plan.p;
-  a.plan_cnt = (int32_t*)((ChainItem*)b.plan.p + (size_t)b.lcap * a.plan_ld);
+  a.plan_cnt = (int32_t*)((ChainItem*)b.plan.p + (size_t)(b.lcap + 1) * a.plan_ld);
   return a;
 }
 
@@ -1176,28 +1008,27 @@ static void enqueue_chain(const IterArgs& a, int prec, hipStream_t st, TraceStat
 }
 
 // q = A_s p, q~ = A_s^T p~ of an iteration (p in the parity-`par` slots):
-// the halo kernel where the chain step uses the halo layout, else row gathers
+// on the halo layout the chain step's kernel in its shifted-pair form (tile
+// of the chain step), else the row-gather kernel
 static void enqueue_spmv(const IterArgs& a, int par, hipStream_t st, TraceState* t) {
-  const int ncs = pick_nc(a.nc, a.ncmax_spmv);
-  if (a.hmax > 0 && !a.narrow) {
-    const int nch = pick_nc(a.nc, std::min(ncs, kSpmvHaloNC));
-    MORX_NC_DISPATCH(nch, {
-      if constexpr (NC <= kSpmvHaloNC)
-        launch(t, TR_SPMV, k_spmv_halo<NC, kHaloMaxW, kHaloCap>, grid_of(a, NC, 1),
-               dim3(kBlock), st, a, par);
-    });
-  } else if (a.hmax > 0) {
-    const int nch = pick_nc(a.nc, std::min(ncs, kSpmvHaloNCNarrow));
-    MORX_NC_DISPATCH(nch, {
-      if constexpr (NC <= kSpmvHaloNCNarrow)
-        launch(t, TR_SPMV, k_spmv_halo<NC, kNarrow, kHaloCapNarrow>, grid_of(a, NC, 1),
-               dim3(kBlock), st, a, par);
-    });
-  } else {
-    MORX_NC_DISPATCH(ncs, {
-      launch(t, TR_SPMV, k_spmv_pair<NC>, grid_of(a, NC, 1), dim3(kBlock), st, a, par);
-    });
+  if (a.hmax > 0) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (t) {
+      e0 = trace_event(t);
+      e1 = trace_event(t);
+      if (e0) hipEventRecord(e0, st);
+    }
+    spmv_halo_launch(a, par, st);
+    if (t && e0 && e1) {
+      hipEventRecord(e1, st);
+      t->pending.push_back({TR_SPMV, e0, e1, 1});
+    }
+    return;
   }
+  const int ncs = pick_nc(a.nc, a.ncmax_spmv);
+  MORX_NC_DISPATCH(ncs, {
+    launch(t, TR_SPMV, k_spmv_pair<NC>, grid_of(a, NC, 1), dim3(kBlock), st, a, par);
+  });
 }
 
 static morx_status enqueue_iterations(const IterArgs& a, int prec, int iters, hipStream_t st,
@@ -1757,6 +1588,7 @@ extern "C" morx_status morx_system_get_tune(morx_system sys, morx_tune* out) {
   out->slices_per_wave = sys->tune_spw;
   out->spmv_cols_per_wave = sys->tune_nc_spmv;
   out->chain_kernel = halo_in_use(sys) ? 1 : 0;
+  out->halo_stride = halo_in_use(sys) ? sys->sell.hstride : 1;
   return MORX_OK;
 }
 
@@ -2029,6 +1861,7 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
   out->slices_per_wave = best_spw;
   out->spmv_cols_per_wave = best_ncs;
   out->chain_kernel = halo_in_use(sys) ? 1 : 0;
+  out->halo_stride = halo_in_use(sys) ? sys->sell.hstride : 1;
   out->factor_ms = best_f;
   out->iter_ms = best_i;
   return MORX_OK;
@@ -2137,6 +1970,7 @@ morx_status hot_shifted_pair(morx_system sys, int ncol, const double* sigmas, co
   if (s == MORX_OK) {
     const IterArgs a = make_args(b, ncol, 1);
     k_probe_in<<<probe_grid(sys, ncol), 256, 0, st>>>(a, V_P0, V_PT0, X, ldx, Xt, ldxt, 0);
+    k_plan<<<1, kFinThreads, 0, st>>>(a);  // the halo form takes its columns from a work list
     enqueue_spmv(a, 0, st, nullptr);
     k_probe_out<<<probe_grid(sys, ncol), 256, 0, st>>>(a, 0, Y, ldy, Yt, ldyt);
     const hipError_t e = hipGetLastError();

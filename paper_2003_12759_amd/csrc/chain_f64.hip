@@ -2,3 +2,7 @@
 #include "chain_kernels.h"
 
 void chain_launch_f64(const IterArgs& a, hipStream_t st) { chain_launch_vt<double>(a, st); }
+
+void spmv_halo_launch(const IterArgs& a, int par, hipStream_t st) {
+  MORX_NC_DISPATCH(a.ncv, spmv_halo_run<NC>(a, par, st));
+}

@@ -59,6 +59,7 @@ struct IterArgs {
   int narrow;      // every slice of S and S^T at most kNarrow slots wide
   int hmax;        // chain step on the halo layout: longest list of S and S^T; 0: gathers
                    // (narrow patterns: the W = 8 kernel, lists of at most kHaloCapNarrow)
+  int hstride;     // halo kernels: a block's row blocks are hstride apart (1: consecutive)
   const int32_t *hoff, *hcol, *hoffT, *hcolT;
   const uint16_t *lidx, *lidxT;
   const int32_t *off, *col, *offT, *colT;
@@ -115,8 +116,9 @@ __device__ __forceinline__ WaveCtx wave_ctx(const IterArgs& a) {
 // ---- reductions --------------------------------------------------------------
 
 // Sum NQ per-lane values of each of the NC columns over the block and store
-// one partial per (quantity, column, block).  Every thread calls it.
-template <int NC, int NQ>
+// one partial per (quantity, column, block); quantity q goes to slot q * QS.
+// Every thread calls it.
+template <int NC, int NQ, int QS = 1>
 __device__ void block_partials_cols(const IterArgs& a, const WaveCtx& t, const int (&cols)[NC],
                                     unsigned valid, double (&v)[NC][NQ], double* part) {
   __shared__ double sh[kWavesPerBlock][NC][NQ];
@@ -134,19 +136,19 @@ __device__ void block_partials_cols(const IterArgs& a, const WaveCtx& t, const i
       double tot = 0.0;
 #pragma unroll
       for (int w = 0; w < kWavesPerBlock; ++w) tot += sh[w][j][q];
-      part[((int64_t)q * a.cap + cols[j]) * a.nblk + t.blk] = tot;
+      part[((int64_t)q * QS * a.cap + cols[j]) * a.nblk + t.blk] = tot;
     }
   }
 }
 
 // the same for the columns c0 ... c0 + NC - 1
-template <int NC, int NQ>
+template <int NC, int NQ, int QS = 1>
 __device__ void block_partials(const IterArgs& a, const WaveCtx& t, int c0, unsigned valid,
                                double (&v)[NC][NQ], double* part) {
   int cols[NC];
 #pragma unroll
   for (int j = 0; j < NC; ++j) cols[j] = c0 + j;
-  block_partials_cols<NC, NQ>(a, t, cols, valid, v, part);
+  block_partials_cols<NC, NQ, QS>(a, t, cols, valid, v, part);
 }
 
 // One wave sums the nblk partials of NQ quantities of column c, every load of
@@ -612,43 +614,106 @@ __device__ __forceinline__ NarrowVal<VT> gload_narrow(const VT* p) {
   else return gld(p);
 }
 
+// Loads of a stream read once per launch (factor or matrix values, local
+// indices), marked non-temporal so that they do not push the staged vectors,
+// which neighbouring row blocks read again, out of the L2
+template <typename T>
+__device__ __forceinline__ T gld_stream(const T* p) {
+  return __builtin_nontemporal_load((const __attribute__((address_space(1))) T*)p);
+}
+template <typename VT>
+__device__ __forceinline__ NarrowVal<VT> gload_stream(const VT* p) {
+  if constexpr (sizeof(VT) == 2) return __uint_as_float(((uint32_t)gld_stream(p)) << 16);
+  else return gld_stream(p);
+}
+
+// What a halo launch computes.  kHaloChain: one chain step (factor s
+// forward, factor maxL-1-s transposed); kHaloRho: the same, and its
+// transposed half also forms the partial sums of rho = z~^T r, ||z~||^2,
+// ||r||^2 (the iteration's last chain launch); kHaloSpmv: the shifted pair
+// q = (sigma E - A) p on the rows of S and q~ = (sigma E - A)^T p~ on the rows
+// of S^T, A's values taking the place of a factor shared by every column (p
+// of parity s & 1), with the partial sums of delta = p~^T q, ||p~||^2,
+// ||q||^2 on the forward half.
+enum HaloMode : int { kHaloChain = 0, kHaloRho = 1, kHaloSpmv = 2 };
+
 // W: slots a slice may have (8 or W); HC: list cap (LDS entries)
-template <typename VT, typename AT, int NC, bool RHO, int W, int HC>
+template <typename VT, typename AT, int NC, int MODE, int W, int HC>
 __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
+  constexpr bool RHO = MODE == kHaloRho;
+  constexpr bool SPMV = MODE == kHaloSpmv;  // VT = AT = double
+  constexpr bool PART = RHO || SPMV;
   constexpr int CB = HaloGroup<NC>::value;
   constexpr int kPT = HC / kBlock;  // list entries per thread
   constexpr int kSG = 4;                  // list entries per thread in flight while staging
   constexpr int kGW = 8;                  // slots per group of the row sums
   using FT = NarrowVal<VT>;
-  // [HC][CB]: the CB vectors' entries at one list position side by
-  // side; every position a staging round covers is written (past the list:
-  // zeros), so the stores need no guard
-  __shared__ AT xs[HC * CB];
+  // [CB][HC]: each vector's entries at the list positions, one vector after
+  // the other, so that the rows of a slice (consecutive list positions in a
+  // stencil's interior) read consecutive LDS words, and one LDS address per
+  // slot serves every vector of the round through the instruction's offset
+  // (c * HC entries); every position a staging round covers is written (past
+  // the list: zeros), so the stores need no guard
+  __shared__ AT xs[CB * HC];
   const WaveCtx t = wave_ctx(a);
   const int64_t nrb = (a.nslices + kHaloSlices - 1) / kHaloSlices;
-  const int64_t rb0 = (int64_t)t.blk * a.spw;  // the block's row blocks: rb0 ... rb0 + spw - 1
-  const int nrbk = (int)max<int64_t>(0, min<int64_t>(a.spw, nrb - rb0));
-  const ChainItem* plan = a.plan + (int64_t)s * a.plan_ld;
-  const int nchunks = gld(a.plan_cnt + s);
+  // the block's row blocks: rb0 + k * hstride, k < spw (hstride 1: the
+  // block's own slices; hstride S: the blocks of a group of S * spw row blocks
+  // take its S strided sequences, neighbours in the group side by side)
+  const int64_t hs = a.hstride;
+  const int64_t rb0 = hs > 1 ? ((int64_t)t.blk / hs) * hs * a.spw + t.blk % hs
+                             : (int64_t)t.blk * a.spw;
+  const int nrbk = hs > 1 ? (rb0 < nrb ? a.spw : 0)
+                          : (int)max<int64_t>(0, min<int64_t>(a.spw, nrb - rb0));
+  // the shifted pair's work list follows the chain steps' lists
+  const int list = SPMV ? a.lcap : s;
+  const int par = s & 1;  // (shifted pair) parity of the p vectors
+  const ChainItem* plan = a.plan + (int64_t)list * a.plan_ld;
+  const int nchunks = gld(a.plan_cnt + list);
   const uint32_t vbytes = (uint32_t)(a.ld * (int64_t)sizeof(AT));
   for (int y = blockIdx.y;; y += gridDim.y) {
     const ChainItem* ck = plan + (int64_t)y * NC;
     if (ck->c < 0) break;  // past the last chunk (uniform over the block)
     const int flags = ck->flags;
     const bool bwd = (flags & 1) != 0;
-    const bool shared = (flags & 2) != 0;
+    const bool shared = SPMV || (flags & 2) != 0;
     const int ncol = flags >> 8;
-    const bool rho_half = RHO && bwd;
-    double v[RHO ? NC : 1][3];
+    const bool part_half = (RHO && bwd) || (SPMV && !bwd);
+    // partial sums per pair: rho, ||z~||^2, ||r||^2 (last chain step), or
+    // delta = p~^T q and ||q||^2 (shifted pair; ||p~||^2 comes from form_p)
+    constexpr int NQ = SPMV ? 2 : 3;
+    // (shifted pair) the list was built before this iteration's convergence
+    // test: columns that have stopped since are skipped
+    unsigned live = (1u << ncol) - 1u;
+    if constexpr (SPMV) {
+      live = 0;
 #pragma unroll
-    for (int j = 0; j < (RHO ? NC : 1); ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
+      for (int j = 0; j < NC; ++j)
+        if (j < ncol && a.cols[ck[j].c].state == COL_ACTIVE) live |= 1u << j;
+      live = __builtin_amdgcn_readfirstlane(live);
+    }
+    double v[PART ? NC : 1][NQ];
+#pragma unroll
+    for (int j = 0; j < (PART ? NC : 1); ++j)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) v[j][q] = 0.0;
     const int32_t* off = bwd ? a.offT : a.off;
     const int32_t* hoff = bwd ? a.hoffT : a.hoff;
     const int32_t* hcol = bwd ? a.hcolT : a.hcol;
     const uint16_t* lidx = bwd ? a.lidxT : a.lidx;
-    const VT* fv0 = (const VT*)uniform(ck->fv);
+    const VT* fv0 = SPMV ? (const VT*)(bwd ? a.valAT : a.valA) : (const VT*)uniform(ck->fv);
+    // the input and output vectors of pair j (the shifted pair's come from the slots)
+    auto col_of = [&](int j) -> int { return __builtin_amdgcn_readfirstlane(ck[j].c); };
+    auto src_of = [&](int j) -> const AT* {
+      if constexpr (SPMV) return (const AT*)vptr(a, (bwd ? V_PT0 : V_P0) + par, col_of(j));
+      else return (const AT*)uniform(ck[j].src);
+    };
+    auto dst_of = [&](int j) -> AT* {
+      if constexpr (SPMV) return (AT*)vptr(a, bwd ? V_QT : V_Q, col_of(j));
+      else return (AT*)uniform(ck[j].dst);
+    };
     for (int k = 0; k < nrbk; ++k) {
-      const int64_t rb = rb0 + k;
+      const int64_t rb = rb0 + k * hs;
       const int64_t sl = rb * kHaloSlices + t.wave;  // this wave's slice (none past the last)
       const int64_t slc = min<int64_t>(sl, a.nslices - 1);
       const int32_t base = __builtin_amdgcn_readfirstlane(gld(off + slc));
@@ -657,6 +722,8 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
                         : 0;
       const int ngw = __builtin_amdgcn_readfirstlane((w + kGW - 1) / kGW);  // slot groups
       const int64_t i = sl * kSlice + t.lane;
+      double ei = 0.0;
+      if constexpr (SPMV) ei = i < a.n ? gld(a.e + i) : 0.0;
       const int32_t h0 = __builtin_amdgcn_readfirstlane(gld(hoff + rb));
       const int H = __builtin_amdgcn_readfirstlane(gld(hoff + rb + 1)) - h0;
       // (the list array carries kHaloCap >= HC entries of padding)
@@ -677,8 +744,8 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
       FT fb[W];
 #pragma unroll
       for (int m = 0; m < W; ++m) {
-        const uint32_t r = gld(lp + m * kSlice);
-        la[m] = m < w ? r * (uint32_t)(CB * sizeof(AT)) : 0u;
+        const uint32_t r = gld_stream(lp + m * kSlice);
+        la[m] = m < w ? r * (uint32_t)sizeof(AT) : 0u;
       }
 #pragma unroll
       for (int m = 0; m < W; ++m) fb[m] = (FT)0;
@@ -686,19 +753,19 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
         const VT* fp = fv0 + base + t.lane;
 #pragma unroll
         for (int m = 0; m < W; ++m) {
-          const FT r = gload_narrow<VT>(fp + m * kSlice);
+          const FT r = gload_stream<VT>(fp + m * kSlice);
           fb[m] = m < w ? r : (FT)0;
         }
       }
 #pragma unroll
       for (int j0 = 0; j0 < NC; j0 += CB) {
         if (j0 >= ncol) break;  // uniform
+        if (((live >> j0) & ((1u << CB) - 1u)) == 0u) continue;  // uniform
         // the CB input vectors at the row block's distinct columns: kSG
         // entries per thread loaded, then stored, at a time
         BufRes rs[CB];
 #pragma unroll
-        for (int c = 0; c < CB; ++c)
-          rs[c] = buf_res(uniform(ck[min(j0 + c, ncol - 1)].src), vbytes);
+        for (int c = 0; c < CB; ++c) rs[c] = buf_res(src_of(min(j0 + c, ncol - 1)), vbytes);
 #pragma unroll
         for (int q0 = 0; q0 < kPT; q0 += kSG) {
           if (q0 * kBlock >= H) break;  // uniform
@@ -714,30 +781,40 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
           for (int q = 0; q < kSG; ++q) {
             const int e = (int)threadIdx.x + kBlock * (q0 + q);
 #pragma unroll
-            for (int c = 0; c < CB; ++c) xs[e * CB + c] = (AT)sv[q][c];
+            for (int c = 0; c < CB; ++c) xs[c * HC + e] = (AT)sv[q][c];
           }
         }
-        // (last step) r_i of the round's pairs, in flight during the sums
-        double rr[RHO ? CB : 1];
-        if constexpr (RHO) {
+        // values at the row itself, in flight during the sums: (last chain
+        // step) r_i of the round's pairs; (shifted pair) p_i or p~_i, and on
+        // the forward half p~_i
+        double rr[PART ? CB : 1], ri2[SPMV ? CB : 1];
+        if constexpr (PART) {
 #pragma unroll
           for (int c = 0; c < CB; ++c) {
             rr[c] = 0.0;
-            if (rho_half && j0 + c < ncol && i < a.n)
-              rr[c] = gld(vptr(a, V_R, __builtin_amdgcn_readfirstlane(ck[j0 + c].c)) + i);
+            if constexpr (SPMV) ri2[c] = 0.0;
+            if (j0 + c < ncol && i < a.n) {
+              const int cc = col_of(j0 + c);
+              if constexpr (RHO) {
+                if (part_half) rr[c] = gld(vptr(a, V_R, cc) + i);
+              } else {
+                rr[c] = gld((const double*)src_of(j0 + c) + i);
+                if (!bwd) ri2[c] = gld(vptr(a, V_PT0 + par, cc) + i);
+              }
+            }
           }
         }
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
           const int j = j0 + c;
-          if (j < NC && j < ncol) {
-            const char* xc = (const char*)(xs + c);
+          if (j < NC && j < ncol && ((live >> j) & 1u)) {
+            const char* xc = (const char*)(xs + c * HC);
             if (!shared) {  // this pair's own factor values
               const VT* fp = (const VT*)uniform(ck[j].fv) + base + t.lane;
 #pragma unroll
               for (int m = 0; m < W; ++m) {
-                const FT r = gload_narrow<VT>(fp + m * kSlice);
+                const FT r = gload_stream<VT>(fp + m * kSlice);
                 fb[m] = m < w ? r : (FT)0;
               }
             }
@@ -755,16 +832,26 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
               for (int u = 0; u < kGW; ++u) acc = fma((double)fb[g * kGW + u], (double)xg[u], acc);
             }
             if (i < a.n) {  // rows past n, and waves past the last slice
-              AT* dst = (AT*)uniform(ck[j].dst);
-              const AT zs = (AT)acc;
-              gst(dst + i, zs);
-              if constexpr (RHO) {
-                if (rho_half) {
-                  const double zi = (double)zs;
-                  const double ri = rr[c];
-                  v[j][0] = fma(zi, ri, v[j][0]);
-                  v[j][1] = fma(zi, zi, v[j][1]);
-                  v[j][2] = fma(ri, ri, v[j][2]);
+              AT* dst = dst_of(j);
+              if constexpr (SPMV) {
+                const double se = a.cols[col_of(j)].sigma * ei;
+                const double qi = fma(se, rr[c], -acc);
+                gst(dst + i, (AT)qi);
+                if (part_half) {
+                  v[j][0] = fma(ri2[c], qi, v[j][0]);
+                  v[j][NQ - 1] = fma(qi, qi, v[j][NQ - 1]);
+                }
+              } else {
+                const AT zs = (AT)acc;
+                gst(dst + i, zs);
+                if constexpr (RHO) {
+                  if (part_half) {
+                    const double zi = (double)zs;
+                    const double ri = rr[c];
+                    v[j][0] = fma(zi, ri, v[j][0]);
+                    v[j][1] = fma(zi, zi, v[j][1]);
+                    v[j][NQ - 1] = fma(ri, ri, v[j][NQ - 1]);
+                  }
                 }
               }
             }
@@ -773,16 +860,17 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
         __syncthreads();  // before the next round overwrites the LDS copies
       }
     }
-    if constexpr (RHO)
-      if (rho_half) {
+    if constexpr (PART)
+      if (part_half) {
         int cols[NC];
         unsigned valid = 0;
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
           cols[j] = j < ncol ? ck[j].c : 0;
-          if (j < ncol) valid |= 1u << j;
+          if (j < ncol && ((live >> j) & 1u)) valid |= 1u << j;
         }
-        block_partials_cols<NC, 3>(a, t, cols, valid, v, a.part_rho);
+        if constexpr (SPMV) block_partials_cols<NC, NQ, 2>(a, t, cols, valid, v, a.part_delta);
+        else block_partials_cols<NC, NQ>(a, t, cols, valid, v, a.part_rho);
         __syncthreads();  // the shared partials are reused by the next chunk
       }
     if (y + (int)gridDim.y >= nchunks) break;
@@ -810,12 +898,12 @@ void chain_run(const IterArgs& a, hipStream_t st) {
   const dim3 g((unsigned)a.nblk, (unsigned)a.ymax, 1);
   if (a.hmax > 0 && a.narrow) {
     for (int s = 0; s + 1 < a.maxL; ++s)
-      k_chain_halo<VT, AT, NC, false, kNarrow, kHaloCapNarrow><<<g, kBlock, 0, st>>>(a, s);
-    k_chain_halo<VT, AT, NC, true, kNarrow, kHaloCapNarrow><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
+      k_chain_halo<VT, AT, NC, kHaloChain, kNarrow, kHaloCapNarrow><<<g, kBlock, 0, st>>>(a, s);
+    k_chain_halo<VT, AT, NC, kHaloRho, kNarrow, kHaloCapNarrow><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
   } else if (a.hmax > 0) {
     for (int s = 0; s + 1 < a.maxL; ++s)
-      k_chain_halo<VT, AT, NC, false, kHaloMaxW, kHaloCap><<<g, kBlock, 0, st>>>(a, s);
-    k_chain_halo<VT, AT, NC, true, kHaloMaxW, kHaloCap><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
+      k_chain_halo<VT, AT, NC, kHaloChain, kHaloMaxW, kHaloCap><<<g, kBlock, 0, st>>>(a, s);
+    k_chain_halo<VT, AT, NC, kHaloRho, kHaloMaxW, kHaloCap><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
   } else if (a.narrow) {
     for (int s = 0; s + 1 < a.maxL; ++s) k_chain_narrow<VT, AT, NC, false><<<g, kBlock, 0, st>>>(a, s);
     k_chain_narrow<VT, AT, NC, true><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
@@ -835,8 +923,21 @@ void chain_launch_vt(const IterArgs& a, hipStream_t st) {
 
 }  // namespace
 
+// The shifted pair on the halo layout (kHaloSpmv), p of parity par, columns
+// in chunks of a.ncv; the grid's y extent covers both halves of every column
+template <int NC>
+void spmv_halo_run(const IterArgs& a, int par, hipStream_t st) {
+  const dim3 g((unsigned)a.nblk, (unsigned)(2 * ((a.nc + NC - 1) / NC)), 1);
+  if (a.narrow)
+    k_chain_halo<double, double, NC, kHaloSpmv, kNarrow, kHaloCapNarrow><<<g, kBlock, 0, st>>>(a, par);
+  else
+    k_chain_halo<double, double, NC, kHaloSpmv, kHaloMaxW, kHaloCap><<<g, kBlock, 0, st>>>(a, par);
+}
+
 // one per file: the chain launches of an iteration for factors stored in
 // FP64, FP32 or BF16 (the apply precision comes from the arguments)
 void chain_launch_f64(const IterArgs& a, hipStream_t st);
+// (in the FP64 file) the shifted pair on the halo layout, tile a.ncv
+void spmv_halo_launch(const IterArgs& a, int par, hipStream_t st);
 void chain_launch_f32(const IterArgs& a, hipStream_t st);
 void chain_launch_bf16(const IterArgs& a, hipStream_t st);

@@ -94,6 +94,10 @@ struct Sell {
   int32_t* hcol = nullptr;
   uint16_t* lidx = nullptr;  // [nnz_sell]
   int32_t hmax = 0;          // longest list; 0: no halo layout
+  // row-block distance whose lists share the most columns (a grid plane
+  // for lexicographically ordered stencils); 1 when no longer one shares more
+  // than the next row block
+  int32_t hstride = 1;
 };
 
 struct morx_ctx_s {

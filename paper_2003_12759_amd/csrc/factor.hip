@@ -342,6 +342,7 @@ __global__ void k_factor_to_csr(const VT* __restrict__ vals, const int32_t* __re
 // shift of that column (and reports a rank-deficient problem as the other
 // kernels do).
 constexpr double kNeTol = 1e-6;
+constexpr int kNeGather = 16;  // entries of a column loaded together in the set-up
 
 struct NeLayout {
   int T;
@@ -382,6 +383,34 @@ NeLayout ne_layout(int maxT, int CG) {
   o += std::max(gather, (size_t)G * tri);
   L.bytes = o;
   return L;
+}
+
+// Lane gbase + c's value for every lane of a group of CG lanes (a group lies
+// within one wave): lane reads of the scalar unit for groups of 16 or 32
+// lanes, an LDS permute for narrower ones
+template <int CG>
+__device__ __forceinline__ double group_bcast(double v, int gbase, int c) {
+  if constexpr (CG >= 16) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    double out = 0.0;
+    const int wl = (int)(threadIdx.x & 63);
+#pragma unroll
+    for (int g2 = 0; g2 < 64 / CG; ++g2) {
+      const double x = __hiloint2double(__builtin_amdgcn_readlane(hi, g2 * CG + c),
+                                        __builtin_amdgcn_readlane(lo, g2 * CG + c));
+      out = (wl / CG == g2) ? x : out;
+    }
+    return out;
+  } else {
+    return __shfl(v, gbase + c, 64);
+  }
+}
+
+// Orders the LDS writes of a group before its lanes' reads: every group lies
+// within one wave, so a wavefront-scope fence replaces a block barrier
+__device__ __forceinline__ void group_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 template <typename VT, int CG>
@@ -431,9 +460,24 @@ __global__ __launch_bounds__(ne_threads(CG)) void k_factor_ne(
       off = wave_excl_scan(len, lane, &T);
       if (lane < m) coff[lane] = off;
       if (lane == 0) coff[m] = T;
-      for (int u = 0; u < len; ++u) {
-        crow[off + u] = tcol[cb + u];
-        cval[off + u] = tval[cb + u];
+      // the column's entries, kNeGather at a time with all of their loads in
+      // flight before the first store (one memory round trip per group
+      // instead of one per entry)
+      for (int u0 = 0; u0 < len; u0 += kNeGather) {
+        int rr[kNeGather];
+        double vv[kNeGather];
+#pragma unroll
+        for (int u = 0; u < kNeGather; ++u) {
+          const int uu = min(u0 + u, len - 1);
+          rr[u] = tcol[cb + uu];
+          vv[u] = tval[cb + uu];
+        }
+#pragma unroll
+        for (int u = 0; u < kNeGather; ++u)
+          if (u0 + u < len) {
+            crow[off + u0 + u] = rr[u];
+            cval[off + u0 + u] = vv[u];
+          }
       }
       const unsigned long long am = __ballot(jc == (int)k);
       if (lane == 0) a_sh = am ? (int)__ffsll((long long)am) - 1 : 0;  // the diagonal is in S
@@ -513,13 +557,13 @@ __global__ __launch_bounds__(ne_threads(CG)) void k_factor_ne(
 #pragma unroll
       for (int c = 0; c < CG; ++c) {
         if (c < m) {
-          const double piv = __shfl(gr[c], gbase + c, 64);
+          const double piv = group_bcast<CG>(gr[c], gbase, c);
           const double d = piv > 0.0 ? sqrt(piv) : 1.0;
           if (i == c && live) bad = bad || !(piv > kNeTol * gd);
           const double lic = i > c ? gr[c] / d : (i == c ? d : 0.0);
           gr[c] = lic;
           if (i >= c) Lc[lix(i, c)] = lic;
-          __syncthreads();
+          group_sync();
 #pragma unroll
           for (int l = c + 1; l < CG; ++l)
             if (l < m) gr[l] = fma(-lic, Lc[lix(l, c)], gr[l]);
@@ -529,7 +573,7 @@ __global__ __launch_bounds__(ne_threads(CG)) void k_factor_ne(
 #pragma unroll
       for (int c = 0; c < CG; ++c) {
         if (c < m) {
-          const double zc = __shfl(y / gr[c], gbase + c, 64);
+          const double zc = group_bcast<CG>(y / gr[c], gbase, c);
           if (i == c) y = zc;
           else if (i > c) y = fma(-gr[c], zc, y);
         }
@@ -537,7 +581,7 @@ __global__ __launch_bounds__(ne_threads(CG)) void k_factor_ne(
 #pragma unroll
       for (int c = CG - 1; c >= 0; --c) {
         if (c < m) {
-          const double qc = __shfl(y / gr[c], gbase + c, 64);
+          const double qc = group_bcast<CG>(y / gr[c], gbase, c);
           if (i == c) y = qc;
           else if (i < c) y = fma(-Lc[lix(c, i)], qc, y);
         }
@@ -547,7 +591,7 @@ __global__ __launch_bounds__(ne_threads(CG)) void k_factor_ne(
         store_val<VT>((VT*)job.valsT + posT, y);
         store_val<VT>((VT*)job.vals + tp2s[lo + i], y);
       }
-      __syncthreads();  // L of this round is read up to here
+      group_sync();  // L of this round is read up to here (each group its own L)
     }
     if (__ballot(bad) != 0ull && (lane & 63) == 0) atomicOr(&bad_sh, 1);
     __syncthreads();

@@ -386,6 +386,52 @@ morx_status build_sell(morx_system sys, const int32_t* rowptr, const int32_t* co
   return MORX_OK;
 }
 
+// The row-block distance d (1..kHaloStrideMax) whose lists share the most
+// columns with row block r's, over a few sample blocks in the middle of the
+// pattern: consecutive row blocks of a grid row share part of their lists,
+// but for a lexicographically ordered 3-D stencil the block one plane further
+// shares more (the halo kernels then walk row blocks a plane apart, and the
+// shared entries are still in the cache when the next row block stages them).
+constexpr int kHaloStrideMax = 512;
+morx_status halo_stride(Sell& sl, int64_t nrb, const int32_t* lists, const std::vector<int32_t>& hc,
+                        hipStream_t st) {
+  sl.hstride = 1;
+  if (nrb < 4 * 8) return MORX_OK;
+  const int64_t dmax = std::min<int64_t>(kHaloStrideMax, nrb / 4);
+  std::vector<int64_t> score(dmax + 1, 0);
+  std::vector<int32_t> buf((size_t)(dmax + 1) * kHaloCap);
+  for (const int64_t r0 : {nrb / 2 - dmax / 2, nrb / 3, (2 * nrb) / 3 - dmax}) {
+    if (r0 < 0 || r0 + dmax >= nrb) continue;
+    MORX_HIP(hipMemcpyAsync(buf.data(), lists + r0 * kHaloCap, buf.size() * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, st));
+    MORX_HIP(hipStreamSynchronize(st));
+    const int32_t* a = buf.data();
+    const int na = hc[r0];
+    for (int64_t d = 1; d <= dmax; ++d) {
+      const int32_t* b = buf.data() + d * kHaloCap;
+      const int nb = hc[r0 + d];
+      int i = 0, j = 0, common = 0;  // both lists ascending
+      while (i < na && j < nb) {
+        if (a[i] == b[j]) {
+          ++common;
+          ++i;
+          ++j;
+        } else if (a[i] < b[j]) {
+          ++i;
+        } else {
+          ++j;
+        }
+      }
+      score[d] += common;
+    }
+  }
+  int64_t best = 1;
+  for (int64_t d = 2; d <= dmax; ++d)
+    if (score[d] > score[best]) best = d;
+  sl.hstride = (int32_t)best;
+  return MORX_OK;
+}
+
 // Halo layout of a pattern whose slices are at most kHaloMaxW slots wide; a
 // pattern with a block of more than kHaloCap distinct columns keeps none
 // (hmax = 0) and the chain step gathers from the vectors instead.
@@ -427,6 +473,7 @@ morx_status build_halo(morx_system sys, Sell& sl, hipStream_t st, std::vector<De
                           hipMemcpyHostToDevice, st));
   k_halo_pack<<<(unsigned)nrb, kHaloThreads, 0, st>>>(sl.hoff, (int32_t*)lists.p, sl.hcol);
   MORX_HIP(hipGetLastError());
+  MORX_TRY(halo_stride(sl, nrb, (const int32_t*)lists.p, hc, st));
   MORX_HIP(hipStreamSynchronize(st));  // hoff's host copy goes out of scope
   sl.hmax = hmax;
   return MORX_OK;

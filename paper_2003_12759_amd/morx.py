@@ -68,7 +68,7 @@ class morx_serve_config(ctypes.Structure):
 class morx_tune(ctypes.Structure):
     _fields_ = [("factor_kernel", ctypes.c_int32), ("cols_per_wave", ctypes.c_int32),
                 ("slices_per_wave", ctypes.c_int32), ("spmv_cols_per_wave", ctypes.c_int32),
-                ("chain_kernel", ctypes.c_int32),
+                ("chain_kernel", ctypes.c_int32), ("halo_stride", ctypes.c_int32),
                 ("factor_ms", ctypes.c_double), ("iter_ms", ctypes.c_double)]
 
 
@@ -264,7 +264,8 @@ def morx_system_info(sys: int):
 def _tune_dict(t: morx_tune) -> dict:
     return {"factor_kernel": t.factor_kernel, "cols_per_wave": t.cols_per_wave,
             "slices_per_wave": t.slices_per_wave, "spmv_cols_per_wave": t.spmv_cols_per_wave,
-            "chain_kernel": t.chain_kernel, "factor_ms": t.factor_ms, "iter_ms": t.iter_ms}
+            "chain_kernel": t.chain_kernel, "halo_stride": t.halo_stride,
+            "factor_ms": t.factor_ms, "iter_ms": t.iter_ms}
 
 
 def morx_system_get_tune(sys: int) -> dict:
@@ -284,7 +285,7 @@ def morx_system_set_tune(sys: int, factor_kernel: int = -1, cols_per_wave: int =
                          slices_per_wave: int = -1, spmv_cols_per_wave: int = -1,
                          chain_kernel: int = -1) -> None:
     t = morx_tune(factor_kernel, cols_per_wave, slices_per_wave, spmv_cols_per_wave,
-                  chain_kernel, 0.0, 0.0)
+                  chain_kernel, 0, 0.0, 0.0)
     _check(_lib.morx_system_set_tune(sys, ctypes.byref(t)), "morx_system_set_tune")
 
 

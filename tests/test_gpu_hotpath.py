@@ -61,10 +61,14 @@ def _rand_wide(n, seed):
 
 
 # 27-point grid of 1331 rows (21 slices: a last block of one partial slice),
-# the 7-point convection-diffusion operator (rows <= 8: the narrow kernels),
-# and a random pattern with rows of ~11 entries
+# a 27-point grid of 32,768 rows, the 7-point convection-diffusion operator
+# (rows <= 8: the narrow kernels), and a random pattern with rows of ~11
+# entries
 CASES = {
     "varcoef27_n1331": lambda: (make_workload(4, N=11).A, make_workload(4, N=11).e),
+    # 32^3: 128 row blocks, a grid plane every 4: the halo kernels walk row
+    # blocks a plane apart
+    "varcoef27_n32768": lambda: (make_workload(4, N=32).A, make_workload(4, N=32).e),
     "convdiff_n1331": lambda: (make_workload(1, N=11).A, make_workload(1, N=11).e),
     "randwide_n1000": lambda: (_rand_wide(1000, 5), np.random.default_rng(6).uniform(1, 2, 1000)),
 }
@@ -222,6 +226,13 @@ def test_chain_kernels_match_oracle_elementwise(ctx, name, kernel, ncol, ncmax):
     """Chains of 1..12 shared factors (forward and transposed at once), FP64
     storage and apply, every tile width, both chain kernels."""
     _say(f"chain {name} kernel={kernel} ncol={ncol} ncmax={ncmax}")
+    if name == "varcoef27_n32768" and kernel == 1:
+        from paper_2003_12759_amd import api
+
+        A, e = CASES[name]()
+        S = api.System(ctx, A, e)
+        assert S.get_tune()["halo_stride"] == 4  # a 32 x 32 plane is 4 row blocks
+        S.close()
     if _chain_case(ctx, name, "f64", "f64", kernel, ncol, ncmax, True) is None:
         pytest.skip(f"{name} has no halo layout")
 
