@@ -21,38 +21,85 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// partial[b] = U[rows_b]^T diag(w[rows_b]) V[rows_b], column-major r1 x r2
-__global__ __launch_bounds__(1024) void k_gram_mfma(const double* __restrict__ U, int64_t ldu,
-                                                    int r1, const double* __restrict__ V,
-                                                    int64_t ldv, int r2,
-                                                    const double* __restrict__ w, int64_t n,
-                                                    int64_t rows_per_block,
-                                                    double* __restrict__ partial) {
+// partial[b] = U[rows_b]^T diag(w[rows_b]) V~[rows_b], column-major r1 x r2,
+// where V~ is V, or with SPARSE the product A V formed row by row on the fly
+// (A's rows on the CSR of S; the product is never stored).  One block of four
+// waves per slab of rows: kGR rows of U and V~ at a time are staged in LDS
+// (U's columns read with consecutive rows per lane, V~'s rows summed from
+// A's entries), then every wave runs the 16 x 16 x 4 FP64 MFMA steps of its
+// output tiles from LDS.
+constexpr int kGR = 32;        // rows staged per step
+constexpr int kGLd = 64 + 2;   // LDS row stride (doubles)
+constexpr int kGThreads = 256;
+
+template <bool SPARSE>
+__global__ __launch_bounds__(kGThreads) void k_gram_mfma(
+    const double* __restrict__ U, int64_t ldu, int r1, const double* __restrict__ V, int64_t ldv,
+    int r2, const double* __restrict__ w, int64_t n, int64_t rows_per_block,
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+    const double* __restrict__ val, double* __restrict__ partial) {
+  __shared__ double su[kGR * kGLd];
+  __shared__ double sv[kGR * kGLd];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int t2n = (r2 + 15) >> 4;
-  const int ti = wave / t2n, tj = wave % t2n;
-  const int i = ti * 16 + (lane & 15), j = tj * 16 + (lane & 15), kk = lane >> 4;
-  const bool iv = i < r1, jv = j < r2;
-  const double* up = U + (int64_t)min(i, r1 - 1) * ldu;
-  const double* vp = V + (int64_t)min(j, r2 - 1) * ldv;
+  const int t1n = (r1 + 15) >> 4, t2n = (r2 + 15) >> 4, ntile = t1n * t2n;
+  const int kk = lane >> 4, li = lane & 15;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t rend = min(n, r0 + rows_per_block);
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
-  // uniform trip count: every lane issues every MFMA
-  for (int64_t base = r0; base < r0 + rows_per_block; base += 4) {
-    const int64_t row = base + kk;
-    const bool in = row < rend;
-    double a = (in && iv) ? up[row] : 0.0;
-    if (w && in) a *= w[row];
-    const double b = (in && jv) ? vp[row] : 0.0;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  v4d acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int64_t base = r0; base < rend; base += kGR) {
+    // stage rows base .. base + kGR - 1 (zeros past the slab and past r)
+    for (int idx = threadIdx.x; idx < kGR * 64; idx += kGThreads) {
+      const int c = idx / kGR, rr = idx % kGR;
+      const int64_t row = base + rr;
+      const bool in = row < rend;
+      double a = 0.0, b = 0.0;
+      if (in && c < r1) {
+        a = U[(int64_t)c * ldu + row];
+        if (w) a *= w[row];
+      }
+      if (in && c < r2) {
+        if constexpr (SPARSE) {
+          const double* vc = V + (int64_t)c * ldv;
+          double s = 0.0;
+          for (int32_t p = rowptr[row]; p < rowptr[row + 1]; ++p) s = fma(val[p], vc[colind[p]], s);
+          b = s;
+        } else {
+          b = V[(int64_t)c * ldv + row];
+        }
+      }
+      su[rr * kGLd + c] = a;
+      sv[rr * kGLd + c] = b;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int tile = wave + 4 * q;
+      if (tile < ntile) {  // uniform over the wave
+        const int ti = tile / t2n, tj = tile % t2n;
+#pragma unroll
+        for (int k = 0; k < kGR; k += 4) {
+          const double a = su[(k + kk) * kGLd + ti * 16 + li];
+          const double b = sv[(k + kk) * kGLd + tj * 16 + li];
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
   }
   // output block: element t of lane l holds D[(l >> 4) + 4t][l & 15]
   double* out = partial + (int64_t)blockIdx.x * r1 * r2;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int ii = ti * 16 + (lane >> 4) + 4 * t, jj = tj * 16 + (lane & 15);
-    if (ii < r1 && jj < r2) out[ii + (int64_t)jj * r1] = acc[t];
+  for (int q = 0; q < 4; ++q) {
+    const int tile = wave + 4 * q;
+    if (tile >= ntile) continue;
+    const int ti = tile / t2n, tj = tile % t2n;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int ii = ti * 16 + kk + 4 * t, jj = tj * 16 + li;
+      if (ii < r1 && jj < r2) out[ii + (int64_t)jj * r1] = acc[q][t];
+    }
   }
 }
 
@@ -146,37 +193,98 @@ __global__ void k_copy_cols(const double* __restrict__ src, int64_t lds, double*
   if (i < n && c < r) dst[(int64_t)c * ldd + i] = src[(int64_t)c * lds + i];
 }
 
+// Partial sums of one n-long contraction: at most kGramBlocks slabs of rows
+// (a multiple of kGR rows each), one partial r1 x r2 block per slab.
+constexpr int kGramBlocks = 256;
+
 struct Gram {
   morx_system sys;
-  DevBuf partial;
+  double* partial = nullptr;  // [nb][64 * 64]
   int64_t rows_per_block = 0;
   int nb = 0;
 };
 
-morx_status gram(Gram& g, const double* U, int64_t ldu, int r1, const double* V, int64_t ldv,
-                 int r2, const double* w, double* out_dev, double scale, hipStream_t st) {
+Gram gram_shape(morx_system sys, double* partial) {
+  Gram g;
+  g.sys = sys;
+  g.partial = partial;
+  const int64_t n = sys->n;
+  const int64_t target = std::min<int64_t>(kGramBlocks, std::max(1, 2 * sys->ctx->num_cu));
+  const int64_t per = (n + target - 1) / target;
+  g.rows_per_block = std::max<int64_t>(kGR, (per + kGR - 1) / kGR * kGR);
+  g.nb = (int)std::max<int64_t>(1, (n + g.rows_per_block - 1) / g.rows_per_block);
+  return g;
+}
+
+// out_dev = scale * U^T diag(w) V~ (V~ = V, or A V when sparse)
+morx_status gram(const Gram& g, const double* U, int64_t ldu, int r1, const double* V,
+                 int64_t ldv, int r2, const double* w, bool sparse, double* out_dev,
+                 double scale, hipStream_t st) {
   const int64_t n = g.sys->n;
-  const int waves = ((r1 + 15) / 16) * ((r2 + 15) / 16);
-  k_gram_mfma<<<g.nb, 64 * waves, 0, st>>>(U, ldu, r1, V, ldv, r2, w, n, g.rows_per_block,
-                                          (double*)g.partial.p);
+  morx_system sys = g.sys;
+  if (sparse)
+    k_gram_mfma<true><<<g.nb, kGThreads, 0, st>>>(U, ldu, r1, V, ldv, r2, w, n, g.rows_per_block,
+                                                   sys->rowptr, sys->colind, sys->valA, g.partial);
+  else
+    k_gram_mfma<false><<<g.nb, kGThreads, 0, st>>>(U, ldu, r1, V, ldv, r2, w, n,
+                                                    g.rows_per_block, nullptr, nullptr, nullptr,
+                                                    g.partial);
   const int cnt = r1 * r2;
-  k_sum_partials<<<(cnt + 3) / 4, 256, 0, st>>>((double*)g.partial.p, g.nb, cnt, out_dev, scale);
+  k_sum_partials<<<(cnt + 3) / 4, 256, 0, st>>>(g.partial, g.nb, cnt, out_dev, scale);
   MORX_HIP(hipGetLastError());
   return MORX_OK;
 }
 
 // shifted Cholesky-QR, then two Cholesky-QR passes, in place on X (n x r, ld)
-morx_status orth_scqr3(Gram& g, double* X, int64_t ld, int r, double* G, double* R, int* status,
-                       hipStream_t st) {
+morx_status orth_scqr3(const Gram& g, double* X, int64_t ld, int r, double* G, double* R,
+                       int* status, hipStream_t st) {
   const int64_t n = g.sys->n;
   const double u = 1.1102230246251565e-16;
   const double coef = 11.0 * ((double)n * r + (double)r * (r + 1)) * u;
   for (int pass = 0; pass < 3; ++pass) {
-    MORX_TRY(gram(g, X, ld, r, X, ld, r, nullptr, G, 1.0, st));
+    MORX_TRY(gram(g, X, ld, r, X, ld, r, nullptr, false, G, 1.0, st));
     k_chol<<<1, 256, 0, st>>>(G, r, pass == 0 ? coef : 0.0, R, status);
     k_trsm_rows<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(X, ld, n, r, R);
     MORX_HIP(hipGetLastError());
   }
+  return MORX_OK;
+}
+
+// the four products of the reduced model into res = [Ar | Er | Br | Cr]
+// (4096 doubles each, column-major with ld r)
+morx_status project_products(const Gram& g, int r, const double* Vd, int64_t ldv,
+                             const double* Wd, int64_t ldw, int m, const double* B, int64_t ldb,
+                             int q, const double* C, int64_t ldc, double* res, hipStream_t st) {
+  MORX_TRY(gram(g, Wd, ldw, r, Vd, ldv, r, nullptr, true, res, 1.0, st));             // W^T A V
+  MORX_TRY(gram(g, Wd, ldw, r, Vd, ldv, r, g.sys->e, false, res + 4096, 1.0, st));     // W^T E V
+  if (m > 0) MORX_TRY(gram(g, Wd, ldw, r, B, ldb, m, nullptr, false, res + 8192, 1.0, st));
+  if (q > 0) MORX_TRY(gram(g, Vd, ldv, r, C, ldc, q, nullptr, false, res + 12288, 1.0, st));
+  return MORX_OK;
+}
+
+morx_status check_project_args(morx_system sys, int32_t r, const double* V, int64_t ldv,
+                               const double* W, int64_t ldw, int32_t m, const double* B,
+                               int64_t ldb, int32_t q, const double* C, int64_t ldc, double* Ar,
+                               double* Er, double* Br, double* Cr, const char* who) {
+  MORX_REQUIRE(sys, MORX_E_INVALID, "%s: null system", who);
+  MORX_REQUIRE(r >= 1 && r <= 64 && m >= 0 && m <= 64 && q >= 0 && q <= 64, MORX_E_INVALID,
+               "%s: r, m, q must be in [1, 64], [0, 64], [0, 64]", who);
+  MORX_REQUIRE(V && W && ldv >= sys->n && ldw >= sys->n && Ar && Er, MORX_E_INVALID,
+               "%s: bad V, W or outputs", who);
+  MORX_REQUIRE(m == 0 || (B && Br && ldb >= sys->n), MORX_E_INVALID, "%s: bad B", who);
+  MORX_REQUIRE(q == 0 || (C && Cr && ldc >= sys->n), MORX_E_INVALID, "%s: bad C", who);
+  return MORX_OK;
+}
+
+// the device results (ld r) into the caller's host arrays
+morx_status copy_results(const double* res, int r, int m, int q, double* Ar, double* Er,
+                         double* Br, double* Cr, hipStream_t st) {
+  MORX_HIP(hipMemcpyAsync(Ar, res, (size_t)r * r * sizeof(double), hipMemcpyDeviceToHost, st));
+  MORX_HIP(hipMemcpyAsync(Er, res + 4096, (size_t)r * r * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (m > 0)
+    MORX_HIP(hipMemcpyAsync(Br, res + 8192, (size_t)r * m * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (q > 0)
+    MORX_HIP(hipMemcpyAsync(Cr, res + 12288, (size_t)r * q * sizeof(double), hipMemcpyDeviceToHost, st));
   return MORX_OK;
 }
 
@@ -187,13 +295,8 @@ extern "C" morx_status morx_project(morx_system sys, int32_t r, const double* V,
                                     int64_t ldb, int32_t q, const double* C, int64_t ldc,
                                     double* Ar, double* Er, double* Br, double* Cr,
                                     int32_t orthonormalize, void* stream) {
-  MORX_REQUIRE(sys, MORX_E_INVALID, "morx_project: null system");
-  MORX_REQUIRE(r >= 1 && r <= 64 && m >= 0 && m <= 64 && q >= 0 && q <= 64, MORX_E_INVALID,
-               "morx_project: r, m, q must be in [1, 64], [0, 64], [0, 64]");
-  MORX_REQUIRE(V && W && ldv >= sys->n && ldw >= sys->n && Ar && Er, MORX_E_INVALID,
-               "morx_project: bad V, W or outputs");
-  MORX_REQUIRE(m == 0 || (B && Br && ldb >= sys->n), MORX_E_INVALID, "morx_project: bad B");
-  MORX_REQUIRE(q == 0 || (C && Cr && ldc >= sys->n), MORX_E_INVALID, "morx_project: bad C");
+  MORX_TRY(check_project_args(sys, r, V, ldv, W, ldw, m, B, ldb, q, C, ldc, Ar, Er, Br, Cr,
+                              "morx_project"));
   morx_ctx ctx = sys->ctx;
   std::lock_guard<std::mutex> lk(ctx->mu);
   MORX_HIP(hipSetDevice(ctx->device));
@@ -201,45 +304,37 @@ extern "C" morx_status morx_project(morx_system sys, int32_t r, const double* V,
   MORX_TRY(stream_enter(ctx, caller));
   hipStream_t st = ctx->stream;
   const int64_t n = sys->n, ld = sys->n_pad;
-  Gram g;
-  g.sys = sys;
-  const int64_t target_blocks = std::max(1, 2 * ctx->num_cu);
-  g.rows_per_block = std::max<int64_t>(256, ((n + target_blocks - 1) / target_blocks + 3) / 4 * 4);
-  g.nb = (int)((n + g.rows_per_block - 1) / g.rows_per_block);
-  DevBuf vv, ww, tt, small, stat;
-  morx_status s = dev_alloc(g.partial, (size_t)g.nb * 64 * 64 * sizeof(double));
-  if (s == MORX_OK) s = dev_alloc(vv, (size_t)ld * r * sizeof(double));
-  if (s == MORX_OK) s = dev_alloc(ww, (size_t)ld * r * sizeof(double));
-  if (s == MORX_OK) s = dev_alloc(tt, (size_t)ld * r * sizeof(double));
-  if (s == MORX_OK) s = dev_alloc(small, (size_t)8 * 64 * 64 * sizeof(double));
+  DevBuf part, vv, ww, small, stat;
+  morx_status s = dev_alloc(part, (size_t)kGramBlocks * 64 * 64 * sizeof(double));
+  const Gram g = gram_shape(sys, (double*)part.p);
+  if (s == MORX_OK && orthonormalize) s = dev_alloc(vv, (size_t)ld * r * sizeof(double));
+  if (s == MORX_OK && orthonormalize) s = dev_alloc(ww, (size_t)ld * r * sizeof(double));
+  if (s == MORX_OK) s = dev_alloc(small, (size_t)6 * 4096 * sizeof(double));
   if (s == MORX_OK) s = dev_alloc(stat, sizeof(int));
-  std::vector<double> h(4 * 64 * 64);
   int status = 0;
   if (s == MORX_OK) {
-    double* Vd = (double*)vv.p;
-    double* Wd = (double*)ww.p;
-    double* T = (double*)tt.p;
     double* S = (double*)small.p;
-    double *G = S, *R = S + 4096, *oA = S + 2 * 4096, *oE = S + 3 * 4096, *oB = S + 4 * 4096,
-           *oC = S + 5 * 4096;
+    double *res = S, *G = S + 4 * 4096, *R = S + 5 * 4096;
+    const double* Vd = V;
+    const double* Wd = W;
+    int64_t ldvd = ldv, ldwd = ldw;
     hipError_t e = hipMemsetAsync(stat.p, 0, sizeof(int), st);
-    dim3 cg((unsigned)((n + 255) / 256), r);
-    k_copy_cols<<<cg, 256, 0, st>>>(V, ldv, Vd, ld, n, r);
-    k_copy_cols<<<cg, 256, 0, st>>>(W, ldw, Wd, ld, n, r);
     if (e != hipSuccess) s = MORX_E_HIP;
     if (s == MORX_OK && orthonormalize) {
-      s = orth_scqr3(g, Vd, ld, r, G, R, (int*)stat.p, st);
-      if (s == MORX_OK) s = orth_scqr3(g, Wd, ld, r, G, R, (int*)stat.p, st);
+      // orthonormal bases of the columns of V and W, in copies
+      dim3 cg((unsigned)((n + 255) / 256), r);
+      k_copy_cols<<<cg, 256, 0, st>>>(V, ldv, (double*)vv.p, ld, n, r);
+      k_copy_cols<<<cg, 256, 0, st>>>(W, ldw, (double*)ww.p, ld, n, r);
+      s = orth_scqr3(g, (double*)vv.p, ld, r, G, R, (int*)stat.p, st);
+      if (s == MORX_OK) s = orth_scqr3(g, (double*)ww.p, ld, r, G, R, (int*)stat.p, st);
+      Vd = (const double*)vv.p;
+      Wd = (const double*)ww.p;
+      ldvd = ldwd = ld;
     }
-    // T = (0 E - A) V = -A V, so Ar = -W^T T
-    if (s == MORX_OK) s = launch_shifted_apply(sys, 0.0, false, r, Vd, ld, T, ld, st);
-    if (s == MORX_OK) s = gram(g, Wd, ld, r, T, ld, r, nullptr, oA, -1.0, st);
-    if (s == MORX_OK) s = gram(g, Wd, ld, r, Vd, ld, r, sys->e, oE, 1.0, st);
-    if (s == MORX_OK && m > 0) s = gram(g, Wd, ld, r, B, ldb, m, nullptr, oB, 1.0, st);
-    if (s == MORX_OK && q > 0) s = gram(g, Vd, ld, r, C, ldc, q, nullptr, oC, 1.0, st);
+    if (s == MORX_OK) s = project_products(g, r, Vd, ldvd, Wd, ldwd, m, B, ldb, q, C, ldc, res, st);
+    if (s == MORX_OK) s = copy_results(res, r, m, q, Ar, Er, Br, Cr, st);
     if (s == MORX_OK) {
-      e = hipMemcpyAsync(h.data(), oA, 4 * 4096 * sizeof(double), hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess) e = hipMemcpyAsync(&status, stat.p, sizeof(int), hipMemcpyDeviceToHost, st);
+      e = hipMemcpyAsync(&status, stat.p, sizeof(int), hipMemcpyDeviceToHost, st);
       if (e == hipSuccess) e = hipStreamSynchronize(st);
       if (e != hipSuccess) {
         morx_set_error("morx_project: %s", hipGetErrorString(e));
@@ -248,18 +343,13 @@ extern "C" morx_status morx_project(morx_system sys, int32_t r, const double* V,
     }
   }
   hipStreamSynchronize(st);
-  dev_free(g.partial);
+  dev_free(part);
   dev_free(vv);
   dev_free(ww);
-  dev_free(tt);
   dev_free(small);
   dev_free(stat);
   if (s != MORX_OK) return s;
   MORX_REQUIRE(status == 0, MORX_E_SINGULAR_LS,
                "morx_project: Cholesky-QR failed (V or W numerically rank deficient)");
-  std::copy(h.begin(), h.begin() + r * r, Ar);
-  std::copy(h.begin() + 4096, h.begin() + 4096 + r * r, Er);
-  if (m > 0) std::copy(h.begin() + 2 * 4096, h.begin() + 2 * 4096 + r * m, Br);
-  if (q > 0) std::copy(h.begin() + 3 * 4096, h.begin() + 3 * 4096 + r * q, Cr);
   return stream_leave(ctx, caller);
 }
