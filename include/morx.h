@@ -324,6 +324,25 @@ morx_status morx_project(morx_system sys, int32_t r, const double* V, int64_t ld
                          double* Br, double* Cr, int32_t orthonormalize, void* stream);
 
 /*
+ * morx_project with orthonormalize = 0 (V and W used as given), for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  It calls no hipMalloc
+ * or hipFree; its partial sums and results live in a fixed device scratch of
+ * 8.1 MiB that every GPU the library runs on holds from morx_create until the
+ * process ends (up to 256 row slabs of 64 x 64 partials, then the four
+ * results).  Work is queued on `stream` and the call returns once the host
+ * outputs are written.  Limits as morx_project (r <= 64, m, q <= 64;
+ * MORX_E_INVALID beyond them).  Calls that overlap on one GPU (other
+ * threads, other contexts on the device) share the scratch and race: one
+ * call at a time per GPU.  Results equal morx_project's with
+ * orthonormalize = 0.
+ */
+morx_status morx_project_noalloc(morx_system sys, int32_t r, const double* V, int64_t ldv,
+                                 const double* W, int64_t ldw, int32_t m, const double* B,
+                                 int64_t ldb, int32_t q, const double* C, int64_t ldc,
+                                 double* Ar, double* Er, double* Br, double* Cr, void* stream);
+
+/*
  * Eigenvalues of the pencil (Ar, Er) (host, column-major r x r, r <= 64):
  * Er^{-1} Ar by LU with partial pivoting, Householder reduction to upper
  * Hessenberg form and double-shift QR steps.  wr, wi (host, r entries)

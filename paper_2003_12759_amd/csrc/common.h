@@ -106,6 +106,7 @@ struct morx_ctx_s {
   hipStream_t stream2 = nullptr;  // factor construction overlapped with solves
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_aux = nullptr;
   int num_cu = 0;
+  double* proj_scratch = nullptr;  // this device's allocation-free projection scratch
   std::mutex mu;
 };
 
@@ -200,6 +201,9 @@ morx_status launch_shifted_apply(morx_system sys, double sigma, bool trans, int 
 morx_status launch_factor_apply(morx_system sys, morx_factor f, bool trans, int ncol,
                                 const double* X, int64_t ldx, double* Y, int64_t ldy,
                                 hipStream_t st);
+
+// project.hip
+morx_status project_scratch_init(morx_ctx ctx);
 
 // bicg.hip
 void krylov_batch_delete(KrylovBatch* kb);

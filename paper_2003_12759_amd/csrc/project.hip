@@ -288,7 +288,25 @@ morx_status copy_results(const double* res, int r, int m, int q, double* Ar, dou
   return MORX_OK;
 }
 
+// Scratch of the allocation-free projection: the slab partials of one
+// contraction at a time, then the four results.  Every GPU the library runs
+// on holds its own copy until the process ends.
+constexpr size_t kScratchPartial = (size_t)kGramBlocks * 64 * 64;  // doubles
+constexpr size_t kScratchResults = 4 * 4096;                        // doubles
+__device__ __align__(256) double scratch[kScratchPartial + kScratchResults];
+
 }  // namespace
+
+// Called by morx_create with the context's device current: the device
+// address of this GPU's scratch (host code never passes the array's name).
+morx_status project_scratch_init(morx_ctx ctx) {
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  MORX_REQUIRE(e == hipSuccess && ptr, MORX_E_HIP, "projection scratch address: %s",
+               hipGetErrorString(e));
+  ctx->proj_scratch = (double*)ptr;
+  return MORX_OK;
+}
 
 extern "C" morx_status morx_project(morx_system sys, int32_t r, const double* V, int64_t ldv,
                                     const double* W, int64_t ldw, int32_t m, const double* B,
@@ -352,4 +370,27 @@ extern "C" morx_status morx_project(morx_system sys, int32_t r, const double* V,
   MORX_REQUIRE(status == 0, MORX_E_SINGULAR_LS,
                "morx_project: Cholesky-QR failed (V or W numerically rank deficient)");
   return stream_leave(ctx, caller);
+}
+
+extern "C" morx_status morx_project_noalloc(morx_system sys, int32_t r, const double* V,
+                                            int64_t ldv, const double* W, int64_t ldw, int32_t m,
+                                            const double* B, int64_t ldb, int32_t q,
+                                            const double* C, int64_t ldc, double* Ar, double* Er,
+                                            double* Br, double* Cr, void* stream) {
+  MORX_TRY(check_project_args(sys, r, V, ldv, W, ldw, m, B, ldb, q, C, ldc, Ar, Er, Br, Cr,
+                              "morx_project_noalloc"));
+  morx_ctx ctx = sys->ctx;
+  MORX_REQUIRE(ctx->proj_scratch, MORX_E_HIP, "morx_project_noalloc: no scratch on device %d",
+               ctx->device);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  MORX_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const Gram g = gram_shape(sys, ctx->proj_scratch);
+  MORX_REQUIRE(g.nb <= kGramBlocks, MORX_E_INVALID,
+               "morx_project_noalloc: %d row slabs exceed the scratch's %d", g.nb, kGramBlocks);
+  double* res = ctx->proj_scratch + kScratchPartial;
+  MORX_TRY(project_products(g, r, V, ldv, W, ldw, m, B, ldb, q, C, ldc, res, st));
+  MORX_TRY(copy_results(res, r, m, q, Ar, Er, Br, Cr, st));
+  MORX_HIP(hipStreamSynchronize(st));
+  return MORX_OK;
 }

@@ -106,6 +106,11 @@ extern "C" morx_status morx_create(morx_ctx* out, int device) {
     morx_destroy(ctx);
     return MORX_E_HIP;
   }
+  const morx_status s = project_scratch_init(ctx);  // with the device current
+  if (s != MORX_OK) {
+    morx_destroy(ctx);
+    return s;
+  }
   *out = ctx;
   return MORX_OK;
 }

@@ -130,6 +130,9 @@ _SIG = {
     "morx_project": (_i32, [_p, _i32, _p, _i64, _p, _i64, _i32, _p, _i64, _i32, _p, _i64,
                             ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
                             ctypes.POINTER(_d), _i32, _p]),
+    "morx_project_noalloc": (_i32, [_p, _i32, _p, _i64, _p, _i64, _i32, _p, _i64, _i32, _p, _i64,
+                                    ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
+                                    ctypes.POINTER(_d), _p]),
     "morx_pencil_eigvals": (_i32, [_i32, ctypes.POINTER(_d), ctypes.POINTER(_d),
                                    ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "morx_irka": (_i32, [_p, _i32, ctypes.POINTER(_d), _p, _p, _i32, _d, ctypes.POINTER(morx_opts),
@@ -525,6 +528,31 @@ def morx_project(sys: int, V: torch.Tensor, W: torch.Tensor, B: Optional[torch.T
     Cr = (_d * max(r * q, 1))()
     _check(_lib.morx_project(sys, r, pv, ldv, pw, ldw, m, pb, ldb, q, pc, ldc, Ar, Er, Br, Cr,
                              int(bool(orthonormalize)), _stream(stream)), "morx_project")
+
+    def mat(buf, rows, cols):
+        return np.frombuffer(buf, dtype=np.float64, count=rows * cols).reshape(cols, rows).T.copy()
+
+    return mat(Ar, r, r), mat(Er, r, r), mat(Br, r, m), mat(Cr, r, q)
+
+
+def morx_project_noalloc(sys: int, V: torch.Tensor, W: torch.Tensor, B: Optional[torch.Tensor],
+                         C: Optional[torch.Tensor], stream=None):
+    """morx_project of V and W as given, through the allocation-free entry
+    point; returns numpy (Ar, Er, Br, Cr)."""
+    import numpy as np
+
+    pv, ldv, r = _block(V, "V")
+    pw, ldw, r2 = _block(W, "W")
+    if r != r2:
+        raise ValueError("V and W column counts differ")
+    pb, ldb, m = _block(B, "B") if B is not None else (None, V.shape[0], 0)
+    pc, ldc, q = _block(C, "C") if C is not None else (None, V.shape[0], 0)
+    Ar = (_d * (r * r))()
+    Er = (_d * (r * r))()
+    Br = (_d * max(r * m, 1))()
+    Cr = (_d * max(r * q, 1))()
+    _check(_lib.morx_project_noalloc(sys, r, pv, ldv, pw, ldw, m, pb, ldb, q, pc, ldc, Ar, Er, Br,
+                                     Cr, _stream(stream)), "morx_project_noalloc")
 
     def mat(buf, rows, cols):
         return np.frombuffer(buf, dtype=np.float64, count=rows * cols).reshape(cols, rows).T.copy()
