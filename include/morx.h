@@ -447,7 +447,7 @@ morx_status morx_system_get_tune(morx_system sys, morx_tune* out);
  * launches now (for every chain step but the last of an iteration, whose
  * instance also forms the rho partial sums), with factors stored at prec and
  * applied at apply_prec, written as its demangled name, e.g.
- * "k_chain_halo<double, double, 12, false, 32, 2048>" (host buf, cap bytes,
+ * "k_chain_halo<double, double, 12, 0, 32, 2048>" (host buf, cap bytes,
  * NUL-terminated; MORX_E_INVALID if it does not fit).
  */
 morx_status morx_chain_kernel_name(morx_system sys, int32_t ncol, int32_t prec,

@@ -236,8 +236,8 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(IterArgs a) {
       a.trace[TR_CHAIN] += 2.0 * a.maxL * mat + 2.0 * 2.0 * ab * n * chain_cols + 8.0 * n * act_cols;
     }
     if (vec_cols > 0.0) {
-      // per column: z, z~ read; p, p~ read (not on a cycle's first step) and
-      // written; q, q~ written
+      // both operator passes (values, 4-byte indices, row offsets), e read;
+      // per column p, p~ read and q, q~ written
       const double amat = 2.0 * (12.0 * nnz + 4.0 * (n + 1.0)) + 8.0 * n;
       a.trace[TR_SPMV] += amat + 32.0 * n * vec_cols;
       // form_p: z, z~ read; p, p~ of the last step read (not on a cycle's
@@ -1606,7 +1606,7 @@ extern "C" morx_status morx_chain_kernel_name(morx_system sys, int32_t ncol, int
   const bool narrow = pattern_narrow(sys);
   char tmp[128];
   if (halo_in_use(sys))
-    snprintf(tmp, sizeof(tmp), "k_chain_halo<%s, %s, %d, false, %d, %d>", vt, at, nc,
+    snprintf(tmp, sizeof(tmp), "k_chain_halo<%s, %s, %d, %d, %d, %d>", vt, at, nc, (int)kHaloChain,
              narrow ? kNarrow : kHaloMaxW, narrow ? kHaloCapNarrow : kHaloCap);
   else
     snprintf(tmp, sizeof(tmp), "%s<%s, %s, %d, false>", narrow ? "k_chain_narrow" : "k_chain_step",
