@@ -384,6 +384,49 @@ def serving_bench(args):
     ctx.close()
 
 
+def projection_bench(args, w):
+    """The Petrov-Galerkin projection alone at the workload's n: r seeded
+    random basis columns for V and W, the workload's B and C.  Times
+    morx_project with and without orthonormalisation (HIP events around the
+    calls, on the library's stream) and prints one JSON line."""
+    import torch
+
+    from paper_2003_12759_amd import api, morx
+
+    r = args.projection
+    ctx = api.Context(0)
+    S = api.System(ctx, w.A, w.e)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    V = torch.randn(r, w.A.shape[0], generator=g, device="cuda", dtype=torch.float64).t()
+    W = torch.randn(r, w.A.shape[0], generator=g, device="cuda", dtype=torch.float64).t()
+    Bd, Cd = api.block_to_dev(w.B), api.block_to_dev(w.C)
+    out = {}
+    for orth in (True, False):
+        for _ in range(2):
+            S.project(V, W, Bd, Cd, orthonormalize=orth)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            S.project(V, W, Bd, Cd, orthonormalize=orth)
+        torch.cuda.synchronize()
+        out["orth" if orth else "plain"] = 1e3 * (time.perf_counter() - t0) / args.steps
+    n, nnz = w.A.shape[0], w.A.nnz
+    # W^T A V (A V formed on the fly), W^T E V, W^T B, C^T V: every operand read once
+    byts = 8.0 * n * (2 * r + w.B.shape[1] + w.C.shape[1] + 1) + 12.0 * nnz + 4.0 * (n + 1)
+    flops = 2.0 * n * r * r * 2 + 2.0 * nnz * r
+    line = {"metric": "projection ms per call", "value": round(out["plain"], 3), "unit": "ms",
+            "n_gpus": 1, "steps": args.steps, "warmup": 2, "higher_is_better": False,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": w.name, "n": n, "r": r, "m": int(w.B.shape[1]),
+                       "q": int(w.C.shape[1])},
+            "orthonormalize_ms": round(out["orth"], 3),
+            "alg_bytes": byts, "GBps": round(byts / (out["plain"] * 1e-3) / 1e9, 1),
+            "TFLOPs": round(flops / (out["plain"] * 1e-3) / 1e12, 3)}
+    print(json.dumps(line), flush=True)
+    S.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -423,6 +466,8 @@ def main():
                     help="also run the IRKA-style shift loop for at most this many rounds")
     ap.add_argument("--irka-tol", type=float, default=1e-4,
                     help="relative change of the shifts that ends the IRKA loop")
+    ap.add_argument("--projection", type=int, default=0,
+                    help="time only the projection, with this many basis columns")
     ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=16, help="serving: slots per system")
     ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 1.0],
@@ -444,6 +489,9 @@ def main():
     index = {"laplace2d_n2025": 0, "convdiff3d_n262144": 1, "varcoef3d_n1191016_mimo4": 2,
              "varcoef27_n2097152": 4}[args.workload]
     w = make_workload(index, prec=args.prec or ("f64" if index == 4 else None))
+    if args.projection:
+        projection_bench(args, w)
+        return
     apply = args.apply or default_apply(w.prec)
     nsolves = sum(len(r) for r in w.rounds) * w.B.shape[1]
     # the CPU oracle's sample runs first: its process pool forks, which is

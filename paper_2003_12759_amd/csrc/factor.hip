@@ -333,10 +333,14 @@ __global__ void k_factor_to_csr(const VT* __restrict__ vals, const int32_t* __re
 // Ajj(a, :)^T; an update column solves G(sn) q = M(sn)^T M(sp) e_a (its
 // right-hand side is column k of sp E - A).  Neither I_k nor the dense
 // |I_k| x m matrix is formed: one wave gathers the m columns of A, forms G0
-// (sorted merges of column pairs) and Ajj, and then groups of CG lanes, lane i
-// holding row i, each take one shift: Cholesky
-// factorisation and the two triangular solves in registers, the columns of
-// L exchanged through LDS.  The normal equations square the condition
+// (sorted merges of column pairs) and Ajj, then H = E_J Ajj + Ajj^T E_J in
+// Ajj's place (G(s) = G0 - s H + s^2 E_J^2, both symmetric), and then groups
+// of CG lanes, lane i holding row i, each take one shift: Cholesky
+// factorisation and the two triangular solves in registers, each column of L
+// passed to the group's lanes through LDS.  Lane i skips its own update at
+// step i, so its entries past i keep L(i, i) times column i of L, which the
+// solve with L^T then reads from the lane's registers.  The normal equations
+// square the condition
 // number, so a column with a pivot below kNeTol times the diagonal entry it
 // started from is listed for the Householder kernel, which rebuilds every
 // shift of that column (and reports a rank-deficient problem as the other
@@ -345,20 +349,19 @@ constexpr double kNeTol = 1e-6;
 constexpr int kNeGather = 16;  // entries of a column loaded together in the set-up
 
 struct NeLayout {
-  int T;
+  int T, G;  // gathered entries, lane groups per block
   size_t off_J, off_off, off_E, off_H, off_G0, off_crow, off_cval, off_L, bytes;
 };
 
-// threads of a normal-equations block, whose lane groups solve as many shifts
-// of one column problem at a time: two waves for groups of 32 lanes (the LDS
-// copy of the column's matrices is then shared by four shifts), one wave for
-// narrower groups (their patterns already fit eight or four shifts per wave)
-constexpr int ne_threads(int CG) { return CG >= 32 ? 128 : 64; }
+// A normal-equations block has nw waves (one to four), whose 64 nw / CG lane
+// groups solve as many shifts of one column problem at a time and share the
+// LDS copy of its matrices; the launch picks nw for the number of shifts.
+constexpr int kNeMaxWaves = 4;
 
-NeLayout ne_layout(int maxT, int CG) {
+NeLayout ne_layout(int maxT, int CG, int nw) {
   NeLayout L;
   L.T = std::max(maxT, 1);
-  const int G = ne_threads(CG) / CG;
+  L.G = nw * 64 / CG;
   const size_t mat = (size_t)CG * (CG + 1) * 8;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -371,16 +374,13 @@ NeLayout ne_layout(int maxT, int CG) {
   L.off_E = take((size_t)CG * 8);
   L.off_H = take(mat);
   L.off_G0 = take(mat);
-  // the gathered columns, later in the same space the L factors of the G
-  // shifts in flight
+  // the gathered columns, later in the same space one column of L per group
   const size_t base = o;
   L.off_crow = base;
   L.off_cval = base + ((size_t)L.T * 4 + 15) / 16 * 16;
   L.off_L = base;
   const size_t gather = L.off_cval - base + (size_t)L.T * 8;
-  // the Cholesky factors: lower triangles, packed by columns
-  const size_t tri = (size_t)CG * (CG + 1) / 2 * 8;
-  o += std::max(gather, (size_t)G * tri);
+  o += std::max(gather, (size_t)L.G * CG * 8);
   L.bytes = o;
   return L;
 }
@@ -414,33 +414,29 @@ __device__ __forceinline__ void group_sync() {
 }
 
 template <typename VT, int CG>
-__global__ __launch_bounds__(ne_threads(CG)) void k_factor_ne(
+__global__ __launch_bounds__(kNeMaxWaves * 64) void k_factor_ne(
     const int32_t* __restrict__ trowptr, const int32_t* __restrict__ tcol,
     const double* __restrict__ tval, const double* __restrict__ e,
     const int32_t* __restrict__ tp2s, const int32_t* __restrict__ sellT_off, int64_t n,
     const FactorJob* __restrict__ jobs, int njobs, NeLayout L, int* __restrict__ fb_count,
     int32_t* __restrict__ fb_list) {
-  constexpr int kNeThreads = ne_threads(CG);
-  constexpr int G = kNeThreads / CG;
   constexpr int LD = CG + 1;  // stride of the m x m matrices in LDS
+  const int nthr = (int)blockDim.x, G = L.G;
   __shared__ int a_sh, bad_sh;  // the diagonal's position in J; a shift's fallback
   extern __shared__ __align__(16) unsigned char lds[];
   int* J = (int*)(lds + L.off_J);
   int* coff = (int*)(lds + L.off_off);
   double* EJ = (double*)(lds + L.off_E);
-  double* Ajj = (double*)(lds + L.off_H);
+  double* H = (double*)(lds + L.off_H);  // Ajj, then H
   double* G0 = (double*)(lds + L.off_G0);
   int* crow = (int*)(lds + L.off_crow);
   double* cval = (double*)(lds + L.off_cval);
   // the column's set-up (gathers, scan, ballot) runs on the first wave; the
-  // lane groups of both waves then take one shift each
+  // lane groups of all waves then take one shift each
   const int lane = threadIdx.x;
   const int g = lane / CG, i = lane % CG, gbase = (g * CG) & 63;  // group's first lane in its wave
   if (lane == 0) bad_sh = 0;
-  // L(r, c), r >= c, at Lc[lix(r, c)]: column c (rows c .. CG-1) starts at
-  // c CG - c (c - 1) / 2
-  double* Lc = (double*)(lds + L.off_L) + (size_t)g * (CG * (CG + 1) / 2);
-  auto lix = [](int r, int c) { return c * CG - (c * (c - 1)) / 2 + (r - c); };
+  double* Lc = (double*)(lds + L.off_L) + (size_t)g * CG;  // the group's current column of L
 
   for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
     const int lo = trowptr[k];
@@ -482,7 +478,7 @@ __global__ __launch_bounds__(ne_threads(CG)) void k_factor_ne(
       const unsigned long long am = __ballot(jc == (int)k);
       if (lane == 0) a_sh = am ? (int)__ffsll((long long)am) - 1 : 0;  // the diagonal is in S
     }
-    for (int t = lane; t < m * LD; t += kNeThreads) Ajj[t] = 0.0;
+    for (int t = lane; t < m * LD; t += nthr) H[t] = 0.0;
     __syncthreads();
     const int a = a_sh;
     // Ajj(r, l) = A(J_r, J_l): the rows of column l that lie in J_k
@@ -495,18 +491,22 @@ __global__ __launch_bounds__(ne_threads(CG)) void k_factor_ne(
           if (J[mid] < row) lo2 = mid + 1;
           else hi2 = mid;
         }
-        if (J[lo2] == row) Ajj[lo2 * LD + lane] = cval[off + u];
+        if (J[lo2] == row) H[lo2 * LD + lane] = cval[off + u];
       }
     }
     // G0(r, l), r <= l: merge of the sorted rows of columns r and l
     const int npair = m * (m + 1) / 2;
-    for (int p = lane; p < npair; p += kNeThreads) {
-      int r = 0, rem = p;
-      while (rem >= m - r) {
-        rem -= m - r;
+    auto pair_of = [m](int p, int& r, int& l) {
+      r = 0;
+      while (p >= m - r) {
+        p -= m - r;
         ++r;
       }
-      const int l = r + rem;
+      l = r + p;
+    };
+    for (int p = lane; p < npair; p += nthr) {
+      int r, l;
+      pair_of(p, r, l);
       int x = coff[r], y = coff[l];
       const int xe = coff[r + 1], ye = coff[l + 1];
       double s = 0.0;
@@ -523,27 +523,38 @@ __global__ __launch_bounds__(ne_threads(CG)) void k_factor_ne(
     // per lane: Ajj(a, i), Ajj(i, a), Ajj(i, i), G0(i, a), G0(i, i)
     const bool row = i < m;
     const double ei = row ? EJ[i] : 0.0, ek = EJ[a];
-    const double aai = row ? Ajj[a * LD + i] : 0.0;
-    const double aia = row ? Ajj[i * LD + a] : 0.0;
-    const double aii = row ? Ajj[i * LD + i] : 0.0;
+    const double aai = row ? H[a * LD + i] : 0.0;
+    const double aia = row ? H[i * LD + a] : 0.0;
     const double g0a = row ? G0[i * LD + a] : 0.0;
     const double g0i = row ? G0[i * LD + i] : 0.0;
-    __syncthreads();  // the gathered columns are dead: their space holds L now
+    __syncthreads();
+    // Ajj -> H in place: each pair (r, l), r <= l, reads and writes only its
+    // two entries
+    for (int p = lane; p < npair; p += nthr) {
+      int r, l;
+      pair_of(p, r, l);
+      const double h = fma(EJ[r], H[r * LD + l], EJ[l] * H[l * LD + r]);
+      H[r * LD + l] = h;
+      H[l * LD + r] = h;
+    }
+    __syncthreads();  // the gathered columns are dead: their space holds L's columns now
+    const double hii = row ? H[i * LD + i] : 0.0;
     bool bad = false;
     for (int r0 = 0; r0 < njobs; r0 += G) {
       const bool live = r0 + g < njobs;
       const FactorJob job = jobs[live ? r0 + g : njobs - 1];
       const double sn = job.sigma_new, sp = job.sigma_prev;
-      // row i of G(sn) = G0 - sn (E_J Ajj + Ajj^T E_J) + sn^2 E_J^2 (identity
-      // rows past m) and the right-hand side
+      // row i of G(sn) = G0 - sn H + sn^2 E_J^2 (identity rows past m) and
+      // the right-hand side
+      const double dsh = sn * sn * ei * ei;
       double gr[CG];
 #pragma unroll
       for (int l = 0; l < CG; ++l) {
         double v = 0.0;
-        if (row && l < m) v = fma(-sn, fma(ei, Ajj[i * LD + l], EJ[l] * Ajj[l * LD + i]), G0[i * LD + l]);
+        if (row && l < m) v = fma(-sn, H[i * LD + l], G0[i * LD + l]);
         gr[l] = v + (l == i ? (row ? sn * sn * ei * ei : 1.0) : 0.0);
       }
-      const double gd = fma(sn * sn, ei * ei, fma(-2.0 * sn * ei, aii, g0i));  // G(sn)(i, i)
+      const double gd = fma(-sn, hii, g0i) + dsh;  // G(sn)(i, i) as built in gr
       double y = 0.0;
       if (row) {
         if (job.is_spai)
@@ -551,39 +562,47 @@ __global__ __launch_bounds__(ne_threads(CG)) void k_factor_ne(
         else
           y = g0a - sp * ek * aai - sn * ei * aia + (i == a ? sn * sp * ek * ek : 0.0);
       }
-      // Cholesky G = L L^T: after step c lane r >= c holds L(r, c) in gr[c]
-      // (the loops run over all CG positions with uniform guards, so that
-      // they unroll completely and gr stays in registers)
+      // Cholesky G = L L^T.  After step c lane r >= c holds L(r, c) in
+      // gr[c]; lane c skips its update at step c, so after the loop lane i
+      // holds L(i, i) L(l, i) in gr[l], l > i, and 1 / L(i, i) in inv (the
+      // loops run over all CG positions with uniform guards, so that they
+      // unroll completely and gr stays in registers)
+      double inv = 0.0;
 #pragma unroll
       for (int c = 0; c < CG; ++c) {
         if (c < m) {
           const double piv = group_bcast<CG>(gr[c], gbase, c);
           const double d = piv > 0.0 ? sqrt(piv) : 1.0;
+          const double rd = 1.0 / d;
           if (i == c && live) bad = bad || !(piv > kNeTol * gd);
-          const double lic = i > c ? gr[c] / d : (i == c ? d : 0.0);
-          gr[c] = lic;
-          if (i >= c) Lc[lix(i, c)] = lic;
+          if (i == c) inv = rd;
+          const double lic = i > c ? gr[c] * rd : (i == c ? d : 0.0);
+          if (i >= c) gr[c] = lic;
+          Lc[i] = lic;
           group_sync();
+          const double mult = i > c ? lic : 0.0;
 #pragma unroll
           for (int l = c + 1; l < CG; ++l)
-            if (l < m) gr[l] = fma(-lic, Lc[lix(l, c)], gr[l]);
+            if (l < m) gr[l] = fma(-mult, Lc[l], gr[l]);
         }
       }
-      // L z = y, then L^T q = z
+      // L z = y, then L^T q = z (lane i < c takes L(c, i) q_c as gr[c] q_c
+      // and divides the sum by L(i, i) once)
 #pragma unroll
       for (int c = 0; c < CG; ++c) {
         if (c < m) {
-          const double zc = group_bcast<CG>(y / gr[c], gbase, c);
+          const double zc = group_bcast<CG>(y * inv, gbase, c);
           if (i == c) y = zc;
           else if (i > c) y = fma(-gr[c], zc, y);
         }
       }
+      double sacc = 0.0;
 #pragma unroll
       for (int c = CG - 1; c >= 0; --c) {
         if (c < m) {
-          const double qc = group_bcast<CG>(y / gr[c], gbase, c);
+          const double qc = group_bcast<CG>(fma(-sacc, inv, y) * inv, gbase, c);
           if (i == c) y = qc;
-          else if (i < c) y = fma(-Lc[lix(c, i)], qc, y);
+          else if (i < c) sacc = fma(gr[c], qc, sacc);
         }
       }
       if (row && live) {
@@ -591,7 +610,6 @@ __global__ __launch_bounds__(ne_threads(CG)) void k_factor_ne(
         store_val<VT>((VT*)job.valsT + posT, y);
         store_val<VT>((VT*)job.vals + tp2s[lo + i], y);
       }
-      group_sync();  // L of this round is read up to here (each group its own L)
     }
     if (__ballot(bad) != 0ull && (lane & 63) == 0) atomicOr(&bad_sh, 1);
     __syncthreads();
@@ -958,7 +976,31 @@ int ls_grid(morx_system sys) {
 static int ne_lanes(morx_system sys) {
   if (!sys->ls_supported || sys->max_J > 32) return 0;
   const int cg = sys->max_J <= 8 ? 8 : (sys->max_J <= 16 ? 16 : 32);
-  return ne_layout(sys->max_T, cg).bytes <= (size_t)kLdsBudget ? cg : 0;
+  return ne_layout(sys->max_T, cg, 1).bytes <= (size_t)kLdsBudget ? cg : 0;
+}
+
+// Waves per normal-equations block: the count whose resident blocks per CU
+// finish the most columns per unit of time, taking a column's set-up
+// (gathers, G0, H) to cost about one round of shifts
+template <typename VT, int CG>
+static int ne_waves(int njobs, int maxT) {
+  int best_nw = 1;
+  double best = -1.0;
+  for (int nw = 1; nw <= kNeMaxWaves; ++nw) {
+    const NeLayout N = ne_layout(maxT, CG, nw);
+    if (N.bytes > (size_t)kLdsBudget) break;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_factor_ne<VT, CG>, nw * 64,
+                                                     N.bytes) != hipSuccess)
+      nb = 0;
+    const int rounds = (njobs + N.G - 1) / N.G;
+    const double score = nb / (1.0 + rounds);
+    if (score > best + 1e-9) {
+      best = score;
+      best_nw = nw;
+    }
+  }
+  return best_nw;
 }
 
 bool factor_kernel_supported(morx_system sys, int variant) {
@@ -1085,13 +1127,17 @@ morx_status factor_build_many(morx_system sys, int32_t prec, const FactorJob* jo
   }
   BlkShape bs{};
   if (cg > 0) {
-    const NeLayout N = ne_layout(sys->max_T, cg);
     const int ngrid = (int)std::min<int64_t>(sys->n, (int64_t)std::max(sys->ctx->num_cu, 1) * 32);
     int* fb_count = (int*)sb.p + 1;
 #define MORX_NE_LAUNCH(VT, CGV)                                                                 \
-  k_factor_ne<VT, CGV><<<ngrid, ne_threads(CGV), N.bytes, st>>>(sys->trowptr, sys->tcol, sys->tval, sys->e, \
-                                                   sys->tp2s, sys->sellT.off, sys->n,         \
-                                                   (FactorJob*)jb.p, njobs, N, fb_count, fb_list)
+  do {                                                                                          \
+    const int nw = ne_waves<VT, CGV>(njobs, sys->max_T);                                        \
+    const NeLayout N = ne_layout(sys->max_T, CGV, nw);                                          \
+    k_factor_ne<VT, CGV><<<ngrid, nw * 64, N.bytes, st>>>(sys->trowptr, sys->tcol, sys->tval,   \
+                                                          sys->e, sys->tp2s, sys->sellT.off,    \
+                                                          sys->n, (FactorJob*)jb.p, njobs, N,   \
+                                                          fb_count, fb_list);                   \
+  } while (0)
 #define MORX_NE_CG(VT)                 \
   if (cg == 8) MORX_NE_LAUNCH(VT, 8);   \
   else if (cg == 16) MORX_NE_LAUNCH(VT, 16); \

@@ -6,7 +6,9 @@
 // the reduced pencil (Ar, Er) (line 3 of Algorithm 2: the eigendecomposition
 // of the reduced matrix).  The r x r eigenvalue problem runs on the host:
 // Er^{-1} Ar by LU with partial pivoting, Householder reduction to upper
-// Hessenberg form, then Francis double-shift QR steps with deflation.
+// Hessenberg form, then Francis double-shift QR steps with deflation
+// (J. G. F. Francis, "The QR transformation", Computer J. 4 (1961-62); the
+// step as in Golub and Van Loan, Matrix Computations, Section 7.5).
 #include <math.h>
 #include <string.h>
 
@@ -117,8 +119,11 @@ void eig2(double a, double b, double c, double d, double* wr, double* wi) {
 // Eigenvalues of the real n x n matrix H (row-major, overwritten): Householder
 // reduction to upper Hessenberg form, then implicitly shifted double-shift QR
 // steps (shifts: the eigenvalues of the trailing 2 x 2 block; every tenth
-// step on one block an exceptional shift) with deflation at negligible
-// subdiagonal entries.  false if a block has not split after 60 n steps.
+// step on one block the exceptional shift of EISPACK's HQR, Martin, Peters and
+// Wilkinson, "The QR algorithm for real Hessenberg matrices", Numer. Math. 14
+// (1970): shift sum 1.5 w and product w^2 from the last two subdiagonal
+// magnitudes) with deflation at negligible subdiagonal entries.  false if a
+// block has not split after 60 n steps.
 bool hessenberg_qr(int n, std::vector<double>& H, double* wr, double* wi) {
   for (int k = 0; k + 2 < n; ++k) {
     double u[64], v[64];

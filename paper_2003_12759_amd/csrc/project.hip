@@ -23,56 +23,108 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 // partial[b] = U[rows_b]^T diag(w[rows_b]) V~[rows_b], column-major r1 x r2,
 // where V~ is V, or with SPARSE the product A V formed row by row on the fly
-// (A's rows on the CSR of S; the product is never stored).  One block of four
-// waves per slab of rows: kGR rows of U and V~ at a time are staged in LDS
-// (U's columns read with consecutive rows per lane, V~'s rows summed from
-// A's entries), then every wave runs the 16 x 16 x 4 FP64 MFMA steps of its
-// output tiles from LDS.
+// (A's rows on the sliced-ELL layout of S; the product is never stored).  One
+// block of four waves per slab of rows: kGR rows of U and V~ at a time are
+// staged in LDS, then every wave runs the 16 x 16 x 4 FP64 MFMA steps of its
+// output tiles from LDS.  Thread t stages row t % kGR of columns t / kGR + 8 u
+// (u < 8): a wave's loads of a column are consecutive rows, and a sparse row's
+// slots are loaded once and serve all of the thread's columns, with every
+// gather of a slot group in flight together.  The next step's loads are issued
+// before the current step's MFMA work.  Slabs are numbered so that
+// consecutive slabs run on one XCD (workgroups go round robin over the 8
+// XCDs): a stencil row's neighbours one plane away lie a few slabs over, so
+// the V entries they share are read through that XCD's L2.
 constexpr int kGR = 32;        // rows staged per step
 constexpr int kGLd = 64 + 2;   // LDS row stride (doubles)
 constexpr int kGThreads = 256;
+constexpr int kGItems = kGR * 64 / kGThreads;  // columns per thread
+constexpr int kGSlots = 8;                     // sparse slots loaded together
+
+template <bool SPARSE>
+__device__ __forceinline__ void gram_load(const double* __restrict__ U, int64_t ldu, int r1,
+                                          const double* __restrict__ V, int64_t ldv, int r2,
+                                          const double* __restrict__ w, int64_t row, bool in,
+                                          int c0, const int32_t* __restrict__ off,
+                                          const int32_t* __restrict__ col,
+                                          const double* __restrict__ val, double (&a)[kGItems],
+                                          double (&b)[kGItems]) {
+  const double wr = (w && in) ? w[row] : 1.0;
+#pragma unroll
+  for (int u = 0; u < kGItems; ++u) {
+    const int c = c0 + 8 * u;
+    a[u] = (in && c < r1) ? U[(int64_t)c * ldu + row] * wr : 0.0;
+    b[u] = 0.0;
+  }
+  if constexpr (SPARSE) {
+    if (!in) return;
+    const int64_t sl = row >> 6;
+    const int32_t p0 = off[sl] + (int32_t)(row & 63);
+    const int width = (off[sl + 1] - off[sl]) >> 6;  // uniform over the 32 rows of a step
+    for (int m0 = 0; m0 < width; m0 += kGSlots) {
+      int32_t cc[kGSlots];
+      double vv[kGSlots];
+#pragma unroll
+      for (int m = 0; m < kGSlots; ++m) {
+        const bool ok = m0 + m < width;
+        cc[m] = ok ? col[p0 + (m0 + m) * kSlice] : 0;
+        vv[m] = ok ? val[p0 + (m0 + m) * kSlice] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kGItems; ++u) {
+        const int c = c0 + 8 * u;
+        if (c < r2) {  // uniform over the 32 lanes of a column
+          const double* vc = V + (int64_t)c * ldv;
+          double x[kGSlots];
+#pragma unroll
+          for (int m = 0; m < kGSlots; ++m) x[m] = vc[cc[m]];
+#pragma unroll
+          for (int m = 0; m < kGSlots; ++m) b[u] = fma(vv[m], x[m], b[u]);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < kGItems; ++u) {
+      const int c = c0 + 8 * u;
+      if (in && c < r2) b[u] = V[(int64_t)c * ldv + row];
+    }
+  }
+}
 
 template <bool SPARSE>
 __global__ __launch_bounds__(kGThreads) void k_gram_mfma(
     const double* __restrict__ U, int64_t ldu, int r1, const double* __restrict__ V, int64_t ldv,
-    int r2, const double* __restrict__ w, int64_t n, int64_t rows_per_block,
-    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+    int r2, const double* __restrict__ w, int64_t n, int64_t rows_per_block, int nb,
+    const int32_t* __restrict__ off, const int32_t* __restrict__ col,
     const double* __restrict__ val, double* __restrict__ partial) {
   __shared__ double su[kGR * kGLd];
   __shared__ double sv[kGR * kGLd];
+  // slab of this block: the grid is a multiple of 8 blocks, XCD-major
+  const int slab = (int)(blockIdx.x & 7) * (int)(gridDim.x >> 3) + (int)(blockIdx.x >> 3);
+  if (slab >= nb) return;  // uniform: the padding blocks of the grid
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int t1n = (r1 + 15) >> 4, t2n = (r2 + 15) >> 4, ntile = t1n * t2n;
   const int kk = lane >> 4, li = lane & 15;
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int rr = threadIdx.x % kGR, c0 = threadIdx.x / kGR;
+  const int64_t r0 = (int64_t)slab * rows_per_block;
   const int64_t rend = min(n, r0 + rows_per_block);
   v4d acc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  double a[kGItems], b[kGItems];
+  gram_load<SPARSE>(U, ldu, r1, V, ldv, r2, w, r0 + rr, r0 + rr < rend, c0, off, col, val, a, b);
   for (int64_t base = r0; base < rend; base += kGR) {
-    // stage rows base .. base + kGR - 1 (zeros past the slab and past r)
-    for (int idx = threadIdx.x; idx < kGR * 64; idx += kGThreads) {
-      const int c = idx / kGR, rr = idx % kGR;
-      const int64_t row = base + rr;
-      const bool in = row < rend;
-      double a = 0.0, b = 0.0;
-      if (in && c < r1) {
-        a = U[(int64_t)c * ldu + row];
-        if (w) a *= w[row];
-      }
-      if (in && c < r2) {
-        if constexpr (SPARSE) {
-          const double* vc = V + (int64_t)c * ldv;
-          double s = 0.0;
-          for (int32_t p = rowptr[row]; p < rowptr[row + 1]; ++p) s = fma(val[p], vc[colind[p]], s);
-          b = s;
-        } else {
-          b = V[(int64_t)c * ldv + row];
-        }
-      }
-      su[rr * kGLd + c] = a;
-      sv[rr * kGLd + c] = b;
+    // rows base .. base + kGR - 1 (zeros past the slab and past r)
+#pragma unroll
+    for (int u = 0; u < kGItems; ++u) {
+      su[rr * kGLd + c0 + 8 * u] = a[u];
+      sv[rr * kGLd + c0 + 8 * u] = b[u];
     }
     __syncthreads();
+    if (base + kGR < rend) {
+      const int64_t row = base + kGR + rr;
+      gram_load<SPARSE>(U, ldu, r1, V, ldv, r2, w, row, row < rend, c0, off, col, val, a, b);
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int tile = wave + 4 * q;
@@ -80,16 +132,16 @@ __global__ __launch_bounds__(kGThreads) void k_gram_mfma(
         const int ti = tile / t2n, tj = tile % t2n;
 #pragma unroll
         for (int k = 0; k < kGR; k += 4) {
-          const double a = su[(k + kk) * kGLd + ti * 16 + li];
-          const double b = sv[(k + kk) * kGLd + tj * 16 + li];
-          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+          const double x = su[(k + kk) * kGLd + ti * 16 + li];
+          const double y = sv[(k + kk) * kGLd + tj * 16 + li];
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[q], 0, 0, 0);
         }
       }
     }
     __syncthreads();
   }
   // output block: element t of lane l holds D[(l >> 4) + 4t][l & 15]
-  double* out = partial + (int64_t)blockIdx.x * r1 * r2;
+  double* out = partial + (int64_t)slab * r1 * r2;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int tile = wave + 4 * q;
@@ -159,30 +211,33 @@ __global__ __launch_bounds__(256) void k_chol(const double* __restrict__ G, int 
   }
 }
 
-// X <- X R^{-1} row by row (R upper triangular, r <= 64)
+// X <- X R^{-1} row by row (R upper triangular, r <= RM, RM in {16, 32, 64}:
+// the loops unroll over RM, so a small basis runs a short kernel)
+template <int RM>
 __global__ __launch_bounds__(256) void k_trsm_rows(double* __restrict__ X, int64_t ld, int64_t n,
                                                    int r, const double* __restrict__ R) {
-  __shared__ double sr[64 * 64];
-  for (int k = threadIdx.x; k < r * r; k += blockDim.x) sr[k] = R[k];
+  __shared__ double sr[RM * RM];  // R with row stride RM, zeros past r
+  for (int k = threadIdx.x; k < RM * RM; k += blockDim.x) {
+    const int l = k % RM, j = k / RM;
+    sr[k] = (l < r && j < r) ? R[l + j * r] : 0.0;
+  }
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double x[64];
+  double x[RM];
 #pragma unroll
-  for (int j = 0; j < 64; ++j)
-    if (j < r) x[j] = X[(int64_t)j * ld + i];
+  for (int j = 0; j < RM; ++j) x[j] = j < r ? X[(int64_t)j * ld + i] : 0.0;
 #pragma unroll
-  for (int j = 0; j < 64; ++j) {
+  for (int j = 0; j < RM; ++j) {
     if (j < r) {
       double s = x[j];
 #pragma unroll
-      for (int l = 0; l < 64; ++l)
-        if (l < j) s -= x[l] * sr[l + j * r];
-      x[j] = s / sr[j + j * r];
+      for (int l = 0; l < j; ++l) s -= x[l] * sr[l + j * RM];
+      x[j] = s / sr[j + j * RM];
     }
   }
 #pragma unroll
-  for (int j = 0; j < 64; ++j)
+  for (int j = 0; j < RM; ++j)
     if (j < r) X[(int64_t)j * ld + i] = x[j];
 }
 
@@ -193,27 +248,33 @@ __global__ void k_copy_cols(const double* __restrict__ src, int64_t lds, double*
   if (i < n && c < r) dst[(int64_t)c * ldd + i] = src[(int64_t)c * lds + i];
 }
 
-// Partial sums of one n-long contraction: at most kGramBlocks slabs of rows
-// (a multiple of kGR rows each), one partial r1 x r2 block per slab.
-constexpr int kGramBlocks = 256;
+// Partial sums of one n-long contraction: one partial r1 x r2 block per slab
+// of rows (a multiple of kGR rows each), at most kPartialDoubles doubles of
+// partials in all and about four slabs per CU.
+constexpr size_t kPartialDoubles = (size_t)256 * 64 * 64;
 
 struct Gram {
   morx_system sys;
-  double* partial = nullptr;  // [nb][64 * 64]
-  int64_t rows_per_block = 0;
-  int nb = 0;
+  double* partial = nullptr;  // kPartialDoubles
 };
 
-Gram gram_shape(morx_system sys, double* partial) {
-  Gram g;
-  g.sys = sys;
-  g.partial = partial;
-  const int64_t n = sys->n;
-  const int64_t target = std::min<int64_t>(kGramBlocks, std::max(1, 2 * sys->ctx->num_cu));
+struct GramShape {
+  int64_t rows_per_block;
+  int nb;    // slabs
+  int grid;  // nb rounded up to a multiple of 8
+};
+
+GramShape gram_shape(const Gram& g, int r1, int r2) {
+  const int64_t n = g.sys->n;
+  const int64_t cap = (int64_t)(kPartialDoubles / ((size_t)r1 * r2));
+  const int64_t target =
+      std::max<int64_t>(1, std::min<int64_t>(cap, 4 * (int64_t)std::max(1, g.sys->ctx->num_cu)));
   const int64_t per = (n + target - 1) / target;
-  g.rows_per_block = std::max<int64_t>(kGR, (per + kGR - 1) / kGR * kGR);
-  g.nb = (int)std::max<int64_t>(1, (n + g.rows_per_block - 1) / g.rows_per_block);
-  return g;
+  GramShape s;
+  s.rows_per_block = std::max<int64_t>(kGR, (per + kGR - 1) / kGR * kGR);
+  s.nb = (int)std::max<int64_t>(1, (n + s.rows_per_block - 1) / s.rows_per_block);
+  s.grid = (s.nb + 7) / 8 * 8;
+  return s;
 }
 
 // out_dev = scale * U^T diag(w) V~ (V~ = V, or A V when sparse)
@@ -222,15 +283,17 @@ morx_status gram(const Gram& g, const double* U, int64_t ldu, int r1, const doub
                  double scale, hipStream_t st) {
   const int64_t n = g.sys->n;
   morx_system sys = g.sys;
+  const GramShape s = gram_shape(g, r1, r2);
   if (sparse)
-    k_gram_mfma<true><<<g.nb, kGThreads, 0, st>>>(U, ldu, r1, V, ldv, r2, w, n, g.rows_per_block,
-                                                   sys->rowptr, sys->colind, sys->valA, g.partial);
+    k_gram_mfma<true><<<s.grid, kGThreads, 0, st>>>(U, ldu, r1, V, ldv, r2, w, n,
+                                                     s.rows_per_block, s.nb, sys->sell.off,
+                                                     sys->sell.col, sys->sell_val, g.partial);
   else
-    k_gram_mfma<false><<<g.nb, kGThreads, 0, st>>>(U, ldu, r1, V, ldv, r2, w, n,
-                                                    g.rows_per_block, nullptr, nullptr, nullptr,
-                                                    g.partial);
+    k_gram_mfma<false><<<s.grid, kGThreads, 0, st>>>(U, ldu, r1, V, ldv, r2, w, n,
+                                                      s.rows_per_block, s.nb, nullptr, nullptr,
+                                                      nullptr, g.partial);
   const int cnt = r1 * r2;
-  k_sum_partials<<<(cnt + 3) / 4, 256, 0, st>>>(g.partial, g.nb, cnt, out_dev, scale);
+  k_sum_partials<<<(cnt + 3) / 4, 256, 0, st>>>(g.partial, s.nb, cnt, out_dev, scale);
   MORX_HIP(hipGetLastError());
   return MORX_OK;
 }
@@ -244,7 +307,10 @@ morx_status orth_scqr3(const Gram& g, double* X, int64_t ld, int r, double* G, d
   for (int pass = 0; pass < 3; ++pass) {
     MORX_TRY(gram(g, X, ld, r, X, ld, r, nullptr, false, G, 1.0, st));
     k_chol<<<1, 256, 0, st>>>(G, r, pass == 0 ? coef : 0.0, R, status);
-    k_trsm_rows<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(X, ld, n, r, R);
+    const unsigned tg = (unsigned)((n + 255) / 256);
+    if (r <= 16) k_trsm_rows<16><<<tg, 256, 0, st>>>(X, ld, n, r, R);
+    else if (r <= 32) k_trsm_rows<32><<<tg, 256, 0, st>>>(X, ld, n, r, R);
+    else k_trsm_rows<64><<<tg, 256, 0, st>>>(X, ld, n, r, R);
     MORX_HIP(hipGetLastError());
   }
   return MORX_OK;
@@ -291,7 +357,7 @@ morx_status copy_results(const double* res, int r, int m, int q, double* Ar, dou
 // Scratch of the allocation-free projection: the slab partials of one
 // contraction at a time, then the four results.  Every GPU the library runs
 // on holds its own copy until the process ends.
-constexpr size_t kScratchPartial = (size_t)kGramBlocks * 64 * 64;  // doubles
+constexpr size_t kScratchPartial = kPartialDoubles;
 constexpr size_t kScratchResults = 4 * 4096;                        // doubles
 __device__ __align__(256) double scratch[kScratchPartial + kScratchResults];
 
@@ -323,8 +389,8 @@ extern "C" morx_status morx_project(morx_system sys, int32_t r, const double* V,
   hipStream_t st = ctx->stream;
   const int64_t n = sys->n, ld = sys->n_pad;
   DevBuf part, vv, ww, small, stat;
-  morx_status s = dev_alloc(part, (size_t)kGramBlocks * 64 * 64 * sizeof(double));
-  const Gram g = gram_shape(sys, (double*)part.p);
+  morx_status s = dev_alloc(part, kPartialDoubles * sizeof(double));
+  const Gram g{sys, (double*)part.p};
   if (s == MORX_OK && orthonormalize) s = dev_alloc(vv, (size_t)ld * r * sizeof(double));
   if (s == MORX_OK && orthonormalize) s = dev_alloc(ww, (size_t)ld * r * sizeof(double));
   if (s == MORX_OK) s = dev_alloc(small, (size_t)6 * 4096 * sizeof(double));
@@ -385,9 +451,7 @@ extern "C" morx_status morx_project_noalloc(morx_system sys, int32_t r, const do
   std::lock_guard<std::mutex> lk(ctx->mu);
   MORX_HIP(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
-  const Gram g = gram_shape(sys, ctx->proj_scratch);
-  MORX_REQUIRE(g.nb <= kGramBlocks, MORX_E_INVALID,
-               "morx_project_noalloc: %d row slabs exceed the scratch's %d", g.nb, kGramBlocks);
+  const Gram g{sys, ctx->proj_scratch};
   double* res = ctx->proj_scratch + kScratchPartial;
   MORX_TRY(project_products(g, r, V, ldv, W, ldw, m, B, ldb, q, C, ldc, res, st));
   MORX_TRY(copy_results(res, r, m, q, Ar, Er, Br, Cr, st));
