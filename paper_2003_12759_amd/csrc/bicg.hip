@@ -1665,6 +1665,10 @@ constexpr int64_t kTuneHouseholderMaxN = (int64_t)1 << 17;
 // relative slowdown that ends a tile's row-block search (single timings of
 // 6 iterations vary by about 1 % between launches)
 constexpr double kTuneMargin = 0.03;
+// a tile this much slower than the best shape so far ends the search over
+// narrower tiles of that chain kernel: a narrower tile reads every factor
+// value for fewer columns, and once that cost shows it only grows
+constexpr double kTuneTileCut = 1.25;
 
 static morx_status time_events(hipEvent_t a, hipEvent_t b, hipStream_t st, double* ms) {
   MORX_HIP(hipStreamSynchronize(st));
@@ -1801,7 +1805,7 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
       const int ncv = pick_nc(ncols, ncmax);
       if (std::find(seen.begin(), seen.end(), ncv) != seen.end()) continue;
       seen.push_back(ncv);
-      double prev = 1e300;
+      double prev = 1e300, tile_best = 1e300;
       for (int mult : {1, 2, 4}) {
         const int spw = spw0 * mult;
         if (mult > 1 && (sys->nslice + (int64_t)kWavesPerBlock * spw - 1) /
@@ -1816,17 +1820,21 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
           best_spw = spw;
           best_chain = kern;
         }
+        tile_best = std::min(tile_best, ms);
         // a wider row block lost at this tile (beyond launch-to-launch jitter)
         if (ms > prev * (1.0 + kTuneMargin)) break;
         prev = std::min(prev, ms);
       }
       if (s != MORX_OK) break;
+      if (tile_best > best_i * kTuneTileCut) break;
     }
     if (s != MORX_OK) break;
   }
   sys->tune_chain = best_chain;
   // ... and the shifted pair's own tile with the chain shape and kernel fixed
-  if (s == MORX_OK) {
+  // (the row-gather pair only: on the halo layout the pair runs as a pass of
+  // the chain kernel, at the chain tile)
+  if (s == MORX_OK && !halo_in_use(sys)) {
     std::vector<int> seen{pick_nc(ncols, best_nc)};
     for (int ncs : {16, 8, 4, 2, 1}) {
       const int ncv = pick_nc(ncols, ncs);

@@ -13,6 +13,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 
 #include "common.h"
@@ -332,9 +333,10 @@ __global__ void k_factor_to_csr(const VT* __restrict__ vals, const int32_t* __re
 // A SPAI column solves G(s) q = M(s)^T e_k with M(s)^T e_k = s E_k e_a -
 // Ajj(a, :)^T; an update column solves G(sn) q = M(sn)^T M(sp) e_a (its
 // right-hand side is column k of sp E - A).  Neither I_k nor the dense
-// |I_k| x m matrix is formed: one wave gathers the m columns of A, forms G0
-// (sorted merges of column pairs) and Ajj, then H = E_J Ajj + Ajj^T E_J in
-// Ajj's place (G(s) = G0 - s H + s^2 E_J^2, both symmetric), and then groups
+// |I_k| x m matrix is formed: the block gathers the m columns of A, and one
+// merge per column pair over their sorted rows gives G0 and the two entries of
+// Ajj, hence H = E_J Ajj + Ajj^T E_J (G(s) = G0 - s H + s^2 E_J^2, both
+// symmetric; Ajj itself is kept only in row and column a), and then groups
 // of CG lanes, lane i holding row i, each take one shift: Cholesky
 // factorisation and the two triangular solves in registers, each column of L
 // passed to the group's lanes through LDS.  Lane i skips its own update at
@@ -350,7 +352,7 @@ constexpr int kNeGather = 16;  // entries of a column loaded together in the set
 
 struct NeLayout {
   int T, G;  // gathered entries, lane groups per block
-  size_t off_J, off_off, off_E, off_H, off_G0, off_crow, off_cval, off_L, bytes;
+  size_t off_J, off_off, off_E, off_H, off_G0, off_A, off_crow, off_cval, off_L, bytes;
 };
 
 // A normal-equations block has nw waves (one to four), whose 64 nw / CG lane
@@ -374,6 +376,7 @@ NeLayout ne_layout(int maxT, int CG, int nw) {
   L.off_E = take((size_t)CG * 8);
   L.off_H = take(mat);
   L.off_G0 = take(mat);
+  L.off_A = take((size_t)2 * CG * 8);
   // the gathered columns, later in the same space one column of L per group
   const size_t base = o;
   L.off_crow = base;
@@ -406,6 +409,17 @@ __device__ __forceinline__ double group_bcast(double v, int gbase, int c) {
   }
 }
 
+// 1 / sqrt(x) for positive normal x: the hardware estimate (about 23 bits)
+// refined by two Newton steps for 1 / y^2 = x, y <- y (3 - x y^2) / 2, each of
+// which doubles the correct bits
+__device__ __forceinline__ double rsqrt_newton(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(y, fma(-h * y, y, 0.5), y);
+  return y;
+}
+
 // Orders the LDS writes of a group before its lanes' reads: every group lies
 // within one wave, so a wavefront-scope fence replaces a block barrier
 __device__ __forceinline__ void group_sync() {
@@ -413,8 +427,9 @@ __device__ __forceinline__ void group_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// (at most 128 registers, four waves per SIMD: a few set-up values spill)
 template <typename VT, int CG>
-__global__ __launch_bounds__(kNeMaxWaves * 64) void k_factor_ne(
+__global__ __launch_bounds__(kNeMaxWaves * 64, 4) void k_factor_ne(
     const int32_t* __restrict__ trowptr, const int32_t* __restrict__ tcol,
     const double* __restrict__ tval, const double* __restrict__ e,
     const int32_t* __restrict__ tp2s, const int32_t* __restrict__ sellT_off, int64_t n,
@@ -427,13 +442,13 @@ __global__ __launch_bounds__(kNeMaxWaves * 64) void k_factor_ne(
   int* J = (int*)(lds + L.off_J);
   int* coff = (int*)(lds + L.off_off);
   double* EJ = (double*)(lds + L.off_E);
-  double* H = (double*)(lds + L.off_H);  // Ajj, then H
+  double* H = (double*)(lds + L.off_H);
   double* G0 = (double*)(lds + L.off_G0);
+  double* rowA = (double*)(lds + L.off_A);  // Ajj(a, :)
+  double* colA = rowA + CG;                 // Ajj(:, a)
   int* crow = (int*)(lds + L.off_crow);
   double* cval = (double*)(lds + L.off_cval);
-  // the column's set-up (gathers, scan, ballot) runs on the first wave; the
-  // lane groups of all waves then take one shift each
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x, wl = lane & 63, wave = lane >> 6, nw = nthr >> 6;
   const int g = lane / CG, i = lane % CG, gbase = (g * CG) & 63;  // group's first lane in its wave
   if (lane == 0) bad_sh = 0;
   double* Lc = (double*)(lds + L.off_L) + (size_t)g * CG;  // the group's current column of L
@@ -441,103 +456,96 @@ __global__ __launch_bounds__(kNeMaxWaves * 64) void k_factor_ne(
   for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
     const int lo = trowptr[k];
     const int m = trowptr[k + 1] - lo;  // <= CG (checked on the host)
-    // gather the columns J_k of A in order (rows sorted within a column)
+    // gather the columns J_k of A in order (rows sorted within a column):
+    // every wave scans the column lengths, wave w copies the entries
+    // w kNeGather, (w + nw) kNeGather, ... of each column, with all of a
+    // group's loads in flight before the first store
     int len = 0, jc = -1, cb = 0;
-    if (lane < m) {
-      jc = tcol[lo + lane];
+    if (wl < m) {
+      jc = tcol[lo + wl];
       cb = trowptr[jc];
       len = trowptr[jc + 1] - cb;
-      J[lane] = jc;
-      EJ[lane] = e[jc];
     }
-    int off = 0;
-    if (lane < 64) {  // uniform over each wave
-      int T;
-      off = wave_excl_scan(len, lane, &T);
-      if (lane < m) coff[lane] = off;
-      if (lane == 0) coff[m] = T;
-      // the column's entries, kNeGather at a time with all of their loads in
-      // flight before the first store (one memory round trip per group
-      // instead of one per entry)
-      for (int u0 = 0; u0 < len; u0 += kNeGather) {
-        int rr[kNeGather];
-        double vv[kNeGather];
-#pragma unroll
-        for (int u = 0; u < kNeGather; ++u) {
-          const int uu = min(u0 + u, len - 1);
-          rr[u] = tcol[cb + uu];
-          vv[u] = tval[cb + uu];
-        }
-#pragma unroll
-        for (int u = 0; u < kNeGather; ++u)
-          if (u0 + u < len) {
-            crow[off + u0 + u] = rr[u];
-            cval[off + u0 + u] = vv[u];
-          }
+    int T;
+    const int off = wave_excl_scan(len, wl, &T);
+    if (wave == 0) {
+      if (wl < m) {
+        J[wl] = jc;
+        EJ[wl] = e[jc];
+        coff[wl] = off;
       }
+      if (wl == 0) coff[m] = T;
       const unsigned long long am = __ballot(jc == (int)k);
-      if (lane == 0) a_sh = am ? (int)__ffsll((long long)am) - 1 : 0;  // the diagonal is in S
+      if (wl == 0) a_sh = am ? (int)__ffsll((long long)am) - 1 : 0;  // the diagonal is in S
     }
-    for (int t = lane; t < m * LD; t += nthr) H[t] = 0.0;
+    for (int u0 = wave * kNeGather; u0 < len; u0 += nw * kNeGather) {
+      int rr[kNeGather];
+      double vv[kNeGather];
+#pragma unroll
+      for (int u = 0; u < kNeGather; ++u) {
+        const int uu = min(u0 + u, len - 1);
+        rr[u] = tcol[cb + uu];
+        vv[u] = tval[cb + uu];
+      }
+#pragma unroll
+      for (int u = 0; u < kNeGather; ++u)
+        if (u0 + u < len) {
+          crow[off + u0 + u] = rr[u];
+          cval[off + u0 + u] = vv[u];
+        }
+    }
     __syncthreads();
     const int a = a_sh;
-    // Ajj(r, l) = A(J_r, J_l): the rows of column l that lie in J_k
-    if (lane < m) {
-      for (int u = 0; u < len; ++u) {
-        const int row = crow[off + u];
-        int lo2 = 0, hi2 = m - 1;
-        while (lo2 < hi2) {
-          const int mid = (lo2 + hi2) >> 1;
-          if (J[mid] < row) lo2 = mid + 1;
-          else hi2 = mid;
-        }
-        if (J[lo2] == row) H[lo2 * LD + lane] = cval[off + u];
-      }
-    }
-    // G0(r, l), r <= l: merge of the sorted rows of columns r and l
+    // one pass per column pair r <= l over the union of their sorted rows:
+    // G0(r, l) sums the products at common rows; the entry of column l at row
+    // J_r is Ajj(r, l) = A(J_r, J_l), the entry of column r at row J_l is
+    // Ajj(l, r).  H(r, l) = E_r Ajj(r, l) + E_l Ajj(l, r); row and column a of
+    // Ajj are kept for the right-hand sides.
     const int npair = m * (m + 1) / 2;
-    auto pair_of = [m](int p, int& r, int& l) {
-      r = 0;
-      while (p >= m - r) {
-        p -= m - r;
+    for (int p = lane; p < npair; p += nthr) {
+      int r = 0, q = p;
+      while (q >= m - r) {
+        q -= m - r;
         ++r;
       }
-      l = r + p;
-    };
-    for (int p = lane; p < npair; p += nthr) {
-      int r, l;
-      pair_of(p, r, l);
+      const int l = r + q;
       int x = coff[r], y = coff[l];
-      const int xe = coff[r + 1], ye = coff[l + 1];
-      double s = 0.0;
-      while (x < xe && y < ye) {
-        const int rx = crow[x], ry = crow[y];
-        if (rx == ry) s = fma(cval[x], cval[y], s);
+      const int xe = coff[r + 1], ye = coff[l + 1];  // both columns hold their diagonal
+      const int jr = J[r], jl = J[l];
+      double sg = 0.0, arl = 0.0, alr = 0.0;
+      while (x < xe || y < ye) {
+        const int xi = min(x, xe - 1), yi = min(y, ye - 1);
+        const int cx = crow[xi], cy = crow[yi];
+        const double vx = cval[xi], vy = cval[yi];
+        const int rx = x < xe ? cx : INT_MAX, ry = y < ye ? cy : INT_MAX;
+        if (rx == ry) sg = fma(vx, vy, sg);
+        if (ry == jr) arl = vy;
+        if (rx == jl) alr = vx;
         x += rx <= ry;
         y += ry <= rx;
       }
-      G0[r * LD + l] = s;
-      G0[l * LD + r] = s;
-    }
-    __syncthreads();
-    // per lane: Ajj(a, i), Ajj(i, a), Ajj(i, i), G0(i, a), G0(i, i)
-    const bool row = i < m;
-    const double ei = row ? EJ[i] : 0.0, ek = EJ[a];
-    const double aai = row ? H[a * LD + i] : 0.0;
-    const double aia = row ? H[i * LD + a] : 0.0;
-    const double g0a = row ? G0[i * LD + a] : 0.0;
-    const double g0i = row ? G0[i * LD + i] : 0.0;
-    __syncthreads();
-    // Ajj -> H in place: each pair (r, l), r <= l, reads and writes only its
-    // two entries
-    for (int p = lane; p < npair; p += nthr) {
-      int r, l;
-      pair_of(p, r, l);
-      const double h = fma(EJ[r], H[r * LD + l], EJ[l] * H[l * LD + r]);
+      G0[r * LD + l] = sg;
+      G0[l * LD + r] = sg;
+      const double h = fma(EJ[r], arl, EJ[l] * alr);
       H[r * LD + l] = h;
       H[l * LD + r] = h;
+      if (r == a) {
+        rowA[l] = arl;
+        colA[l] = alr;
+      }
+      if (l == a) {
+        colA[r] = arl;
+        rowA[r] = alr;
+      }
     }
     __syncthreads();  // the gathered columns are dead: their space holds L's columns now
+    // per lane: Ajj(a, i), Ajj(i, a), G0(i, a), G0(i, i), H(i, i)
+    const bool row = i < m;
+    const double ei = row ? EJ[i] : 0.0, ek = EJ[a];
+    const double aai = row ? rowA[i] : 0.0;
+    const double aia = row ? colA[i] : 0.0;
+    const double g0a = row ? G0[i * LD + a] : 0.0;
+    const double g0i = row ? G0[i * LD + i] : 0.0;
     const double hii = row ? H[i * LD + i] : 0.0;
     bool bad = false;
     for (int r0 = 0; r0 < njobs; r0 += G) {
@@ -572,8 +580,8 @@ __global__ __launch_bounds__(kNeMaxWaves * 64) void k_factor_ne(
       for (int c = 0; c < CG; ++c) {
         if (c < m) {
           const double piv = group_bcast<CG>(gr[c], gbase, c);
-          const double d = piv > 0.0 ? sqrt(piv) : 1.0;
-          const double rd = 1.0 / d;
+          const double rd = piv > 0.0 ? rsqrt_newton(piv) : 1.0;
+          const double d = piv > 0.0 ? piv * rd : 1.0;
           if (i == c && live) bad = bad || !(piv > kNeTol * gd);
           if (i == c) inv = rd;
           const double lic = i > c ? gr[c] * rd : (i == c ? d : 0.0);
