@@ -41,7 +41,7 @@ def test_traffic_files_describe_their_workload():
         assert d["kernels"]
         for label, e in d["kernels"].items():
             assert label.startswith("k_chain_")
-            assert e["bytes_per_launch"] > 0 and 0.5 < e["traffic_over_alg"] < 2.0
+            assert e["bytes_per_launch"] > 0 and 0.5 < e["traffic_over_alg"] < 3.0
             cal = e["calibration"]
             # a 1 GiB copy reads FETCH_SIZE in half units and WRITE_SIZE in whole ones
             assert abs(cal["fetch_scale"] - 2.0) < 0.05 and abs(cal["write_scale"] - 1.0) < 0.05

@@ -2,9 +2,10 @@
 parity of the factor schedules, through the C ABI.
 
 The chain step (``k_chain_halo`` 8- and 32-slot, ``k_chain_narrow``,
-``k_chain_step``) and the shifted pair (``k_spmv_halo``, ``k_spmv_pair``) are
-run by ``morx_chain_apply_batch`` / ``morx_shifted_apply_pair``, which launch
-them with the work lists, tile widths and row blocks of a solve.  Factors are
+``k_chain_step``) and the shifted pair (the halo chain kernel's shifted-pair
+pass, ``k_spmv_pair``) are run by ``morx_chain_apply_batch`` /
+``morx_shifted_apply_pair``, which launch them with the work lists, tile
+widths and row blocks of a solve.  Factors are
 imported from seeded random values on the pattern S (the same values, rounded
 by the oracle's storage rounding, feed ``oracle.chain.apply``), so both sides
 apply the same operator.
@@ -421,7 +422,8 @@ def test_factor_build_many_jobs_match_oracle(ctx):
 
 
 def test_normal_equations_fallback_on_a_late_job_of_a_wide_column(ctx):
-    """A dense 20 x 20 system (|J_k| = 20: 32-lane groups, two-wave blocks).
+    """A dense 20 x 20 system (|J_k| = 20: 32-lane groups; the groups of jobs
+    2 and 3 lie on a block's second wave).
     With A = 2 I - B, the shifted matrix s I - A = (s - 2) I + B, where B is
     symmetric positive definite with eigenvalues 5e-4 and 1..5 and the
     eigenvector of 5e-4 is (e_0 - e_1)/sqrt(2): columns 0 and 1 of B nearly
