@@ -962,6 +962,8 @@ static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   a.lidx = sys->sell.lidx;
   a.hoffT = sys->sellT.hoff;
   a.hcolT = sys->sellT.hcol;
+  a.hrun = sys->sell.hrun;
+  a.hrunT = sys->sellT.hrun;
   a.lidxT = sys->sellT.lidx;
   a.offT = sys->sellT.off;
   a.colT = sys->sellT.col;

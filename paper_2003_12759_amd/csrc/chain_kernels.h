@@ -61,6 +61,7 @@ struct IterArgs {
                    // (narrow patterns: the W = 8 kernel, lists of at most kHaloCapNarrow)
   int hstride;     // halo kernels: a block's row blocks are hstride apart (1: consecutive)
   const int32_t *hoff, *hcol, *hoffT, *hcolT;
+  const int32_t *hrun, *hrunT;  // the lists as runs (kHaloRunInts per row block)
   const uint16_t *lidx, *lidxT;
   const int32_t *off, *col, *offT, *colT;
   const double *valA, *valAT, *e;
@@ -700,6 +701,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
     const int32_t* off = bwd ? a.offT : a.off;
     const int32_t* hoff = bwd ? a.hoffT : a.hoff;
     const int32_t* hcol = bwd ? a.hcolT : a.hcol;
+    const int32_t* hrun = bwd ? a.hrunT : a.hrun;
     const uint16_t* lidx = bwd ? a.lidxT : a.lidx;
     const VT* fv0 = SPMV ? (const VT*)(bwd ? a.valAT : a.valA) : (const VT*)uniform(ck->fv);
     // the input and output vectors of pair j (the shifted pair's come from the slots)
@@ -726,13 +728,35 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
       if constexpr (SPMV) ei = i < a.n ? gld(a.e + i) : 0.0;
       const int32_t h0 = __builtin_amdgcn_readfirstlane(gld(hoff + rb));
       const int H = __builtin_amdgcn_readfirstlane(gld(hoff + rb + 1)) - h0;
-      // (the list array carries kHaloCap >= HC entries of padding)
+      // the list entries of this thread: from the block's runs (entry e of
+      // run r is column s_r + e - o_r), or read from the list (which carries
+      // kHaloCap >= HC entries of padding)
       int32_t hv[kPT];
-      const int32_t* hp = hcol + h0 + threadIdx.x;
+      const int32_t* rp = hrun + rb * kHaloRunInts;
+      const int nrun = __builtin_amdgcn_readfirstlane(gld(rp));
+      if (nrun > 0) {
+        int32_t rd[kHaloRuns], ro[kHaloRuns];
 #pragma unroll
-      for (int q = 0; q < kPT; ++q) {
-        const int32_t r = gld(hp + kBlock * q);
-        hv[q] = (int)threadIdx.x + kBlock * q < H ? r : 0;
+        for (int r = 0; r < kHaloRuns; ++r) {
+          ro[r] = __builtin_amdgcn_readfirstlane(gld(rp + 2 + 2 * r));
+          rd[r] = __builtin_amdgcn_readfirstlane(gld(rp + 1 + 2 * r)) - ro[r];
+        }
+#pragma unroll
+        for (int q = 0; q < kPT; ++q) {
+          const int e = (int)threadIdx.x + kBlock * q;
+          int32_t c = e + rd[0];
+#pragma unroll
+          for (int r = 1; r < kHaloRuns; ++r)
+            if (r < nrun && e >= ro[r]) c = e + rd[r];
+          hv[q] = e < H ? c : 0;
+        }
+      } else {
+        const int32_t* hp = hcol + h0 + threadIdx.x;
+#pragma unroll
+        for (int q = 0; q < kPT; ++q) {
+          const int32_t r = gld(hp + kBlock * q);
+          hv[q] = (int)threadIdx.x + kBlock * q < H ? r : 0;
+        }
       }
       // local indices, kept as LDS byte offsets, and (shared factor)
       // values: all W slots read from one address (slot m at a

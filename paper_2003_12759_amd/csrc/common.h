@@ -49,6 +49,12 @@ constexpr int kHaloSlices = 4;
 constexpr int kHaloCap = 2048;
 constexpr int kHaloCapNarrow = 1024;  // list cap of the kernel for slices of <= 8 slots
 constexpr int kHaloMaxW = 32;      // widest slice the halo layout takes
+// A block's list in runs of consecutive columns (a stencil's block lists one
+// run per grid plane): kHaloRunInts integers per block, the run count (0: the
+// list has more than kHaloRuns runs and is read as it is) then per run its
+// first column and its first list position
+constexpr int kHaloRuns = 7;
+constexpr int kHaloRunInts = 16;
 // Entries past the end of a sliced-ELL value or local-index array: the halo
 // chain step reads all kHaloMaxW slots of a slice with one address and
 // discards those past its width, so the last slice may read this far beyond.
@@ -93,6 +99,7 @@ struct Sell {
   int32_t* hoff = nullptr;   // [ceil(nslice / kHaloSlices) + 1]
   int32_t* hcol = nullptr;
   uint16_t* lidx = nullptr;  // [nnz_sell]
+  int32_t* hrun = nullptr;   // [blocks * kHaloRunInts]: the lists as runs
   int32_t hmax = 0;          // longest list; 0: no halo layout
   // row-block distance whose lists share the most columns (a grid plane
   // for lexicographically ordered stencils); 1 when no longer one shares more

@@ -340,6 +340,35 @@ __global__ __launch_bounds__(kHaloThreads) void k_halo_pack(const int32_t* __res
   for (int q = threadIdx.x; q < H; q += kHaloThreads) hcol[h0 + q] = tmp[b * kHaloCap + q];
 }
 
+// Each block's list as runs of consecutive columns (one wave per block): a
+// run starts where a column is not its predecessor plus one; more than
+// kHaloRuns runs leave the count 0 and the list is read as it is
+__global__ __launch_bounds__(64) void k_halo_runs(const int32_t* __restrict__ lists,
+                                                  const int32_t* __restrict__ cnt,
+                                                  int32_t* __restrict__ hrun) {
+  const int64_t b = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int H = cnt[b];
+  const int32_t* L = lists + b * kHaloCap;
+  int32_t* out = hrun + b * kHaloRunInts;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int nr = 0;
+  for (int q0 = 0; q0 < H; q0 += 64) {
+    const int q = q0 + lane;
+    const bool brk = q < H && (q == 0 || L[q] != L[q - 1] + 1);
+    const unsigned long long m = __ballot(brk);
+    if (brk) {
+      const int r = nr + __popcll(m & below);
+      if (r < kHaloRuns) {
+        out[1 + 2 * r] = L[q];
+        out[2 + 2 * r] = q;
+      }
+    }
+    nr += __popcll(m);
+  }
+  if (lane == 0) out[0] = nr <= kHaloRuns ? nr : 0;
+}
+
 template <typename T>
 morx_status owned_alloc(morx_system sys, T** p, int64_t count) {
   DevBuf b;
@@ -472,6 +501,11 @@ morx_status build_halo(morx_system sys, Sell& sl, hipStream_t st, std::vector<De
   MORX_HIP(hipMemcpyAsync(sl.hoff, hoff.data(), (nrb + 1) * sizeof(int32_t),
                           hipMemcpyHostToDevice, st));
   k_halo_pack<<<(unsigned)nrb, kHaloThreads, 0, st>>>(sl.hoff, (int32_t*)lists.p, sl.hcol);
+  MORX_HIP(hipGetLastError());
+  MORX_TRY(owned_alloc(sys, &sl.hrun, nrb * kHaloRunInts));
+  MORX_HIP(hipMemsetAsync(sl.hrun, 0, (size_t)nrb * kHaloRunInts * sizeof(int32_t), st));
+  k_halo_runs<<<(unsigned)nrb, 64, 0, st>>>((const int32_t*)lists.p, (const int32_t*)cnt.p,
+                                            sl.hrun);
   MORX_HIP(hipGetLastError());
   MORX_TRY(halo_stride(sl, nrb, (const int32_t*)lists.p, hc, st));
   MORX_HIP(hipStreamSynchronize(st));  // hoff's host copy goes out of scope
