@@ -396,11 +396,12 @@ morx_status morx_irka(morx_system sys, int32_t r, double* sigmas, const double* 
  *                    them (1..16);
  *   slices_per_wave  iteration kernels: 64-row slices per wave (1..64; raised
  *                    to the least value that keeps <= 1024 row blocks);
- *   spmv_cols_per_wave  shifted pair (row-gather form) and true residual:
- *                    the same as cols_per_wave for the operator's loads
- *                    (1..16; -1 follows cols_per_wave); on the halo layout
- *                    the shifted pair runs as a pass of the chain kernel and
- *                    takes the chain's tile;
+ *   spmv_cols_per_wave  shifted pair and true residual: the same as
+ *                    cols_per_wave for the operator's loads (1..16; -1
+ *                    follows cols_per_wave); on the halo layout the shifted
+ *                    pair runs as a pass of the chain kernel, a block taking
+ *                    this many columns per chunk (A is read once per chunk;
+ *                    a chunk's staged vectors share the L2);
  *   chain_kernel     chain step: 0 gathers the input vectors row by row; 1
  *                    copies, per block of 256 rows, the input entries at the
  *                    block's distinct columns into LDS and sums from there (the

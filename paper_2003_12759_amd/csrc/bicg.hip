@@ -122,6 +122,7 @@ __device__ void build_plan(const IterArgs& a) {
   for (int s = threadIdx.x >> 6; s <= a.maxL; s += kFinThreads / 64) {
     const bool spmv = s == a.maxL;
     const int list = spmv ? a.lcap : s;
+    const int nv = spmv ? a.ncv_spmv : a.ncv;  // chunk width of this list
     const int fill = spmv ? a.plan_ld : min(a.plan_ld, a.ymax * a.ncv);
     ChainItem* out = a.plan + (int64_t)list * a.plan_ld;
     int pos = 0;
@@ -156,25 +157,26 @@ __device__ void build_plan(const IterArgs& a) {
         }
         pos += __popcll(m);
       }
-      const int pad = (a.ncv - pos % a.ncv) % a.ncv;
+      const int pad = (nv - pos % nv) % nv;
       if (lane < pad) out[pos + lane] = ChainItem{nullptr, nullptr, nullptr, -1, h};
       pos += pad;
     }
     for (int q = pos + lane; q < fill; q += 64) out[q] = ChainItem{nullptr, nullptr, nullptr, -1, 0};
-    if (lane == 0) a.plan_cnt[list] = pos / a.ncv;
+    if (lane == 0) a.plan_cnt[list] = pos / nv;
   }
   __syncthreads();
   // chunk summaries on each chunk's first pair (the same wave per step)
   for (int s = threadIdx.x >> 6; s <= a.maxL; s += kFinThreads / 64) {
     const int list = s == a.maxL ? a.lcap : s;
+    const int nv = s == a.maxL ? a.ncv_spmv : a.ncv;
     ChainItem* out = a.plan + (int64_t)list * a.plan_ld;
     const int nch = a.plan_cnt[list];
     for (int q = lane; q < nch; q += 64) {
-      ChainItem* ck = out + (int64_t)q * a.ncv;
+      ChainItem* ck = out + (int64_t)q * nv;
       const void* f0 = ck[0].fv;
       int ncol = 0;
       bool same = true;
-      for (int j = 0; j < a.ncv; ++j)
+      for (int j = 0; j < nv; ++j)
         if (ck[j].c >= 0) {
           ++ncol;
           same = same && ck[j].fv == f0;
@@ -195,10 +197,10 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(IterArgs a) {
   for (int c = threadIdx.x >> 6; c < a.nc; c += kFinThreads / 64) {
     ColInfo& ci = a.cols[c];
     if (ci.state != COL_ACTIVE) continue;
-    double tn[2], tr[3];
+    double tn[2], tr[2];
     wave_totals<2>(a, a.part_norm, c, tn);
-    wave_totals<3>(a, a.part_rho, c, tr);
-    const double rr = tn[0], rtrt = tn[1], rho = tr[0], zz = tr[1], r2 = tr[2];
+    wave_totals<2>(a, a.part_rho, c, tr);
+    const double rr = tn[0], rtrt = tn[1], rho = tr[0], zz = tr[1];
     if ((threadIdx.x & 63) == 0) {
       if (a.trace) {
         atomicAdd(&chain_cols, (double)ci.L);
@@ -210,7 +212,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_rho(IterArgs a) {
         ci.state = COL_CONVERGED;
       } else if (ci.it_cycle >= ci.maxit) {
         ci.state = COL_MAXIT;
-      } else if (fabs(rho) <= kBreakdown * sqrt(zz) * sqrt(r2)) {
+      } else if (fabs(rho) <= kBreakdown * sqrt(zz) * sqrt(rr)) {
         ci.state = COL_BREAKDOWN;
         ci.broke = 1;
       } else {
@@ -918,6 +920,10 @@ static IterArgs make_args(KrylovBatch& b, int nc, int maxL) {
   a.ncmax = sys->tune_nc > 0 ? (int)sys->tune_nc : kDefaultNC;
   a.ncmax_spmv = sys->tune_nc_spmv > 0 ? (int)sys->tune_nc_spmv : a.ncmax;
   a.ncv = pick_nc(nc, a.ncmax);
+  // the shifted pair's tile on the halo layout: A is read once per chunk of
+  // columns, and a chunk's staged vectors share the L2 (the autotuner weighs
+  // the two)
+  a.ncv_spmv = pick_nc(nc, a.ncmax_spmv);
   // chain grid: the most chunks of (half, column) pairs any step has, from
   // the chain lengths of the occupied slots; a batch whose slots change
   // between segments (serving) takes the bound for nc columns instead, so
@@ -1834,9 +1840,7 @@ static morx_status autotune_impl(morx_system sys, double sigma, int ncols, int c
   }
   sys->tune_chain = best_chain;
   // ... and the shifted pair's own tile with the chain shape and kernel fixed
-  // (the row-gather pair only: on the halo layout the pair runs as a pass of
-  // the chain kernel, at the chain tile)
-  if (s == MORX_OK && !halo_in_use(sys)) {
+  if (s == MORX_OK) {
     std::vector<int> seen{pick_nc(ncols, best_nc)};
     for (int ncs : {16, 8, 4, 2, 1}) {
       const int ncv = pick_nc(ncols, ncs);

@@ -4,5 +4,5 @@
 void chain_launch_f64(const IterArgs& a, hipStream_t st) { chain_launch_vt<double>(a, st); }
 
 void spmv_halo_launch(const IterArgs& a, int par, hipStream_t st) {
-  MORX_NC_DISPATCH(a.ncv, spmv_halo_run<NC>(a, par, st));
+  MORX_NC_DISPATCH(a.ncv_spmv, spmv_halo_run<NC>(a, par, st));
 }

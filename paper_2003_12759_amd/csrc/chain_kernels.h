@@ -54,6 +54,7 @@ struct IterArgs {
   int ncmax;       // most columns per wave, chain step
   int ncmax_spmv;  // most columns per wave, shifted pair and true residual
   int ncv;         // chain tile width of this launch sequence
+  int ncv_spmv;    // shifted pair on the halo layout: columns per block (chunks of its list)
   int ymax;        // chain launches: chunks of ncv (half, column) pairs in the grid
   int plan_ld;     // work-list entries per step
   int narrow;      // every slice of S and S^T at most kNarrow slots wide
@@ -70,7 +71,7 @@ struct IterArgs {
   int abytes;    // 8 or 4
   ColInfo* cols;
   const void* const* ftab;  // [2][cap][lcap]: factor values, forward then transposed order
-  double* part_rho;    // [3][cap][nblk]
+  double* part_rho;    // [2][cap][nblk] (room for 3)
   double* part_delta;  // [3][cap][nblk]
   double* part_norm;   // [2][cap][nblk]
   double* trace;       // [kTraceClasses] or null
@@ -242,7 +243,7 @@ __device__ __forceinline__ double chunk_dot_p(const SliceChunk& ch, const double
 // One chain step s applies, for every column whose chain is long enough,
 // factor s of the forward chain on the rows of S and factor maxL-1-s of the
 // transposed chain on the rows of S^T; the last step also forms the partial
-// sums of rho = z~^T r, ||z~||^2, ||r||^2.  The (half, column) pairs that
+// sums of rho = z~^T r and ||z~||^2.  The (half, column) pairs that
 // have work at a step come from the step's work list, built on the device by
 // the one-block kernels before the iteration (build_plan): blockIdx.y picks a
 // chunk of NC pairs of one half, so no block is launched for a column whose
@@ -306,9 +307,9 @@ __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s) {
     const int32_t* col = bwd ? a.colT : a.col;
     int32_t ow = bwd ? owB : owF;
     int wb = 0;
-    double v[RHO ? NC : 1][3];
+    double v[RHO ? NC : 1][2];
 #pragma unroll
-    for (int j = 0; j < (RHO ? NC : 1); ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
+    for (int j = 0; j < (RHO ? NC : 1); ++j) v[j][0] = v[j][1] = 0.0;
     if (nsl > 0) {
       // bounds of relative slice k; refills the window so that k and k+1 are in it
       auto bounds = [&](int k, int32_t& base, int32_t& w) {
@@ -389,7 +390,6 @@ __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s) {
                     const double ri = gld(vptr(a, V_R, it[j].c) + i);
                     v[j][0] = fma(zi, ri, v[j][0]);
                     v[j][1] = fma(zi, zi, v[j][1]);
-                    v[j][2] = fma(ri, ri, v[j][2]);
                   }
                 }
               }
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_step(IterArgs a, int s) {
         int cols[NC];
 #pragma unroll
         for (int j = 0; j < NC; ++j) cols[j] = it[j].c;
-        block_partials_cols<NC, 3>(a, t, cols, valid, v, a.part_rho);
+        block_partials_cols<NC, 2>(a, t, cols, valid, v, a.part_rho);
       }
     if (y + (int)gridDim.y >= nchunks) break;
   }
@@ -461,7 +461,7 @@ __device__ __forceinline__ void narrow_slice(const IterArgs& a, const WaveCtx& t
                                              const ChainItem* ck, int ncol, BufRes rcol,
                                              int32_t base, int w, int64_t i, int64_t fbytes,
                                              int64_t vbytes, bool rho_half,
-                                             double (&v)[RHO ? NC : 1][3]) {
+                                             double (&v)[RHO ? NC : 1][2]) {
   using FT = NarrowVal<VT>;
   constexpr uint32_t kVB = sizeof(VT), kAB = sizeof(AT);
   const uint32_t oi = (uint32_t)(base + t.lane) * 4u;
@@ -507,7 +507,6 @@ __device__ __forceinline__ void narrow_slice(const IterArgs& a, const WaveCtx& t
           const double zi = (double)zs, ri = rb[q];
           v[j][0] = fma(zi, ri, v[j][0]);
           v[j][1] = fma(zi, zi, v[j][1]);
-          v[j][2] = fma(ri, ri, v[j][2]);
         }
       }
     }
@@ -552,9 +551,9 @@ __global__ __launch_bounds__(kBlock) void k_chain_narrow(IterArgs a, int s) {
     const bool shared = (flags & 2) != 0;  // every pair of the chunk applies one factor
     const int ncol = flags >> 8;           // pairs of the chunk
     const bool rho_half = RHO && bwd;
-    double v[RHO ? NC : 1][3];  // per-lane rho partials of the chunk's pairs
+    double v[RHO ? NC : 1][2];  // per-lane rho partials of the chunk's pairs
 #pragma unroll
-    for (int j = 0; j < (RHO ? NC : 1); ++j) v[j][0] = v[j][1] = v[j][2] = 0.0;
+    for (int j = 0; j < (RHO ? NC : 1); ++j) v[j][0] = v[j][1] = 0.0;
     const int64_t nsell = bwd ? a.nsellT : a.nsell;
     const int64_t fbytes = nsell * (int64_t)sizeof(VT), vbytes = a.ld * (int64_t)sizeof(AT);
     const BufRes rcol = buf_res(bwd ? a.colT : a.col, nsell * 4);
@@ -585,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_narrow(IterArgs a, int s) {
           cols[j] = j < ncol ? ck[j].c : 0;
           if (j < ncol) valid |= 1u << j;
         }
-        block_partials_cols<NC, 3>(a, t, cols, valid, v, a.part_rho);
+        block_partials_cols<NC, 2>(a, t, cols, valid, v, a.part_rho);
         __syncthreads();  // the shared partials are reused by the next chunk
       }
     if (y + (int)gridDim.y >= nchunks) break;
@@ -630,12 +629,12 @@ __device__ __forceinline__ NarrowVal<VT> gload_stream(const VT* p) {
 
 // What a halo launch computes.  kHaloChain: one chain step (factor s
 // forward, factor maxL-1-s transposed); kHaloRho: the same, and its
-// transposed half also forms the partial sums of rho = z~^T r, ||z~||^2,
-// ||r||^2 (the iteration's last chain launch); kHaloSpmv: the shifted pair
+// transposed half also forms the partial sums of rho = z~^T r and ||z~||^2
+// (the iteration's last chain launch); kHaloSpmv: the shifted pair
 // q = (sigma E - A) p on the rows of S and q~ = (sigma E - A)^T p~ on the rows
 // of S^T, A's values taking the place of a factor shared by every column (p
-// of parity s & 1), with the partial sums of delta = p~^T q, ||p~||^2,
-// ||q||^2 on the forward half.
+// of parity s & 1), with the partial sums of delta = p~^T q and ||q||^2 on
+// the forward half.
 enum HaloMode : int { kHaloChain = 0, kHaloRho = 1, kHaloSpmv = 2 };
 
 // W: slots a slice may have (8 or W); HC: list cap (LDS entries)
@@ -680,9 +679,10 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
     const bool shared = SPMV || (flags & 2) != 0;
     const int ncol = flags >> 8;
     const bool part_half = (RHO && bwd) || (SPMV && !bwd);
-    // partial sums per pair: rho, ||z~||^2, ||r||^2 (last chain step), or
-    // delta = p~^T q and ||q||^2 (shifted pair; ||p~||^2 comes from form_p)
-    constexpr int NQ = SPMV ? 2 : 3;
+    // partial sums per pair: rho = z~^T r and ||z~||^2 (last chain step), or
+    // delta = p~^T q and ||q||^2 (shifted pair; ||p~||^2 comes from form_p);
+    // ||r||^2 comes from the update pass, which writes r
+    constexpr int NQ = 2;
     // (shifted pair) the list was built before this iteration's convergence
     // test: columns that have stopped since are skipped
     unsigned live = (1u << ncol) - 1u;
@@ -874,7 +874,6 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
                     const double ri = rr[c];
                     v[j][0] = fma(zi, ri, v[j][0]);
                     v[j][1] = fma(zi, zi, v[j][1]);
-                    v[j][NQ - 1] = fma(ri, ri, v[j][NQ - 1]);
                   }
                 }
               }
@@ -948,7 +947,8 @@ void chain_launch_vt(const IterArgs& a, hipStream_t st) {
 }  // namespace
 
 // The shifted pair on the halo layout (kHaloSpmv), p of parity par, columns
-// in chunks of a.ncv; the grid's y extent covers both halves of every column
+// in chunks of a.ncv_spmv; the grid's y extent covers both halves of every
+// column
 template <int NC>
 void spmv_halo_run(const IterArgs& a, int par, hipStream_t st) {
   const dim3 g((unsigned)a.nblk, (unsigned)(2 * ((a.nc + NC - 1) / NC)), 1);
