@@ -61,6 +61,9 @@ struct IterArgs {
   int hmax;        // chain step on the halo layout: longest list of S and S^T; 0: gathers
                    // (narrow patterns: the W = 8 kernel, lists of at most kHaloCapNarrow)
   int hstride;     // halo kernels: a block's row blocks are hstride apart (1: consecutive)
+  // chain steps without partial sums on the halo layout: their own, smaller
+  // row blocks (more workgroups than the partial-sum budget allows the others)
+  int spw_chain, nblk_chain, hstride_chain;
   const int32_t *hoff, *hcol, *hoffT, *hcolT;
   const int32_t *hrun, *hrunT;  // the lists as runs (kHaloRunInts per row block)
   const uint16_t *lidx, *lidxT;
@@ -919,13 +922,19 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
 template <typename VT, typename AT, int NC>
 void chain_run(const IterArgs& a, hipStream_t st) {
   const dim3 g((unsigned)a.nblk, (unsigned)a.ymax, 1);
+  // the steps before the last (no partial sums) on their own row blocks
+  IterArgs c = a;
+  c.spw = a.spw_chain;
+  c.nblk = a.nblk_chain;
+  c.hstride = a.hstride_chain;
+  const dim3 gc((unsigned)c.nblk, (unsigned)a.ymax, 1);
   if (a.hmax > 0 && a.narrow) {
     for (int s = 0; s + 1 < a.maxL; ++s)
-      k_chain_halo<VT, AT, NC, kHaloChain, kNarrow, kHaloCapNarrow><<<g, kBlock, 0, st>>>(a, s);
+      k_chain_halo<VT, AT, NC, kHaloChain, kNarrow, kHaloCapNarrow><<<gc, kBlock, 0, st>>>(c, s);
     k_chain_halo<VT, AT, NC, kHaloRho, kNarrow, kHaloCapNarrow><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
   } else if (a.hmax > 0) {
     for (int s = 0; s + 1 < a.maxL; ++s)
-      k_chain_halo<VT, AT, NC, kHaloChain, kHaloMaxW, kHaloCap><<<g, kBlock, 0, st>>>(a, s);
+      k_chain_halo<VT, AT, NC, kHaloChain, kHaloMaxW, kHaloCap><<<gc, kBlock, 0, st>>>(c, s);
     k_chain_halo<VT, AT, NC, kHaloRho, kHaloMaxW, kHaloCap><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
   } else if (a.narrow) {
     for (int s = 0; s + 1 < a.maxL; ++s) k_chain_narrow<VT, AT, NC, false><<<g, kBlock, 0, st>>>(a, s);
