@@ -1135,7 +1135,10 @@ morx_status factor_build_many(morx_system sys, int32_t prec, const FactorJob* jo
   }
   BlkShape bs{};
   if (cg > 0) {
-    const int ngrid = (int)std::min<int64_t>(sys->n, (int64_t)std::max(sys->ctx->num_cu, 1) * 32);
+    // many short-lived workgroups (about 16 columns each on the 27-point job):
+    // 512 per CU built the 12-shift set in 134 ms, 128 per CU in 136 ms, 32
+    // per CU in 141 ms, one per resident slot in 155 ms
+    const int ngrid = (int)std::min<int64_t>(sys->n, (int64_t)std::max(sys->ctx->num_cu, 1) * 512);
     int* fb_count = (int*)sb.p + 1;
 #define MORX_NE_LAUNCH(VT, CGV)                                                                 \
   do {                                                                                          \
