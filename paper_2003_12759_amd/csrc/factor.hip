@@ -988,8 +988,11 @@ static int ne_lanes(morx_system sys) {
 }
 
 // Waves per normal-equations block: the count whose resident blocks per CU
-// finish the most columns per unit of time, taking a column's set-up
-// (gathers, G0, H) to cost about one round of shifts
+// finish the most columns per unit of time.  A block's time per column is its
+// set-up (gathers, G0, H; shared by its waves) plus one round of shifts per
+// G of them; on the 27-point job (|J_k| = 27) the set-up measured 1.37 rounds
+// with one wave, about nw^-0.6 of that with nw (builds of 1, 4, 6 and 12
+// shifts: 96.6, 78.6, 85.0 and 133.6 ms at one, two, three and three waves)
 template <typename VT, int CG>
 static int ne_waves(int njobs, int maxT) {
   int best_nw = 1;
@@ -1002,7 +1005,7 @@ static int ne_waves(int njobs, int maxT) {
                                                      N.bytes) != hipSuccess)
       nb = 0;
     const int rounds = (njobs + N.G - 1) / N.G;
-    const double score = nb / (1.0 + rounds);
+    const double score = nb / (1.37 * pow((double)nw, -0.6) + rounds);
     if (score > best + 1e-9) {
       best = score;
       best_nw = nw;
