@@ -509,15 +509,16 @@ __global__ __launch_bounds__(kNeMaxWaves * 64, 4) void k_factor_ne(
         ++r;
       }
       const int l = r + q;
+      // Column r holds row J_r (its diagonal) and column l row J_l, so when
+      // either list ends the other's entries at those rows, if any, have been
+      // passed: the merge stops there.
       int x = coff[r], y = coff[l];
-      const int xe = coff[r + 1], ye = coff[l + 1];  // both columns hold their diagonal
+      const int xe = coff[r + 1], ye = coff[l + 1];
       const int jr = J[r], jl = J[l];
       double sg = 0.0, arl = 0.0, alr = 0.0;
-      while (x < xe || y < ye) {
-        const int xi = min(x, xe - 1), yi = min(y, ye - 1);
-        const int cx = crow[xi], cy = crow[yi];
-        const double vx = cval[xi], vy = cval[yi];
-        const int rx = x < xe ? cx : INT_MAX, ry = y < ye ? cy : INT_MAX;
+      while (x < xe && y < ye) {
+        const int rx = crow[x], ry = crow[y];
+        const double vx = cval[x], vy = cval[y];
         if (rx == ry) sg = fma(vx, vy, sg);
         if (ry == jr) arl = vy;
         if (rx == jl) alr = vx;
