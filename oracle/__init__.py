@@ -24,6 +24,9 @@ Projection based Model Order Reduction Algorithms":
 * ``projection`` -- two-sided Petrov-Galerkin projection and transfer functions
                     (Section II, interpolation of H and H').
 * ``job``        -- a whole multi-round shifted-solve job in the paper's order.
+* ``second_order`` -- AIRGA's solves (Algorithm 1, lines 4 and 10) for a
+                    proportionally damped second-order model, with the same
+                    reuse on its matrices ``s^2 M + s D + K``.
 
 Every floating-point step is IEEE FP64 unless a storage precision is asked for.
 Parity status of each function is stated in its module docstring.

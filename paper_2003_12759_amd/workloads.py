@@ -44,6 +44,9 @@ __all__ = [
     "make_workload",
     "ServingPool",
     "make_serving_pool",
+    "centered_convection",
+    "SecondOrderWorkload",
+    "make_second_order",
     "WORKLOAD_NAMES",
 ]
 
@@ -277,6 +280,92 @@ def make_workload(index: int, seed: int = 0, N: Optional[int] = None,
         return Workload(f"varcoef27_n{n}", A, e, B, C, [sig], prec or "bf16",
                         1e-10, len(sig), {"grid": N, "stencil": "27pt-varcoef"})
     raise ValueError("workload index must be 0, 1, 2 or 4 (3 is the serving pool)")
+
+
+def centered_convection(N: int, b=(20.0, 10.0, 5.0)) -> sp.csr_matrix:
+    """Skew-symmetric ``b . grad_h`` on an N^3 grid (central differences,
+    Dirichlet boundaries): row p holds ``+b_d / 2h`` at the upper and
+    ``-b_d / 2h`` at the lower neighbour in direction d."""
+    n = N**3
+    h = 1.0 / (N + 1)
+    idx, coords = _grid_coords(N, 3)
+    strides = (1, N, N * N)
+    rows, cols, vals = [], [], []
+    for d in range(3):
+        for sgn in (-1, 1):
+            ok = (coords[d] + sgn >= 0) & (coords[d] + sgn < N)
+            p = idx[ok]
+            rows.append(p)
+            cols.append(p + sgn * strides[d])
+            vals.append(np.full(p.size, sgn * b[d] / (2.0 * h)))
+    return _assemble(n, rows, cols, vals)
+
+
+@dataclasses.dataclass
+class SecondOrderWorkload:
+    """A proportionally damped second-order system ``M x'' + D x' + K x = F u``,
+    ``y = C^T x``, ``D = alpha M + beta K``, with a lumped (diagonal) mass
+    ``m``; ``rounds[z]`` are the expansion points of outer round z.  The
+    first-order system the solver is given is ``A = -K``, ``E = diag(m)``."""
+
+    name: str
+    K: sp.csr_matrix
+    m: np.ndarray
+    alpha: float
+    beta: float
+    F: np.ndarray
+    C: np.ndarray
+    rounds: List[np.ndarray]
+    prec: str
+    tol: float
+    meta: dict
+
+    @property
+    def n(self) -> int:
+        return self.K.shape[0]
+
+    @property
+    def A(self) -> sp.csr_matrix:
+        A = (-self.K).tocsr()
+        A.sort_indices()
+        A.indices = A.indices.astype(np.int32)
+        A.indptr = A.indptr.astype(np.int32)
+        return A
+
+
+def make_second_order(seed: int = 0, N: int = 106, nround: int = 2, npoint: int = 4,
+                      unit_io: bool = True, prec: str = "f64") -> SecondOrderWorkload:
+    """Stand-in for the disk-brake models of the AIRGA experiments: stiffness
+    ``K = K_E + K_R`` with ``K_E`` the 27-point variable-coefficient diffusion
+    operator (coefficients log-uniform in [0.1, 10]) and ``K_R`` a
+    skew-symmetric centred convection (the nonsymmetric part), lumped mass
+    uniform in [1, 2], the paper's damping ``alpha = 5e-2``, ``beta = 5e-6``,
+    ``npoint`` expansion points linearly spaced in [1, 500] (later rounds
+    jittered by up to 10 %), and ``F = C = e_1`` (``unit_io``) or standard
+    normal columns.  N = 106 gives n = 1,191,016, the size class of the
+    industrial model.  Draws: coefficient field, mass, F, C, point jitter."""
+    rng = np.random.default_rng(seed)
+    n = N**3
+    kappa = 10.0 ** rng.uniform(-1.0, 1.0, n)
+    KE = -varcoef_stencil(N, 3, 27, kappa)
+    K = (KE + centered_convection(N)).tocsr()
+    K.sum_duplicates()
+    K.sort_indices()
+    K.indices = K.indices.astype(np.int32)
+    K.indptr = K.indptr.astype(np.int32)
+    m = rng.uniform(1.0, 2.0, n)
+    if unit_io:
+        F = np.zeros((n, 1), order="F")
+        C = np.zeros((n, 1), order="F")
+        F[0, 0] = C[0, 0] = 1.0
+    else:
+        F, C = _blocks(rng, n, 1)
+    base = np.linspace(1.0, 500.0, npoint)
+    rounds = [base]
+    for _ in range(1, nround):
+        rounds.append(rounds[-1] * (1.0 + rng.uniform(-0.1, 0.1, npoint)))
+    return SecondOrderWorkload(f"airga_varcoef27_n{n}", K, m, 5e-2, 5e-6, F, C, rounds, prec,
+                               1e-10, {"grid": N, "stencil": "27pt-varcoef + skew 7pt"})
 
 
 @dataclasses.dataclass
