@@ -427,6 +427,61 @@ def projection_bench(args, w):
     ctx.close()
 
 
+def second_order_bench(args):
+    """AIRGA's solves on the proportionally damped second-order stand-in
+    (106^3, 27-point stiffness with a skew part, lumped mass, the paper's
+    alpha and beta, four points in [1, 500] and a jittered second round,
+    F = C = e_1): every round through morx_solve_second_order with
+    ``args.second_order`` moments per point, FP64 factors.  Prints one JSON
+    line with second-order solve pairs per second."""
+    import torch
+
+    from paper_2003_12759_amd import api
+    from paper_2003_12759_amd.workloads import make_second_order
+
+    w = make_second_order()
+    nmom = args.second_order
+    ctx = api.Context(0)
+    S = api.System(ctx, w.A, w.m)
+    Fd, Cd = api.block_to_dev(w.F), api.block_to_dev(w.C)
+    s0 = float(w.rounds[0][0])
+    sig0 = (s0 * s0 + w.alpha * s0) / (1.0 + w.beta * s0)
+    t0 = time.perf_counter()
+    tuned = S.autotune(sig0, ncols=len(w.rounds[0]))
+    tune_s = time.perf_counter() - t0
+
+    def job():
+        iters = []
+        for z, pts in enumerate(w.rounds):
+            _, _, st, stats = S.solve_second_order(w.alpha, w.beta, pts, Fd, Cd, nmom=nmom,
+                                                   next_round=z > 0)
+            if st != 0:
+                raise RuntimeError(f"second-order solve failed in round {z}: status {st}")
+            iters += [c.iters for c in stats]
+        return iters
+
+    for _ in range(args.warmup):
+        job()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        iters = job()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    nsolves = sum(len(r) for r in w.rounds) * nmom
+    line = {"metric": "second-order solve pairs per second", "value": round(nsolves / ms * 1e3, 3),
+            "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms, 2), "higher_is_better": True, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": w.name, "n": w.n, "points": [list(map(float, r)) for r in w.rounds],
+                       "alpha": w.alpha, "beta": w.beta, "moments": nmom, "prec": w.prec,
+                       "tol": w.tol},
+            "iters": iters, "autotune_s": round(tune_s, 3), "launch_shapes": tuned}
+    print(json.dumps(line), flush=True)
+    S.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -468,6 +523,9 @@ def main():
                     help="relative change of the shifts that ends the IRKA loop")
     ap.add_argument("--projection", type=int, default=0,
                     help="time only the projection, with this many basis columns")
+    ap.add_argument("--second-order", type=int, default=0,
+                    help="time only AIRGA's second-order solves (proportional damping) on the "
+                         "106^3 stand-in, with this many moments per point")
     ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=16, help="serving: slots per system")
     ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 1.0],
@@ -483,6 +541,9 @@ def main():
     from paper_2003_12759_amd import api, morx
     from paper_2003_12759_amd.workloads import make_workload
 
+    if args.second_order:
+        second_order_bench(args)
+        return
     if args.workload == "serving_pool16":
         serving_bench(args)
         return

@@ -291,6 +291,38 @@ morx_status morx_solve_moments(morx_system sys, int32_t nshift, const double* si
                                const morx_opts* opts, morx_col_stats* stats, void* stream);
 
 /*
+ * Second-order systems with proportional damping (Section II's AIRGA model
+ * M x'' + D x' + K x = F u, y = C^T x, D = alpha M + beta K; Algorithm 1,
+ * lines 4 and 10, with the preconditioner reuse of Section III-C): for the
+ * system created from A = -K and E = M (a lumped, i.e. diagonal, mass given
+ * as e_diag) and the npoint real expansion points points[] (host, chain
+ * order), with A(s) = s^2 M + s D + K,
+ *   X_0(i) = A(s_i)^{-1} F,       X_j(i) = -A(s_i)^{-1} M X_{j-1}(i),
+ *   Y_0(i) = A(s_i)^{-T} C,       Y_j(i) = -A(s_i)^{-T} M Y_{j-1}(i),
+ * for j < nmom (Algorithm 1 normalises each moment before the next solve;
+ * these are the unnormalised moments, with the same span).  Each point is
+ * solved as the first-order pair at sigma_i = (s_i^2 + alpha s_i) /
+ * (1 + beta s_i), since A(s) = (1 + beta s)(sigma E - A), by the batched
+ * path of morx_solve_moments, and moment j of point i is then scaled by
+ * (-1)^j (1 + beta s_i)^{-(j+1)}.  The SPAI and update factors of A(s_i)
+ * are those of sigma_i E - A times scalars, so the iterates, iteration
+ * counts and relative residuals (stats) are those of the paper's method on
+ * A(s_i).  Layout of F, C, X, Y, stats and the use of opts as in
+ * morx_solve_moments (F in place of B; points in place of sigmas; the
+ * system remembers sigma of the first point for opts->chain NEXT_ROUND).
+ * The Galerkin projection of Section II is morx_project with W = V: it
+ * returns Ar = -V^T K V and Er = V^T M V, so K^ = -Ar, M^ = Er and
+ * D^ = alpha Er - beta Ar.  MORX_E_NONFINITE for a non-finite alpha, beta
+ * or point; MORX_E_INVALID where 1 + beta s_i = 0 or sigma_i overflows;
+ * otherwise the statuses of morx_solve_moments.
+ */
+morx_status morx_solve_second_order(morx_system sys, double alpha, double beta, int32_t npoint,
+                                    const double* points, int32_t m, const double* F,
+                                    int64_t ldf, const double* C, int64_t ldc, int32_t nmom,
+                                    double* X, int64_t ldx, double* Y, int64_t ldy,
+                                    const morx_opts* opts, morx_col_stats* stats, void* stream);
+
+/*
  * Restarted GMRES(m), right-preconditioned (the solver of the paper's
  * experiments, Section IV; a comparator of morx_solve_shifts' BiCG on the
  * same factor chains, policy opts->chain).  Every system, the primal one with

@@ -135,6 +135,32 @@ class System:
                                             raise_on_error=raise_on_error)
         return X, Y, st, stats
 
+    def solve_second_order(self, alpha: float, beta: float, points: Sequence[float], F, C=None,
+                           nmom: int = 1, prec: str = "f64", tol: float = 1e-10,
+                           batched: bool = True, next_round: bool = False,
+                           raise_on_error: bool = True):
+        """AIRGA's solves on a system made from A = -K and E = M (diagonal):
+        ``X_0 = A(s)^{-1} F``, ``X_j = -A(s)^{-1} M X_{j-1}`` with
+        ``A(s) = s^2 M + s (alpha M + beta K) + K``, and the transposed ones
+        with C; returns (X, Y, status, stats) in solve_moments' layout."""
+        Fd = F if isinstance(F, torch.Tensor) else block_to_dev(F, self.device)
+        Cd = None
+        if C is not None:
+            Cd = C if isinstance(C, torch.Tensor) else block_to_dev(C, self.device)
+        m = Fd.shape[1]
+        npt = len(points)
+        X = morx.colmajor(nmom * m * npt, self.n, device=self.device)
+        Y = morx.colmajor(nmom * m * npt, self.n, device=self.device) if Cd is not None else None
+        o = morx.morx_opts_default()
+        o.tol = tol
+        o.precond_prec = morx.PREC[prec]
+        o.want_dual = 1 if Cd is not None else 0
+        o.batched = 1 if batched else 0
+        o.chain = morx.MORX_CHAIN_NEXT_ROUND if next_round else morx.MORX_CHAIN_RESET
+        st, stats = morx.morx_solve_second_order(self.handle, alpha, beta, points, Fd, Cd, nmom,
+                                                 X, Y, o, raise_on_error=raise_on_error)
+        return X, Y, st, stats
+
     def gmres_shifts(self, sigmas: Sequence[float], B, C=None, restart: int = 30,
                      prec: str = "f64", tol: float = 1e-10, policy: str = "reuse",
                      next_round: bool = False, max_restarts: int = 3, maxit: int = 0,

@@ -1596,6 +1596,78 @@ extern "C" morx_status morx_solve_moments(morx_system sys, int32_t nshift, const
                      Y, ldy, opts, stats, stream);
 }
 
+namespace {
+
+// X[:, c] *= f for the gridDim.y columns of a block
+__global__ __launch_bounds__(256) void k_scale_block(double* __restrict__ X, int64_t ld, int64_t n,
+                                                     double f) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  X[(int64_t)blockIdx.y * ld + i] *= f;
+}
+
+}  // namespace
+
+// With proportional damping the second-order matrix is a multiple of a
+// first-order one: s^2 M + s (alpha M + beta K) + K = c(s) (sigma(s) M + K),
+// c(s) = 1 + beta s, sigma(s) = (s^2 + alpha s) / c(s).  The system holds
+// E = M and A = -K, so every point is the first-order pair at sigma(s_i), and
+// moment j there, Z_j = (sigma E - A)^{-1} E Z_{j-1}, gives the second-order
+// one as X_j = (-1)^j c^{-(j+1)} Z_j (likewise Y_j).  Relative residuals are
+// invariant under that scaling.  The least-squares problems scale too: the
+// SPAI of c A_1 is P / c, and min ||c' A' - c A Q|| is solved by (c' / c) Q,
+// so every chain is the first-order chain times a positive or negative
+// scalar, and right-preconditioned BiCG runs the same iterates.
+extern "C" morx_status morx_solve_second_order(morx_system sys, double alpha, double beta,
+                                               int32_t npoint, const double* points, int32_t m,
+                                               const double* F, int64_t ldf, const double* C,
+                                               int64_t ldc, int32_t nmom, double* X, int64_t ldx,
+                                               double* Y, int64_t ldy, const morx_opts* opts,
+                                               morx_col_stats* stats, void* stream) {
+  const char* who = "morx_solve_second_order";
+  MORX_REQUIRE(sys, MORX_E_INVALID, "%s: null system", who);
+  MORX_REQUIRE(std::isfinite(alpha) && std::isfinite(beta), MORX_E_NONFINITE,
+               "%s: alpha and beta must be finite", who);
+  MORX_REQUIRE(npoint >= 1 && points && m >= 1 && nmom >= 1 &&
+                   (int64_t)nmom * npoint * m <= (1 << 20),
+               MORX_E_INVALID, "%s: need at least one point, column and moment", who);
+  std::vector<double> sig(npoint), cs(npoint);
+  for (int i = 0; i < npoint; ++i) {
+    const double s = points[i];
+    MORX_REQUIRE(std::isfinite(s), MORX_E_NONFINITE, "%s: point %d not finite", who, i);
+    cs[i] = 1.0 + beta * s;
+    MORX_REQUIRE(cs[i] != 0.0, MORX_E_INVALID, "%s: 1 + beta s is zero at point %d", who, i);
+    sig[i] = (s * s + alpha * s) / cs[i];
+    MORX_REQUIRE(std::isfinite(sig[i]), MORX_E_INVALID,
+                 "%s: the first-order shift of point %d overflows", who, i);
+  }
+  morx_opts o;
+  if (opts) o = *opts;
+  else morx_opts_default(&o);
+  const morx_status st = solve_entry(who, sys, npoint, sig.data(), m, F, ldf, C, ldc, nmom, X, ldx,
+                                     Y, ldy, &o, stats, stream);
+  // column statuses leave every result in place; other failures return as they are
+  if (st != MORX_OK && st != MORX_E_NOT_CONVERGED && st != MORX_E_BREAKDOWN) return st;
+  morx_ctx ctx = sys->ctx;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  MORX_HIP(hipSetDevice(ctx->device));
+  hipStream_t hs = (hipStream_t)stream;
+  const int64_t n = sys->n;
+  const dim3 grid((unsigned)((n + 255) / 256), (unsigned)m);
+  for (int j = 0; j < nmom; ++j)
+    for (int i = 0; i < npoint; ++i) {
+      const double f = (j % 2 ? -1.0 : 1.0) * std::pow(cs[i], -(double)(j + 1));
+      if (f == 1.0) continue;
+      const int64_t col = ((int64_t)j * npoint + i) * m;
+      k_scale_block<<<grid, 256, 0, hs>>>(X + col * ldx, ldx, n, f);
+      if (o.want_dual) k_scale_block<<<grid, 256, 0, hs>>>(Y + col * ldy, ldy, n, f);
+    }
+  MORX_HIP(hipGetLastError());
+  MORX_HIP(hipStreamSynchronize(hs));
+  return st;
+}
+
+
 // ---------------------------------------------------------------------------
 // launch shapes: get, set, autotune
 

@@ -124,6 +124,9 @@ _SIG = {
     "morx_solve_moments": (_i32, [_p, _i32, ctypes.POINTER(_d), _i32, _p, _i64, _p, _i64, _i32,
                                   _p, _i64, _p, _i64, ctypes.POINTER(morx_opts),
                                   ctypes.POINTER(morx_col_stats), _p]),
+    "morx_solve_second_order": (_i32, [_p, _d, _d, _i32, ctypes.POINTER(_d), _i32, _p, _i64, _p,
+                                       _i64, _i32, _p, _i64, _p, _i64, ctypes.POINTER(morx_opts),
+                                       ctypes.POINTER(morx_col_stats), _p]),
     "morx_gmres_shifts": (_i32, [_p, _i32, ctypes.POINTER(_d), _i32, _p, _i64, _p, _i64, _i32,
                                  _p, _i64, _p, _i64, ctypes.POINTER(morx_opts),
                                  ctypes.POINTER(morx_col_stats), _p]),
@@ -484,6 +487,32 @@ def morx_solve_moments(sys: int, sigmas: Sequence[float], B: torch.Tensor,
                                  ctypes.byref(opts), stats, _stream(stream))
     if raise_on_error and st != MORX_OK:
         raise MorxError(st, "morx_solve_moments")
+    return st, list(stats)
+
+
+def morx_solve_second_order(sys: int, alpha: float, beta: float, points: Sequence[float],
+                            F: torch.Tensor, C: Optional[torch.Tensor], nmom: int,
+                            X: torch.Tensor, Y: Optional[torch.Tensor],
+                            opts: Optional[morx_opts] = None, stream=None,
+                            raise_on_error: bool = True):
+    """Returns (status, list of morx_col_stats); X, Y hold nmom * len(points) * m columns."""
+    if opts is None:
+        opts = morx_opts_default()
+    pf, ldf, m = _block(F, "F")
+    px, ldx, _ = _block(X, "X")
+    if C is not None:
+        pc, ldc, _ = _block(C, "C")
+        py, ldy, _ = _block(Y, "Y")
+    else:
+        pc, ldc, py, ldy = None, F.shape[0], None, F.shape[0]
+    npt = len(points)
+    pts = (_d * npt)(*[float(s) for s in points])
+    stats = (morx_col_stats * (nmom * npt * m))()
+    st = _lib.morx_solve_second_order(sys, float(alpha), float(beta), npt, pts, m, pf, ldf, pc,
+                                      ldc, int(nmom), px, ldx, py, ldy, ctypes.byref(opts), stats,
+                                      _stream(stream))
+    if raise_on_error and st != MORX_OK:
+        raise MorxError(st, "morx_solve_second_order")
     return st, list(stats)
 
 
