@@ -24,11 +24,17 @@ them as in the first-order pair; the loop over points is read per point.
 * :func:`factors` -- SPAI of ``A(s_1)`` and the updates
   ``min ||A(s_{i-1}) - A(s_i) Q||_F`` column by column, on these matrices.
 * :func:`solve`   -- lines 4 and 10 by two-sided BiCG with those chains.
+* :func:`reduce`, :func:`transfer` -- Section II's Ritz-Galerkin reduced
+  model ``(V^T M V, V^T D V, V^T K V, V^T F, V^T C)`` and its transfer
+  function ``C^T A(s)^{-1} F``.
 
 Pinned by: the companion (first-order, 2n) linearisation of the model solved
 densely, and the modal closed form ``X_j = (-1)^j Phi d(s)^{-(j+1)} Phi^T F``
 for symmetric K (``K Phi = M Phi Lambda``, ``Phi^T M Phi = I``,
-``d(s) = s^2 + s(alpha + beta lambda) + lambda``) (tests/test_oracle_pins.py).
+``d(s) = s^2 + s(alpha + beta lambda) + lambda``), and for the reduction:
+interpolation of the full transfer function at the points whose solutions V
+spans, and the exact model for a complete basis
+(tests/test_oracle_second_order.py).
 """
 from __future__ import annotations
 
@@ -140,3 +146,30 @@ def solve(m, K, alpha, beta, F, C, rounds, nmom: int = 1, prec: str = "f64",
                     b, cc = -(m * res.x), -(m * res.y)
         out.append((X, Y, stats))
     return out
+
+
+def reduce(m, K, alpha, beta, F, C, V):
+    """Ritz-Galerkin reduction on the orthonormalised columns of V (Householder
+    QR): returns ``(Mh, Dh, Kh, Fh, Ch)`` with ``Dh = V^T D V``."""
+    Q, _ = np.linalg.qr(np.asarray(V, dtype=np.float64), mode="reduced")
+    m = np.asarray(m, dtype=np.float64)
+    K = sp.csr_matrix(K)
+    Mh = Q.T @ (m[:, None] * Q)
+    Kh = Q.T @ (K @ Q)
+    D = alpha * sp.diags(m) + beta * K
+    Dh = Q.T @ (D @ Q)
+    Fh = Q.T @ np.asarray(F, dtype=np.float64).reshape(m.size, -1)
+    Ch = Q.T @ np.asarray(C, dtype=np.float64).reshape(m.size, -1)
+    return Mh, Dh, Kh, Fh, Ch
+
+
+def transfer(Mh, Dh, Kh, Fh, Ch, s: float) -> np.ndarray:
+    """``Ch^T (s^2 Mh + s Dh + Kh)^{-1} Fh`` (dense)."""
+    return Ch.T @ np.linalg.solve(s * s * Mh + s * Dh + Kh, Fh)
+
+
+def full_transfer(m, K, alpha, beta, F, C, s: float) -> np.ndarray:
+    """``C^T A(s)^{-1} F`` by sparse LU."""
+    n = np.asarray(m).size
+    X = spla.splu(matrix(m, K, alpha, beta, s)).solve(np.asarray(F, dtype=np.float64).reshape(n, -1))
+    return np.asarray(C, dtype=np.float64).reshape(n, -1).T @ X

@@ -130,3 +130,25 @@ def test_second_order_full_size_unit_io(ctx):
             A = oso.matrix(w.m, w.K, w.alpha, w.beta, s).tocsr()
             assert residual_ok(A, Xg[:, i], w.F[:, 0]) and residual_ok(A.T, Yg[:, i], w.C[:, 0])
     S.close()
+
+
+def test_galerkin_projection_interpolates_the_second_order_transfer_function(ctx):
+    """Section II's reduction through morx_project with W = V: K^ = -Ar,
+    M^ = Er, D^ = alpha Er - beta Ar, F^ = Br, C^ = Cr; the reduced
+    H(s) = C^T (s^2 M^ + s D^ + K^)^{-1} F^ equals the full one at every point
+    (the basis spans the GPU's solutions there)."""
+    from paper_2003_12759_amd import api
+
+    w = make_second_order(N=10, nround=1, npoint=4, unit_io=False)
+    S = api.System(ctx, w.A, w.m)
+    pts = list(w.rounds[0])
+    _say(f"second order projection n={w.n}")
+    X, _, st, _ = S.solve_second_order(w.alpha, w.beta, pts, w.F, None)
+    assert st == 0
+    Ar, Er, Br, Cr = S.project(X, X, api.block_to_dev(w.F), api.block_to_dev(w.C))
+    Kh, Mh, Dh = -Ar, Er, w.alpha * Er - w.beta * Ar
+    for s in pts:
+        full = oso.full_transfer(w.m, w.K, w.alpha, w.beta, w.F, w.C, s)
+        red = oso.transfer(Mh, Dh, Kh, Br, Cr, s)
+        assert abs(red - full).max() <= 1e-8 * abs(full).max(), s
+    S.close()

@@ -156,3 +156,25 @@ def test_preconditioned_solve_matches_direct():
                 assert np.linalg.norm(cc - A.T @ Y[:, k]) <= 1e-10 * np.linalg.norm(cc)
                 cond = np.linalg.cond(A.toarray())
                 assert np.linalg.norm(X[:, k] - Xd[:, k]) <= 4e-10 * cond * np.linalg.norm(Xd[:, k])
+
+
+def test_reduction_interpolates_at_the_points_and_is_exact_on_a_full_basis():
+    """Galerkin with V spanning A(s_i)^{-1} F interpolates H(s) = C^T A(s)^{-1} F at
+    every s_i (and only there, in general); a complete basis reproduces H
+    everywhere; and V^T D V = alpha M^ + beta K^."""
+    n, alpha, beta = 40, 0.3, 0.02
+    K, m, F, C = _model(n, 17)
+    pts = [0.5, 2.0, 5.0]
+    X, _ = so.direct(m, K, alpha, beta, F, C, pts)
+    Mh, Dh, Kh, Fh, Ch = so.reduce(m, K, alpha, beta, F, C, X)
+    assert np.allclose(Dh, alpha * Mh + beta * Kh, rtol=1e-12, atol=1e-12 * abs(Kh).max())
+    for s in pts:
+        full = so.full_transfer(m, K, alpha, beta, F, C, s)
+        red = so.transfer(Mh, Dh, Kh, Fh, Ch, s)
+        assert abs(red - full).max() <= 1e-10 * abs(full).max(), s
+    off = so.full_transfer(m, K, alpha, beta, F, C, 1.1)
+    assert abs(so.transfer(Mh, Dh, Kh, Fh, Ch, 1.1) - off).max() > 1e-8 * abs(off).max()
+    full_basis = so.reduce(m, K, alpha, beta, F, C, np.eye(n))
+    for s in (0.3, 1.1, 7.0):
+        full = so.full_transfer(m, K, alpha, beta, F, C, s)
+        assert abs(so.transfer(*full_basis, s) - full).max() <= 1e-10 * abs(full).max()
