@@ -519,6 +519,9 @@ def main():
                          "(one system at a time, the paper's solver)")
     ap.add_argument("--irka", type=int, default=0,
                     help="also run the IRKA-style shift loop for at most this many rounds")
+    ap.add_argument("--irka-tangential", type=int, default=0,
+                    help="also run the MIMO (tangential) IRKA-style loop on all of B's columns "
+                         "(C = B) for at most this many rounds")
     ap.add_argument("--irka-tol", type=float, default=1e-4,
                     help="relative change of the shifts that ends the IRKA loop")
     ap.add_argument("--projection", type=int, default=0,
@@ -745,6 +748,34 @@ def main():
               "mode": "IRKA (Algorithm 2 shift update), c = b, r = shifts per round"}
         print(f"[irka] {ik['status']} rounds={rounds} {dt_:.2f} s", file=sys.stderr, flush=True)
 
+    ikt = None
+    if args.irka_tangential > 0:
+        # the MIMO (tangential) loop from the workload's first-round shifts on
+        # all of B's columns with C = B and equal seeded initial directions (a
+        # symmetric operator then has real reduced poles)
+        import numpy as np
+
+        m = w.B.shape[1]
+        d0 = np.random.default_rng(5).standard_normal((m, len(w.rounds[0])))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st_, res = S.irka_tangential(list(w.rounds[0]), Bd, Bd, d0, d0,
+                                     max_rounds=args.irka_tangential, shift_tol=args.irka_tol,
+                                     prec=w.prec, tol=w.tol, raise_on_error=False)
+        torch.cuda.synchronize()
+        dt_ = time.perf_counter() - t1
+        rounds = res["rounds"]
+        r = len(w.rounds[0])
+        ikt = {"status": morx.morx_status_str(st_), "rounds": rounds,
+               "shift_tol": args.irka_tol, "final_change": res["change"],
+               "seconds": round(dt_, 3),
+               "pairs_per_s": round(rounds * r / dt_, 3) if rounds else None,
+               "shifts": [round(x, 6) for x in res["sigmas"]],
+               "iters_last_round": sum(x.iters for x in res["stats"]),
+               "mode": f"tangential IRKA, m = q = {m}, C = B, r = shifts per round"}
+        print(f"[irka-tangential] {ikt['status']} rounds={rounds} {dt_:.2f} s", file=sys.stderr,
+              flush=True)
+
     cpu = None
     if sample is not None:
         from oracle import chain as ochain
@@ -791,6 +822,8 @@ def main():
         out["gmres"] = gm
     if ik is not None:
         out["irka"] = ik
+    if ikt is not None:
+        out["irka_tangential"] = ikt
     print(json.dumps(out), flush=True)
     S.close()
     ctx.close()

@@ -291,6 +291,22 @@ morx_status morx_solve_moments(morx_system sys, int32_t nshift, const double* si
                                const morx_opts* opts, morx_col_stats* stats, void* stream);
 
 /*
+ * One right-hand side per shift (the tangential solves of Algorithm 2, lines 4
+ * and 5, in the linear case): for the nshift shifts sigmas[] (host, chain
+ * order), column i of B (dev, n x nshift, ldb) and of C (dev, likewise; NULL
+ * when opts->want_dual == 0) belong to shift i only, and
+ *   (sigma_i E - A) x_i = b_i,   (sigma_i E - A)^T y_i = c_i
+ * are solved in one batch with the chains of morx_solve_shifts (policy
+ * opts->chain; the factors are built in one launch).  X, Y (dev, n x nshift)
+ * and stats (host, nshift entries) are in shift order.  Statuses as
+ * morx_solve_shifts.
+ */
+morx_status morx_solve_pairs(morx_system sys, int32_t nshift, const double* sigmas,
+                             const double* B, int64_t ldb, const double* C, int64_t ldc, double* X,
+                             int64_t ldx, double* Y, int64_t ldy, const morx_opts* opts,
+                             morx_col_stats* stats, void* stream);
+
+/*
  * Second-order systems with proportional damping (Section II's AIRGA model
  * M x'' + D x' + K x = F u, y = C^T x, D = alpha M + beta K; Algorithm 1,
  * lines 4 and 10, with the preconditioner reuse of Section III-C): for the
@@ -408,6 +424,35 @@ morx_status morx_irka(morx_system sys, int32_t r, double* sigmas, const double* 
                       double* Ar, double* Er, double* Br, double* Cr, double* poles_re,
                       double* poles_im, int32_t* rounds, double* change, morx_col_stats* stats,
                       void* stream);
+
+/*
+ * The MIMO (tangential) form of the IRKA-style loop: Algorithm 2 (BIRKA)
+ * without its bilinear terms for B (dev, n x m, ldb) and C (dev, n x q, ldc).
+ * Round z solves, for each shift sigma_i and its directions bdir_i (m) and
+ * cdir_i (q), (sigma_i E - A) v_i = B bdir_i and (sigma_i E - A)^T w_i =
+ * C cdir_i in one batch (morx_solve_pairs; round 1 under opts->chain, RESET or
+ * NEXT_ROUND, later rounds under NEXT_ROUND), projects with the
+ * orthonormalised V = [v_i] and W = [w_i] (morx_project), and diagonalises
+ * the reduced matrix Er^{-1} Ar = R diag(lambda) R^{-1} (line 3; eigenvalues
+ * as morx_pencil_eigvals, eigenvectors by inverse iteration on the host):
+ * the next shifts are -lambda_i, the next bdir_i row i of R^{-1} Er^{-1} Br
+ * and cdir_i column i of Cr^T R, each scaled to unit length with its largest
+ * entry positive (the scaling leaves the subspaces alone), in ascending shift
+ * order.  Stopping and errors as morx_irka.  sigmas (host, r), bdir (host,
+ * m x r column-major: column i for shift i) and cdir (host, q x r) hold the
+ * initial shifts and directions on entry and those of the last model
+ * projected on return (nonzero directions; shifts distinct); Ar, Er (host,
+ * r x r), Br (host, r x m), Cr (host, r x q) that model, column-major;
+ * poles_re/poles_im, rounds, change and stats (r entries, may be null) as
+ * morx_irka.  r 1..64, m and q 1..64.
+ */
+morx_status morx_irka_tangential(morx_system sys, int32_t r, double* sigmas, int32_t m,
+                                 const double* B, int64_t ldb, int32_t q, const double* C,
+                                 int64_t ldc, double* bdir, double* cdir, int32_t max_rounds,
+                                 double tol, const morx_opts* opts, double* Ar, double* Er,
+                                 double* Br, double* Cr, double* poles_re, double* poles_im,
+                                 int32_t* rounds, double* change, morx_col_stats* stats,
+                                 void* stream);
 
 /*
  * Launch shapes of a system's kernels (the batching extension: the tile and

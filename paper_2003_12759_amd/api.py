@@ -205,6 +205,41 @@ class System:
                               cd.reshape(-1).contiguous(), max_rounds, shift_tol, o,
                               raise_on_error=raise_on_error)
 
+    def solve_pairs(self, sigmas: Sequence[float], B, C=None, prec: str = "f64",
+                    tol: float = 1e-10, batched: bool = True, next_round: bool = False,
+                    raise_on_error: bool = True):
+        """Column i of B (and C) is the right-hand side of shift i only; returns
+        (X, Y, status, stats) in shift order."""
+        Bd = B if isinstance(B, torch.Tensor) else block_to_dev(B, self.device)
+        Cd = None
+        if C is not None:
+            Cd = C if isinstance(C, torch.Tensor) else block_to_dev(C, self.device)
+        ns = len(sigmas)
+        X = morx.colmajor(ns, self.n, device=self.device)
+        Y = morx.colmajor(ns, self.n, device=self.device) if Cd is not None else None
+        o = morx.morx_opts_default()
+        o.tol = tol
+        o.precond_prec = morx.PREC[prec]
+        o.want_dual = 1 if Cd is not None else 0
+        o.batched = 1 if batched else 0
+        o.chain = morx.MORX_CHAIN_NEXT_ROUND if next_round else morx.MORX_CHAIN_RESET
+        st, stats = morx.morx_solve_pairs(self.handle, sigmas, Bd, Cd, X, Y, o,
+                                          raise_on_error=raise_on_error)
+        return X, Y, st, stats
+
+    def irka_tangential(self, sigmas: Sequence[float], B, C, bdir, cdir, max_rounds: int = 20,
+                        shift_tol: float = 1e-6, prec: str = "f64", tol: float = 1e-10,
+                        raise_on_error: bool = True):
+        """The MIMO (tangential) IRKA-style loop; returns (status, result dict)
+        as morx.morx_irka_tangential."""
+        Bd = B if isinstance(B, torch.Tensor) else block_to_dev(B, self.device)
+        Cd = C if isinstance(C, torch.Tensor) else block_to_dev(C, self.device)
+        o = morx.morx_opts_default()
+        o.tol = tol
+        o.precond_prec = morx.PREC[prec]
+        return morx.morx_irka_tangential(self.handle, sigmas, Bd, Cd, bdir, cdir, max_rounds,
+                                         shift_tol, o, raise_on_error=raise_on_error)
+
     def autotune(self, sigma: float, ncols: int, chain_len: int = 1, prec: str = "f64") -> dict:
         """Time the launch-shape candidates on this system and keep the fastest."""
         return morx.morx_autotune(self.handle, sigma, ncols, chain_len, prec)

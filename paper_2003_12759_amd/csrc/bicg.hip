@@ -1415,21 +1415,26 @@ void commit_chains(morx_system sys, const ChainPlan& plan, const double* sigmas,
 // E times moment j-1 as right-hand sides.  The factors and chains (policy
 // o.chain) are built once and serve every moment.  X holds moment j of
 // column c of shift i at column (j * nshift + i) * m + c (Y, stats alike).
+// per_shift: column i of B and C is the right-hand side of shift i only (m = 1,
+// nmom = 1); otherwise every shift takes all m columns
 static morx_status solve_shifts_impl(morx_system sys, int32_t nshift, const double* sigmas,
                                      int32_t m, const double* B, int64_t ldb, const double* C,
                                      int64_t ldc, int32_t nmom, double* X, int64_t ldx, double* Y,
                                      int64_t ldy, const morx_opts& o, morx_col_stats* stats,
                                      hipStream_t st, std::vector<morx_factor>& horizontal,
-                                     std::vector<morx_factor>& fresh) {
+                                     std::vector<morx_factor>& fresh, bool per_shift = false) {
   const bool want_dual = o.want_dual != 0;
   const int prec = o.precond_prec;
   MORX_REQUIRE(sys->ls_supported, MORX_E_UNSUPPORTED,
                "factor pattern exceeds the local least-squares limits");
+  MORX_REQUIRE(!per_shift || (m == 1 && nmom == 1), MORX_E_INVALID,
+               "per-shift right-hand sides take one column and one moment");
   // right-hand-side norms decide how each column pair runs
-  std::vector<double> norms(2 * m, 0.0);
-  MORX_TRY(rhs_norms(sys, B, ldb, m, norms.data(), st));
-  if (want_dual) MORX_TRY(rhs_norms(sys, C, ldc, m, norms.data() + m, st));
-  for (int j = 0; j < 2 * m; ++j)
+  const int nrhs = per_shift ? nshift : m;
+  std::vector<double> norms(2 * nrhs, 0.0);
+  MORX_TRY(rhs_norms(sys, B, ldb, nrhs, norms.data(), st));
+  if (want_dual) MORX_TRY(rhs_norms(sys, C, ldc, nrhs, norms.data() + nrhs, st));
+  for (int j = 0; j < 2 * nrhs; ++j)
     MORX_REQUIRE(std::isfinite(norms[j]), MORX_E_NONFINITE, "B or C holds NaN or Inf");
 
   ChainPlan plan;
@@ -1453,8 +1458,9 @@ static morx_status solve_shifts_impl(morx_system sys, int32_t nshift, const doub
   std::vector<double> nb(nm), nc(nm, 0.0);  // per (shift, column) of the current moment
   for (int i = 0; i < nshift; ++i)
     for (int c = 0; c < m; ++c) {
-      nb[i * m + c] = norms[c];
-      nc[i * m + c] = want_dual ? norms[m + c] : 0.0;
+      const int k = per_shift ? i : c;
+      nb[i * m + c] = norms[k];
+      nc[i * m + c] = want_dual ? norms[nrhs + k] : 0.0;
     }
   auto trivial = [&](int64_t k) { return nb[k] == 0.0 && (!want_dual || nc[k] == 0.0); };
   morx_status s = MORX_OK;
@@ -1477,9 +1483,10 @@ static morx_status solve_shifts_impl(morx_system sys, int32_t nshift, const doub
     }
     auto col = [&](int i, int c) -> BatchCol {
       const int64_t k = (int64_t)i * m + c;
-      const double* b = mom == 0 ? B + (int64_t)c * ldb : (const double*)rb.p + k * sys->n_pad;
+      const int64_t j = per_shift ? i : c;  // the right-hand-side column
+      const double* b = mom == 0 ? B + j * ldb : (const double*)rb.p + k * sys->n_pad;
       const double* cc = !want_dual ? nullptr
-                         : mom == 0 ? C + (int64_t)c * ldc
+                         : mom == 0 ? C + j * ldc
                                     : (const double*)rc.p + k * sys->n_pad;
       return pair_col(sigmas[i], &chains[i], b, cc, nb[k], nc[k], want_dual, Xm + k * ldx,
                       Ym ? Ym + k * ldy : nullptr, Sm ? &Sm[k] : nullptr);
@@ -1538,7 +1545,7 @@ static morx_status solve_entry(const char* who, morx_system sys, int32_t nshift,
                                const double* sigmas, int32_t m, const double* B, int64_t ldb,
                                const double* C, int64_t ldc, int32_t nmom, double* X, int64_t ldx,
                                double* Y, int64_t ldy, const morx_opts* opts,
-                               morx_col_stats* stats, void* stream) {
+                               morx_col_stats* stats, void* stream, bool per_shift = false) {
   MORX_REQUIRE(sys, MORX_E_INVALID, "%s: null system", who);
   morx_opts o;
   if (opts) o = *opts;
@@ -1569,7 +1576,7 @@ static morx_status solve_entry(const char* who, morx_system sys, int32_t nshift,
   std::vector<morx_factor> horizontal, fresh;
   morx_status s = solve_shifts_impl(sys, nshift, sigmas, m, B, ldb, want_dual ? C : nullptr, ldc,
                                     nmom, X, ldx, want_dual ? Y : nullptr, ldy, o, stats,
-                                    ctx->stream, horizontal, fresh);
+                                    ctx->stream, horizontal, fresh, per_shift);
   hipStreamSynchronize(ctx->stream);
   for (morx_factor f : horizontal) factor_release(f);
   for (morx_factor f : fresh) factor_release(f);
@@ -1594,6 +1601,15 @@ extern "C" morx_status morx_solve_moments(morx_system sys, int32_t nshift, const
                                           void* stream) {
   return solve_entry("morx_solve_moments", sys, nshift, sigmas, m, B, ldb, C, ldc, nmom, X, ldx,
                      Y, ldy, opts, stats, stream);
+}
+
+extern "C" morx_status morx_solve_pairs(morx_system sys, int32_t nshift, const double* sigmas,
+                                        const double* B, int64_t ldb, const double* C, int64_t ldc,
+                                        double* X, int64_t ldx, double* Y, int64_t ldy,
+                                        const morx_opts* opts, morx_col_stats* stats,
+                                        void* stream) {
+  return solve_entry("morx_solve_pairs", sys, nshift, sigmas, 1, B, ldb, C, ldc, 1, X, ldx, Y, ldy,
+                     opts, stats, stream, true);
 }
 
 namespace {

@@ -4,7 +4,10 @@
 // link carried from one round to the next), projects (morx_project), and
 // takes the next shifts as the mirror images -lambda_i of the eigenvalues of
 // the reduced pencil (Ar, Er) (line 3 of Algorithm 2: the eigendecomposition
-// of the reduced matrix).  The r x r eigenvalue problem runs on the host:
+// of the reduced matrix).  The MIMO form takes from the same
+// eigendecomposition the tangential directions of the next round's
+// right-hand sides (one per shift, solved by morx_solve_pairs), its
+// eigenvectors found by inverse iteration.  The r x r eigenvalue problem runs on the host:
 // Er^{-1} Ar by LU with partial pivoting, Householder reduction to upper
 // Hessenberg form, then Francis double-shift QR steps with deflation
 // (J. G. F. Francis, "The QR transformation", Computer J. 4 (1961-62); the
@@ -231,6 +234,132 @@ morx_status pencil_eigs(int r, const double* Ar, const double* Er, double* wr, d
   return MORX_OK;
 }
 
+// LU with partial pivoting of the row-major r x r matrix M, in place; pivots
+// smaller than tiny are set to tiny (inverse iteration factors the matrix at
+// an eigenvalue, where a pivot vanishes)
+void lu_factor(int r, std::vector<double>& M, std::vector<int>& piv, double tiny) {
+  piv.resize(r);
+  for (int k = 0; k < r; ++k) {
+    int p = k;
+    for (int i = k + 1; i < r; ++i)
+      if (fabs(M[(size_t)i * r + k]) > fabs(M[(size_t)p * r + k])) p = i;
+    piv[k] = p;
+    if (p != k)
+      for (int j = 0; j < r; ++j) std::swap(M[(size_t)p * r + j], M[(size_t)k * r + j]);
+    double& d = M[(size_t)k * r + k];
+    if (fabs(d) < tiny) d = d < 0.0 ? -tiny : tiny;
+    for (int i = k + 1; i < r; ++i) {
+      const double f = M[(size_t)i * r + k] / d;
+      M[(size_t)i * r + k] = f;
+      for (int j = k + 1; j < r; ++j) M[(size_t)i * r + j] -= f * M[(size_t)k * r + j];
+    }
+  }
+}
+
+// x <- M^{-1} x with the factors of lu_factor
+void lu_solve(int r, const std::vector<double>& LU, const std::vector<int>& piv, double* x) {
+  for (int k = 0; k < r; ++k) {
+    std::swap(x[k], x[piv[k]]);
+    for (int i = k + 1; i < r; ++i) x[i] -= LU[(size_t)i * r + k] * x[k];
+  }
+  for (int i = r - 1; i >= 0; --i) {
+    double t = x[i];
+    for (int j = i + 1; j < r; ++j) t -= LU[(size_t)i * r + j] * x[j];
+    x[i] = t / LU[(size_t)i * r + i];
+  }
+}
+
+// unit length, largest-magnitude entry positive
+void normalise_dir(double* v, int len) {
+  double nrm = 0.0, big = 0.0;
+  int at = 0;
+  for (int i = 0; i < len; ++i) {
+    nrm += v[i] * v[i];
+    if (fabs(v[i]) > big) {
+      big = fabs(v[i]);
+      at = i;
+    }
+  }
+  nrm = sqrt(nrm);
+  if (!(nrm > 0.0)) return;
+  const double f = (v[at] < 0.0 ? -1.0 : 1.0) / nrm;
+  for (int i = 0; i < len; ++i) v[i] *= f;
+}
+
+// Tangential directions of the reduced model (column-major Ar, Er (r x r),
+// Br (r x m), Cr (r x q)) at its real eigenvalues lam[0..r): with
+// Er^{-1} Ar = R diag(lam) R^{-1} (R's columns by inverse iteration),
+// bdir_i = row i of R^{-1} Er^{-1} Br and cdir_i = column i of Cr^T R
+morx_status tangent_dirs(int r, int m, int q, const double* Ar, const double* Er,
+                         const double* Br, const double* Cr, const double* lam, double* bdir,
+                         double* cdir) {
+  std::vector<double> H;
+  MORX_REQUIRE(pencil_to_standard(r, Ar, Er, H), MORX_E_INVALID, "reduced pencil: Er is singular");
+  double hn = 0.0;
+  for (double v : H) hn = std::max(hn, fabs(v));
+  std::vector<double> R((size_t)r * r), M((size_t)r * r), x(r);
+  std::vector<int> piv;
+  for (int i = 0; i < r; ++i) {
+    M = H;
+    for (int d = 0; d < r; ++d) M[(size_t)d * r + d] -= lam[i];
+    lu_factor(r, M, piv, 1e-14 * std::max(hn, fabs(lam[i])));
+    for (int d = 0; d < r; ++d) x[d] = 1.0 + 0.01 * d;
+    for (int it = 0; it < 3; ++it) {
+      lu_solve(r, M, piv, x.data());
+      double nrm = 0.0;
+      for (double v : x) nrm += v * v;
+      nrm = sqrt(nrm);
+      MORX_REQUIRE(std::isfinite(nrm) && nrm > 0.0, MORX_E_NOT_CONVERGED,
+                   "reduced pencil: inverse iteration failed at eigenvalue %d", i);
+      for (double& v : x) v /= nrm;
+    }
+    for (int d = 0; d < r; ++d) R[(size_t)d * r + i] = x[d];  // row-major, column i
+  }
+  // Er^{-1} Br, then R^{-1} of that
+  std::vector<double> Ef((size_t)r * r), Rf(R);
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < r; ++j) Ef[(size_t)i * r + j] = Er[(size_t)j * r + i];
+  std::vector<int> pe, pr;
+  lu_factor(r, Ef, pe, 1e-300);
+  lu_factor(r, Rf, pr, 1e-300);
+  for (int k = 0; k < m; ++k) {
+    for (int d = 0; d < r; ++d) x[d] = Br[(size_t)k * r + d];
+    lu_solve(r, Ef, pe, x.data());
+    lu_solve(r, Rf, pr, x.data());
+    for (int i = 0; i < r; ++i) bdir[(size_t)i * m + k] = x[i];
+  }
+  for (int i = 0; i < r; ++i)
+    for (int k = 0; k < q; ++k) {
+      double t = 0.0;
+      for (int d = 0; d < r; ++d) t += Cr[(size_t)k * r + d] * R[(size_t)d * r + i];
+      cdir[(size_t)i * q + k] = t;
+    }
+  for (int i = 0; i < r; ++i) {
+    normalise_dir(bdir + (size_t)i * m, m);
+    normalise_dir(cdir + (size_t)i * q, q);
+    for (int k = 0; k < m; ++k)
+      MORX_REQUIRE(std::isfinite(bdir[(size_t)i * m + k]), MORX_E_NOT_CONVERGED,
+                   "reduced pencil: eigenvector matrix is singular");
+    for (int k = 0; k < q; ++k)
+      MORX_REQUIRE(std::isfinite(cdir[(size_t)i * q + k]), MORX_E_NOT_CONVERGED,
+                   "reduced pencil: eigenvector matrix is singular");
+  }
+  return MORX_OK;
+}
+
+// out[:, j] = M dir_j for the r columns j (M: n x k, dir: k x r column-major)
+__global__ __launch_bounds__(256) void k_tangent(const double* __restrict__ M, int64_t ldm, int k,
+                                                 const double* __restrict__ dir,
+                                                 double* __restrict__ out, int64_t ldo,
+                                                 int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int j = blockIdx.y;
+  double s = 0.0;
+  for (int c = 0; c < k; ++c) s = fma(M[(int64_t)c * ldm + i], dir[(int64_t)j * k + c], s);
+  out[(int64_t)j * ldo + i] = s;
+}
+
 }  // namespace
 
 extern "C" morx_status morx_pencil_eigvals(int32_t r, const double* Ar, const double* Er,
@@ -329,5 +458,148 @@ extern "C" morx_status morx_irka(morx_system sys, int32_t r, double* sigmas, con
   if (stats)
     for (int i = 0; i < r; ++i) stats[i] = st[i];
   dev_free(xy);
+  return s;
+}
+
+extern "C" morx_status morx_irka_tangential(morx_system sys, int32_t r, double* sigmas,
+                                            int32_t m, const double* B, int64_t ldb, int32_t q,
+                                            const double* C, int64_t ldc, double* bdir,
+                                            double* cdir, int32_t max_rounds, double tol,
+                                            const morx_opts* opts, double* Ar, double* Er,
+                                            double* Br, double* Cr, double* poles_re,
+                                            double* poles_im, int32_t* rounds, double* change,
+                                            morx_col_stats* stats, void* stream) {
+  const char* who = "morx_irka_tangential";
+  MORX_REQUIRE(sys && sigmas && B && C && bdir && cdir && Ar && Er && Br && Cr && poles_re &&
+                   poles_im && rounds && change,
+               MORX_E_INVALID, "%s: null argument", who);
+  MORX_REQUIRE(r >= 1 && r <= 64 && m >= 1 && m <= 64 && q >= 1 && q <= 64, MORX_E_INVALID,
+               "%s: r, m and q must be 1..64", who);
+  MORX_REQUIRE(ldb >= sys->n && ldc >= sys->n, MORX_E_INVALID, "%s: bad leading dimension", who);
+  MORX_REQUIRE(max_rounds >= 1, MORX_E_INVALID, "%s: max_rounds must be >= 1", who);
+  MORX_REQUIRE(tol >= 0.0 && std::isfinite(tol), MORX_E_INVALID, "%s: bad tolerance", who);
+  morx_opts o;
+  if (opts) o = *opts;
+  else morx_opts_default(&o);
+  MORX_REQUIRE(o.chain == MORX_CHAIN_RESET || o.chain == MORX_CHAIN_NEXT_ROUND, MORX_E_INVALID,
+               "%s: the rounds keep Algorithm 4's vertical chain (RESET or NEXT_ROUND)", who);
+  // shifts ascending, each with its directions
+  std::vector<int> ord(r);
+  for (int i = 0; i < r; ++i) {
+    ord[i] = i;
+    MORX_REQUIRE(std::isfinite(sigmas[i]), MORX_E_NONFINITE, "%s: shift not finite", who);
+  }
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return sigmas[a] < sigmas[b]; });
+  std::vector<double> sig(r), bd((size_t)r * m), cd((size_t)r * q);
+  for (int i = 0; i < r; ++i) {
+    sig[i] = sigmas[ord[i]];
+    double nb = 0.0, nc = 0.0;
+    for (int k = 0; k < m; ++k) {
+      bd[(size_t)i * m + k] = bdir[(size_t)ord[i] * m + k];
+      nb += fabs(bd[(size_t)i * m + k]);
+    }
+    for (int k = 0; k < q; ++k) {
+      cd[(size_t)i * q + k] = cdir[(size_t)ord[i] * q + k];
+      nc += fabs(cd[(size_t)i * q + k]);
+    }
+    MORX_REQUIRE(std::isfinite(nb) && std::isfinite(nc), MORX_E_NONFINITE,
+                 "%s: direction not finite", who);
+    MORX_REQUIRE(nb > 0.0 && nc > 0.0, MORX_E_INVALID, "%s: zero direction", who);
+  }
+  for (int i = 1; i < r; ++i)
+    MORX_REQUIRE(sig[i] > sig[i - 1], MORX_E_INVALID, "%s: shifts must be distinct", who);
+  const int64_t n = sys->n;
+  MORX_HIP(hipSetDevice(sys->ctx->device));
+  hipStream_t hs = (hipStream_t)stream;
+  DevBuf buf;
+  MORX_TRY(dev_alloc(buf, ((size_t)4 * r * n + (size_t)r * (m + q)) * sizeof(double)));
+  double* X = (double*)buf.p;
+  double* Y = X + (int64_t)r * n;
+  double* Bt = Y + (int64_t)r * n;
+  double* Ct = Bt + (int64_t)r * n;
+  double* ddir = Ct + (int64_t)r * n;
+  std::vector<morx_col_stats> st(r);
+  std::vector<double> wr(r), wi(r), lam(r), nbd((size_t)r * m), ncd((size_t)r * q);
+  morx_status s = MORX_OK;
+  *rounds = 0;
+  *change = INFINITY;
+  const dim3 grid((unsigned)((n + 255) / 256), (unsigned)r);
+  for (int z = 1; z <= max_rounds; ++z) {
+    // right-hand sides B bdir_i and C cdir_i
+    if (hipMemcpyAsync(ddir, bd.data(), bd.size() * sizeof(double), hipMemcpyHostToDevice, hs) !=
+            hipSuccess ||
+        hipMemcpyAsync(ddir + (size_t)r * m, cd.data(), cd.size() * sizeof(double),
+                       hipMemcpyHostToDevice, hs) != hipSuccess) {
+      morx_set_error("%s: copying the directions failed", who);
+      s = MORX_E_HIP;
+      break;
+    }
+    k_tangent<<<grid, 256, 0, hs>>>(B, ldb, m, ddir, Bt, n, n);
+    k_tangent<<<grid, 256, 0, hs>>>(C, ldc, q, ddir + (size_t)r * m, Ct, n, n);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(hs) != hipSuccess) {
+      morx_set_error("%s: forming the right-hand sides failed", who);
+      s = MORX_E_HIP;
+      break;
+    }
+    morx_opts oz = o;
+    oz.want_dual = 1;
+    if (z > 1) oz.chain = MORX_CHAIN_NEXT_ROUND;
+    s = morx_solve_pairs(sys, r, sig.data(), Bt, n, Ct, n, X, n, Y, n, &oz, st.data(), stream);
+    if (s != MORX_OK) break;
+    s = morx_project(sys, r, X, n, Y, n, m, B, ldb, q, C, ldc, Ar, Er, Br, Cr, 1, stream);
+    if (s != MORX_OK) break;
+    *rounds = z;
+    for (int i = 0; i < r; ++i) sigmas[i] = sig[i];
+    memcpy(bdir, bd.data(), bd.size() * sizeof(double));
+    memcpy(cdir, cd.data(), cd.size() * sizeof(double));
+    s = pencil_eigs(r, Ar, Er, wr.data(), wi.data());
+    if (s != MORX_OK) break;
+    for (int i = 0; i < r; ++i) {
+      poles_re[i] = wr[i];
+      poles_im[i] = wi[i];
+    }
+    double amax = 0.0, imax = 0.0;
+    for (int i = 0; i < r; ++i) {
+      amax = std::max(amax, hypot(wr[i], wi[i]));
+      imax = std::max(imax, fabs(wi[i]));
+    }
+    if (imax > 1e-10 * amax) {
+      morx_set_error("%s: the reduced pencil has a complex pole pair in round %d "
+                     "(real shifts only)", who, z);
+      s = MORX_E_UNSUPPORTED;
+      break;
+    }
+    // next shifts: the mirror images, ascending; lam[i] the pole of shift i
+    std::vector<double> next(r);
+    for (int i = 0; i < r; ++i) {
+      lam[i] = wr[r - 1 - i];
+      next[i] = -lam[i];
+    }
+    double ch = 0.0;
+    for (int i = 0; i < r; ++i) ch = std::max(ch, fabs(next[i] - sig[i]) / fabs(sig[i]));
+    *change = ch;
+    if (ch <= tol) break;
+    if (z == max_rounds) {
+      morx_set_error("%s: shifts still moving after %d rounds (relative change %.3g)", who, z, ch);
+      s = MORX_E_NOT_CONVERGED;
+      break;
+    }
+    bool distinct = true;
+    for (int i = 1; i < r; ++i) distinct = distinct && next[i] > next[i - 1];
+    if (!distinct) {
+      morx_set_error("%s: repeated mirror images in round %d", who, z);
+      s = MORX_E_UNSUPPORTED;
+      break;
+    }
+    s = tangent_dirs(r, m, q, Ar, Er, Br, Cr, lam.data(), nbd.data(), ncd.data());
+    if (s != MORX_OK) break;
+    sig = next;
+    bd = nbd;
+    cd = ncd;
+  }
+  if (stats)
+    for (int i = 0; i < r; ++i) stats[i] = st[i];
+  hipStreamSynchronize(hs);
+  dev_free(buf);
   return s;
 }

@@ -143,6 +143,15 @@ _SIG = {
                          ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
                          ctypes.POINTER(_i32), ctypes.POINTER(_d), ctypes.POINTER(morx_col_stats),
                          _p]),
+    "morx_irka_tangential": (_i32, [_p, _i32, ctypes.POINTER(_d), _i32, _p, _i64, _i32, _p, _i64,
+                                    ctypes.POINTER(_d), ctypes.POINTER(_d), _i32, _d,
+                                    ctypes.POINTER(morx_opts), ctypes.POINTER(_d),
+                                    ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
+                                    ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_i32),
+                                    ctypes.POINTER(_d), ctypes.POINTER(morx_col_stats), _p]),
+    "morx_solve_pairs": (_i32, [_p, _i32, ctypes.POINTER(_d), _p, _i64, _p, _i64, _p, _i64, _p,
+                                _i64, ctypes.POINTER(morx_opts), ctypes.POINTER(morx_col_stats),
+                                _p]),
     "morx_system_get_tune": (_i32, [_p, ctypes.POINTER(morx_tune)]),
     "morx_chain_kernel_name": (_i32, [_p, _i32, _i32, _i32, ctypes.c_char_p, _i32]),
     "morx_system_set_tune": (_i32, [_p, ctypes.POINTER(morx_tune)]),
@@ -640,6 +649,73 @@ def morx_irka(sys: int, sigmas: Sequence[float], b: torch.Tensor, c: torch.Tenso
                 "Br": np.array(Br[:]).reshape(r, 1), "Cr": np.array(Cr[:]).reshape(r, 1),
                 "poles": np.array(pr[:]) + 1j * np.array(pi[:]), "rounds": rounds.value,
                 "change": change.value, "stats": list(stats)}
+
+
+def morx_solve_pairs(sys: int, sigmas: Sequence[float], B: torch.Tensor,
+                     C: Optional[torch.Tensor], X: torch.Tensor, Y: Optional[torch.Tensor],
+                     opts: Optional[morx_opts] = None, stream=None, raise_on_error: bool = True):
+    """Column i of B and C belongs to shift i; returns (status, list of morx_col_stats)."""
+    if opts is None:
+        opts = morx_opts_default()
+    pb, ldb, _ = _block(B, "B")
+    px, ldx, _ = _block(X, "X")
+    if C is not None:
+        pc, ldc, _ = _block(C, "C")
+        py, ldy, _ = _block(Y, "Y")
+    else:
+        pc, ldc, py, ldy = None, B.shape[0], None, B.shape[0]
+    ns = len(sigmas)
+    sig = (_d * ns)(*[float(s) for s in sigmas])
+    stats = (morx_col_stats * ns)()
+    st = _lib.morx_solve_pairs(sys, ns, sig, pb, ldb, pc, ldc, px, ldx, py, ldy,
+                               ctypes.byref(opts), stats, _stream(stream))
+    if raise_on_error and st != MORX_OK:
+        raise MorxError(st, "morx_solve_pairs")
+    return st, list(stats)
+
+
+def morx_irka_tangential(sys: int, sigmas: Sequence[float], B: torch.Tensor, C: torch.Tensor,
+                         bdir, cdir, max_rounds: int = 20, tol: float = 1e-6,
+                         opts: Optional[morx_opts] = None, stream=None,
+                         raise_on_error: bool = True):
+    """bdir (m x r) and cdir (q x r): column i the directions of shift i.
+    Returns (status, dict): sigmas, bdir, cdir, Ar, Er, Br (r x m), Cr (r x q),
+    poles (complex), rounds, change, stats (the last round's)."""
+    import numpy as np
+
+    if opts is None:
+        opts = morx_opts_default()
+    r = len(sigmas)
+    pb, ldb, m = _block(B, "B")
+    pc, ldc, q = _block(C, "C")
+    bd = np.asfortranarray(np.asarray(bdir, dtype=np.float64).reshape(m, r))
+    cd = np.asfortranarray(np.asarray(cdir, dtype=np.float64).reshape(q, r))
+    sig = (_d * r)(*[float(x) for x in sigmas])
+    bb = (_d * (m * r))(*bd.ravel(order="F"))
+    cb = (_d * (q * r))(*cd.ravel(order="F"))
+    Ar = (_d * (r * r))()
+    Er = (_d * (r * r))()
+    Br = (_d * (r * m))()
+    Cr = (_d * (r * q))()
+    pr = (_d * r)()
+    pi = (_d * r)()
+    rounds = _i32(0)
+    change = _d(0.0)
+    stats = (morx_col_stats * r)()
+    st = _lib.morx_irka_tangential(sys, r, sig, m, pb, ldb, q, pc, ldc, bb, cb, int(max_rounds),
+                                   float(tol), ctypes.byref(opts), Ar, Er, Br, Cr, pr, pi,
+                                   ctypes.byref(rounds), ctypes.byref(change), stats,
+                                   _stream(stream))
+    if raise_on_error and st != MORX_OK:
+        raise MorxError(st, "morx_irka_tangential")
+
+    def mat(buf, rows, cols):
+        return np.frombuffer(buf, dtype=np.float64, count=rows * cols).reshape(cols, rows).T.copy()
+
+    return st, {"sigmas": np.array(sig[:]), "bdir": mat(bb, m, r), "cdir": mat(cb, q, r),
+                "Ar": mat(Ar, r, r), "Er": mat(Er, r, r), "Br": mat(Br, r, m),
+                "Cr": mat(Cr, r, q), "poles": np.array(pr[:]) + 1j * np.array(pi[:]),
+                "rounds": rounds.value, "change": change.value, "stats": list(stats)}
 
 
 def morx_trace_enable(ctx: int, enable: bool) -> None:

@@ -144,3 +144,100 @@ def test_irka_rejects_bad_arguments(ctx):
         morx.morx_irka(S.handle, [1.0, 10.0], bd, bd, opts=o)
     assert ei.value.status == MORX_E_INVALID
     S.close()
+
+
+def test_solve_pairs_one_right_hand_side_per_shift(ctx):
+    """morx_solve_pairs: every pair against sparse LU (host true residuals
+    <= 1e-10, solutions to 1e-8), and with every column equal to b the same
+    bits and iteration counts as morx_solve_shifts with b."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+
+    from host_residual import residual_ok
+    from paper_2003_12759_amd import api
+
+    w = make_workload(1, N=10)  # nonsymmetric convection-diffusion, n = 1000
+    sig = list(w.rounds[0][:5])
+    rng = np.random.default_rng(4)
+    Bt = np.asfortranarray(rng.standard_normal((w.n, len(sig))))
+    Ct = np.asfortranarray(rng.standard_normal((w.n, len(sig))))
+    S = api.System(ctx, w.A, w.e)
+    _say(f"solve_pairs n={w.n} shifts={len(sig)}")
+    X, Y, st, stats = S.solve_pairs(sig, Bt, Ct)
+    assert st == 0 and all(c.status == 0 for c in stats)
+    Xg, Yg = X.cpu().numpy(), Y.cpu().numpy()
+    E = sp.diags(w.e)
+    for i, s in enumerate(sig):
+        M = (s * E - w.A).tocsc()
+        assert residual_ok(M, Xg[:, i], Bt[:, i]) and residual_ok(M.T, Yg[:, i], Ct[:, i])
+        lu = spla.splu(M)
+        xr, yr = lu.solve(Bt[:, i]), lu.solve(Ct[:, i], trans="T")
+        assert np.linalg.norm(Xg[:, i] - xr) <= 1e-8 * np.linalg.norm(xr)
+        assert np.linalg.norm(Yg[:, i] - yr) <= 1e-8 * np.linalg.norm(yr)
+    rep_b = np.asfortranarray(np.repeat(w.B[:, :1], len(sig), axis=1))
+    rep_c = np.asfortranarray(np.repeat(w.C[:, :1], len(sig), axis=1))
+    X1, Y1, _, s1 = S.solve_pairs(sig, rep_b, rep_c)
+    X2, Y2, _, s2 = S.solve_shifts(sig, w.B[:, :1], w.C[:, :1])
+    assert torch.equal(X1, X2) and torch.equal(Y1, Y2)
+    assert [c.iters for c in s1] == [c.iters for c in s2]
+    S.close()
+
+
+def test_irka_tangential_matches_the_oracle_loop(ctx):
+    """MIMO (4 inputs, C = B, symmetric operator, equal initial left and right
+    directions: real reduced poles): converged shifts, directions and round
+    count against the oracle's tangential loop, and the bitangential
+    interpolation conditions of the GPU's model against the full transfer
+    function."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+
+    from paper_2003_12759_amd import api
+
+    w = make_workload(2, N=6)  # n = 216
+    rng = np.random.default_rng(5)
+    r = 4
+    d0 = rng.standard_normal((4, r))
+    sig0 = np.geomspace(1.0, 5000.0, r)
+    ref = oirka.run_tangential(w.A, w.e, w.B, w.B, sig0, d0, d0, max_rounds=100, tol=1e-8)
+    assert ref.status == "converged"
+    S = api.System(ctx, w.A, w.e)
+    _say("irka tangential vs oracle, n=216, r=4, m=4")
+    st, res = S.irka_tangential(sig0, w.B, w.B, d0, d0, max_rounds=100, shift_tol=1e-8)
+    assert st == 0
+    assert abs(res["rounds"] - ref.rounds) <= 1, (res["rounds"], ref.rounds)
+    assert np.allclose(res["sigmas"], ref.sigmas, rtol=1e-6, atol=0)
+    assert np.allclose(res["bdir"], ref.bdir, atol=1e-5)
+    assert np.allclose(res["cdir"], ref.cdir, atol=1e-5)
+    assert np.all(res["poles"].imag == 0.0)
+    E = sp.diags(w.e)
+    for i, s in enumerate(res["sigmas"]):
+        lu = spla.splu((s * E - w.A).tocsc())
+        Xf = lu.solve(w.B)
+        H = w.B.T @ Xf
+        dH = -w.B.T @ lu.solve(w.e[:, None] * Xf)
+        Mr = s * res["Er"] - res["Ar"]
+        Xr = np.linalg.solve(Mr, res["Br"])
+        Hr = res["Cr"].T @ Xr
+        dHr = -res["Cr"].T @ np.linalg.solve(Mr, res["Er"] @ Xr)
+        b, c = res["bdir"][:, i], res["cdir"][:, i]
+        assert np.allclose(Hr @ b, H @ b, rtol=1e-7, atol=1e-9 * abs(H).max())
+        assert np.allclose(c @ Hr, c @ H, rtol=1e-7, atol=1e-9 * abs(H).max())
+        assert abs(c @ dHr @ b - c @ dH @ b) <= 1e-6 * abs(dH).max()
+    for c_ in res["stats"]:
+        assert c_.status == 0 and c_.relres_primal <= 1e-10 and c_.relres_dual <= 1e-10
+    S.close()
+
+
+def test_irka_tangential_rejects_bad_arguments(ctx):
+    from paper_2003_12759_amd import api, morx
+
+    w = make_workload(2, N=5)
+    S = api.System(ctx, w.A, w.e)
+    d = np.ones((4, 3))
+    _say("irka tangential argument checks")
+    for sig, bd in (([1.0, 1.0, 2.0], d), ([1.0, 2.0, 3.0], np.zeros((4, 3)))):
+        with pytest.raises(morx.MorxError) as ei:
+            S.irka_tangential(sig, w.B, w.B, bd, d)
+        assert ei.value.status == MORX_E_INVALID
+    S.close()
