@@ -256,12 +256,12 @@ void lu_factor(int r, std::vector<double>& M, std::vector<int>& piv, double tiny
   }
 }
 
-// x <- M^{-1} x with the factors of lu_factor
+// x <- M^{-1} x with the factors of lu_factor (P M = L U, the interchanges
+// applied to whole rows, so all of them come before the forward substitution)
 void lu_solve(int r, const std::vector<double>& LU, const std::vector<int>& piv, double* x) {
-  for (int k = 0; k < r; ++k) {
-    std::swap(x[k], x[piv[k]]);
+  for (int k = 0; k < r; ++k) std::swap(x[k], x[piv[k]]);
+  for (int k = 0; k < r; ++k)
     for (int i = k + 1; i < r; ++i) x[i] -= LU[(size_t)i * r + k] * x[k];
-  }
   for (int i = r - 1; i >= 0; --i) {
     double t = x[i];
     for (int j = i + 1; j < r; ++j) t -= LU[(size_t)i * r + j] * x[j];

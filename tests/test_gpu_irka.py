@@ -241,3 +241,28 @@ def test_irka_tangential_rejects_bad_arguments(ctx):
             S.irka_tangential(sig, w.B, w.B, bd, d)
         assert ei.value.status == MORX_E_INVALID
     S.close()
+
+
+def test_irka_tangential_directions_follow_the_reduced_model(ctx):
+    """Round 2's directions are those of round 1's model: against the oracle's
+    residue directions (LAPACK eigenvectors) from the model the GPU returned
+    after one round, at eight shifts of a 4-input system (the host's
+    eigenvector and LU routines pivot there)."""
+    from paper_2003_12759_amd import api
+
+    w = make_workload(2, N=12)  # n = 1728
+    rng = np.random.default_rng(5)
+    sig0 = list(w.rounds[0])
+    d0 = rng.standard_normal((4, len(sig0)))
+    S = api.System(ctx, w.A, w.e)
+    _say("irka tangential directions, n=1728, r=8")
+    st1, one = S.irka_tangential(sig0, w.B, w.B, d0, d0, max_rounds=1, shift_tol=0.0,
+                                 raise_on_error=False)
+    assert one["rounds"] == 1
+    _, sig, bd, cd = oirka.tangent_directions(one["Ar"], one["Er"], one["Br"], one["Cr"])
+    st2, two = S.irka_tangential(sig0, w.B, w.B, d0, d0, max_rounds=2, shift_tol=0.0,
+                                 raise_on_error=False)
+    assert two["rounds"] == 2
+    assert np.allclose(two["sigmas"], sig, rtol=1e-9, atol=0)
+    assert np.allclose(two["bdir"], bd, atol=1e-8) and np.allclose(two["cdir"], cd, atol=1e-8)
+    S.close()
