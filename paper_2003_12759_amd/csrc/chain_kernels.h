@@ -674,13 +674,35 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
   const ChainItem* plan = a.plan + (int64_t)list * a.plan_ld;
   const int nchunks = gld(a.plan_cnt + list);
   const uint32_t vbytes = (uint32_t)(a.ld * (int64_t)sizeof(AT));
+  // A narrow chain step without partial sums walks every chunk of its half
+  // inside each row block (grid y = the half), so that the row block's local
+  // indices, list and shared factor values are loaded once for all of the
+  // half's columns (the wide form keeps one chunk per grid row: walking costs
+  // it registers past three waves per SIMD); the other modes take one chunk
+  // per grid row.  The list holds the forward chunks first.
+  constexpr bool WALK = MODE == kHaloChain && W == kNarrow;
+  int nfwd = 0;
+  if constexpr (WALK) {
+    for (int q = 0; q < nchunks; ++q) nfwd += (gld(&plan[(int64_t)q * NC].flags) & 1) == 0;
+    nfwd = __builtin_amdgcn_readfirstlane(nfwd);
+  }
+  const int ngroups = WALK ? 2 : nchunks;
   for (int y = blockIdx.y;; y += gridDim.y) {
-    const ChainItem* ck = plan + (int64_t)y * NC;
+    if (y >= ngroups) break;  // uniform over the block
+    const int g0 = WALK ? (y == 0 ? 0 : nfwd) : y;
+    const int g1 = WALK ? (y == 0 ? nfwd : nchunks) : y + 1;
+    if (g0 >= g1) {
+      if (y + (int)gridDim.y >= ngroups) break;
+      continue;
+    }
+    const ChainItem* ck = plan + (int64_t)g0 * NC;
     if (ck->c < 0) break;  // past the last chunk (uniform over the block)
-    const int flags = ck->flags;
+    int flags = ck->flags;
     const bool bwd = (flags & 1) != 0;
-    const bool shared = SPMV || (flags & 2) != 0;
-    const int ncol = flags >> 8;
+    // (shared) the group's first chunk's factor, loaded once per row block
+    const bool gshared = SPMV || (flags & 2) != 0;
+    bool shared = gshared;
+    int ncol = flags >> 8;
     const bool part_half = (RHO && bwd) || (SPMV && !bwd);
     // partial sums per pair: rho = z~^T r and ||z~||^2 (last chain step), or
     // delta = p~^T q and ||q||^2 (shifted pair; ||p~||^2 comes from form_p);
@@ -776,13 +798,33 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
       }
 #pragma unroll
       for (int m = 0; m < W; ++m) fb[m] = (FT)0;
-      if (shared) {
+      if (gshared) {
         const VT* fp = fv0 + base + t.lane;
 #pragma unroll
         for (int m = 0; m < W; ++m) {
           const FT r = gload_stream<VT>(fp + m * kSlice);
           fb[m] = m < w ? r : (FT)0;
         }
+      }
+      bool fb_ok = gshared;  // fb holds the values of fv0
+      for (int yc = g0; yc < g1; ++yc) {
+      if constexpr (WALK) {
+        ck = plan + (int64_t)yc * NC;
+        flags = ck->flags;
+        ncol = flags >> 8;
+        // a chunk whose pairs share fv0 reads fb; any other reads its pairs'
+        // own values (which overwrite fb)
+        shared = (flags & 2) != 0 && uniform(ck->fv) == (const void*)fv0;
+        if (shared && !fb_ok) {
+          const VT* fp = fv0 + base + t.lane;
+#pragma unroll
+          for (int m = 0; m < W; ++m) {
+            const FT r = gload_stream<VT>(fp + m * kSlice);
+            fb[m] = m < w ? r : (FT)0;
+          }
+          fb_ok = true;
+        }
+        if (!shared) fb_ok = false;
       }
 #pragma unroll
       for (int j0 = 0; j0 < NC; j0 += CB) {
@@ -885,6 +927,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
         }
         __syncthreads();  // before the next round overwrites the LDS copies
       }
+      }  // chunks of the group
     }
     if constexpr (PART)
       if (part_half) {
@@ -899,7 +942,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
         else block_partials_cols<NC, NQ>(a, t, cols, valid, v, a.part_rho);
         __syncthreads();  // the shared partials are reused by the next chunk
       }
-    if (y + (int)gridDim.y >= nchunks) break;
+    if (y + (int)gridDim.y >= ngroups) break;
   }
 }
 
@@ -928,9 +971,10 @@ void chain_run(const IterArgs& a, hipStream_t st) {
   c.nblk = a.nblk_chain;
   c.hstride = a.hstride_chain;
   const dim3 gc((unsigned)c.nblk, (unsigned)a.ymax, 1);
+  const dim3 gw((unsigned)c.nblk, 2u, 1);  // the narrow halo chain steps walk their half's chunks
   if (a.hmax > 0 && a.narrow) {
     for (int s = 0; s + 1 < a.maxL; ++s)
-      k_chain_halo<VT, AT, NC, kHaloChain, kNarrow, kHaloCapNarrow><<<gc, kBlock, 0, st>>>(c, s);
+      k_chain_halo<VT, AT, NC, kHaloChain, kNarrow, kHaloCapNarrow><<<gw, kBlock, 0, st>>>(c, s);
     k_chain_halo<VT, AT, NC, kHaloRho, kNarrow, kHaloCapNarrow><<<g, kBlock, 0, st>>>(a, a.maxL - 1);
   } else if (a.hmax > 0) {
     for (int s = 0; s + 1 < a.maxL; ++s)
