@@ -160,6 +160,7 @@ __device__ void build_plan(const IterArgs& a) {
       const int pad = (nv - pos % nv) % nv;
       if (lane < pad) out[pos + lane] = ChainItem{nullptr, nullptr, nullptr, -1, h};
       pos += pad;
+      if (h == 0 && lane == 0) a.plan_cnt[a.lcap + 1 + list] = pos / nv;  // forward chunks
     }
     for (int q = pos + lane; q < fill; q += 64) out[q] = ChainItem{nullptr, nullptr, nullptr, -1, 0};
     if (lane == 0) a.plan_cnt[list] = pos / nv;
@@ -806,7 +807,8 @@ void krylov_batch_delete(KrylovBatch* kb) {
 static int plan_ld(int cap) { return 2 * cap + 2 * kMaxNC; }
 // lcap chain-step lists and the shifted pair's, then their chunk counts
 static size_t plan_bytes(int cap, int lcap) {
-  return (size_t)(lcap + 1) * plan_ld(cap) * sizeof(ChainItem) + (size_t)(lcap + 1) * sizeof(int32_t);
+  return (size_t)(lcap + 1) * plan_ld(cap) * sizeof(ChainItem) +
+         2 * (size_t)(lcap + 1) * sizeof(int32_t);
 }
 
 size_t batch_bytes(morx_system sys, int cap, int aprec) {

@@ -79,7 +79,7 @@ struct IterArgs {
   double* part_norm;   // [2][cap][nblk]
   double* trace;       // [kTraceClasses] or null
   ChainItem* plan;     // [lcap][plan_ld] work lists of the chain steps
-  int32_t* plan_cnt;   // [lcap] chunks per step
+  int32_t* plan_cnt;   // [2][lcap + 1]: chunks per list, then the forward ones
 };
 
 namespace {
@@ -682,10 +682,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_halo(IterArgs a, int s) {
   // per grid row.  The list holds the forward chunks first.
   constexpr bool WALK = MODE == kHaloChain && W == kNarrow;
   int nfwd = 0;
-  if constexpr (WALK) {
-    for (int q = 0; q < nchunks; ++q) nfwd += (gld(&plan[(int64_t)q * NC].flags) & 1) == 0;
-    nfwd = __builtin_amdgcn_readfirstlane(nfwd);
-  }
+  if constexpr (WALK) nfwd = __builtin_amdgcn_readfirstlane(gld(a.plan_cnt + a.lcap + 1 + list));
   const int ngroups = WALK ? 2 : nchunks;
   for (int y = blockIdx.y;; y += gridDim.y) {
     if (y >= ngroups) break;  // uniform over the block
