@@ -13,7 +13,6 @@
 #include <math.h>
 
 #include <algorithm>
-#include <climits>
 #include <cmath>
 
 #include "common.h"
